@@ -1,0 +1,278 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle (oracle/) is checked against things that do not come from itself:
+the paper's printed matrices, the plain definition (classify every k-subset),
+textbook closed forms, trace formulas for cycle counts, per-item counts written
+out from their definitions with numpy, and invariants (sums over items, sum of
+all induced counts = C(n,k), independence of the vertex order).
+"""
+import os
+import random
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import patterns as pat
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_matrix(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rows.append([int(x) for x in line.split()])
+    return rows
+
+
+# ------------------------------------------------------------ pattern library
+
+def test_number_of_isomorphism_classes():
+    # there are 11 graphs on 4 vertices and 34 on 5 (up to isomorphism)
+    assert len(set(pat.canon(4, m) for m in range(1 << 6))) == 11
+    assert len(set(pat.canon(5, m) for m in range(1 << 10))) == 34
+    assert sorted(set(pat.class_lut(4))) == list(range(11))
+    assert sorted(set(pat.class_lut(5))) == list(range(34))
+
+
+def test_connectivity_of_drawings():
+    for _, e in pat.FOUR_CONNECTED:
+        assert pat.is_connected(4, e)
+    for _, e in pat.FOUR_DISCONNECTED:
+        assert not pat.is_connected(4, e)
+    for _, e in pat.FIVE_CONNECTED:
+        assert pat.is_connected(5, e)
+    for _, e in pat.FIVE_DISCONNECTED:
+        assert not pat.is_connected(5, e)
+
+
+def test_matrix_A_equals_paper_fig_A():
+    paper = _read_matrix("paper_fig_A.txt")
+    A = pat.a_matrix(5)
+    assert [list(r[:21]) for r in A[:21]] == paper
+
+
+def test_matrix_Ainv_equals_paper_fig_Ainv():
+    paper = _read_matrix("paper_fig_Ainv.txt")
+    Ai = pat.a_inverse(5)
+    assert [list(r[:21]) for r in Ai[:21]] == paper
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_inverse_sign_rule(k):
+    A = pat.a_matrix(k)
+    Ai = pat.a_inverse(k)
+    n = len(A)
+    for i in range(n):
+        for j in range(n):
+            s = (-1) ** (pat.edge_count(k, j) - pat.edge_count(k, i))
+            assert Ai[i][j] == s * A[i][j]
+
+
+def test_clique_columns_are_textbook_copy_counts():
+    A4 = pat.a_matrix(4)
+    # copies inside K4: 3-stars 4, 3-paths 4!/2, tailed triangles 12, 4-cycles 3, diamonds 6
+    assert [A4[i][5] for i in range(6)] == [4, 12, 12, 3, 6, 1]
+    A5 = pat.a_matrix(5)
+    # inside K5: 4-stars 5, 5-cycles 4!/2, K_{2,3} C(5,2), wheels 5*3, K4+pendant 5*4
+    assert A5[0][20] == 5 and A5[7][20] == 12 and A5[12][20] == 10
+    assert A5[17][20] == 15 and A5[14][20] == 20 and A5[20][20] == 1
+
+
+# ---------------------------------------------------- brute force vs closed forms
+
+def _induced(g, k):
+    return oracle.brute(g, k)
+
+
+def test_brute_empty_and_complete():
+    for n in (4, 7, 10):
+        empty = synth.from_edges(n, [])
+        full = synth.from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+        b4, b5 = _induced(empty, 4), _induced(empty, 5)
+        assert b4[6] == comb(n, 4) and sum(b4) == comb(n, 4)
+        assert b5[21] == comb(n, 5) and sum(b5) == comb(n, 5)
+        c4, c5 = _induced(full, 4), _induced(full, 5)
+        assert c4[5] == comb(n, 4) and sum(c4) == comb(n, 4)
+        assert c5[20] == comb(n, 5) and sum(c5) == comb(n, 5)
+
+
+def test_brute_star_cycle_bipartite():
+    n = 9
+    star = synth.from_edges(n, [(0, v) for v in range(1, n)])
+    b4, b5 = _induced(star, 4), _induced(star, 5)
+    assert b4[0] == comb(n - 1, 3) and b4[6] == comb(n - 1, 4)
+    assert b5[0] == comb(n - 1, 4) and b5[21] == comb(n - 1, 5)
+    for n in (5, 11):
+        cyc = synth.from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+        b5 = _induced(cyc, 5)
+        if n == 5:
+            assert b5[7] == 1
+        else:
+            assert b5[2] == n            # induced paths on 5 vertices
+        b4 = _induced(cyc, 4)
+        if n > 5:
+            assert b4[1] == n            # induced 3-paths
+    for a, b in ((3, 4), (4, 5), (2, 6)):
+        kab = synth.from_edges(a + b, [(u, a + v) for u in range(a) for v in range(b)])
+        b4, b5 = _induced(kab, 4), _induced(kab, 5)
+        assert b4[3] == comb(a, 2) * comb(b, 2)
+        assert b4[0] == a * comb(b, 3) + b * comb(a, 3)
+        assert b5[12] == comb(a, 2) * comb(b, 3) + comb(a, 3) * comb(b, 2)
+        assert b5[0] == a * comb(b, 4) + b * comb(a, 4)
+
+
+def test_brute_three_vertex_matches_adjacency_powers():
+    g = synth.erdos_renyi(25, 0.3, 7)
+    A = _dense(g)
+    tri = int(np.trace(A @ A @ A)) // 6
+    d = A.sum(1)
+    wedges = int(sum(x * (x - 1) // 2 for x in d))
+    b3 = oracle.brute(g, 3)
+    assert b3[3] == tri
+    assert b3[2] == wedges - 3 * tri
+    assert sum(b3) == comb(25, 3)
+
+
+# --------------------------------------------------------- oracle vs definition
+
+def _dense(g):
+    A = np.zeros((g.n, g.n), dtype=np.int64)
+    for u in range(g.n):
+        A[u, g.col[g.row_ptr[u]:g.row_ptr[u + 1]]] = 1
+    return A
+
+
+def _random_graphs():
+    out = []
+    for s in range(24):
+        out.append(synth.erdos_renyi(10 + s % 9, 0.15 + 0.04 * (s % 12), 100 + s))
+    for s in range(16):
+        out.append(synth.chung_lu(16 + s % 8, 2.0 + 0.1 * (s % 5), 4.0 + (s % 4), 12.0, 200 + s))
+    # dense and hub-heavy shapes
+    out.append(synth.erdos_renyi(14, 0.85, 5))
+    out.append(synth.from_edges(13, [(0, v) for v in range(1, 13)] + [(v, v + 1) for v in range(1, 12)]))  # wheel-like fan
+    out.append(synth.from_edges(10, [(u, v) for u in range(5) for v in range(u + 1, 10)]))  # split graph
+    return out
+
+
+@pytest.mark.parametrize("g", _random_graphs(), ids=lambda g: g.name or "special")
+def test_oracle_equals_brute_force(g):
+    got = oracle.count(g, 5)
+    assert got[:11] == _induced(g, 4)
+    assert got[11:] == _induced(g, 5)
+
+
+def test_each_noninduced_formula_against_brute_force():
+    """N = A . C with C from brute force pins each cut formula on its own."""
+    for g in _random_graphs()[:30]:
+        S = oracle.sums(g, 5)
+        for k in (4, 5):
+            C = _induced(g, k)
+            A = pat.a_matrix(k)
+            N_brute = [sum(A[i][j] * C[j] for j in range(len(C))) for i in range(len(C))]
+            assert oracle.noninduced_from_sums(S, k) == N_brute, (g.name, k)
+
+
+def test_small_n_and_degenerate():
+    for n in range(0, 6):
+        for g in (synth.from_edges(n, []), synth.from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n)])):
+            got = oracle.count(g, 5)
+            assert sum(got[:11]) == comb(n, 4)
+            assert sum(got[11:]) == comb(n, 5)
+            if n >= 4:
+                assert got[:11] == _induced(g, 4)
+            if n >= 5:
+                assert got[11:] == _induced(g, 5)
+
+
+def test_order_independence():
+    rng = random.Random(3)
+    for g in _random_graphs()[::3]:
+        base = oracle.count(g, 5)
+        perm = list(range(g.n))
+        rng.shuffle(perm)
+        assert oracle.count(g, 5, order_rank=np.array(perm, dtype=np.int64)) == base
+
+
+def test_relabel_invariance():
+    rng = random.Random(11)
+    g = synth.chung_lu(60, 2.1, 8.0, 30.0, 9)
+    perm = list(range(g.n))
+    rng.shuffle(perm)
+    edges = [(perm[u], perm[int(v)]) for u in range(g.n) for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]] if u < v]
+    h = synth.from_edges(g.n, edges)
+    assert oracle.count(g, 5) == oracle.count(h, 5)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_er200_equals_brute_force(seed):
+    """G(200, 0.05): 2.5e9 five-subsets classified one by one."""
+    g = synth.er_small(seed)
+    got = oracle.count(g, 5)
+    assert got[11:] == _induced(g, 5)
+    assert got[:11] == _induced(g, 4)
+    assert sum(got[11:]) == comb(200, 5)
+
+
+# ------------------------------------------------------- per-item definitions
+
+def test_per_item_counts_match_definitions():
+    g = synth.chung_lu(120, 2.0, 10.0, 60.0, 4)
+    S, it = oracle.sums(g, 5, per_item=True)
+    A = _dense(g)
+    A2 = A @ A
+    n = g.n
+    T = int(np.trace(A2 @ A)) // 6
+    assert S["T"] == T
+    for u in range(n):
+        nbrs = g.col[g.row_ptr[u]:g.row_ptr[u + 1]]
+        sub = A[np.ix_(nbrs, nbrs)]
+        # t(v) = edges inside N(v); K4(v) = triangles inside N(v)
+        assert it["t_v"][u] == sub.sum() // 2
+        assert it["k4_v"][u] == int(np.trace(sub @ sub @ sub)) // 6
+        for p in range(g.row_ptr[u], g.row_ptr[u + 1]):
+            v = int(g.col[p])
+            common = np.nonzero(A[u] & A[v])[0]
+            assert it["t_e"][p] == len(common)
+            assert it["k4_e"][p] == A[np.ix_(common, common)].sum() // 2
+            # 4-cycles through edge uv: u - v - j - x - u with x != v
+            c4 = sum(int(A2[u, j]) - 1 for j in np.nonzero(A[v])[0] if j != u)
+            assert it["c4_e"][p] == c4
+    assert int(it["t_v"].sum()) == 3 * S["T"]
+    assert int(it["t_e"].sum()) == 2 * 3 * S["T"]
+    assert int(it["c4_e"].sum()) == 2 * 4 * S["C4"]
+    assert int(it["c4_v"].sum()) == 4 * S["C4"]
+    assert int(it["k4_v"].sum()) == 4 * S["K4"]
+    assert int(it["k4_e"].sum()) == 2 * 6 * S["K4"]
+
+
+@pytest.mark.parametrize("n,p,seed", [(300, 0.08, 1), (400, 0.03, 2), (250, 0.3, 3)])
+def test_cycle_counts_match_trace_formulas(n, p, seed):
+    """C4 = (tr A^4 - 4 W - 2 m)/8;
+    C5 = (tr A^5 - 5 tr A^3 - 5 sum_i (d_i - 2) (A^3)_ii) / 10."""
+    g = synth.erdos_renyi(n, p, seed)
+    A = _dense(g)
+    d = A.sum(1)
+    A2 = A @ A
+    A3 = A2 @ A
+    m = int(d.sum()) // 2
+    W = int(sum(x * (x - 1) // 2 for x in d))
+    c4 = (int(np.trace(A2 @ A2)) - 4 * W - 2 * m) // 8
+    c5 = (int(np.trace(A3 @ A2)) - 5 * int(np.trace(A3)) - 5 * int(((d - 2) * np.diag(A3)).sum())) // 10
+    S = oracle.sums(g, 5)
+    assert S["C4"] == c4
+    assert S["N8"] == c5
+
+
+def test_sum_of_induced_counts_is_binomial():
+    g = synth.chung_lu(3000, 2.1, 10.0, 300.0, 5)
+    got = oracle.count(g, 5)
+    assert sum(got[:11]) == comb(g.n, 4)
+    assert sum(got[11:]) == comb(g.n, 5)
+    assert min(got) >= 0

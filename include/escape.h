@@ -1,0 +1,147 @@
+/*
+ * escape.h -- C ABI of the MI355X (gfx950) exact 4- and 5-vertex subgraph
+ * counter.
+ *
+ * Method: Pinar, Seshadhri, Vishal, "ESCAPE: Efficiently Counting All
+ * 5-Vertex Subgraphs" (arXiv 1610.09411).  The input is a simple undirected
+ * graph (Sec. 2.1, problem statement); the output is, for every pattern on k
+ * vertices (k = 4 or 5), the number of k-vertex subsets whose induced subgraph
+ * is that pattern (Sec. 2.1; induced counts come from non-induced ones through
+ * the matrix of Appendix B, disconnected patterns through Appendix A).
+ *
+ * Counts are exact unsigned integers.  Every step runs on the GPU: the
+ * degree-ordered DAG (Sec. 2.2), the enumeration of triangles, wedges,
+ * 4-cycles and 4-cliques (Thms 4vertex-tri, 4cycle, 4clique), the cut-formula
+ * sums (Thms 5cutvertex, 5cutedge, 5cuttri, 5cutwed, 5formula), 5-cycles
+ * (Thm 5cycle), 5-cliques (Thm 5clique) and the final linear map.
+ *
+ * Output order (45 slots for k = 5; the first 11 alone for k = 4):
+ *   [0..5]   connected 4-vertex: 3-star, 3-path, tailed triangle, 4-cycle,
+ *            diamond, 4-clique (the 4-vertex row of Fig. 5vertex)
+ *   [6..10]  disconnected 4-vertex: independent set, only edge, matching,
+ *            only wedge, only triangle (Fig. 4vertex-disc)
+ *   [11..31] connected 5-vertex patterns 1..21 (Fig. 5vertex)
+ *   [32..42] disconnected 5-vertex patterns (1)..(11) (Fig. 5vertex-disc)
+ *   [43]     wedge plus a disjoint edge, [44] triangle plus a disjoint edge
+ *            (the two disconnected 5-vertex graphs the figure leaves out)
+ *
+ * Threading: one context per host thread (calls on one context are
+ * serialised by the caller).  No call throws; every error is a status code.
+ */
+#ifndef ESCAPE_H
+#define ESCAPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esc_ctx esc_ctx;
+
+/* Exact count, little-endian 128-bit: value = hi * 2^64 + lo. */
+typedef struct {
+    uint64_t lo, hi;
+} esc_u128;
+
+typedef enum {
+    ESC_OK = 0,
+    ESC_EINVAL = 1,      /* bad argument: null pointer, k not 4/5, n < 0, ... */
+    ESC_ENOTSIMPLE = 2,  /* input not a simple undirected graph in sorted CSR:
+                            self-loop, duplicate, unsorted row, asymmetric */
+    ESC_ERANGE = 3,      /* a column id outside [0, n), or row_ptr not monotone */
+    ESC_ENOMEM = 4,      /* device allocation failed or exceeds the context budget */
+    ESC_EDEVICE = 5,     /* a HIP runtime call failed */
+    ESC_EOVERFLOW = 6    /* a count does not fit the requested output width */
+} esc_status;
+
+/* Flags for esc_count_subgraphs. */
+enum {
+    ESC_F_VALIDATE = 1,        /* check the CSR on the device (ESC_ENOTSIMPLE /
+                                  ESC_ERANGE on failure); without it the input
+                                  must already be simple, sorted and symmetric */
+    ESC_F_INPUT_ON_DEVICE = 4, /* row_ptr / col are device pointers */
+    ESC_F_RANDOM_ORDER = 8     /* orient by a seeded pseudo-random total order
+                                  instead of the degree order (test hook: counts
+                                  do not depend on the order, work does) */
+};
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
+ * device memory the context may hold (0 = no cap).  On success *out owns all
+ * device scratch memory; release it with esc_destroy. */
+esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budget_bytes);
+
+/* Release every resource held by the context.  NULL is ignored. */
+void esc_destroy(esc_ctx *ctx);
+
+/* Count all induced k-vertex patterns of one graph.
+ *   n        number of vertices, 0 <= n < 2^31
+ *   row_ptr  n+1 int32 offsets, row_ptr[0] = 0, non-decreasing
+ *   col      row_ptr[n] int32 neighbour ids: each undirected edge appears in
+ *            both rows, rows sorted ascending, no self-loops, no duplicates
+ *   k        4 or 5
+ *   flags    ESC_F_* bits
+ *   out      host array of 11 (k = 4) or 45 (k = 5) esc_u128, in the order
+ *            documented above; untouched on error
+ *   stream   hipStream_t to run on, or NULL for the context's own stream
+ * Input arrays are read-only and not retained after return (host arrays are
+ * copied to the device; device arrays are read in place).  n < k is valid: the
+ * k-vertex counts are then all zero.  The call returns after the counts are on
+ * the host. */
+esc_status esc_count_subgraphs(esc_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                               const int32_t *col, int k, uint32_t flags,
+                               esc_u128 *out, void *stream);
+
+/* Same enumeration, also returning the per-vertex and per-edge fragment counts
+ * of Thm 4vertex-tri, in the caller's vertex ids:
+ *   tri_v, c4_v, k4_v   n uint64 each: triangles, 4-cycles and 4-cliques
+ *                       containing each vertex
+ *   tri_e, c4_e, k4_e   row_ptr[n] uint64 each, one per arc of the input CSR
+ *                       (both arcs of an edge carry the edge's value):
+ *                       triangles, 4-cycles and 4-cliques containing the edge
+ * Any output pointer may be NULL.  Host memory.  Counts of the k-vertex
+ * patterns go to `out` exactly as in esc_count_subgraphs. */
+esc_status esc_count_fragments(esc_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                               const int32_t *col, int k, uint32_t flags,
+                               esc_u128 *out,
+                               uint64_t *tri_v, uint64_t *c4_v, uint64_t *k4_v,
+                               uint64_t *tri_e, uint64_t *c4_e, uint64_t *k4_e,
+                               void *stream);
+
+/* Work counters of the last successful call on this context (Thm fourvertex
+ * and Thm fivevertex state the running time in these terms):
+ *   [0] W++  out-wedges of the DAG      [1] W+-  in-out wedges
+ *   [2] W    wedges                     [3] T    triangles
+ *   [4] D    diamonds                   [5] max out-degree
+ *   [6] n    vertices                   [7] m    edges
+ * `out` is a host array of 8 uint64. */
+esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out);
+
+/* Per-stage profile of the last successful call.  Stages, in order:
+ *   [0] degree order and relabelled CSR      [1] triangles, per-arc lists
+ *   [2] 4-cycles                             [3] per-triangle pass (4- and
+ *       5-cliques, triangle-cut sums)        [4] vertex and edge sums
+ *   [5] pattern 13/17 pair pass              [6] wheels (pattern 18)
+ *   [7] 5-cycles                             [8] final combination
+ * `ms_out` (9 floats, may be NULL): device milliseconds per stage (HIP events
+ * on the call's stream).  `visits_out` (9 uint64, may be NULL): elements the
+ * stage's main loop visited (neighbour or triangle-list entries read; 0 where
+ * not counted). */
+esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64_t *visits_out);
+
+/* The signed inverse of the matrix that maps induced to non-induced counts
+ * (Appendix B, figures A and A^-1), as the library builds and applies it:
+ * 11 x 11 for k = 4, 34 x 34 for k = 5, rows and columns in the output order
+ * above, row-major into the host array `out`.  Host-only (no device call);
+ * ESC_EINVAL for other k or a NULL pointer. */
+esc_status esc_inverse_matrix(int k, int32_t *out);
+
+/* Human-readable text for a status code (static storage). */
+const char *esc_strerror(esc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESCAPE_H */

@@ -1,0 +1,220 @@
+"""Exact induced 4- and 5-vertex subgraph counts on an MI355X (gfx950).
+
+Thin ctypes binding over ``libescape.so`` (C ABI in ``include/escape.h``); the
+functions keep the ABI's names.  Every step of the computation runs in the
+library's HIP kernels; this module only marshals arguments.  PyTorch is used
+for device memory and streams when the caller passes device tensors.
+
+    import paper_1610_09411_amd as esc
+    ctx = esc.esc_create(0)
+    counts = esc.esc_count_subgraphs(ctx, n, row_ptr, col, k=5)   # 45 Python ints
+    esc.esc_destroy(ctx)
+
+The library must have been built (``python -m paper_1610_09411_amd.build``);
+without it every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libescape.so")
+
+ESC_OK, ESC_EINVAL, ESC_ENOTSIMPLE, ESC_ERANGE, ESC_ENOMEM, ESC_EDEVICE, ESC_EOVERFLOW = range(7)
+ESC_F_VALIDATE = 1
+ESC_F_INPUT_ON_DEVICE = 4
+ESC_F_RANDOM_ORDER = 8
+
+ABI_FUNCTIONS = [
+    "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments",
+    "esc_last_work", "esc_last_profile", "esc_inverse_matrix", "esc_strerror",
+]
+
+PATTERN_NAMES = [
+    "3-star", "3-path", "tailed-triangle", "4-cycle", "diamond", "4-clique",
+    "4-ind-set", "4-only-edge", "4-matching", "4-only-wedge", "4-only-triangle",
+] + ["P%d" % i for i in range(1, 22)] + [
+    "5-ind-set", "5-only-edge", "5-matching", "5-only-wedge", "5-only-triangle",
+    "5-only-3-star", "5-only-3-path", "5-only-tailed-triangle", "5-only-4-cycle",
+    "5-only-diamond", "5-only-4-clique", "5-wedge+edge", "5-triangle+edge",
+]
+
+
+class EscapeError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (where, esc_strerror(status), status))
+
+
+class _U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libescape.so is not built; run `python -m paper_1610_09411_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+        lib.esc_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t]
+        lib.esc_create.restype = ctypes.c_int
+        lib.esc_destroy.argtypes = [vp]
+        lib.esc_destroy.restype = None
+        lib.esc_count_subgraphs.argtypes = [vp, i32, vp, vp, ctypes.c_int, u32, vp, vp]
+        lib.esc_count_subgraphs.restype = ctypes.c_int
+        lib.esc_count_fragments.argtypes = [vp, i32, vp, vp, ctypes.c_int, u32, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.esc_count_fragments.restype = ctypes.c_int
+        lib.esc_last_work.argtypes = [vp, vp]
+        lib.esc_last_work.restype = ctypes.c_int
+        lib.esc_last_profile.argtypes = [vp, vp, vp]
+        lib.esc_last_profile.restype = ctypes.c_int
+        lib.esc_inverse_matrix.argtypes = [ctypes.c_int, vp]
+        lib.esc_inverse_matrix.restype = ctypes.c_int
+        lib.esc_strerror.argtypes = [ctypes.c_int]
+        lib.esc_strerror.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def esc_strerror(status: int) -> str:
+    return _load().esc_strerror(status).decode()
+
+
+def _check(status, where):
+    if status != ESC_OK:
+        raise EscapeError(status, where)
+
+
+class Context:
+    """Owns an ``esc_ctx``; usable as a context manager."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.ptr = esc_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.ptr:
+            esc_destroy(self.ptr)
+            self.ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def count(self, graph, k=5, flags=0, stream=None):
+        return esc_count_subgraphs(self.ptr, graph.n, graph.row_ptr, graph.col, k, flags, stream)
+
+    def fragments(self, graph, k=5, flags=0, stream=None):
+        return esc_count_fragments(self.ptr, graph.n, graph.row_ptr, graph.col, k, flags, stream)
+
+    def last_work(self):
+        return esc_last_work(self.ptr)
+
+    def last_profile(self):
+        return esc_last_profile(self.ptr)
+
+
+def esc_create(device: int = 0, hbm_budget_bytes: int = 0):
+    ptr = ctypes.c_void_p()
+    _check(_load().esc_create(ctypes.byref(ptr), device, hbm_budget_bytes), "esc_create")
+    return ptr
+
+
+def esc_destroy(ctx):
+    _load().esc_destroy(ctx)
+
+
+def _csr_args(row_ptr, col, flags):
+    """Pointers for host numpy arrays or device torch tensors."""
+    try:
+        import torch
+        is_dev = isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda
+    except ImportError:  # pragma: no cover
+        is_dev = False
+    if is_dev:
+        if row_ptr.dtype != torch.int32 or col.dtype != torch.int32:
+            raise TypeError("device CSR must be int32")
+        return (ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                flags | ESC_F_INPUT_ON_DEVICE, (row_ptr, col))
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    return rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p), flags, (rp, ci)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ints(buf, cnt):
+    return [buf[i].lo | (buf[i].hi << 64) for i in range(cnt)]
+
+
+def esc_count_subgraphs(ctx, n, row_ptr, col, k=5, flags=0, stream=None):
+    """Induced counts of all k-vertex patterns (11 for k=4, 45 for k=5)."""
+    rp, ci, flags, keep = _csr_args(row_ptr, col, flags)
+    out = (_U128 * 45)()
+    st = _load().esc_count_subgraphs(ctx, int(n), rp, ci, int(k), flags, out, _stream_ptr(stream))
+    _check(st, "esc_count_subgraphs")
+    del keep
+    return _ints(out, 11 if k == 4 else 45)
+
+
+def esc_count_fragments(ctx, n, row_ptr, col, k=5, flags=0, stream=None):
+    """Counts plus per-vertex / per-arc fragment arrays (numpy uint64):
+    returns (counts, {"tri_v","c4_v","k4_v","tri_e","c4_e","k4_e"})."""
+    rp, ci, flags, keep = _csr_args(row_ptr, col, flags)
+    m2 = int(keep[0][-1]) if not (flags & ESC_F_INPUT_ON_DEVICE) else int(keep[0][-1].item())
+    arrs = {name: np.zeros(int(n) if name.endswith("_v") else m2, dtype=np.uint64)
+            for name in ("tri_v", "c4_v", "k4_v", "tri_e", "c4_e", "k4_e")}
+    ptrs = [arrs[x].ctypes.data_as(ctypes.c_void_p) for x in ("tri_v", "c4_v", "k4_v", "tri_e", "c4_e", "k4_e")]
+    out = (_U128 * 45)()
+    st = _load().esc_count_fragments(ctx, int(n), rp, ci, int(k), flags, out, *ptrs, _stream_ptr(stream))
+    _check(st, "esc_count_fragments")
+    del keep
+    return _ints(out, 11 if k == 4 else 45), arrs
+
+
+def esc_last_work(ctx):
+    out = (ctypes.c_uint64 * 8)()
+    _check(_load().esc_last_work(ctx, out), "esc_last_work")
+    keys = ["W++", "W+-", "W", "T", "D", "max_dplus", "n", "m"]
+    return dict(zip(keys, [int(x) for x in out]))
+
+
+STAGES = ["orient", "triangles", "four_cycles", "triangle_pass", "reduce", "pairs_13_17", "wheels",
+          "five_cycles", "combine"]
+
+
+def esc_last_profile(ctx):
+    """{stage: (device ms, elements visited)} of the last call."""
+    ms = (ctypes.c_float * 9)()
+    vis = (ctypes.c_uint64 * 9)()
+    _check(_load().esc_last_profile(ctx, ms, vis), "esc_last_profile")
+    return {k: (float(ms[i]), int(vis[i])) for i, k in enumerate(STAGES)}
+
+
+def esc_inverse_matrix(k):
+    """The library's signed inverse of the induced-to-non-induced matrix
+    (11x11 for k=4, 34x34 for k=5), host-only."""
+    cnt = 11 if k == 4 else 34
+    out = (ctypes.c_int32 * (cnt * cnt))()
+    _check(_load().esc_inverse_matrix(int(k), out), "esc_inverse_matrix")
+    return [[int(out[i * cnt + j]) for j in range(cnt)] for i in range(cnt)]

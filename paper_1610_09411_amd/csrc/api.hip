@@ -1,0 +1,284 @@
+// C ABI entry points (include/escape.h): context, memory, pipeline order.
+#include <stdlib.h>
+#include <string.h>
+#include "device.h"
+#include "ctx.h"
+
+void *ctx_buf(esc_ctx *c, Buf b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (c->buf[b] && c->cap[b] >= bytes) return c->buf[b];
+    if (c->buf[b]) {
+        hipStreamSynchronize(c->stream);
+        hipFree(c->buf[b]);
+        c->held -= c->cap[b];
+        c->buf[b] = nullptr;
+        c->cap[b] = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    want = (want + ((size_t)2 << 20) - 1) & ~(((size_t)2 << 20) - 1);
+    if (c->budget && c->held + want > c->budget) return nullptr;
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    c->buf[b] = p;
+    c->cap[b] = want;
+    c->held += want;
+    if (b == B_WG_SCRATCH) {
+        // the pair passes rely on these tables being zero between uses
+        if (hipMemsetAsync(p, 0, want, c->stream) != hipSuccess) return nullptr;
+    }
+    return p;
+}
+
+extern "C" const char *esc_strerror(esc_status s) {
+    switch (s) {
+        case ESC_OK: return "ok";
+        case ESC_EINVAL: return "invalid argument";
+        case ESC_ENOTSIMPLE: return "input is not a simple undirected graph in sorted symmetric CSR";
+        case ESC_ERANGE: return "vertex id or row offset out of range";
+        case ESC_ENOMEM: return "device memory exhausted or over the context budget";
+        case ESC_EDEVICE: return "HIP runtime error";
+        case ESC_EOVERFLOW: return "count does not fit the output width";
+    }
+    return "unknown status";
+}
+
+extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budget_bytes) {
+    if (!out) return ESC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ESC_EDEVICE;
+    if (hip_device < 0 || hip_device >= ndev) return ESC_EINVAL;
+    HIP_TRY(hipSetDevice(hip_device));
+    esc_ctx *c = (esc_ctx *)calloc(1, sizeof(esc_ctx));
+    if (!c) return ESC_ENOMEM;
+    c->device = hip_device;
+    c->budget = hbm_budget_bytes;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess || cu <= 0) cu = 256;
+    c->num_cu = cu;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) != hipSuccess || lds <= 0)
+        lds = 65536;
+    c->max_lds = lds;
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) { free(c); return ESC_EDEVICE; }
+    c->stream = c->own_stream;
+    for (int i = 0; i < 10; i++)
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
+    int32_t h4[121], h5[1156];
+    combine_tables(h4, h5);
+    if (hipMalloc((void **)&c->d_inv4, sizeof(h4)) != hipSuccess ||
+        hipMalloc((void **)&c->d_inv5, sizeof(h5)) != hipSuccess) { esc_destroy(c); return ESC_ENOMEM; }
+    if (hipMemcpy(c->d_inv4, h4, sizeof(h4), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_inv5, h5, sizeof(h5), hipMemcpyHostToDevice) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
+    c->scratch_clean = true;
+    *out = c;
+    return ESC_OK;
+}
+
+extern "C" void esc_destroy(esc_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->own_stream) hipStreamSynchronize(c->own_stream);
+    for (int b = 0; b < B_COUNT; b++)
+        if (c->buf[b]) hipFree(c->buf[b]);
+    if (c->d_inv4) hipFree(c->d_inv4);
+    if (c->d_inv5) hipFree(c->d_inv5);
+    for (int i = 0; i < 10; i++)
+        if (c->ev[i]) hipEventDestroy(c->ev[i]);
+    if (c->own_stream) hipStreamDestroy(c->own_stream);
+    free(c);
+}
+
+// per input vertex / arc: fragment counts in the caller's ids
+__global__ void k_fragments_out(int32_t n, const int32_t *rp, const int32_t *col, const int32_t *rank,
+                                const int32_t *off, const int32_t *adj, const int32_t *arc_eid, const uint32_t *te,
+                                const unsigned long long *c4e, const unsigned long long *k4e, const uint64_t *tv,
+                                uint64_t *o_tv, uint64_t *o_c4v, uint64_t *o_k4v, uint64_t *o_te, uint64_t *o_c4e,
+                                uint64_t *o_k4e) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t r = rank[v];
+        uint64_t c4 = 0, k4 = 0;
+        for (int32_t p = off[r]; p < off[r + 1]; p++) {
+            int32_t e = arc_eid[p];
+            c4 += c4e ? c4e[e] : 0;
+            k4 += k4e[e];
+        }
+        o_tv[v] = tv[r];
+        o_c4v[v] = c4 / 2;
+        o_k4v[v] = k4 / 3;
+        for (int32_t p = rp[v]; p < rp[v + 1]; p++) {
+            int32_t y = rank[col[p]];
+            int32_t q = lower_bound_i32(adj, off[r], off[r + 1], y);
+            int32_t e = arc_eid[q];
+            o_te[p] = te[e];
+            o_c4e[p] = c4e ? c4e[e] : 0;
+            o_k4e[p] = k4e[e];
+        }
+    }
+}
+
+static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags,
+                      esc_u128 *out, uint64_t **frag, void *stream) {
+    if (!c || !out || (k != 4 && k != 5) || n < 0) return ESC_EINVAL;
+    if (n > 0 && (!row_ptr || (!col && flags & ESC_F_INPUT_ON_DEVICE))) return ESC_EINVAL;
+    if (!row_ptr) return ESC_EINVAL;
+    if (k == 5 && n > 100000000) return ESC_EOVERFLOW;   // C(n,5) must fit 128 bits with headroom
+    HIP_TRY(hipSetDevice(c->device));
+    c->stream = stream ? (hipStream_t)stream : c->own_stream;
+    hipStream_t st = c->stream;
+    int32_t rp0 = 0, m2 = 0;
+    const bool on_dev = (flags & ESC_F_INPUT_ON_DEVICE) != 0;
+    if (on_dev) {
+        HIP_TRY(hipMemcpyAsync(&rp0, row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&m2, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        rp0 = row_ptr[0];
+        m2 = row_ptr[n];
+    }
+    if (rp0 != 0 || m2 < 0) return ESC_ERANGE;
+    if (m2 & 1) return ESC_ENOTSIMPLE;
+    if (m2 > 0 && !col) return ESC_EINVAL;
+    c->n = n;
+    c->m2 = m2;
+    c->m = m2 / 2;
+    c->k = k;
+    c->flags = flags;
+    esc_status s = ESC_OK;
+    const int32_t *d_rp = row_ptr, *d_col = col;
+    if (!on_dev) {
+        int32_t *brp = (int32_t *)ctx_buf(c, B_RP_IN, sizeof(int32_t) * ((size_t)n + 1));
+        int32_t *bcol = (int32_t *)ctx_buf(c, B_COL_IN, sizeof(int32_t) * ((size_t)m2 + 1));
+        if (!brp || !bcol) return ESC_ENOMEM;
+        HIP_TRY(hipMemcpyAsync(brp, row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, st));
+        if (m2) HIP_TRY(hipMemcpyAsync(bcol, col, sizeof(int32_t) * (size_t)m2, hipMemcpyHostToDevice, st));
+        d_rp = brp;
+        d_col = bcol;
+    }
+    unsigned long long *acc = (unsigned long long *)ctx_buf(c, B_ACC, sizeof(uint64_t) * 2 * AC_COUNT);
+    uint64_t *work = (uint64_t *)ctx_buf(c, B_WORK, sizeof(uint64_t) * WORK_WORDS);
+    if (!acc || !work) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(acc, 0, sizeof(uint64_t) * 2 * AC_COUNT, st));
+    HIP_TRY(hipMemsetAsync(work, 0, sizeof(uint64_t) * WORK_WORDS, st));
+    if (!c->scratch_clean && c->buf[B_WG_SCRATCH]) {
+        HIP_TRY(hipMemsetAsync(c->buf[B_WG_SCRATCH], 0, c->cap[B_WG_SCRATCH], st));
+    }
+    c->scratch_clean = false;   // until the pipeline completes
+    HIP_TRY(hipEventRecord(c->ev[0], st));
+    s = stage_orient(c, d_rp, d_col);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(c->ev[1], st));
+    s = stage_triangles(c);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(c->ev[2], st));
+    s = stage_four(c, frag != nullptr);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(c->ev[3], st));
+    s = stage_triangle_sums(c);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(c->ev[4], st));
+    s = stage_reduce(c);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(c->ev[5], st));
+    if (k == 5) {
+        s = stage_pairs(c);
+        if (s) return s;
+    }
+    HIP_TRY(hipEventRecord(c->ev[6], st));
+    if (k == 5) {
+        s = stage_wheels(c);
+        if (s) return s;
+    }
+    HIP_TRY(hipEventRecord(c->ev[7], st));
+    if (k == 5) {
+        s = stage_cycles(c);
+        if (s) return s;
+    }
+    HIP_TRY(hipEventRecord(c->ev[8], st));
+    s = stage_combine(c, out, c->d_inv4, c->d_inv5);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(c->ev[9], st));
+    if (frag) {
+        size_t nn = (size_t)n, aa = (size_t)m2;
+        uint64_t *fb = (uint64_t *)ctx_buf(c, B_FRAG, sizeof(uint64_t) * (3 * nn + 3 * aa + 8));
+        if (!fb) return ESC_ENOMEM;
+        uint64_t *o_tv = fb, *o_c4v = fb + nn, *o_k4v = fb + 2 * nn;
+        uint64_t *o_te = fb + 3 * nn, *o_c4e = o_te + aa, *o_k4e = o_c4e + aa;
+        if (n > 0) {
+            int g = (int)((n + 255) / 256);
+            if (g > c->num_cu * 16) g = c->num_cu * 16;
+            k_fragments_out<<<g, 256, 0, st>>>(n, d_rp, d_col, (const int32_t *)c->buf[B_RANK],
+                                               (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+                                               (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TE],
+                                               (const unsigned long long *)c->buf[B_C4E],
+                                               (const unsigned long long *)c->buf[B_K4E],
+                                               (const uint64_t *)c->buf[B_TV], o_tv, o_c4v, o_k4v, o_te, o_c4e, o_k4e);
+            HIP_TRY(hipGetLastError());
+        }
+        uint64_t *src[6] = {o_tv, o_c4v, o_k4v, o_te, o_c4e, o_k4e};
+        size_t cnt[6] = {nn, nn, nn, aa, aa, aa};
+        for (int i = 0; i < 6; i++)
+            if (frag[i] && cnt[i]) HIP_TRY(hipMemcpyAsync(frag[i], src[i], sizeof(uint64_t) * cnt[i], hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    // work counters
+    uint64_t hw[WORK_WORDS];
+    unsigned long long hacc[2 * AC_COUNT];
+    HIP_TRY(hipMemcpyAsync(hw, work, sizeof(hw), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hacc, acc, sizeof(hacc), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    c->work[0] = hw[0];
+    c->work[1] = hw[1];
+    c->work[2] = hacc[2 * AC_W];
+    c->work[3] = hacc[2 * AC_T3] / 3;
+    c->work[4] = hacc[2 * AC_D];
+    c->work[5] = (uint64_t)c->maxdplus;
+    c->work[6] = (uint64_t)n;
+    c->work[7] = (uint64_t)c->m;
+    for (int i = 0; i < 9; i++) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+        c->stage_ms[i] = ms;
+        c->visits[i] = hw[WORK_VISITS + i];
+    }
+    c->scratch_clean = true;
+    return ESC_OK;
+}
+
+extern "C" esc_status esc_count_subgraphs(esc_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col, int k,
+                                          uint32_t flags, esc_u128 *out, void *stream) {
+    return run(ctx, n, row_ptr, col, k, flags, out, nullptr, stream);
+}
+
+extern "C" esc_status esc_count_fragments(esc_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col, int k,
+                                          uint32_t flags, esc_u128 *out, uint64_t *tri_v, uint64_t *c4_v,
+                                          uint64_t *k4_v, uint64_t *tri_e, uint64_t *c4_e, uint64_t *k4_e,
+                                          void *stream) {
+    uint64_t *frag[6] = {tri_v, c4_v, k4_v, tri_e, c4_e, k4_e};
+    return run(ctx, n, row_ptr, col, k, flags, out, frag, stream);
+}
+
+extern "C" esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out) {
+    if (!ctx || !out) return ESC_EINVAL;
+    memcpy(out, ctx->work, sizeof(uint64_t) * 8);
+    return ESC_OK;
+}
+
+extern "C" esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64_t *visits_out) {
+    if (!ctx) return ESC_EINVAL;
+    if (ms_out) memcpy(ms_out, ctx->stage_ms, sizeof(float) * 9);
+    if (visits_out) memcpy(visits_out, ctx->visits, sizeof(uint64_t) * 9);
+    return ESC_OK;
+}
+
+extern "C" esc_status esc_inverse_matrix(int k, int32_t *out) {
+    if (!out || (k != 4 && k != 5)) return ESC_EINVAL;
+    int32_t h4[121], h5[1156];
+    combine_tables(h4, h5);
+    if (k == 4) memcpy(out, h4, sizeof(h4));
+    else memcpy(out, h5, sizeof(h5));
+    return ESC_OK;
+}

@@ -1,0 +1,121 @@
+// Host-side context shared by the pipeline stages.  All device memory is
+// owned here: buffers grow on demand and are reused across calls.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include "../../include/escape.h"
+
+// Indices of the exact 128-bit sums produced on the device.  Each stage adds
+// its terms into acc[2*slot] (lo) / acc[2*slot+1] (hi).
+enum AccSlot {
+    AC_W,      // sum_v C(d,2)                      wedges
+    AC_S3,     // sum_v C(d,3)                      3-stars
+    AC_S4,     // sum_v C(d,4)                      4-stars (pattern 1)
+    AC_T3,     // sum_e t(e) = 3 T
+    AC_TT,     // sum_v t(v)(d(v)-2)                tailed triangles
+    AC_D,      // sum_e C(t(e),2)                   diamonds
+    AC_C4,     // 4-cycles
+    AC_K4X4,   // sum_t K4(t) = 4 K4
+    AC_EP,     // sum_e (d(u)-1)(d(v)-1)
+    AC_N2,     // sum over ordered edges (d(j)-1) C(d(i)-1,2)
+    AC_N3,     // sum_i sum_{j<k in N(i)} (d(j)-1)(d(k)-1)
+    AC_N4,     // sum_i t(i) C(d(i)-2,2)
+    AC_N5,     // sum over ordered edges (d(i)-1)(t(j)-t(ij))
+    AC_N6,     // sum_e t(e)(d(u)-2)(d(v)-2)
+    AC_N7X2,   // sum_e C4(e)(d(u)+d(v)-4) = 2 sum_v C4(v)(d(v)-2)
+    AC_N9,     // sum_v C(t(v),2)
+    AC_N10,    // sum_t sum_{k in t} (t(opposite edge)-1)(d(k)-2)
+    AC_N11,    // sum over ordered edges C(t(e),2)(d(i)-3)
+    AC_N12,    // sum_e C4(e) t(e)
+    AC_N13,    // sum over pairs C(W(i,j),3)
+    AC_N14,    // sum_e C(t(e),3)
+    AC_N15,    // sum_v K4(v)(d(v)-3)
+    AC_N16,    // sum_t sum_{i in t} (t(ij)-1)(t(ik)-1)
+    AC_N17,    // sum over pairs (W(i,j)-2) D(i,j)
+    AC_N18,    // wheels
+    AC_N19,    // sum_e K4(e)(t(e)-2)
+    AC_N20,    // sum_t C(K4(t),2)
+    AC_CYC,    // sum over ordered pairs P(i,j) Wnt(i,j)
+    AC_Z,      // directed tailed triangles of the 5-cycle correction
+    AC_K5,     // 5-cliques
+    AC_SW,     // sum_b [C(d_b,2) d_b + (d_b-1) sum_{a in N(b)} d_a]
+    AC_TD,     // sum_v t(v) d(v)
+    AC_COUNT
+};
+
+enum Buf {
+    B_RP_IN, B_COL_IN,          // input CSR copied to the device
+    B_DEG, B_PERM, B_RANK,      // degree (input ids), rank -> input id, input id -> rank
+    B_KEYS_A, B_KEYS_B, B_VALS_A, B_VALS_B, B_HIST,
+    B_OFF, B_ADJ, B_SPLIT,      // relabelled CSR (rank ids), rows sorted
+    B_EOFF, B_ARC_EID, B_REV,   // out-arc prefix, edge id of each arc, reverse arc
+    B_EARC, B_ELO,              // out-arc position and lower endpoint of each edge
+    B_TE, B_TV, B_K4E, B_C4E,   // per-edge / per-vertex fragment counts
+    B_AOFF, B_ACUR, B_AA, B_AV, // per-arc triangle lists: offsets, cursors, arc index of apex, apex id
+    B_SEGCLS, B_SEGQ,           // segmented-sort work lists
+    B_SCAN_TMP,
+    B_ACC, B_ERR, B_OUT, B_WORK,
+    B_WG_SCRATCH,               // per-workgroup dense tables for the pair passes
+    B_WG_TOUCH,
+    B_TASK,
+    B_FRAG,                     // fragment outputs in input order
+    B_COUNT
+};
+
+struct esc_ctx {
+    int device;
+    size_t budget;
+    hipStream_t own_stream;
+    hipStream_t stream;        // stream of the current call
+    void *buf[B_COUNT];
+    size_t cap[B_COUNT];
+    size_t held;
+    int num_cu;
+    int max_lds;               // bytes of LDS one workgroup may allocate
+    uint64_t work[8];
+    float stage_ms[9];
+    uint64_t visits[9];
+    hipEvent_t ev[10];
+    // current graph
+    int32_t n;
+    int64_t m2;                // number of arcs (2m)
+    int64_t m;
+    int64_t narcs_apex;        // total per-arc triangle list entries (6T)
+    int32_t maxdeg;
+    int32_t maxdplus;
+    int k;
+    uint32_t flags;
+    bool scratch_clean;        // per-workgroup tables are all zero
+    int32_t *d_inv4, *d_inv5;  // signed inverse matrices (Appendix B), device copies
+};
+
+// Grow-only device buffer; returns nullptr on failure (status set by caller).
+void *ctx_buf(esc_ctx *c, Buf b, size_t bytes);
+esc_status ctx_check(hipError_t e);
+
+// B_WORK layout: [0] W++, [1] W+-, [2 + s] visits of stage s (see esc_last_profile)
+#define WORK_VISITS 2
+#define WORK_WORDS 16
+
+#define ESC_TRY(x) do { esc_status _s = (x); if (_s != ESC_OK) return _s; } while (0)
+#define HIP_TRY(x) do { hipError_t _e = (x); if (_e != hipSuccess) return ESC_EDEVICE; } while (0)
+
+// pipeline stages (each returns ESC_OK or an error)
+esc_status stage_orient(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col);
+esc_status stage_triangles(esc_ctx *c);
+esc_status stage_four(esc_ctx *c, bool per_edge_c4);
+esc_status stage_pairs(esc_ctx *c);
+esc_status stage_wheels(esc_ctx *c);
+esc_status stage_cycles(esc_ctx *c);
+esc_status stage_triangle_sums(esc_ctx *c);
+esc_status stage_reduce(esc_ctx *c);
+esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, const int32_t *d_inv5);
+esc_status combine_tables(int32_t *host_inv4, int32_t *host_inv5);
+esc_status stage_fragments_out(esc_ctx *c, uint64_t *tri_v, uint64_t *c4_v, uint64_t *k4_v,
+                               uint64_t *tri_e, uint64_t *c4_e, uint64_t *k4_e);
+
+// generic device primitives (orient.hip)
+esc_status dev_exclusive_scan_i64(esc_ctx *c, const int64_t *in, int64_t *out, int64_t n);
+esc_status dev_segsort_u32(esc_ctx *c, uint32_t *keys, const int64_t *seg_off, int64_t nseg,
+                           int32_t maxlen);

@@ -1,0 +1,129 @@
+// Device-side helpers shared by the gfx950 kernels: exact 128-bit
+// accumulation, block reductions and scans, load-balanced expansion of
+// variable-length segments across a workgroup.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+#define ESC_WAVE 64
+
+// Two 64-bit words hold one exact 128-bit sum.  Adding x: add the low word
+// atomically; a wrap of that word is a carry into the high word.  Every
+// individual addition detects its own wrap, so the total is exact.
+__device__ inline void atomic_add_u128(unsigned long long *slot, u128 x) {
+    unsigned long long lo = (unsigned long long)x;
+    unsigned long long hi = (unsigned long long)(x >> 64);
+    if (lo) {
+        unsigned long long old = atomicAdd(slot, lo);
+        if (old + lo < old) hi += 1;
+    }
+    if (hi) atomicAdd(slot + 1, hi);
+}
+
+__device__ inline u128 shfl_xor_u128(u128 x, int mask) {
+    unsigned long long lo = (unsigned long long)x, hi = (unsigned long long)(x >> 64);
+    lo = __shfl_xor(lo, mask);
+    hi = __shfl_xor(hi, mask);
+    return ((u128)hi << 64) | lo;
+}
+
+__device__ inline u128 wave_sum_u128(u128 x) {
+    for (int o = ESC_WAVE / 2; o > 0; o >>= 1) x += shfl_xor_u128(x, o);
+    return x;
+}
+
+// Sum NV 128-bit values over the block and add them to `slots[2*s]`.
+// `scratch` must hold NV * (blockDim/64) u128 in LDS.
+template <int NV>
+__device__ inline void block_flush_u128(u128 (&v)[NV], u128 *scratch, unsigned long long *slots,
+                                        const int *slot_ids) {
+    const int lane = threadIdx.x & (ESC_WAVE - 1), wid = threadIdx.x / ESC_WAVE;
+    const int nw = blockDim.x / ESC_WAVE;
+#pragma unroll
+    for (int s = 0; s < NV; s++) {
+        u128 x = wave_sum_u128(v[s]);
+        if (lane == 0) scratch[s * nw + wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        u128 t = 0;
+        for (int w = 0; w < nw; w++) t += scratch[threadIdx.x * nw + w];
+        if (t) atomic_add_u128(slots + 2 * slot_ids[threadIdx.x], t);
+    }
+    __syncthreads();
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t x) {
+    for (int o = ESC_WAVE / 2; o > 0; o >>= 1) x += __shfl_xor((unsigned long long)x, o);
+    return x;
+}
+
+// Exclusive scan of one int per thread over the block; returns the prefix and
+// writes the total into *total.  `tmp` holds blockDim/64 + 1 ints in LDS.
+__device__ inline int block_exclusive_scan(int x, int *tmp, int *total) {
+    const int lane = threadIdx.x & (ESC_WAVE - 1), wid = threadIdx.x / ESC_WAVE;
+    const int nw = blockDim.x / ESC_WAVE;
+    int incl = x;
+    for (int o = 1; o < ESC_WAVE; o <<= 1) {
+        int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == ESC_WAVE - 1) tmp[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < nw; w++) { int t = tmp[w]; tmp[w] = run; run += t; }
+        tmp[nw] = run;
+    }
+    __syncthreads();
+    int res = tmp[wid] + incl - x;
+    *total = tmp[nw];
+    __syncthreads();
+    return res;
+}
+
+// Load-balanced expansion.  A batch of up to blockDim segments, thread t
+// describing segment t by (start, len); every element (segment s, position
+// start_s + r) is visited exactly once, spread evenly over the block.
+// `pref` and `beg` are LDS arrays of blockDim+1 entries, `tmp` as above.
+template <class Item>
+__device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg, int *tmp, Item item) {
+    int total;
+    int ex = block_exclusive_scan(len, tmp, &total);
+    pref[threadIdx.x] = ex;
+    beg[threadIdx.x] = start;
+    if (threadIdx.x == 0) pref[blockDim.x] = total;
+    __syncthreads();
+    for (int x = threadIdx.x; x < total; x += blockDim.x) {
+        // last segment whose prefix is <= x
+        int lo = 0, hi = blockDim.x - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (pref[mid] <= x) lo = mid; else hi = mid - 1;
+        }
+        item(lo, beg[lo] + (x - pref[lo]));
+    }
+    __syncthreads();
+}
+
+// add a per-thread count to a global counter, one atomic per wave
+__device__ inline void flush_count(uint64_t x, unsigned long long *dst) {
+    x = wave_sum_u64(x);
+    if ((threadIdx.x & (ESC_WAVE - 1)) == 0 && x) atomicAdd(dst, (unsigned long long)x);
+}
+
+__device__ inline uint64_t c2(uint64_t x) { return x < 2 ? 0 : x * (x - 1) / 2; }
+__device__ inline u128 c3(uint64_t x) { return x < 3 ? 0 : (u128)x * (x - 1) * (x - 2) / 6; }
+__device__ inline u128 c4(uint64_t x) { return x < 4 ? 0 : (u128)x * (x - 1) * (x - 2) / 6 * (x - 3) / 4; }
+
+// first index in sorted a[lo, hi) with a[idx] >= key
+__device__ inline int lower_bound_i32(const int32_t *a, int lo, int hi, int32_t key) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}

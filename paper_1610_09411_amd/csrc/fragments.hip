@@ -1,0 +1,482 @@
+// Fragment counts of Thm 4vertex-tri and the linear cut-formula sums.
+//
+//  * triangles from out-wedges of the DAG (Thm 4vertex-tri): t(e) per edge,
+//    then per-arc sorted triangle lists.  The list of arc (u->v) holds, for
+//    every common neighbour w of u and v, the index of arc (u,w) in u's row;
+//    the lists of an arc and of its reverse enumerate the same apexes in the
+//    same order, which lets every triangle find all three of its arcs.
+//  * 4-cycles (Thm 4cycle) from wedges below their latest vertex; only the
+//    sums the 5-vertex formulas need (sum C4(e) t(e), sum C4(v)(d(v)-2)) are
+//    formed, both linear in the per-edge counts.
+//  * per-triangle pass: K4(t) = |common neighbours of t|, from which K4(e),
+//    K4(v), K4 (Thm 4clique), the triangle-cut sums of Thm 5cuttri, the
+//    5-cycle correction Z (Thm 5cycle) and 5-cliques (Thm 5clique).
+//  * vertex and edge reductions for Thms 4vertex-easy, 5cutvertex, 5cutedge.
+#include "device.h"
+#include "ctx.h"
+
+static int grid_cap(esc_ctx *c, int64_t items, int threads, int per_cu = 16) {
+    int64_t b = (items + threads - 1) / threads;
+    int64_t cap = (int64_t)c->num_cu * per_cu;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// ---------------------------------------------------------------- triangles
+
+// One wave per vertex u; lanes take the out-arcs u->v and intersect N+(u)
+// with N+(v).  Every triangle u<v<w is found once, from its first arc.
+// mode 0: count t(e) (atomics on the two arcs other than u->v)
+// mode 1: write the six per-arc list entries through per-arc cursors
+__global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off, const int32_t *adj,
+                                                   const int32_t *split, const int32_t *arc_eid,
+                                                   const int32_t *rev, uint32_t *te, int mode,
+                                                   unsigned long long *cur, uint32_t *aa,
+                                                   unsigned long long *visits) {
+    uint64_t nvis = 0;
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int32_t u = wave; u < n; u += nwaves) {
+        const int32_t su = split[u], eu = off[u + 1];
+        for (int32_t p = su + lane; p < eu; p += 64) {
+            const int32_t v = adj[p];
+            int32_t x = p + 1, y = split[v];
+            const int32_t ev = off[v + 1];
+            uint32_t cnt = 0;
+            while (x < eu && y < ev) {
+                int32_t a = adj[x], b = adj[y];
+                nvis += 2;
+                if (a < b) x++;
+                else if (a > b) y++;
+                else {
+                    if (mode == 0) {
+                        atomicAdd(&te[arc_eid[x]], 1u);
+                        atomicAdd(&te[arc_eid[y]], 1u);
+                    } else {
+                        // arcs: p=(u,v) x=(u,w) y=(v,w) and reverses
+                        int32_t rp = rev[p], rx = rev[x], ry = rev[y];
+                        aa[atomicAdd(&cur[p], 1ull)] = (uint32_t)x;    // list(u->v): apex w -> (u,w)
+                        aa[atomicAdd(&cur[rp], 1ull)] = (uint32_t)y;   // list(v->u): apex w -> (v,w)
+                        aa[atomicAdd(&cur[x], 1ull)] = (uint32_t)p;    // list(u->w): apex v -> (u,v)
+                        aa[atomicAdd(&cur[rx], 1ull)] = (uint32_t)ry;  // list(w->u): apex v -> (w,v)
+                        aa[atomicAdd(&cur[y], 1ull)] = (uint32_t)rp;   // list(v->w): apex u -> (v,u)
+                        aa[atomicAdd(&cur[ry], 1ull)] = (uint32_t)rx;  // list(w->v): apex u -> (w,u)
+                    }
+                    cnt++;
+                    x++;
+                    y++;
+                }
+            }
+            if (mode == 0 && cnt) atomicAdd(&te[arc_eid[p]], cnt);
+        }
+    }
+    if (visits) flush_count(nvis, visits);
+}
+
+__global__ void k_arc_len(int64_t m2, const int32_t *arc_eid, const uint32_t *te, int64_t *len) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m2; p += (int64_t)gridDim.x * blockDim.x)
+        len[p] = te[arc_eid[p]];
+}
+
+__global__ void k_copy_cursor(int64_t m2, const int64_t *aoff, unsigned long long *cur) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m2; p += (int64_t)gridDim.x * blockDim.x)
+        cur[p] = (unsigned long long)aoff[p];
+}
+
+__global__ void k_apex_ids(int64_t total, const uint32_t *aa, const int32_t *adj, int32_t *av) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x)
+        av[k] = adj[aa[k]];
+}
+
+esc_status stage_triangles(esc_ctx *c) {
+    const int32_t n = c->n;
+    const int64_t m2 = c->m2, m = c->m;
+    hipStream_t st = c->stream;
+    const int32_t *off = (const int32_t *)c->buf[B_OFF], *adj = (const int32_t *)c->buf[B_ADJ];
+    const int32_t *split = (const int32_t *)c->buf[B_SPLIT], *arc_eid = (const int32_t *)c->buf[B_ARC_EID];
+    const int32_t *rev = (const int32_t *)c->buf[B_REV];
+    uint32_t *te = (uint32_t *)ctx_buf(c, B_TE, sizeof(uint32_t) * (size_t)(m + 1));
+    int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(m2 + 2));
+    int64_t *aoff = (int64_t *)ctx_buf(c, B_AOFF, sizeof(int64_t) * (size_t)(m2 + 2));
+    unsigned long long *cur = (unsigned long long *)ctx_buf(c, B_ACUR, sizeof(uint64_t) * (size_t)(m2 + 1));
+    if (!te || !len || !aoff || !cur) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(te, 0, sizeof(uint32_t) * (size_t)(m + 1), st));
+    if (n == 0) { c->narcs_apex = 0; return ESC_OK; }
+    int g = grid_cap(c, (int64_t)n * 64, 256);
+    unsigned long long *work = (unsigned long long *)c->buf[B_WORK];
+    k_triangles<<<g, 256, 0, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr,
+                                   work + WORK_VISITS + 1);
+    HIP_TRY(hipGetLastError());
+    k_arc_len<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, arc_eid, te, len);
+    HIP_TRY(hipGetLastError());
+    ESC_TRY(dev_exclusive_scan_i64(c, len, aoff, m2));
+    int64_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, aoff + m2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    c->narcs_apex = total;
+    uint32_t *aa = (uint32_t *)ctx_buf(c, B_AA, sizeof(uint32_t) * (size_t)(total + 1));
+    int32_t *av = (int32_t *)ctx_buf(c, B_AV, sizeof(int32_t) * (size_t)(total + 1));
+    if (!aa || !av) return ESC_ENOMEM;
+    if (total == 0) return ESC_OK;
+    k_copy_cursor<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, aoff, cur);
+    HIP_TRY(hipGetLastError());
+    k_triangles<<<g, 256, 0, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, nullptr);
+    HIP_TRY(hipGetLastError());
+    ESC_TRY(dev_segsort_u32(c, aa, aoff, m2, c->maxdeg));
+    k_apex_ids<<<grid_cap(c, total, 256), 256, 0, st>>>(total, aa, adj, av);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
+// ------------------------------------------------------------------ 4-cycles
+
+// One workgroup per top vertex h (latest vertex of the 4-cycle), taken from a
+// shared counter, heaviest (latest) vertices first.  A dense per-workgroup
+// table over all vertices accumulates, for every o before h, c(h,o) = number
+// of middles k (k before h, adjacent to h and o), plus the sums over those
+// middles of t(hk)+t(ko) and of d(k).  Then every (h,o) pair contributes
+//   C(c,2)                                    4-cycles
+//   (c-1) * sum_k [t(hk) + t(ko)]             to sum_e C4(e) t(e)
+//   (c-1) * sum_k [d(h)+2d(k)+d(o)-8]         to sum_e C4(e)(d(u)+d(v)-4)
+// With per_edge set, a second pass also adds c-1 to C4 of edges hk and ko.
+__global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *off, const int32_t *adj,
+                                                     const int32_t *split, const int32_t *rev,
+                                                     const int32_t *arc_eid, const uint32_t *te,
+                                                     uint32_t *tab_c, uint32_t *tab_t, uint32_t *tab_k,
+                                                     int32_t *touch_all, int *task, unsigned long long *acc,
+                                                     unsigned long long *c4e, unsigned long long *visits) {
+    uint64_t nvis = 0;
+    __shared__ int pref[513], tmp[16];
+    __shared__ int64_t beg[513];
+    __shared__ int s_h, s_nt;
+    __shared__ u128 red[3 * 8];
+    uint32_t *cnt = tab_c + (size_t)blockIdx.x * n;
+    uint32_t *ft = tab_t + (size_t)blockIdx.x * n;
+    uint32_t *fk = tab_k + (size_t)blockIdx.x * n;
+    int32_t *touch = touch_all + (size_t)blockIdx.x * n;
+    u128 sums[3] = {0, 0, 0};
+    for (;;) {
+        if (threadIdx.x == 0) { s_h = atomicAdd(task, 1); s_nt = 0; }
+        __syncthreads();
+        const int32_t t = s_h;
+        if (t >= n) break;
+        const int32_t h = n - 1 - t;
+        const int32_t oh = off[h], sh = split[h];
+        // wedges h - k - o with k, o before h: k in N-(h), o in the prefix of N(k) below h
+        for (int32_t base = oh; base < sh; base += blockDim.x) {
+            int32_t p = base + threadIdx.x;
+            int start = 0, len = 0;
+            if (p < sh) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
+            lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
+                int32_t pk = base + s;
+                int32_t k = adj[pk];
+                int32_t o = adj[q];
+                uint32_t old = atomicAdd(&cnt[o], 1u);
+                nvis++;
+                if (old == 0) touch[atomicAdd(&s_nt, 1)] = o;
+                atomicAdd(&ft[o], te[arc_eid[pk]] + te[arc_eid[q]]);
+                atomicAdd(&fk[o], (uint32_t)(off[k + 1] - off[k]));
+            });
+        }
+        __syncthreads();
+        const int nt = s_nt;
+        const int64_t dh = off[h + 1] - oh;
+        if (c4e) {
+            for (int32_t base = oh; base < sh; base += blockDim.x) {
+                int32_t p = base + threadIdx.x;
+                int start = 0, len = 0;
+                if (p < sh) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
+                lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
+                    int32_t pk = base + s;
+                    uint32_t cc = cnt[adj[q]];
+                    if (cc >= 2) {
+                        atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
+                        atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
+                    }
+                });
+            }
+        }
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            int32_t o = touch[i];
+            uint64_t cc = cnt[o];
+            if (cc >= 2) {
+                int64_t dsum = (int64_t)cc * (dh + (off[o + 1] - off[o]) - 8) + 2 * (int64_t)fk[o];
+                sums[0] += c2(cc);
+                sums[1] += (u128)(cc - 1) * ft[o];
+                sums[2] += (u128)(cc - 1) * (uint64_t)dsum;
+            }
+            cnt[o] = 0; ft[o] = 0; fk[o] = 0;
+        }
+        __syncthreads();
+    }
+    const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
+    block_flush_u128<3>(sums, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
+    const int32_t n = c->n;
+    hipStream_t st = c->stream;
+    if (n == 0) return ESC_OK;
+    int nwg = c->num_cu;
+    size_t per = (size_t)n * sizeof(uint32_t);
+    uint32_t *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
+    int32_t *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * nwg);
+    int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
+    if (!tab || !touch || !task) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
+    unsigned long long *c4e = nullptr;
+    if (per_edge_c4) {
+        c4e = (unsigned long long *)ctx_buf(c, B_C4E, sizeof(uint64_t) * (size_t)(c->m + 1));
+        if (!c4e) return ESC_ENOMEM;
+        HIP_TRY(hipMemsetAsync(c4e, 0, sizeof(uint64_t) * (size_t)(c->m + 1), st));
+    }
+    k_four_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+                                       (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
+                                       (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TE],
+                                       tab, tab + (size_t)n * nwg, tab + 2 * (size_t)n * nwg, touch, task,
+                                       (unsigned long long *)c->buf[B_ACC], c4e,
+                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
+// ------------------------------------------------------------ per triangle
+
+// merge-count of two sorted int lists
+__device__ inline uint32_t count_common(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, uint64_t &nvis) {
+    int64_t x = 0, y = 0;
+    uint32_t c = 0;
+    while (x < na && y < nb) {
+        int32_t p = a[x], q = b[y];
+        c += (p == q);
+        x += (p <= q);
+        y += (q <= p);
+    }
+    nvis += x + y;
+    return c;
+}
+
+// One wave per out-arc a->b (a before b); lanes take the triangles a<b<c owned
+// by it (apexes after b in the sorted list).  For each triangle:
+//   K4(t) = common neighbours of a, b, c = |apex(ab) & apex(ac)|
+//   K4(e) += K4(t) for its three edges; sum K4(t) = 4 K4
+//   C(K4(t),2) -> pattern 20; the triangle-cut sums of patterns 10 and 16;
+//   Z term d+(a)+d+(b)+d+(c)-3 (5-cycle correction);
+//   L = common neighbours after c; every edge inside L closes a 5-clique.
+__global__ void __launch_bounds__(256) k_triangle_pass(int64_t m, const int32_t *off, const int32_t *adj,
+                                                       const int32_t *split, const int32_t *rev,
+                                                       const int32_t *arc_eid, const int32_t *earc,
+                                                       const int32_t *elo, const uint32_t *te,
+                                                       const int64_t *aoff, const uint32_t *aa,
+                                                       const int32_t *av, unsigned long long *k4e,
+                                                       int32_t *lbuf, int32_t lcap, unsigned long long *acc,
+                                                       unsigned long long *visits) {
+    uint64_t nvis = 0;
+    __shared__ u128 red[7 * 4];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int32_t *L = lbuf + (size_t)((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * lcap;
+    u128 s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = wave; e < m; e += nwaves) {
+        const int32_t p = earc[e];
+        const int32_t a = elo[e], b = adj[p];
+        const int32_t rp = rev[p];
+        const int64_t l0 = aoff[p], l1 = aoff[p + 1];
+        if (l1 - l0 == 0) continue;
+        const int64_t r0 = aoff[rp];
+        // first apex after b
+        int64_t lo = l0, hi = l1;
+        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] <= b) lo = mid + 1; else hi = mid; }
+        const uint64_t da = off[a + 1] - off[a], db = off[b + 1] - off[b];
+        const uint64_t dpa = off[a + 1] - split[a], dpb = off[b + 1] - split[b];
+        const uint64_t tab = te[e];
+        for (int64_t k = lo + lane; k < l1; k += 64) {
+            const int32_t cc = av[k];
+            const int32_t pac = (int32_t)aa[k];             // arc (a,c) in row a
+            const int32_t pbc = (int32_t)aa[r0 + (k - l0)]; // arc (b,c) in row b
+            const uint64_t tac = te[arc_eid[pac]], tbc = te[arc_eid[pbc]];
+            const uint64_t dc = off[cc + 1] - off[cc], dpc = off[cc + 1] - split[cc];
+            // K4(t): intersect the two shortest apex lists among ab, ac, bc
+            const int32_t *A1 = av + l0; int64_t n1 = l1 - l0;
+            const int32_t *A2 = av + aoff[pac]; int64_t n2 = aoff[pac + 1] - aoff[pac];
+            const int32_t *A3 = av + aoff[pbc]; int64_t n3 = aoff[pbc + 1] - aoff[pbc];
+            if (n3 < n1 || n3 < n2) {
+                if (n1 >= n2) { A1 = A3; n1 = n3; } else { A2 = A3; n2 = n3; }
+            }
+            const uint32_t k4 = count_common(A1, n1, A2, n2, nvis);
+            if (k4) {
+                atomicAdd(&k4e[e], (unsigned long long)k4);
+                atomicAdd(&k4e[arc_eid[pac]], (unsigned long long)k4);
+                atomicAdd(&k4e[arc_eid[pbc]], (unsigned long long)k4);
+            }
+            s[0] += k4;
+            s[1] += c2(k4);
+            s[2] += (u128)(tbc - 1) * (da - 2) + (u128)(tac - 1) * (db - 2) + (u128)(tab - 1) * (dc - 2);
+            s[3] += (u128)(tab - 1) * (tac - 1) + (u128)(tab - 1) * (tbc - 1) + (u128)(tac - 1) * (tbc - 1);
+            s[4] += dpa + dpb + dpc - 3;
+            // 5-cliques: L = common neighbours after c (a subset of N+(c))
+            if (k4 >= 2) {
+                int64_t x = 0, y = 0;
+                int nl = 0;
+                while (x < n1 && y < n2) {
+                    int32_t pp = A1[x], qq = A2[y];
+                    if (pp == qq && pp > cc) { if (nl < lcap) L[nl] = pp; nl++; }
+                    x += (pp <= qq);
+                    y += (qq <= pp);
+                }
+                if (nl > lcap) nl = lcap;   // cannot happen: L lies inside N+(c)
+                uint64_t k5 = 0;
+                for (int i = 0; i + 1 < nl; i++) {
+                    const int32_t xv = L[i];
+                    // |{y in L after x} & N+(x)|
+                    int32_t q = split[xv];
+                    const int32_t qe = off[xv + 1];
+                    int j = i + 1;
+                    while (j < nl && q < qe) {
+                        int32_t u = L[j], w = adj[q];
+                        nvis += 2;
+                        k5 += (u == w);
+                        j += (u <= w);
+                        q += (w <= u);
+                    }
+                }
+                s[5] += k5;
+            }
+        }
+    }
+    const int ids[6] = {AC_K4X4, AC_N20, AC_N10, AC_N16, AC_Z, AC_K5};
+    u128 v6[6] = {s[0], s[1], s[2], s[3], s[4], s[5]};
+    block_flush_u128<6>(v6, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+esc_status stage_triangle_sums(esc_ctx *c) {
+    hipStream_t st = c->stream;
+    const int64_t m = c->m;
+    unsigned long long *k4e = (unsigned long long *)ctx_buf(c, B_K4E, sizeof(uint64_t) * (size_t)(m + 1));
+    if (!k4e) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(k4e, 0, sizeof(uint64_t) * (size_t)(m + 1), st));
+    if (m == 0 || c->narcs_apex == 0) return ESC_OK;
+    int g = grid_cap(c, m * 64, 256, 8);
+    int32_t lcap = c->maxdplus + 1;
+    int32_t *lbuf = (int32_t *)ctx_buf(c, B_WG_TOUCH, sizeof(int32_t) * (size_t)g * 256 * lcap);
+    if (!lbuf) return ESC_ENOMEM;
+    k_triangle_pass<<<g, 256, 0, st>>>(m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+                                       (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
+                                       (const int32_t *)c->buf[B_ARC_EID], (const int32_t *)c->buf[B_EARC],
+                                       (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE],
+                                       (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
+                                       (const int32_t *)c->buf[B_AV], k4e, lbuf, lcap,
+                                       (unsigned long long *)c->buf[B_ACC],
+                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
+// -------------------------------------------------------------- reductions
+
+// per vertex r (rank ids): t(v) = half the sum of t(e) over its edges,
+// K4(v) = a third of the sum of K4(e).
+__global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t *off, const int32_t *adj,
+                                                       const int32_t *split, const int32_t *arc_eid,
+                                                       const uint32_t *te, const unsigned long long *k4e,
+                                                       uint64_t *tv, unsigned long long *acc, uint64_t *work) {
+    __shared__ u128 red[12 * 4];
+    u128 s[12] = {0};
+    uint64_t wpp = 0, wpm = 0, nvis = 0;
+    for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int32_t a = off[r], b = off[r + 1];
+        const uint64_t d = b - a;
+        nvis += d;
+        uint64_t t2 = 0, k3 = 0, A = 0, sd = 0;
+        u128 B = 0;
+        for (int32_t p = a; p < b; p++) {
+            int32_t e = arc_eid[p];
+            t2 += te[e];
+            k3 += k4e[e];
+            int32_t j = adj[p];
+            uint64_t dj = off[j + 1] - off[j];
+            A += dj - 1;
+            B += (u128)(dj - 1) * (dj - 1);
+            sd += dj;
+        }
+        const uint64_t t = t2 / 2, k4v = k3 / 3;
+        tv[r] = t;
+        s[0] += c2(d);
+        s[1] += c3(d);
+        s[2] += c4(d);
+        if (t) s[3] += (u128)t * (d - 2);
+        s[4] += ((u128)A * A - B) / 2;
+        if (t && d >= 4) s[5] += (u128)t * c2(d - 2);
+        s[6] += c2(t);
+        if (d >= 3) s[7] += (u128)k4v * (d - 3);
+        s[8] += (u128)c2(d) * d + (u128)(d ? d - 1 : 0) * sd;
+        s[9] += (u128)t * d;
+        const uint64_t dp = b - split[r], dm = split[r] - a;
+        wpp += c2(dp);
+        wpm += dp * dm;
+    }
+    const int ids[10] = {AC_W, AC_S3, AC_S4, AC_TT, AC_N3, AC_N4, AC_N9, AC_N15, AC_SW, AC_TD};
+    u128 v[10] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8], s[9]};
+    block_flush_u128<10>(v, red, acc, ids);
+    wpp = wave_sum_u64(wpp);
+    wpm = wave_sum_u64(wpm);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long *)&work[0], (unsigned long long)wpp);
+        atomicAdd((unsigned long long *)&work[1], (unsigned long long)wpm);
+    }
+    flush_count(nvis, (unsigned long long *)&work[WORK_VISITS + 4]);
+}
+
+__global__ void __launch_bounds__(256) k_edge_reduce(int64_t m, const int32_t *off, const int32_t *adj,
+                                                     const int32_t *earc, const int32_t *elo, const uint32_t *te,
+                                                     const uint64_t *tv, const unsigned long long *k4e,
+                                                     unsigned long long *acc) {
+    __shared__ u128 red[10 * 4];
+    u128 s[10] = {0};
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = elo[e], v = adj[earc[e]];
+        const uint64_t du = off[u + 1] - off[u], dv = off[v + 1] - off[v];
+        const uint64_t t = te[e], tu = tv[u], tw = tv[v], k4 = k4e[e];
+        s[0] += t;
+        s[1] += c2(t);
+        s[2] += (u128)(du - 1) * (dv - 1);
+        s[3] += (u128)(dv - 1) * c2(du - 1) + (u128)(du - 1) * c2(dv - 1);
+        s[4] += (u128)(du - 1) * (tw - t) + (u128)(dv - 1) * (tu - t);
+        if (t) s[5] += (u128)t * (du - 2) * (dv - 2);
+        if (t >= 2) s[6] += (u128)c2(t) * ((du - 3) + (dv - 3));
+        s[7] += c3(t);
+        if (t >= 2) s[8] += (u128)k4 * (t - 2);
+    }
+    const int ids[9] = {AC_T3, AC_D, AC_EP, AC_N2, AC_N5, AC_N6, AC_N11, AC_N14, AC_N19};
+    u128 v[9] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8]};
+    block_flush_u128<9>(v, red, acc, ids);
+}
+
+esc_status stage_reduce(esc_ctx *c) {
+    hipStream_t st = c->stream;
+    const int32_t n = c->n;
+    const int64_t m = c->m;
+    uint64_t *tv = (uint64_t *)ctx_buf(c, B_TV, sizeof(uint64_t) * (size_t)(n + 1));
+    if (!tv) return ESC_ENOMEM;
+    unsigned long long *acc = (unsigned long long *)c->buf[B_ACC];
+    if (n > 0) {
+        k_vertex_reduce<<<grid_cap(c, n, 256), 256, 0, st>>>(
+            n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
+            (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TE],
+            (const unsigned long long *)c->buf[B_K4E], tv, acc, (uint64_t *)c->buf[B_WORK]);
+        HIP_TRY(hipGetLastError());
+    }
+    if (m > 0) {
+        k_edge_reduce<<<grid_cap(c, m, 256), 256, 0, st>>>(
+            m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_EARC],
+            (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], tv,
+            (const unsigned long long *)c->buf[B_K4E], acc);
+        HIP_TRY(hipGetLastError());
+    }
+    return ESC_OK;
+}

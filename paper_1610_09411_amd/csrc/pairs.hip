@@ -1,0 +1,327 @@
+// Pair-level sums (Thm 5cutwed with the algorithm of Thm 5formula) and
+// 5-cycles (Thm 5cycle).
+//
+//  * pattern 13 and 17: for every source i and every j before i,
+//      W(i,j) = common neighbours (2-step search from i),
+//      D(i,j) = edges inside the common neighbourhood, generated from a
+//               triangle (i,k,l) followed by a triangle (k,l,j);
+//    sum C(W,3) and sum (W-2) D over the pairs.
+//  * pattern 18 (wheel, hub h): the 4-cycles inside G[N(h)], counted at their
+//    latest rim vertex i like Thm 4cycle: for j before i in N(h),
+//    c = #{l in N(h) & N(i) & N(j), l before i}, and sum C(c,2).  Keys j are
+//    positions inside the row of h, so the table is dense and small.
+//  * 5-cycles: sum over ordered pairs of P(i,j) Wnt(i,j) where P counts
+//    directed 3-paths i <- a -> b -> j and Wnt the common neighbours not after
+//    both i and j.  Per source i this is summed as
+//      sum_b X(i,b) * sum_{j in N+(b)} Wnt(i,j),   X(i,b) = |N-(i) & N-(b)|,
+//    which visits each distinct (i,b) once instead of every 3-path.
+//
+// Every per-source table is a dense per-workgroup array over all vertices,
+// reset through a list of touched keys.
+#include "device.h"
+#include "ctx.h"
+
+// ------------------------------------------------------- patterns 13 and 17
+
+__global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off, const int32_t *adj,
+                                                  const int32_t *rev, const int64_t *aoff, const uint32_t *aa,
+                                                  const int32_t *av, uint32_t *tab_all, int32_t *touch_all,
+                                                  int *task, unsigned long long *acc, unsigned long long *visits) {
+    uint64_t nvis = 0;
+    __shared__ int pref[513], tmp[16];
+    __shared__ int64_t beg[513], opref[513];
+    __shared__ int s_i, s_nt;
+    __shared__ u128 red[2 * 8];
+    uint32_t *W = tab_all + (size_t)blockIdx.x * n;
+    int32_t *touch = touch_all + (size_t)blockIdx.x * n;
+    u128 s13 = 0, s17 = 0;
+    for (;;) {
+        if (threadIdx.x == 0) { s_i = atomicAdd(task, 1); s_nt = 0; }
+        __syncthreads();
+        const int32_t t = s_i;
+        if (t >= n) break;
+        const int32_t i = n - 1 - t;
+        const int32_t oi = off[i], ei = off[i + 1];
+        // W(i,j) for j before i: k in N(i), j in the prefix of N(k) below i
+        for (int32_t base = oi; base < ei; base += blockDim.x) {
+            int32_t p = base + threadIdx.x;
+            int start = 0, len = 0;
+            if (p < ei) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
+            lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
+                int32_t j = adj[q];
+                nvis++;
+                if (atomicAdd(&W[j], 1u) == 0) touch[atomicAdd(&s_nt, 1)] = j;
+            });
+        }
+        __syncthreads();
+        // diamonds with tips i and j (j before i): triangles (i,k,l), k<l, then
+        // apexes j of edge (k,l) below i.  Level 1 walks the triangle lists of
+        // the arcs of i; each entry (k,l) yields one level-2 segment.
+        for (int32_t base = oi; base < ei; base += blockDim.x) {
+            int32_t p = base + threadIdx.x;
+            int len = (p < ei) ? (int)(aoff[p + 1] - aoff[p]) : 0;
+            int total;
+            int ex = block_exclusive_scan(len, tmp, &total);
+            opref[threadIdx.x] = ex;
+            __syncthreads();
+            for (int x0 = 0; x0 < total; x0 += blockDim.x) {
+                int x = x0 + threadIdx.x;
+                int64_t s2 = 0;
+                int l2 = 0;
+                if (x < total) {
+                    int lo = 0, hi = blockDim.x - 1;
+                    while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (opref[mid] <= x) lo = mid; else hi = mid - 1; }
+                    const int32_t pk = base + lo;          // arc (i,k)
+                    const int32_t k = adj[pk];
+                    const int64_t idx = x - opref[lo];
+                    const int32_t l = av[aoff[pk] + idx];
+                    if (k < l) {
+                        const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + idx];   // arc (k,l) in row k
+                        const int64_t a0 = aoff[qkl], a1 = aoff[qkl + 1];
+                        // apexes of (k,l) below i: prefix of the sorted list
+                        int64_t lo2 = a0, hi2 = a1;
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
+                        s2 = a0;
+                        l2 = (int)(lo2 - a0);
+                    }
+                }
+                lbs_batch(s2, l2, pref, beg, tmp, [&](int, int64_t q) {
+                    s17 += (uint64_t)W[av[q]] - 2;
+                    nvis++;
+                });
+            }
+            __syncthreads();
+        }
+        const int nt = s_nt;
+        for (int q = threadIdx.x; q < nt; q += blockDim.x) {
+            int32_t j = touch[q];
+            s13 += c3(W[j]);
+            W[j] = 0;
+        }
+        __syncthreads();
+    }
+    const int ids[2] = {AC_N13, AC_N17};
+    u128 v[2] = {s13, s17};
+    block_flush_u128<2>(v, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+// ------------------------------------------------------------ pattern 18
+
+// One workgroup per hub h.  For each neighbour i of h (latest rim vertex):
+// l runs over the triangle list of arc (h,i) below i, j over the triangle
+// list of arc (h,l) below i; key = position of j in the row of h.  The table
+// lives in LDS when d(h) fits, else in the workgroup's global scratch.
+__global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
+                                                const int64_t *aoff, const uint32_t *aa, const int32_t *av,
+                                                uint32_t *gtab_all, int32_t *gtouch_all, int32_t lds_cap,
+                                                int *task, unsigned long long *acc, unsigned long long *visits) {
+    uint64_t nvis = 0;
+    extern __shared__ uint32_t dyn[];
+    __shared__ int pref[257], tmp[8];
+    __shared__ int64_t beg[257];
+    __shared__ int s_h, s_nt;
+    __shared__ u128 red[4];
+    u128 s18 = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
+        __syncthreads();
+        const int32_t t = s_h;
+        if (t >= n) break;
+        const int32_t h = n - 1 - t;
+        const int32_t oh = off[h], dh = off[h + 1] - oh;
+        const bool in_lds = dh <= lds_cap;
+        uint32_t *cnt = in_lds ? dyn : gtab_all + (size_t)blockIdx.x * n;
+        int32_t *tch = in_lds ? (int32_t *)(dyn + lds_cap) : gtouch_all + (size_t)blockIdx.x * n;
+        if (in_lds)
+            for (int q = threadIdx.x; q < dh; q += blockDim.x) cnt[q] = 0;
+        __syncthreads();
+        for (int32_t pi = oh; pi < oh + dh; pi++) {
+            const int32_t i = adj[pi];
+            const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
+            if (l1 - l0 < 2) continue;   // a rim 4-cycle needs two triangles on (h,i)
+            // entries l of list(h,i) below i
+            int64_t lo = l0, hi = l1;
+            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] < i) lo = mid + 1; else hi = mid; }
+            const int nl = (int)(lo - l0);
+            if (nl == 0) continue;
+            if (threadIdx.x == 0) s_nt = 0;
+            __syncthreads();
+            for (int x0 = 0; x0 < nl; x0 += blockDim.x) {
+                int x = x0 + threadIdx.x;
+                int64_t s2 = 0;
+                int len2 = 0;
+                if (x < nl) {
+                    const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
+                    const int64_t b0 = aoff[qhl], b1 = aoff[qhl + 1];
+                    int64_t lo2 = b0, hi2 = b1;
+                    while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
+                    s2 = b0;
+                    len2 = (int)(lo2 - b0);
+                }
+                lbs_batch(s2, len2, pref, beg, tmp, [&](int, int64_t q) {
+                    int32_t key = (int32_t)aa[q] - oh;
+                    nvis++;
+                    if (atomicAdd(&cnt[key], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = key;
+                });
+            }
+            __syncthreads();
+            const int nt = s_nt;
+            for (int q = threadIdx.x; q < nt; q += blockDim.x) {
+                int32_t key = tch[q];
+                s18 += c2(cnt[key]);
+                cnt[key] = 0;
+            }
+            __syncthreads();
+        }
+    }
+    const int ids[1] = {AC_N18};
+    u128 v[1] = {s18};
+    block_flush_u128<1>(v, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+// ---------------------------------------------------------------- 5-cycles
+
+__global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *off, const int32_t *adj,
+                                                     const int32_t *split, uint32_t *tabX_all, uint32_t *tabW_all,
+                                                     int32_t *touchX_all, int32_t *touchW_all, int *task,
+                                                     unsigned long long *acc, unsigned long long *visits) {
+    uint64_t nvis = 0;
+    __shared__ int pref[513], tmp[16];
+    __shared__ int64_t beg[513];
+    __shared__ int s_i, s_nx, s_nw;
+    __shared__ u128 red[8];
+    uint32_t *X = tabX_all + (size_t)blockIdx.x * n;
+    uint32_t *Wn = tabW_all + (size_t)blockIdx.x * n;
+    int32_t *tx = touchX_all + (size_t)blockIdx.x * n;
+    int32_t *tw = touchW_all + (size_t)blockIdx.x * n;
+    u128 sc = 0;
+    for (;;) {
+        if (threadIdx.x == 0) { s_i = atomicAdd(task, 1); s_nx = 0; s_nw = 0; }
+        __syncthreads();
+        const int32_t t = s_i;
+        if (t >= n) break;
+        const int32_t i = n - 1 - t;
+        const int32_t oi = off[i], si = split[i], ei = off[i + 1];
+        // X(i,b): a in N-(i), b in N+(a), b != i
+        for (int32_t base = oi; base < si; base += blockDim.x) {
+            int32_t p = base + threadIdx.x;
+            int start = 0, len = 0;
+            if (p < si) { int32_t a = adj[p]; start = split[a]; len = off[a + 1] - split[a]; }
+            lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
+                int32_t b = adj[q];
+                nvis++;
+                if (b != i && atomicAdd(&X[b], 1u) == 0) tx[atomicAdd(&s_nx, 1)] = b;
+            });
+        }
+        __syncthreads();
+        if (s_nx == 0) { __syncthreads(); continue; }
+        // Wnt(i,j): c in N(i); all of N(c) when c is before i, else only N+(c)
+        for (int32_t base = oi; base < ei; base += blockDim.x) {
+            int32_t p = base + threadIdx.x;
+            int start = 0, len = 0;
+            if (p < ei) {
+                int32_t cv = adj[p];
+                if (cv < i) { start = off[cv]; len = off[cv + 1] - off[cv]; }
+                else { start = split[cv]; len = off[cv + 1] - split[cv]; }
+            }
+            lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
+                int32_t j = adj[q];
+                nvis++;
+                if (j != i && atomicAdd(&Wn[j], 1u) == 0) tw[atomicAdd(&s_nw, 1)] = j;
+            });
+        }
+        __syncthreads();
+        // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j)
+        const int nx = s_nx;
+        for (int base = 0; base < nx; base += blockDim.x) {
+            int xi = base + threadIdx.x;
+            int start = 0, len = 0;
+            if (xi < nx) { int32_t b = tx[xi]; start = split[b]; len = off[b + 1] - split[b]; }
+            lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
+                int32_t b = tx[base + s];
+                nvis++;
+                sc += (u128)X[b] * Wn[adj[q]];
+            });
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < nx; q += blockDim.x) X[tx[q]] = 0;
+        const int nw = s_nw;
+        for (int q = threadIdx.x; q < nw; q += blockDim.x) Wn[tw[q]] = 0;
+        __syncthreads();
+    }
+    const int ids[1] = {AC_CYC};
+    u128 v[1] = {sc};
+    block_flush_u128<1>(v, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+// ------------------------------------------------------------------- stages
+
+static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int **task) {
+    size_t per = (size_t)c->n * sizeof(uint32_t);
+    int nwg = c->num_cu;
+    *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
+    *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * 2 * nwg);
+    *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
+    if (!*tab || !*touch || !*task) return ESC_ENOMEM;
+    return ESC_OK;
+}
+
+esc_status stage_pairs(esc_ctx *c) {
+    const int32_t n = c->n;
+    hipStream_t st = c->stream;
+    if (n == 0) return ESC_OK;
+    uint32_t *tab;
+    int32_t *touch;
+    int *task;
+    ESC_TRY(pair_scratch(c, &tab, &touch, &task));
+    HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
+    k_pairs_wd<<<c->num_cu, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+                                          (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
+                                          (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], tab, touch,
+                                          task, (unsigned long long *)c->buf[B_ACC],
+                                          (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 5);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
+esc_status stage_wheels(esc_ctx *c) {
+    const int32_t n = c->n;
+    hipStream_t st = c->stream;
+    if (n == 0 || c->narcs_apex == 0) return ESC_OK;
+    uint32_t *tab;
+    int32_t *touch;
+    int *task;
+    ESC_TRY(pair_scratch(c, &tab, &touch, &task));
+    // table + touched list in LDS, leaving room for the kernel's static arrays
+    int lds_cap = (c->max_lds - 8192) / 8;
+    if (lds_cap > 16384) lds_cap = 16384;
+    if (c->maxdeg + 1 < lds_cap) lds_cap = c->maxdeg + 1;
+    size_t lds = sizeof(uint32_t) * 2 * (size_t)lds_cap;
+    k_wheels<<<c->num_cu * 2, 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+                                              (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
+                                              (const int32_t *)c->buf[B_AV], tab, touch, lds_cap, task + 1,
+                                              (unsigned long long *)c->buf[B_ACC],
+                                              (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
+esc_status stage_cycles(esc_ctx *c) {
+    const int32_t n = c->n;
+    hipStream_t st = c->stream;
+    if (n == 0) return ESC_OK;
+    uint32_t *tab;
+    int32_t *touch;
+    int *task;
+    ESC_TRY(pair_scratch(c, &tab, &touch, &task));
+    int nwg = c->num_cu;
+    k_five_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+                                       (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)n * nwg, touch,
+                                       touch + (size_t)n * nwg, task + 2, (unsigned long long *)c->buf[B_ACC],
+                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}

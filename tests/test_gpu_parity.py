@@ -1,0 +1,190 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Exact integer counts: the bar is equality of every one of the 45 counts
+(and of every per-item fragment count).
+"""
+import json
+import os
+import random
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1610_09411_amd as esc
+    c = esc.Context(0)
+    yield c
+    c.close()
+
+
+def _cases_small():
+    out = []
+    for s in range(12):
+        out.append(synth.erdos_renyi(10 + 3 * s, 0.1 + 0.05 * (s % 8), 500 + s))
+    for s in range(10):
+        out.append(synth.chung_lu(40 + 17 * s, 2.0 + 0.08 * s, 5.0 + s, 30.0, 600 + s))
+    out.append(synth.from_edges(9, [(u, v) for u in range(9) for v in range(u + 1, 9)]))          # K9
+    out.append(synth.from_edges(12, [(u, 6 + v) for u in range(6) for v in range(6)]))            # K6,6
+    out.append(synth.from_edges(15, [(i, (i + 1) % 15) for i in range(15)]))                      # C15
+    out.append(synth.from_edges(20, [(0, v) for v in range(1, 20)]))                              # star
+    out.append(synth.from_edges(30, [(0, v) for v in range(1, 30)] + [(v, v + 1) for v in range(1, 29)]))  # fan
+    return out
+
+
+def test_library_is_native_and_loaded(ctx):
+    import paper_1610_09411_amd as esc
+    assert os.path.exists(esc.LIB_PATH)
+    assert esc._lib is not None
+
+
+@pytest.mark.parametrize("idx", range(len(_cases_small())))
+def test_small_graphs_equal_oracle(ctx, idx):
+    g = _cases_small()[idx]
+    print("case", idx, g.name, g.n, g.m, flush=True)
+    assert ctx.count(g, 5) == oracle.count(g, 5)
+    assert ctx.count(g, 4) == oracle.count(g, 4)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 6])
+def test_tiny_and_degenerate(ctx, n):
+    empty = synth.from_edges(n, [])
+    full = synth.from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+    for g in (empty, full):
+        got = ctx.count(g, 5)
+        assert got == oracle.count(g, 5)
+        assert sum(got[:11]) == comb(n, 4) and sum(got[11:]) == comb(n, 5)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_er200_equals_brute_force(ctx, seed):
+    g = synth.er_small(seed)
+    got = ctx.count(g, 5)
+    assert got[:11] == oracle.brute(g, 4)
+    assert got[11:] == oracle.brute(g, 5)
+
+
+@pytest.mark.parametrize("n,gamma,dbar,dmax,seed", [
+    (3000, 2.1, 12.0, 400.0, 1),
+    (20000, 2.1, 20.0, 1500.0, 2),
+    (12000, 1.9, 30.0, 3000.0, 3),
+])
+def test_power_law_graphs_equal_oracle(ctx, n, gamma, dbar, dmax, seed):
+    """Several thousand vertices: many workgroups, hubs, ragged lists."""
+    g = synth.chung_lu(n, gamma, dbar, dmax, seed)
+    print("chung_lu", n, g.m, flush=True)
+    assert ctx.count(g, 5) == oracle.count(g, 5, threads=8)
+
+
+def test_random_order_gives_same_counts(ctx):
+    import paper_1610_09411_amd as esc
+    g = synth.chung_lu(5000, 2.1, 15.0, 600.0, 9)
+    assert ctx.count(g, 5, flags=esc.ESC_F_RANDOM_ORDER) == ctx.count(g, 5)
+
+
+def test_repeat_calls_are_identical(ctx):
+    g = synth.chung_lu(8000, 2.0, 16.0, 900.0, 4)
+    a = ctx.count(g, 5)
+    small = synth.er_small(1)
+    ctx.count(small, 5)
+    assert ctx.count(g, 5) == a
+
+
+def test_fragments_equal_oracle(ctx):
+    g = synth.chung_lu(4000, 2.1, 14.0, 500.0, 5)
+    counts, fr = ctx.fragments(g, 5)
+    S, it = oracle.sums(g, 5, per_item=True)
+    assert counts == oracle.count(g, 5)
+    assert np.array_equal(fr["tri_v"], it["t_v"])
+    assert np.array_equal(fr["c4_v"], it["c4_v"])
+    assert np.array_equal(fr["k4_v"], it["k4_v"])
+    assert np.array_equal(fr["tri_e"], it["t_e"])
+    assert np.array_equal(fr["c4_e"], it["c4_e"])
+    assert np.array_equal(fr["k4_e"], it["k4_e"])
+
+
+def test_device_input(ctx):
+    import torch
+    g = synth.chung_lu(2000, 2.2, 10.0, 300.0, 6)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col).cuda()
+    import paper_1610_09411_amd as esc
+    got = esc.esc_count_subgraphs(ctx.ptr, g.n, rp, ci, 5)
+    assert got == oracle.count(g, 5)
+
+
+def test_invalid_input_is_rejected(ctx):
+    import paper_1610_09411_amd as esc
+    bad_range = synth.Graph(3, np.array([0, 1, 2, 2], np.int32), np.array([1, 7], np.int32))
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.count(bad_range, 5, flags=esc.ESC_F_VALIDATE)
+    assert e.value.status == esc.ESC_ERANGE
+    loop = synth.Graph(2, np.array([0, 2, 3], np.int32), np.array([0, 1, 0], np.int32))
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.count(loop, 5, flags=esc.ESC_F_VALIDATE)
+    assert e.value.status in (esc.ESC_ENOTSIMPLE, esc.ESC_ERANGE)
+    asym = synth.Graph(3, np.array([0, 1, 2, 2], np.int32), np.array([1, 2], np.int32))
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.count(asym, 5, flags=esc.ESC_F_VALIDATE)
+    assert e.value.status == esc.ESC_ENOTSIMPLE
+    with pytest.raises(esc.EscapeError) as e:
+        esc.esc_count_subgraphs(ctx.ptr, 3, np.array([0, 1, 2, 2], np.int32), np.array([1, 0], np.int32), k=6)
+    assert e.value.status == esc.ESC_EINVAL
+    # the context still works afterwards
+    g = synth.er_small(2)
+    assert ctx.count(g, 5) == oracle.count(g, 5)
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip("golden file %s not generated" % name)
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_chung_lu_1m_full_size(ctx):
+    """n=1e6, gamma=2.1, mean degree 20, max expected degree 1e4: the benchmark
+    workload, checked against the oracle's stored counts and by properties
+    that hold at any size."""
+    gold = _golden("chung_lu_1m_seed0.json")
+    g = synth.chung_lu_1m(0)
+    assert g.m == gold["m"]
+    got = ctx.count(g, 5)
+    assert sum(got[:11]) == comb(g.n, 4)
+    assert sum(got[11:]) == comb(g.n, 5)
+    assert [int(x) for x in gold["counts"]] == got
+
+
+def test_chung_lu_1m_sampled_fragments(ctx):
+    """Per-vertex and per-edge fragment counts at full size, sampled and
+    recomputed one by one from their definitions."""
+    g = synth.chung_lu_1m(0)
+    _, fr = ctx.fragments(g, 4)
+    rng = random.Random(0)
+    deg = g.degrees()
+    hubs = list(np.argsort(-deg)[:5])
+    verts = hubs + [rng.randrange(g.n) for _ in range(20)]
+    for v in verts:
+        v = int(v)
+        s, t = g.row_ptr[v], g.row_ptr[v + 1]
+        if t == s:
+            continue
+        arcs = [s, t - 1] + [rng.randrange(s, t) for _ in range(2)]
+        for p in arcs:
+            u = int(g.col[p])
+            exp = oracle.edge_fragments(g, v, u)
+            assert fr["tri_e"][p] == exp["t"], (v, u)
+            assert fr["k4_e"][p] == exp["k4"], (v, u)
+            if deg[v] < 3000 and deg[u] < 3000:
+                assert fr["c4_e"][p] == exp["c4"], (v, u)
+        assert fr["tri_v"][v] == oracle.vertex_triangles(g, v)

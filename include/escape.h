@@ -118,6 +118,12 @@ esc_status esc_count_fragments(esc_ctx *ctx, int32_t n, const int32_t *row_ptr,
  * `out` is a host array of 8 uint64. */
 esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out);
 
+/* Non-induced counts of the last successful call (the number of subgraphs,
+ * not necessarily induced, isomorphic to each pattern; Sec. 2.1), same order
+ * and length as its induced output: 11 values for k = 4, 45 for k = 5.
+ * `out` is a host array of that many esc_u128. */
+esc_status esc_last_noninduced(const esc_ctx *ctx, esc_u128 *out);
+
 /* Per-stage profile of the last successful call.  Stages, in order:
  *   [0] degree order and relabelled CSR      [1] triangles, per-arc lists
  *   [2] 4-cycles                             [3] per-triangle pass (4- and

@@ -30,7 +30,7 @@ ESC_F_RANDOM_ORDER = 8
 
 ABI_FUNCTIONS = [
     "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments",
-    "esc_last_work", "esc_last_profile", "esc_inverse_matrix", "esc_strerror",
+    "esc_last_work", "esc_last_profile", "esc_last_noninduced", "esc_inverse_matrix", "esc_strerror",
 ]
 
 PATTERN_NAMES = [
@@ -61,6 +61,12 @@ def _load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libescape.so is not built; run `python -m paper_1610_09411_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 with the
+        # same soname, so load it first and let the library bind to that copy.
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
         lib.esc_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t]
@@ -75,6 +81,8 @@ def _load():
         lib.esc_last_work.restype = ctypes.c_int
         lib.esc_last_profile.argtypes = [vp, vp, vp]
         lib.esc_last_profile.restype = ctypes.c_int
+        lib.esc_last_noninduced.argtypes = [vp, vp]
+        lib.esc_last_noninduced.restype = ctypes.c_int
         lib.esc_inverse_matrix.argtypes = [ctypes.c_int, vp]
         lib.esc_inverse_matrix.restype = ctypes.c_int
         lib.esc_strerror.argtypes = [ctypes.c_int]
@@ -126,6 +134,9 @@ class Context:
 
     def last_profile(self):
         return esc_last_profile(self.ptr)
+
+    def last_noninduced(self, k=5):
+        return esc_last_noninduced(self.ptr, k)
 
 
 def esc_create(device: int = 0, hbm_budget_bytes: int = 0):
@@ -197,6 +208,13 @@ def esc_last_work(ctx):
     _check(_load().esc_last_work(ctx, out), "esc_last_work")
     keys = ["W++", "W+-", "W", "T", "D", "max_dplus", "n", "m"]
     return dict(zip(keys, [int(x) for x in out]))
+
+
+def esc_last_noninduced(ctx, k=5):
+    """Non-induced counts of the last call (same order as its induced output)."""
+    out = (_U128 * 45)()
+    _check(_load().esc_last_noninduced(ctx, out), "esc_last_noninduced")
+    return _ints(out, 11 if k == 4 else 45)
 
 
 STAGES = ["orient", "triangles", "four_cycles", "triangle_pass", "reduce", "pairs_13_17", "wheels",

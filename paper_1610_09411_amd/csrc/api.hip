@@ -108,14 +108,14 @@ __global__ void k_fragments_out(int32_t n, const int32_t *rp, const int32_t *col
         }
         o_tv[v] = tv[r];
         o_c4v[v] = c4 / 2;
-        o_k4v[v] = k4 / 3;
+        o_k4v[v] = k4 / 6;          // k4e holds twice K4(e)
         for (int32_t p = rp[v]; p < rp[v + 1]; p++) {
             int32_t y = rank[col[p]];
             int32_t q = lower_bound_i32(adj, off[r], off[r + 1], y);
             int32_t e = arc_eid[q];
             o_te[p] = te[e];
             o_c4e[p] = c4e ? c4e[e] : 0;
-            o_k4e[p] = k4e[e];
+            o_k4e[p] = k4e[e] / 2;
         }
     }
 }
@@ -264,6 +264,12 @@ extern "C" esc_status esc_count_fragments(esc_ctx *ctx, int32_t n, const int32_t
 extern "C" esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out) {
     if (!ctx || !out) return ESC_EINVAL;
     memcpy(out, ctx->work, sizeof(uint64_t) * 8);
+    return ESC_OK;
+}
+
+extern "C" esc_status esc_last_noninduced(const esc_ctx *ctx, esc_u128 *out) {
+    if (!ctx || !out) return ESC_EINVAL;
+    memcpy(out, ctx->noninduced, sizeof(esc_u128) * (ctx->k == 4 ? 11 : 45));
     return ESC_OK;
 }
 

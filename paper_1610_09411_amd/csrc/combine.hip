@@ -186,6 +186,7 @@ __global__ void k_combine(const unsigned long long *acc, const int32_t *inv4, co
     N4[9] = n >= 3 ? W * (n - 3) : 0;
     N4[10] = n >= 3 ? T * (n - 3) : 0;
     for (int i = 0; i < 11; i++) out[i] = apply_inv(inv4, 11, i, N4);
+    for (int i = 0; i < 11; i++) out[45 + i] = N4[i];
     if (k < 5) return;
     u128 N5[34];
     N5[0] = S[AC_S4];
@@ -225,21 +226,24 @@ __global__ void k_combine(const unsigned long long *acc, const int32_t *inv4, co
     // triangle + disjoint edge
     N5[33] = T * m - S[AC_TD] + 3 * T;
     for (int i = 0; i < 34; i++) out[11 + i] = apply_inv(inv5, 34, i, N5);
+    for (int i = 0; i < 34; i++) out[56 + i] = N5[i];
 }
 
 esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, const int32_t *d_inv5) {
-    u128 *dout = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * 48);
+    u128 *dout = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * 96);
     if (!dout) return ESC_ENOMEM;
     k_combine<<<1, 64, 0, c->stream>>>((const unsigned long long *)c->buf[B_ACC], d_inv4, d_inv5, c->n, c->m, c->k,
                                        dout);
     HIP_TRY(hipGetLastError());
-    u128 h[45];
+    u128 h[90];
     int cnt = c->k == 4 ? 11 : 45;
-    HIP_TRY(hipMemcpyAsync(h, dout, sizeof(u128) * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(h, dout, sizeof(u128) * 90, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (int i = 0; i < cnt; i++) {
         host_out[i].lo = (uint64_t)h[i];
         host_out[i].hi = (uint64_t)(h[i] >> 64);
+        c->noninduced[i].lo = (uint64_t)h[45 + i];
+        c->noninduced[i].hi = (uint64_t)(h[45 + i] >> 64);
     }
     return ESC_OK;
 }

@@ -76,6 +76,7 @@ struct esc_ctx {
     uint64_t work[8];
     float stage_ms[9];
     uint64_t visits[9];
+    esc_u128 noninduced[45];
     hipEvent_t ev[10];
     // current graph
     int32_t n;

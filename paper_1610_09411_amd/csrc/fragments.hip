@@ -262,7 +262,8 @@ __device__ inline uint32_t count_common(const int32_t *a, int64_t na, const int3
 // One wave per out-arc a->b (a before b); lanes take the triangles a<b<c owned
 // by it (apexes after b in the sorted list).  For each triangle:
 //   K4(t) = common neighbours of a, b, c = |apex(ab) & apex(ac)|
-//   K4(e) += K4(t) for its three edges; sum K4(t) = 4 K4
+//   k4e(e) += K4(t) for its three edges, so k4e(e) = 2 K4(e) (a 4-clique on
+//   an edge holds two triangles through it); sum K4(t) = 4 K4
 //   C(K4(t),2) -> pattern 20; the triangle-cut sums of patterns 10 and 16;
 //   Z term d+(a)+d+(b)+d+(c)-3 (5-cycle correction);
 //   L = common neighbours after c; every edge inside L closes a 5-clique.
@@ -380,7 +381,7 @@ esc_status stage_triangle_sums(esc_ctx *c) {
 // -------------------------------------------------------------- reductions
 
 // per vertex r (rank ids): t(v) = half the sum of t(e) over its edges,
-// K4(v) = a third of the sum of K4(e).
+// K4(v) = a third of the sum of K4(e) = a sixth of the sum of k4e.
 __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t *off, const int32_t *adj,
                                                        const int32_t *split, const int32_t *arc_eid,
                                                        const uint32_t *te, const unsigned long long *k4e,
@@ -404,7 +405,7 @@ __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t 
             B += (u128)(dj - 1) * (dj - 1);
             sd += dj;
         }
-        const uint64_t t = t2 / 2, k4v = k3 / 3;
+        const uint64_t t = t2 / 2, k4v = k3 / 6;
         tv[r] = t;
         s[0] += c2(d);
         s[1] += c3(d);
@@ -441,7 +442,7 @@ __global__ void __launch_bounds__(256) k_edge_reduce(int64_t m, const int32_t *o
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t u = elo[e], v = adj[earc[e]];
         const uint64_t du = off[u + 1] - off[u], dv = off[v + 1] - off[v];
-        const uint64_t t = te[e], tu = tv[u], tw = tv[v], k4 = k4e[e];
+        const uint64_t t = te[e], tu = tv[u], tw = tv[v], k4 = k4e[e] / 2;
         s[0] += t;
         s[1] += c2(t);
         s[2] += (u128)(du - 1) * (dv - 1);

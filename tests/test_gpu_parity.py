@@ -47,12 +47,27 @@ def test_library_is_native_and_loaded(ctx):
     assert esc._lib is not None
 
 
+def _check_equal(ctx, g, k=5, **kw):
+    """GPU counts == oracle counts; on a mismatch name the non-induced counts
+    that differ (they map one-to-one onto the device sums)."""
+    from oracle import patterns as pat
+    got = ctx.count(g, k, **kw)
+    want = oracle.count(g, k, threads=8)
+    if got != want:
+        S = oracle.sums(g, k)
+        nonind = oracle.noninduced_from_sums(S, 4) + (oracle.noninduced_from_sums(S, 5) if k == 5 else [])
+        gpu_non = ctx.last_noninduced(k)
+        diff = [(pat.ALL_NAMES[i], gpu_non[i], nonind[i]) for i in range(len(nonind)) if gpu_non[i] != nonind[i]]
+        raise AssertionError("%s: non-induced (name, gpu, oracle) differing: %s" % (g.name, diff))
+    return got
+
+
 @pytest.mark.parametrize("idx", range(len(_cases_small())))
 def test_small_graphs_equal_oracle(ctx, idx):
     g = _cases_small()[idx]
     print("case", idx, g.name, g.n, g.m, flush=True)
-    assert ctx.count(g, 5) == oracle.count(g, 5)
-    assert ctx.count(g, 4) == oracle.count(g, 4)
+    _check_equal(ctx, g, 5)
+    _check_equal(ctx, g, 4)
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 6])
@@ -82,7 +97,7 @@ def test_power_law_graphs_equal_oracle(ctx, n, gamma, dbar, dmax, seed):
     """Several thousand vertices: many workgroups, hubs, ragged lists."""
     g = synth.chung_lu(n, gamma, dbar, dmax, seed)
     print("chung_lu", n, g.m, flush=True)
-    assert ctx.count(g, 5) == oracle.count(g, 5, threads=8)
+    _check_equal(ctx, g, 5)
 
 
 def test_random_order_gives_same_counts(ctx):

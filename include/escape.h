@@ -126,14 +126,15 @@ esc_status esc_last_noninduced(const esc_ctx *ctx, esc_u128 *out);
 
 /* Per-stage profile of the last successful call.  Stages, in order:
  *   [0] degree order and relabelled CSR      [1] triangles, per-arc lists
- *   [2] 4-cycles                             [3] per-triangle pass (4- and
- *       5-cliques, triangle-cut sums)        [4] vertex and edge sums
- *   [5] pattern 13/17 pair pass              [6] wheels (pattern 18)
- *   [7] 5-cycles                             [8] final combination
- * `ms_out` (9 floats, may be NULL): device milliseconds per stage (HIP events
- * on the call's stream).  `visits_out` (9 uint64, may be NULL): elements the
- * stage's main loop visited (neighbour or triangle-list entries read; 0 where
- * not counted). */
+ *   [2] 4-cycles                             [3] 4-cliques per triangle and
+ *                                                the triangle-cut sums
+ *   [4] 5-cliques                            [5] vertex and edge sums
+ *   [6] pattern 13/17 pair pass              [7] wheels (pattern 18)
+ *   [8] 5-cycles                             [9] final combination
+ * `ms_out` (10 floats, may be NULL): device milliseconds per stage (HIP
+ * events on the call's stream).  `visits_out` (10 uint64, may be NULL):
+ * elements the stage's main loop visited (neighbour or triangle-list entries
+ * read, bitmap words for 5-cliques; 0 where not counted). */
 esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64_t *visits_out);
 
 /* The signed inverse of the matrix that maps induced to non-induced counts

@@ -217,14 +217,14 @@ def esc_last_noninduced(ctx, k=5):
     return _ints(out, 11 if k == 4 else 45)
 
 
-STAGES = ["orient", "triangles", "four_cycles", "triangle_pass", "reduce", "pairs_13_17", "wheels",
-          "five_cycles", "combine"]
+STAGES = ["orient", "triangles", "four_cycles", "k4_triangles", "five_cliques", "reduce", "pairs_13_17",
+          "wheels", "five_cycles", "combine"]
 
 
 def esc_last_profile(ctx):
     """{stage: (device ms, elements visited)} of the last call."""
-    ms = (ctypes.c_float * 9)()
-    vis = (ctypes.c_uint64 * 9)()
+    ms = (ctypes.c_float * len(STAGES))()
+    vis = (ctypes.c_uint64 * len(STAGES))()
     _check(_load().esc_last_profile(ctx, ms, vis), "esc_last_profile")
     return {k: (float(ms[i]), int(vis[i])) for i, k in enumerate(STAGES)}
 

@@ -65,7 +65,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     c->max_lds = lds;
     if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) { free(c); return ESC_EDEVICE; }
     c->stream = c->own_stream;
-    for (int i = 0; i < 10; i++)
+    for (int i = 0; i <= NSTAGES; i++)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     int32_t h4[121], h5[1156];
     combine_tables(h4, h5);
@@ -86,7 +86,7 @@ extern "C" void esc_destroy(esc_ctx *c) {
         if (c->buf[b]) hipFree(c->buf[b]);
     if (c->d_inv4) hipFree(c->d_inv4);
     if (c->d_inv5) hipFree(c->d_inv5);
-    for (int i = 0; i < 10; i++)
+    for (int i = 0; i <= NSTAGES; i++)
         if (c->ev[i]) hipEventDestroy(c->ev[i]);
     if (c->own_stream) hipStreamDestroy(c->own_stream);
     free(c);
@@ -147,7 +147,6 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
     c->m = m2 / 2;
     c->k = k;
     c->flags = flags;
-    esc_status s = ESC_OK;
     const int32_t *d_rp = row_ptr, *d_col = col;
     if (!on_dev) {
         int32_t *brp = (int32_t *)ctx_buf(c, B_RP_IN, sizeof(int32_t) * ((size_t)n + 1));
@@ -167,40 +166,29 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
         HIP_TRY(hipMemsetAsync(c->buf[B_WG_SCRATCH], 0, c->cap[B_WG_SCRATCH], st));
     }
     c->scratch_clean = false;   // until the pipeline completes
-    HIP_TRY(hipEventRecord(c->ev[0], st));
-    s = stage_orient(c, d_rp, d_col);
-    if (s) return s;
-    HIP_TRY(hipEventRecord(c->ev[1], st));
-    s = stage_triangles(c);
-    if (s) return s;
-    HIP_TRY(hipEventRecord(c->ev[2], st));
-    s = stage_four(c, frag != nullptr);
-    if (s) return s;
-    HIP_TRY(hipEventRecord(c->ev[3], st));
-    s = stage_triangle_sums(c);
-    if (s) return s;
-    HIP_TRY(hipEventRecord(c->ev[4], st));
-    s = stage_reduce(c);
-    if (s) return s;
-    HIP_TRY(hipEventRecord(c->ev[5], st));
-    if (k == 5) {
-        s = stage_pairs(c);
-        if (s) return s;
-    }
-    HIP_TRY(hipEventRecord(c->ev[6], st));
-    if (k == 5) {
-        s = stage_wheels(c);
-        if (s) return s;
-    }
-    HIP_TRY(hipEventRecord(c->ev[7], st));
-    if (k == 5) {
-        s = stage_cycles(c);
-        if (s) return s;
-    }
-    HIP_TRY(hipEventRecord(c->ev[8], st));
-    s = stage_combine(c, out, c->d_inv4, c->d_inv5);
-    if (s) return s;
-    HIP_TRY(hipEventRecord(c->ev[9], st));
+    // stages, each bracketed by events on the call's stream (see esc_last_profile)
+    int ev = 0;
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_orient(c, d_rp, d_col));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_triangles(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_four(c, frag != nullptr));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_k4_triangles(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_k5(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_reduce(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_pairs(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_wheels(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_cycles(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_combine(c, out, c->d_inv4, c->d_inv5));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
     if (frag) {
         size_t nn = (size_t)n, aa = (size_t)m2;
         uint64_t *fb = (uint64_t *)ctx_buf(c, B_FRAG, sizeof(uint64_t) * (3 * nn + 3 * aa + 8));
@@ -238,7 +226,7 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
     c->work[5] = (uint64_t)c->maxdplus;
     c->work[6] = (uint64_t)n;
     c->work[7] = (uint64_t)c->m;
-    for (int i = 0; i < 9; i++) {
+    for (int i = 0; i < NSTAGES; i++) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
         c->stage_ms[i] = ms;
@@ -275,8 +263,8 @@ extern "C" esc_status esc_last_noninduced(const esc_ctx *ctx, esc_u128 *out) {
 
 extern "C" esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64_t *visits_out) {
     if (!ctx) return ESC_EINVAL;
-    if (ms_out) memcpy(ms_out, ctx->stage_ms, sizeof(float) * 9);
-    if (visits_out) memcpy(visits_out, ctx->visits, sizeof(uint64_t) * 9);
+    if (ms_out) memcpy(ms_out, ctx->stage_ms, sizeof(float) * NSTAGES);
+    if (visits_out) memcpy(visits_out, ctx->visits, sizeof(uint64_t) * NSTAGES);
     return ESC_OK;
 }
 

@@ -1,0 +1,275 @@
+// 4-cliques per triangle (Thm 4clique) and 5-cliques (Thm 5clique).
+//
+// K4(t) for every triangle t = {a<b<c} is the number of common neighbours of
+// a, b and c.  The triangle list of arc (a,b) is the common neighbourhood of
+// a and b, stored as positions in the row of a; the list of arc (a,c) is the
+// common neighbourhood of a and c in the same coordinates.  One wave takes
+// an edge (a,b), marks its list in an LDS bitmap over the row of a, and each
+// lane counts, for one triangle (a,b,c) with c after b, the marked entries of
+// the list of (a,c).  From K4(t): K4(e) (scattered to the three edges),
+// sum C(K4(t),2) (pattern 20), the triangle-cut sums of patterns 10 and 16 and
+// the 5-cycle correction term of each triangle.
+//
+// 5-cliques: a 5-clique is found once, from its earliest vertex a, as a
+// 4-clique of the DAG restricted to N+(a).  For every out-arc (c,x) a bitmap
+// over the positions of N+(c) marks N+(c) & N+(x) (read off the triangle list
+// of (c,x)); with these rows, for a and b<c<x in N+(a):
+//   S = row(a,b) & row(a,c)           (common out-neighbours of a, b, c)
+//   5-cliques += popcount(S & row(a,x)) for every x in S.
+#include "device.h"
+#include "ctx.h"
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+#define BM_WORDS 512   // LDS bitmap per wave: rows of up to 16384 vertices
+
+static int grid_cap(esc_ctx *c, int64_t items, int threads, int per_cu = 16) {
+    int64_t b = (items + threads - 1) / threads;
+    int64_t cap = (int64_t)c->num_cu * per_cu;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// merge-count of two sorted id lists (rows too long for the bitmap)
+__device__ inline uint32_t count_common(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, uint64_t &nvis) {
+    int64_t x = 0, y = 0;
+    uint32_t c = 0;
+    while (x < na && y < nb) {
+        int32_t p = a[x], q = b[y];
+        c += (p == q);
+        x += (p <= q);
+        y += (q <= p);
+    }
+    nvis += x + y;
+    return c;
+}
+
+__global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *off, const int32_t *adj,
+                                                      const int32_t *split, const int32_t *rev,
+                                                      const int32_t *arc_eid, const int32_t *earc,
+                                                      const int32_t *elo, const uint32_t *te, const int64_t *aoff,
+                                                      const uint32_t *aa, const int32_t *av,
+                                                      unsigned long long *k4e, unsigned long long *acc,
+                                                      unsigned long long *visits) {
+    __shared__ uint32_t bm_all[4][BM_WORDS];
+    __shared__ u128 red[5 * 4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t *bm = bm_all[wid];
+    for (int w = lane; w < BM_WORDS; w += 64) bm[w] = 0;
+    wave_sync();
+    const int64_t wave = (int64_t)blockIdx.x * 4 + wid;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    u128 s[5] = {0, 0, 0, 0, 0};
+    uint64_t nvis = 0;
+    for (int64_t e = wave; e < m; e += nwaves) {
+        const int32_t p = earc[e];
+        const int64_t l0 = aoff[p], l1 = aoff[p + 1];
+        if (l1 == l0) continue;
+        const int32_t a = elo[e], b = adj[p];
+        int64_t lo = l0, hi = l1;   // first apex after b
+        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] <= b) lo = mid + 1; else hi = mid; }
+        if (lo == l1) continue;
+        const int32_t oa = off[a];
+        const int32_t da_i = off[a + 1] - oa;
+        const bool use_bm = da_i <= BM_WORDS * 32;
+        if (use_bm) {
+            for (int64_t k = l0 + lane; k < l1; k += 64) {
+                int32_t pos = (int32_t)aa[k] - oa;
+                atomicOr(&bm[pos >> 5], 1u << (pos & 31));
+            }
+            wave_sync();
+        }
+        const int64_t r0 = aoff[rev[p]];
+        const uint64_t da = da_i, db = off[b + 1] - off[b];
+        const uint64_t dpa = off[a + 1] - split[a], dpb = off[b + 1] - split[b];
+        const uint64_t tab = te[e];
+        for (int64_t k = lo + lane; k < l1; k += 64) {
+            const int32_t cc = av[k];
+            const int32_t pac = (int32_t)aa[k];             // arc (a,c) in row a
+            const int32_t pbc = (int32_t)aa[r0 + (k - l0)]; // arc (b,c) in row b
+            const int32_t eac = arc_eid[pac], ebc = arc_eid[pbc];
+            const uint64_t tac = te[eac], tbc = te[ebc];
+            const uint64_t dc = off[cc + 1] - off[cc], dpc = off[cc + 1] - split[cc];
+            uint32_t k4 = 0;
+            const int64_t q0 = aoff[pac], q1 = aoff[pac + 1];
+            if (use_bm) {
+                for (int64_t q = q0; q < q1; q++) {
+                    int32_t pos = (int32_t)aa[q] - oa;
+                    k4 += (bm[pos >> 5] >> (pos & 31)) & 1u;
+                }
+                nvis += q1 - q0;
+            } else {
+                k4 = count_common(av + l0, l1 - l0, av + q0, q1 - q0, nvis);
+            }
+            if (k4) {
+                atomicAdd(&k4e[e], (unsigned long long)k4);
+                atomicAdd(&k4e[eac], (unsigned long long)k4);
+                atomicAdd(&k4e[ebc], (unsigned long long)k4);
+            }
+            s[0] += k4;
+            s[1] += c2(k4);
+            s[2] += (u128)(tbc - 1) * (da - 2) + (u128)(tac - 1) * (db - 2) + (u128)(tab - 1) * (dc - 2);
+            s[3] += (u128)(tab - 1) * (tac - 1) + (u128)(tab - 1) * (tbc - 1) + (u128)(tac - 1) * (tbc - 1);
+            s[4] += dpa + dpb + dpc - 3;
+        }
+        if (use_bm) {
+            wave_sync();
+            for (int64_t k = l0 + lane; k < l1; k += 64) {
+                int32_t pos = (int32_t)aa[k] - oa;
+                bm[pos >> 5] = 0;
+            }
+            wave_sync();
+        }
+    }
+    const int ids[5] = {AC_K4X4, AC_N20, AC_N10, AC_N16, AC_Z};
+    block_flush_u128<5>(s, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+// ---------------------------------------------------------------- 5-cliques
+
+__global__ void k_ob_sizes(int32_t n, const int32_t *off, const int32_t *split, int64_t *len) {
+    for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        int64_t dp = off[c + 1] - split[c];
+        len[c] = dp * ((dp + 63) >> 6);
+    }
+}
+
+// one thread per out-arc (c,x): the row of (c,x) marks the apexes of its
+// triangle list that come after x, by position in N+(c)
+__global__ void k_ob_rows(int32_t n, const int32_t *off, const int32_t *split, const int64_t *aoff,
+                          const uint32_t *aa, const int32_t *av, const int32_t *adj, const int64_t *ob_off,
+                          unsigned long long *ob) {
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int32_t c = wave; c < n; c += nwaves) {
+        const int32_t sc = split[c], ec = off[c + 1];
+        const int32_t dp = ec - sc;
+        const int wc = (dp + 63) >> 6;
+        for (int32_t p = sc + lane; p < ec; p += 64) {
+            const int32_t x = adj[p];
+            unsigned long long *row = ob + ob_off[c] + (int64_t)(p - sc) * wc;
+            const int64_t k1 = aoff[p + 1];
+            int64_t k = aoff[p];
+            while (k < k1 && av[k] <= x) k++;   // apexes after x only
+            for (; k < k1; k++) {
+                int32_t pos = (int32_t)aa[k] - sc;
+                row[pos >> 6] |= 1ull << (pos & 63);
+            }
+        }
+    }
+}
+
+__device__ inline int nth_set_bit(const unsigned long long *row, int words, int r) {
+    for (int w = 0; w < words; w++) {
+        unsigned long long x = row[w];
+        int c = __popcll(x);
+        if (r < c) {
+            for (int t = 0; t < r; t++) x &= x - 1;
+            return w * 64 + __ffsll((long long)x) - 1;
+        }
+        r -= c;
+    }
+    return -1;
+}
+
+// one workgroup per vertex a; items = pairs (b, c) with c in row(a,b)
+__global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const int32_t *split,
+                                            const int64_t *ob_off, const unsigned long long *ob, int *task,
+                                            unsigned long long *acc, unsigned long long *visits) {
+    __shared__ int pref[257], tmp[8];
+    __shared__ int64_t beg[257];
+    __shared__ int s_a;
+    __shared__ u128 red[4];
+    u128 k5 = 0;
+    uint64_t nvis = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_a = atomicAdd(task, 1);
+        __syncthreads();
+        const int32_t a = s_a;
+        if (a >= n) break;
+        const int32_t dpa = off[a + 1] - split[a];
+        if (dpa < 4) { __syncthreads(); continue; }
+        const int wa = (dpa + 63) >> 6;
+        const unsigned long long *rows = ob + ob_off[a];
+        for (int ib = 0; ib < dpa; ib += blockDim.x) {
+            int i = ib + threadIdx.x;
+            int len = 0;
+            if (i < dpa)
+                for (int w = 0; w < wa; w++) len += __popcll(rows[(int64_t)i * wa + w]);
+            lbs_batch(0, len, pref, beg, tmp, [&](int s, int64_t r) {
+                const unsigned long long *rb = rows + (int64_t)(ib + s) * wa;
+                const int j = nth_set_bit(rb, wa, (int)r);
+                const unsigned long long *rc = rows + (int64_t)j * wa;
+                for (int w = 0; w < wa; w++) {
+                    unsigned long long sw = rb[w] & rc[w];
+                    while (sw) {
+                        const int x = w * 64 + __ffsll((long long)sw) - 1;
+                        sw &= sw - 1;
+                        const unsigned long long *rx = rows + (int64_t)x * wa;
+                        for (int w2 = 0; w2 < wa; w2++) k5 += __popcll(rb[w2] & rc[w2] & rx[w2]);
+                        nvis += wa;
+                    }
+                }
+            });
+        }
+    }
+    const int ids[1] = {AC_K5};
+    u128 v[1] = {k5};
+    block_flush_u128<1>(v, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+// ------------------------------------------------------------------- stages
+
+esc_status stage_k4_triangles(esc_ctx *c) {
+    hipStream_t st = c->stream;
+    const int64_t m = c->m;
+    unsigned long long *k4e = (unsigned long long *)ctx_buf(c, B_K4E, sizeof(uint64_t) * (size_t)(m + 1));
+    if (!k4e) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(k4e, 0, sizeof(uint64_t) * (size_t)(m + 1), st));
+    if (m == 0 || c->narcs_apex == 0) return ESC_OK;
+    k_k4_triangles<<<grid_cap(c, m * 64, 256, 8), 256, 0, st>>>(
+        m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
+        (const int32_t *)c->buf[B_REV], (const int32_t *)c->buf[B_ARC_EID], (const int32_t *)c->buf[B_EARC],
+        (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], (const int64_t *)c->buf[B_AOFF],
+        (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], k4e, (unsigned long long *)c->buf[B_ACC],
+        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
+esc_status stage_k5(esc_ctx *c) {
+    hipStream_t st = c->stream;
+    const int32_t n = c->n;
+    if (n == 0 || c->narcs_apex == 0) return ESC_OK;
+    const int32_t *off = (const int32_t *)c->buf[B_OFF], *split = (const int32_t *)c->buf[B_SPLIT];
+    int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
+    int64_t *ob_off = (int64_t *)ctx_buf(c, B_OB_OFF, sizeof(int64_t) * (size_t)(n + 2));
+    if (!len || !ob_off) return ESC_ENOMEM;
+    k_ob_sizes<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, len);
+    HIP_TRY(hipGetLastError());
+    ESC_TRY(dev_exclusive_scan_i64(c, len, ob_off, n));
+    int64_t words = 0;
+    HIP_TRY(hipMemcpyAsync(&words, ob_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    unsigned long long *ob = (unsigned long long *)ctx_buf(c, B_OB, sizeof(uint64_t) * (size_t)(words + 1));
+    int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
+    if (!ob || !task) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(ob, 0, sizeof(uint64_t) * (size_t)(words + 1), st));
+    HIP_TRY(hipMemsetAsync(task + 3, 0, sizeof(int), st));
+    k_ob_rows<<<grid_cap(c, (int64_t)n * 64, 256), 256, 0, st>>>(
+        n, off, split, (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV],
+        (const int32_t *)c->buf[B_ADJ], ob_off, ob);
+    HIP_TRY(hipGetLastError());
+    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, task + 3, (unsigned long long *)c->buf[B_ACC],
+                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}

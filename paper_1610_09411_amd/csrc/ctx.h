@@ -60,8 +60,11 @@ enum Buf {
     B_WG_TOUCH,
     B_TASK,
     B_FRAG,                     // fragment outputs in input order
+    B_OB, B_OB_OFF,             // out-neighbourhood bitmaps for 5-cliques
     B_COUNT
 };
+
+#define NSTAGES 10
 
 struct esc_ctx {
     int device;
@@ -74,10 +77,10 @@ struct esc_ctx {
     int num_cu;
     int max_lds;               // bytes of LDS one workgroup may allocate
     uint64_t work[8];
-    float stage_ms[9];
-    uint64_t visits[9];
+    float stage_ms[NSTAGES];
+    uint64_t visits[NSTAGES];
     esc_u128 noninduced[45];
-    hipEvent_t ev[10];
+    hipEvent_t ev[NSTAGES + 1];
     // current graph
     int32_t n;
     int64_t m2;                // number of arcs (2m)
@@ -109,7 +112,8 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4);
 esc_status stage_pairs(esc_ctx *c);
 esc_status stage_wheels(esc_ctx *c);
 esc_status stage_cycles(esc_ctx *c);
-esc_status stage_triangle_sums(esc_ctx *c);
+esc_status stage_k4_triangles(esc_ctx *c);
+esc_status stage_k5(esc_ctx *c);
 esc_status stage_reduce(esc_ctx *c);
 esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, const int32_t *d_inv5);
 esc_status combine_tables(int32_t *host_inv4, int32_t *host_inv5);

@@ -8,9 +8,6 @@
 //  * 4-cycles (Thm 4cycle) from wedges below their latest vertex; only the
 //    sums the 5-vertex formulas need (sum C4(e) t(e), sum C4(v)(d(v)-2)) are
 //    formed, both linear in the per-edge counts.
-//  * per-triangle pass: K4(t) = |common neighbours of t|, from which K4(e),
-//    K4(v), K4 (Thm 4clique), the triangle-cut sums of Thm 5cuttri, the
-//    5-cycle correction Z (Thm 5cycle) and 5-cliques (Thm 5clique).
 //  * vertex and edge reductions for Thms 4vertex-easy, 5cutvertex, 5cutedge.
 #include "device.h"
 #include "ctx.h"
@@ -243,141 +240,6 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     return ESC_OK;
 }
 
-// ------------------------------------------------------------ per triangle
-
-// merge-count of two sorted int lists
-__device__ inline uint32_t count_common(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, uint64_t &nvis) {
-    int64_t x = 0, y = 0;
-    uint32_t c = 0;
-    while (x < na && y < nb) {
-        int32_t p = a[x], q = b[y];
-        c += (p == q);
-        x += (p <= q);
-        y += (q <= p);
-    }
-    nvis += x + y;
-    return c;
-}
-
-// One wave per out-arc a->b (a before b); lanes take the triangles a<b<c owned
-// by it (apexes after b in the sorted list).  For each triangle:
-//   K4(t) = common neighbours of a, b, c = |apex(ab) & apex(ac)|
-//   k4e(e) += K4(t) for its three edges, so k4e(e) = 2 K4(e) (a 4-clique on
-//   an edge holds two triangles through it); sum K4(t) = 4 K4
-//   C(K4(t),2) -> pattern 20; the triangle-cut sums of patterns 10 and 16;
-//   Z term d+(a)+d+(b)+d+(c)-3 (5-cycle correction);
-//   L = common neighbours after c; every edge inside L closes a 5-clique.
-__global__ void __launch_bounds__(256) k_triangle_pass(int64_t m, const int32_t *off, const int32_t *adj,
-                                                       const int32_t *split, const int32_t *rev,
-                                                       const int32_t *arc_eid, const int32_t *earc,
-                                                       const int32_t *elo, const uint32_t *te,
-                                                       const int64_t *aoff, const uint32_t *aa,
-                                                       const int32_t *av, unsigned long long *k4e,
-                                                       int32_t *lbuf, int32_t lcap, unsigned long long *acc,
-                                                       unsigned long long *visits) {
-    uint64_t nvis = 0;
-    __shared__ u128 red[7 * 4];
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    int32_t *L = lbuf + (size_t)((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * lcap;
-    u128 s[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t e = wave; e < m; e += nwaves) {
-        const int32_t p = earc[e];
-        const int32_t a = elo[e], b = adj[p];
-        const int32_t rp = rev[p];
-        const int64_t l0 = aoff[p], l1 = aoff[p + 1];
-        if (l1 - l0 == 0) continue;
-        const int64_t r0 = aoff[rp];
-        // first apex after b
-        int64_t lo = l0, hi = l1;
-        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] <= b) lo = mid + 1; else hi = mid; }
-        const uint64_t da = off[a + 1] - off[a], db = off[b + 1] - off[b];
-        const uint64_t dpa = off[a + 1] - split[a], dpb = off[b + 1] - split[b];
-        const uint64_t tab = te[e];
-        for (int64_t k = lo + lane; k < l1; k += 64) {
-            const int32_t cc = av[k];
-            const int32_t pac = (int32_t)aa[k];             // arc (a,c) in row a
-            const int32_t pbc = (int32_t)aa[r0 + (k - l0)]; // arc (b,c) in row b
-            const uint64_t tac = te[arc_eid[pac]], tbc = te[arc_eid[pbc]];
-            const uint64_t dc = off[cc + 1] - off[cc], dpc = off[cc + 1] - split[cc];
-            // K4(t): intersect the two shortest apex lists among ab, ac, bc
-            const int32_t *A1 = av + l0; int64_t n1 = l1 - l0;
-            const int32_t *A2 = av + aoff[pac]; int64_t n2 = aoff[pac + 1] - aoff[pac];
-            const int32_t *A3 = av + aoff[pbc]; int64_t n3 = aoff[pbc + 1] - aoff[pbc];
-            if (n3 < n1 || n3 < n2) {
-                if (n1 >= n2) { A1 = A3; n1 = n3; } else { A2 = A3; n2 = n3; }
-            }
-            const uint32_t k4 = count_common(A1, n1, A2, n2, nvis);
-            if (k4) {
-                atomicAdd(&k4e[e], (unsigned long long)k4);
-                atomicAdd(&k4e[arc_eid[pac]], (unsigned long long)k4);
-                atomicAdd(&k4e[arc_eid[pbc]], (unsigned long long)k4);
-            }
-            s[0] += k4;
-            s[1] += c2(k4);
-            s[2] += (u128)(tbc - 1) * (da - 2) + (u128)(tac - 1) * (db - 2) + (u128)(tab - 1) * (dc - 2);
-            s[3] += (u128)(tab - 1) * (tac - 1) + (u128)(tab - 1) * (tbc - 1) + (u128)(tac - 1) * (tbc - 1);
-            s[4] += dpa + dpb + dpc - 3;
-            // 5-cliques: L = common neighbours after c (a subset of N+(c))
-            if (k4 >= 2) {
-                int64_t x = 0, y = 0;
-                int nl = 0;
-                while (x < n1 && y < n2) {
-                    int32_t pp = A1[x], qq = A2[y];
-                    if (pp == qq && pp > cc) { if (nl < lcap) L[nl] = pp; nl++; }
-                    x += (pp <= qq);
-                    y += (qq <= pp);
-                }
-                if (nl > lcap) nl = lcap;   // cannot happen: L lies inside N+(c)
-                uint64_t k5 = 0;
-                for (int i = 0; i + 1 < nl; i++) {
-                    const int32_t xv = L[i];
-                    // |{y in L after x} & N+(x)|
-                    int32_t q = split[xv];
-                    const int32_t qe = off[xv + 1];
-                    int j = i + 1;
-                    while (j < nl && q < qe) {
-                        int32_t u = L[j], w = adj[q];
-                        nvis += 2;
-                        k5 += (u == w);
-                        j += (u <= w);
-                        q += (w <= u);
-                    }
-                }
-                s[5] += k5;
-            }
-        }
-    }
-    const int ids[6] = {AC_K4X4, AC_N20, AC_N10, AC_N16, AC_Z, AC_K5};
-    u128 v6[6] = {s[0], s[1], s[2], s[3], s[4], s[5]};
-    block_flush_u128<6>(v6, red, acc, ids);
-    flush_count(nvis, visits);
-}
-
-esc_status stage_triangle_sums(esc_ctx *c) {
-    hipStream_t st = c->stream;
-    const int64_t m = c->m;
-    unsigned long long *k4e = (unsigned long long *)ctx_buf(c, B_K4E, sizeof(uint64_t) * (size_t)(m + 1));
-    if (!k4e) return ESC_ENOMEM;
-    HIP_TRY(hipMemsetAsync(k4e, 0, sizeof(uint64_t) * (size_t)(m + 1), st));
-    if (m == 0 || c->narcs_apex == 0) return ESC_OK;
-    int g = grid_cap(c, m * 64, 256, 8);
-    int32_t lcap = c->maxdplus + 1;
-    int32_t *lbuf = (int32_t *)ctx_buf(c, B_WG_TOUCH, sizeof(int32_t) * (size_t)g * 256 * lcap);
-    if (!lbuf) return ESC_ENOMEM;
-    k_triangle_pass<<<g, 256, 0, st>>>(m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
-                                       (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
-                                       (const int32_t *)c->buf[B_ARC_EID], (const int32_t *)c->buf[B_EARC],
-                                       (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE],
-                                       (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
-                                       (const int32_t *)c->buf[B_AV], k4e, lbuf, lcap,
-                                       (unsigned long long *)c->buf[B_ACC],
-                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
-    HIP_TRY(hipGetLastError());
-    return ESC_OK;
-}
-
 // -------------------------------------------------------------- reductions
 
 // per vertex r (rank ids): t(v) = half the sum of t(e) over its edges,
@@ -430,7 +292,7 @@ __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t 
         atomicAdd((unsigned long long *)&work[0], (unsigned long long)wpp);
         atomicAdd((unsigned long long *)&work[1], (unsigned long long)wpm);
     }
-    flush_count(nvis, (unsigned long long *)&work[WORK_VISITS + 4]);
+    flush_count(nvis, (unsigned long long *)&work[WORK_VISITS + 5]);
 }
 
 __global__ void __launch_bounds__(256) k_edge_reduce(int64_t m, const int32_t *off, const int32_t *adj,

@@ -282,7 +282,7 @@ esc_status stage_pairs(esc_ctx *c) {
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
                                           (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], tab, touch,
                                           task, (unsigned long long *)c->buf[B_ACC],
-                                          (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 5);
+                                          (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
 }
@@ -304,7 +304,7 @@ esc_status stage_wheels(esc_ctx *c) {
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               (const int32_t *)c->buf[B_AV], tab, touch, lds_cap, task + 1,
                                               (unsigned long long *)c->buf[B_ACC],
-                                              (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
+                                              (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
 }
@@ -321,7 +321,7 @@ esc_status stage_cycles(esc_ctx *c) {
     k_five_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)n * nwg, touch,
                                        touch + (size_t)n * nwg, task + 2, (unsigned long long *)c->buf[B_ACC],
-                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
+                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 8);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
 }

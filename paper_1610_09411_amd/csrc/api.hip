@@ -8,8 +8,8 @@ void *ctx_buf(esc_ctx *c, Buf b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (c->buf[b] && c->cap[b] >= bytes) return c->buf[b];
     if (c->buf[b]) {
-        hipStreamSynchronize(c->stream);
-        hipFree(c->buf[b]);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->buf[b]);
         c->held -= c->cap[b];
         c->buf[b] = nullptr;
         c->cap[b] = 0;
@@ -80,15 +80,15 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
 
 extern "C" void esc_destroy(esc_ctx *c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    if (c->own_stream) hipStreamSynchronize(c->own_stream);
+    (void)hipSetDevice(c->device);
+    if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
     for (int b = 0; b < B_COUNT; b++)
-        if (c->buf[b]) hipFree(c->buf[b]);
-    if (c->d_inv4) hipFree(c->d_inv4);
-    if (c->d_inv5) hipFree(c->d_inv5);
+        if (c->buf[b]) (void)hipFree(c->buf[b]);
+    if (c->d_inv4) (void)hipFree(c->d_inv4);
+    if (c->d_inv5) (void)hipFree(c->d_inv5);
     for (int i = 0; i <= NSTAGES; i++)
-        if (c->ev[i]) hipEventDestroy(c->ev[i]);
-    if (c->own_stream) hipStreamDestroy(c->own_stream);
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     free(c);
 }
 
@@ -228,7 +228,7 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
     c->work[7] = (uint64_t)c->m;
     for (int i = 0; i < NSTAGES; i++) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+        (void)hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
         c->stage_ms[i] = ms;
         c->visits[i] = hw[WORK_VISITS + i];
     }

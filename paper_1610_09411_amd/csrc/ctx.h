@@ -66,6 +66,9 @@ enum Buf {
 
 #define NSTAGES 10
 
+struct esc_ctx;
+inline int pair_wgs(const esc_ctx *c);
+
 struct esc_ctx {
     int device;
     size_t budget;
@@ -93,6 +96,10 @@ struct esc_ctx {
     bool scratch_clean;        // per-workgroup tables are all zero
     int32_t *d_inv4, *d_inv5;  // signed inverse matrices (Appendix B), device copies
 };
+
+// Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):
+// two per CU; each owns dense n-entry tables in B_WG_SCRATCH.
+inline int pair_wgs(const esc_ctx *c) { return 2 * c->num_cu; }
 
 // Grow-only device buffer; returns nullptr on failure (status set by caller).
 void *ctx_buf(esc_ctx *c, Buf b, size_t bytes);

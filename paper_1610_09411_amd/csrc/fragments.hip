@@ -217,10 +217,10 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
     if (n == 0) return ESC_OK;
-    int nwg = c->num_cu;
+    int nwg = pair_wgs(c);
     size_t per = (size_t)n * sizeof(uint32_t);
     uint32_t *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
-    int32_t *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * nwg);
+    int32_t *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * 2 * nwg);
     int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
     if (!tab || !touch || !task) return ESC_ENOMEM;
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));

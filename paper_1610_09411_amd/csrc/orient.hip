@@ -245,12 +245,27 @@ __global__ void k_edges(int32_t n, const int32_t *off, const int32_t *adj, const
 
 __global__ void k_seg_classify(const int64_t *seg_off, int64_t nseg, int32_t *q, int32_t *counts, int64_t qcap,
                                int64_t lds_keys) {
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * blockDim.x) {
-        int64_t len = seg_off[s + 1] - seg_off[s];
-        if (len <= 1) continue;
-        int cls = len <= SEG_SMALL ? 0 : (len <= lds_keys ? 1 : 2);
-        int32_t pos = atomicAdd(&counts[cls], 1);
-        q[cls * qcap + pos] = (int32_t)s;
+    // one atomic per wave and class: lanes of the same class take
+    // consecutive slots from their leader's reservation
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nseg; base += stride) {
+        const int64_t s = base + threadIdx.x;
+        int cls = -1;
+        if (s < nseg) {
+            int64_t len = seg_off[s + 1] - seg_off[s];
+            if (len > 1) cls = len <= SEG_SMALL ? 0 : (len <= lds_keys ? 1 : 2);
+        }
+        for (int c = 0; c < 3; c++) {
+            const uint64_t m = __ballot(cls == c);
+            if (!m) continue;
+            const int leader = __ffsll((long long)m) - 1;
+            int32_t basepos = 0;
+            if (lane == leader) basepos = atomicAdd(&counts[c], __popcll(m));
+            basepos = __shfl(basepos, leader);
+            if (cls == c) q[c * qcap + basepos + __popcll(m & lt)] = (int32_t)s;
+        }
     }
 }
 

@@ -22,14 +22,22 @@
 #include "ctx.h"
 
 // ------------------------------------------------------- patterns 13 and 17
+//
+// Keys j in the top `slab` ranks [n - slab, n) are counted in an LDS array:
+// the latest sources (hubs) carry almost all diamonds, and the tips of their
+// diamonds are mostly other hubs, so the diamond gathers stay in LDS.  Lower
+// keys use the workgroup's dense global table.
 
 __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off, const int32_t *adj,
                                                   const int32_t *rev, const int64_t *aoff, const uint32_t *aa,
                                                   const int32_t *av, uint32_t *tab_all, int32_t *touch_all,
-                                                  int *task, unsigned long long *acc, unsigned long long *visits) {
+                                                  int *task, int32_t slab, unsigned long long *acc,
+                                                  unsigned long long *visits) {
+    extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
+    const int32_t hi0 = n - slab;   // first key held in LDS
     __shared__ int pref[513], tmp[16];
-    __shared__ int64_t beg[513], opref[513];
+    __shared__ int64_t beg[513];
     __shared__ int s_i, s_nt;
     __shared__ u128 red[2 * 8];
     uint32_t *W = tab_all + (size_t)blockIdx.x * n;
@@ -42,6 +50,9 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         if (t >= n) break;
         const int32_t i = n - 1 - t;
         const int32_t oi = off[i], ei = off[i + 1];
+        const int32_t nsl = i > hi0 ? i - hi0 : 0;   // LDS keys [hi0, i)
+        for (int q = threadIdx.x; q < nsl; q += blockDim.x) sl[q] = 0;
+        __syncthreads();
         // W(i,j) for j before i: k in N(i), j in the prefix of N(k) below i
         for (int32_t base = oi; base < ei; base += blockDim.x) {
             int32_t p = base + threadIdx.x;
@@ -50,45 +61,57 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
                 int32_t j = adj[q];
                 nvis++;
-                if (atomicAdd(&W[j], 1u) == 0) touch[atomicAdd(&s_nt, 1)] = j;
+                if (j >= hi0) atomicAdd(&sl[j - hi0], 1u);
+                else if (atomicAdd(&W[j], 1u) == 0) touch[atomicAdd(&s_nt, 1)] = j;
             });
         }
         __syncthreads();
         // diamonds with tips i and j (j before i): triangles (i,k,l), k<l, then
-        // apexes j of edge (k,l) below i.  Level 1 walks the triangle lists of
-        // the arcs of i; each entry (k,l) yields one level-2 segment.
-        for (int32_t base = oi; base < ei; base += blockDim.x) {
-            int32_t p = base + threadIdx.x;
-            int len = (p < ei) ? (int)(aoff[p + 1] - aoff[p]) : 0;
-            int total;
-            int ex = block_exclusive_scan(len, tmp, &total);
-            opref[threadIdx.x] = ex;
-            __syncthreads();
-            for (int x0 = 0; x0 < total; x0 += blockDim.x) {
-                int x = x0 + threadIdx.x;
-                int64_t s2 = 0;
-                int l2 = 0;
-                if (x < total) {
-                    int lo = 0, hi = blockDim.x - 1;
-                    while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (opref[mid] <= x) lo = mid; else hi = mid - 1; }
-                    const int32_t pk = base + lo;          // arc (i,k)
-                    const int32_t k = adj[pk];
-                    const int64_t idx = x - opref[lo];
-                    const int32_t l = av[aoff[pk] + idx];
-                    if (k < l) {
-                        const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + idx];   // arc (k,l) in row k
-                        const int64_t a0 = aoff[qkl], a1 = aoff[qkl + 1];
-                        // apexes of (k,l) below i: prefix of the sorted list
-                        int64_t lo2 = a0, hi2 = a1;
-                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
-                        s2 = a0;
-                        l2 = (int)(lo2 - a0);
+        // apexes j of edge (k,l) below i.  Each wave takes arcs (i,k); for
+        // every entry l of the arc's triangle list the lanes stride over the
+        // prefix of the list of (k,l) below i.
+        {
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+            for (int32_t pk = oi + wid; pk < ei; pk += nw) {
+                const int32_t k = adj[pk];
+                const int64_t e0 = aoff[pk], e1 = aoff[pk + 1];
+                const int64_t r0 = aoff[rev[pk]];
+                // 64 entries at a time: each lane finds one segment (the prefix
+                // of the list of (k,l) below i), then the wave walks them
+                for (int64_t xb = e0; xb < e1; xb += 64) {
+                    const int64_t x = xb + lane;
+                    int64_t a0 = 0, a1 = 0;
+                    if (x < e1) {
+                        const int32_t l = av[x];
+                        if (l > k) {
+                            const int32_t qkl = (int32_t)aa[r0 + (x - e0)];   // arc (k,l) in row k
+                            a0 = aoff[qkl];
+                            int64_t lo2 = a0, hi2 = aoff[qkl + 1];
+                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
+                            a1 = lo2;
+                        }
                     }
+                    nvis += (uint64_t)(a1 - a0);
+                    const int cnt = (int)((e1 - xb) < 64 ? (e1 - xb) : 64);
+                    uint64_t acc17 = 0;
+                    for (int y = 0; y < cnt; y++) {
+                        const int64_t b0 = __shfl(a0, y), b1 = __shfl(a1, y);
+                        int64_t q = b0 + lane;
+                        for (; q + 192 < b1; q += 256) {   // four loads in flight per lane
+                            const int32_t j0 = av[q], j1 = av[q + 64], j2 = av[q + 128], j3 = av[q + 192];
+                            const uint32_t w0 = j0 >= hi0 ? sl[j0 - hi0] : W[j0];
+                            const uint32_t w1 = j1 >= hi0 ? sl[j1 - hi0] : W[j1];
+                            const uint32_t w2 = j2 >= hi0 ? sl[j2 - hi0] : W[j2];
+                            const uint32_t w3 = j3 >= hi0 ? sl[j3 - hi0] : W[j3];
+                            acc17 += (uint64_t)w0 + w1 + w2 + w3 - 8;
+                        }
+                        for (; q < b1; q += 64) {
+                            const int32_t j = av[q];
+                            acc17 += (uint64_t)(j >= hi0 ? sl[j - hi0] : W[j]) - 2;
+                        }
+                    }
+                    s17 += acc17;
                 }
-                lbs_batch(s2, l2, pref, beg, tmp, [&](int, int64_t q) {
-                    s17 += (uint64_t)W[av[q]] - 2;
-                    nvis++;
-                });
             }
             __syncthreads();
         }
@@ -98,6 +121,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             s13 += c3(W[j]);
             W[j] = 0;
         }
+        for (int q = threadIdx.x; q < nsl; q += blockDim.x) s13 += c3(sl[q]);
         __syncthreads();
     }
     const int ids[2] = {AC_N13, AC_N17};
@@ -131,10 +155,10 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
         const int32_t h = n - 1 - t;
         const int32_t oh = off[h], dh = off[h + 1] - oh;
         const bool in_lds = dh <= lds_cap;
-        uint32_t *cnt = in_lds ? dyn : gtab_all + (size_t)blockIdx.x * n;
+        uint32_t *cnt_ = in_lds ? dyn : gtab_all + (size_t)blockIdx.x * n;
         int32_t *tch = in_lds ? (int32_t *)(dyn + lds_cap) : gtouch_all + (size_t)blockIdx.x * n;
         if (in_lds)
-            for (int q = threadIdx.x; q < dh; q += blockDim.x) cnt[q] = 0;
+            for (int q = threadIdx.x; q < dh; q += blockDim.x) cnt_[q] = 0;
         __syncthreads();
         for (int32_t pi = oh; pi < oh + dh; pi++) {
             const int32_t i = adj[pi];
@@ -147,30 +171,46 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
             if (nl == 0) continue;
             if (threadIdx.x == 0) s_nt = 0;
             __syncthreads();
-            for (int x0 = 0; x0 < nl; x0 += blockDim.x) {
-                int x = x0 + threadIdx.x;
-                int64_t s2 = 0;
-                int len2 = 0;
-                if (x < nl) {
-                    const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
-                    const int64_t b0 = aoff[qhl], b1 = aoff[qhl + 1];
-                    int64_t lo2 = b0, hi2 = b1;
-                    while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
-                    s2 = b0;
-                    len2 = (int)(lo2 - b0);
+            {
+                // each wave takes entries l; its lanes stride over the list of (h,l) below i
+                const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+                for (int xb = wid * 64; xb < nl; xb += nw * 64) {
+                    // each lane finds one segment: the list of (h,l) below i
+                    const int x = xb + lane;
+                    int64_t b0 = 0, b1 = 0;
+                    if (x < nl) {
+                        const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
+                        b0 = aoff[qhl];
+                        int64_t lo2 = b0, hi2 = aoff[qhl + 1];
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
+                        b1 = lo2;
+                    }
+                    nvis += (uint64_t)(b1 - b0);
+                    const int cnt = (nl - xb) < 64 ? (nl - xb) : 64;
+                    for (int y = 0; y < cnt; y++) {
+                        const int64_t c0 = __shfl(b0, y), c1 = __shfl(b1, y);
+                        int64_t q = c0 + lane;
+                        for (; q + 192 < c1; q += 256) {   // four loads in flight per lane
+                            const int32_t k0 = (int32_t)aa[q] - oh, k1 = (int32_t)aa[q + 64] - oh;
+                            const int32_t k2 = (int32_t)aa[q + 128] - oh, k3 = (int32_t)aa[q + 192] - oh;
+                            if (atomicAdd(&cnt_[k0], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k0;
+                            if (atomicAdd(&cnt_[k1], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k1;
+                            if (atomicAdd(&cnt_[k2], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k2;
+                            if (atomicAdd(&cnt_[k3], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k3;
+                        }
+                        for (; q < c1; q += 64) {
+                            const int32_t key = (int32_t)aa[q] - oh;
+                            if (atomicAdd(&cnt_[key], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = key;
+                        }
+                    }
                 }
-                lbs_batch(s2, len2, pref, beg, tmp, [&](int, int64_t q) {
-                    int32_t key = (int32_t)aa[q] - oh;
-                    nvis++;
-                    if (atomicAdd(&cnt[key], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = key;
-                });
             }
             __syncthreads();
             const int nt = s_nt;
             for (int q = threadIdx.x; q < nt; q += blockDim.x) {
                 int32_t key = tch[q];
-                s18 += c2(cnt[key]);
-                cnt[key] = 0;
+                s18 += c2(cnt_[key]);
+                cnt_[key] = 0;
             }
             __syncthreads();
         }
@@ -261,7 +301,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
 
 static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int **task) {
     size_t per = (size_t)c->n * sizeof(uint32_t);
-    int nwg = c->num_cu;
+    int nwg = pair_wgs(c);
     *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
     *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * 2 * nwg);
     *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
@@ -278,10 +318,16 @@ esc_status stage_pairs(esc_ctx *c) {
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
-    k_pairs_wd<<<c->num_cu, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    // LDS slab for the latest keys, leaving room for the static arrays
+    int32_t slab = (c->max_lds - 16384) / 4;
+    if (slab > 16384) slab = 16384;
+    if (slab > n) slab = n;
+    if (slab < 0) slab = 0;
+    k_pairs_wd<<<pair_wgs(c), 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
+                                          n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
                                           (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], tab, touch,
-                                          task, (unsigned long long *)c->buf[B_ACC],
+                                          task, slab, (unsigned long long *)c->buf[B_ACC],
                                           (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
@@ -300,7 +346,7 @@ esc_status stage_wheels(esc_ctx *c) {
     if (lds_cap > 16384) lds_cap = 16384;
     if (c->maxdeg + 1 < lds_cap) lds_cap = c->maxdeg + 1;
     size_t lds = sizeof(uint32_t) * 2 * (size_t)lds_cap;
-    k_wheels<<<c->num_cu * 2, 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    k_wheels<<<pair_wgs(c), 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               (const int32_t *)c->buf[B_AV], tab, touch, lds_cap, task + 1,
                                               (unsigned long long *)c->buf[B_ACC],
@@ -317,7 +363,7 @@ esc_status stage_cycles(esc_ctx *c) {
     int32_t *touch;
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
-    int nwg = c->num_cu;
+    int nwg = pair_wgs(c);
     k_five_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)n * nwg, touch,
                                        touch + (size_t)n * nwg, task + 2, (unsigned long long *)c->buf[B_ACC],

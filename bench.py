@@ -37,6 +37,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="oracle timing sample: 1/N of sources and edges (0 = skip the CPU leg)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -45,6 +47,15 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
 
     import torch
+    if args.copy_probe > 0:
+        # a copy kernel of known size: rocprofv3 FETCH_SIZE / WRITE_SIZE on it
+        # give the factor between counter units and bytes moved
+        src = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     import synth
     import paper_1610_09411_amd as esc
 

@@ -144,6 +144,7 @@ static int triangles(graph *g) {
     g->te = (u64 *)calloc((size_t)m + 1, sizeof(u64));
     if (!g->tv || !g->te) return -1;
     u128 T = 0;
+    #pragma omp parallel for schedule(dynamic, 256) reduction(+:T)
     for (int32_t a = 0; a < n; a++)
         for (int64_t p = g->rp[a]; p < g->rp[a + 1]; p++) {
             int32_t b = g->ci[p];
@@ -157,8 +158,12 @@ static int triangles(graph *g) {
                 else {
                     if (prec(g, b, ca)) {
                         T++;
-                        g->tv[a]++; g->tv[b]++; g->tv[ca]++;
-                        g->te[g->eid[p]]++; g->te[g->eid[x]]++; g->te[g->eid[y]]++;
+                        __atomic_fetch_add(&g->tv[a], 1, __ATOMIC_RELAXED);
+                        __atomic_fetch_add(&g->tv[b], 1, __ATOMIC_RELAXED);
+                        __atomic_fetch_add(&g->tv[ca], 1, __ATOMIC_RELAXED);
+                        __atomic_fetch_add(&g->te[g->eid[p]], 1, __ATOMIC_RELAXED);
+                        __atomic_fetch_add(&g->te[g->eid[x]], 1, __ATOMIC_RELAXED);
+                        __atomic_fetch_add(&g->te[g->eid[y]], 1, __ATOMIC_RELAXED);
                     }
                     x++; y++;
                 }

@@ -52,6 +52,7 @@ enum Buf {
     B_EOFF, B_ARC_EID, B_REV,   // out-arc prefix, edge id of each arc, reverse arc
     B_EARC, B_ELO,              // out-arc position and lower endpoint of each edge
     B_TE, B_TV, B_K4E, B_C4E,   // per-edge / per-vertex fragment counts
+    B_TARC,                     // t(e) of each arc's edge, indexed like adj
     B_AOFF, B_ACUR, B_AA, B_AV, // per-arc triangle lists: offsets, cursors, arc index of apex, apex id
     B_SEGCLS, B_SEGQ,           // segmented-sort work lists
     B_SCAN_TMP,

@@ -72,9 +72,14 @@ __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off
     if (visits) flush_count(nvis, visits);
 }
 
-__global__ void k_arc_len(int64_t m2, const int32_t *arc_eid, const uint32_t *te, int64_t *len) {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m2; p += (int64_t)gridDim.x * blockDim.x)
-        len[p] = te[arc_eid[p]];
+// per arc: list length (= t of its edge) for the offsets, and t itself as a
+// u32 array indexed like adj, so later passes read it sequentially
+__global__ void k_arc_len(int64_t m2, const int32_t *arc_eid, const uint32_t *te, int64_t *len, uint32_t *tarc) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m2; p += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t t = te[arc_eid[p]];
+        len[p] = t;
+        tarc[p] = t;
+    }
 }
 
 __global__ void k_copy_cursor(int64_t m2, const int64_t *aoff, unsigned long long *cur) {
@@ -98,7 +103,8 @@ esc_status stage_triangles(esc_ctx *c) {
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(m2 + 2));
     int64_t *aoff = (int64_t *)ctx_buf(c, B_AOFF, sizeof(int64_t) * (size_t)(m2 + 2));
     unsigned long long *cur = (unsigned long long *)ctx_buf(c, B_ACUR, sizeof(uint64_t) * (size_t)(m2 + 1));
-    if (!te || !len || !aoff || !cur) return ESC_ENOMEM;
+    uint32_t *tarc = (uint32_t *)ctx_buf(c, B_TARC, sizeof(uint32_t) * (size_t)(m2 + 1));
+    if (!te || !len || !aoff || !cur || !tarc) return ESC_ENOMEM;
     HIP_TRY(hipMemsetAsync(te, 0, sizeof(uint32_t) * (size_t)(m + 1), st));
     if (n == 0) { c->narcs_apex = 0; return ESC_OK; }
     int g = grid_cap(c, (int64_t)n * 64, 256);
@@ -106,7 +112,7 @@ esc_status stage_triangles(esc_ctx *c) {
     k_triangles<<<g, 256, 0, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr,
                                    work + WORK_VISITS + 1);
     HIP_TRY(hipGetLastError());
-    k_arc_len<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, arc_eid, te, len);
+    k_arc_len<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, arc_eid, te, len, tarc);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, aoff, m2));
     int64_t total = 0;
@@ -140,7 +146,7 @@ esc_status stage_triangles(esc_ctx *c) {
 // With per_edge set, a second pass also adds c-1 to C4 of edges hk and ko.
 __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, const int32_t *rev,
-                                                     const int32_t *arc_eid, const uint32_t *te,
+                                                     const int32_t *arc_eid, const uint32_t *tarc,
                                                      uint32_t *tab_c, uint32_t *tab_t, uint32_t *tab_k,
                                                      int32_t *touch_all, int *task, unsigned long long *acc,
                                                      unsigned long long *c4e, unsigned long long *visits) {
@@ -149,9 +155,11 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     __shared__ int64_t beg[513];
     __shared__ int s_h, s_nt;
     __shared__ u128 red[3 * 8];
-    uint32_t *cnt = tab_c + (size_t)blockIdx.x * n;
-    uint32_t *ft = tab_t + (size_t)blockIdx.x * n;
-    uint32_t *fk = tab_k + (size_t)blockIdx.x * n;
+    // the three counters of a key sit side by side (one cache line per key)
+    uint32_t *tab3 = tab_c + (size_t)blockIdx.x * 3 * n;
+#define CNT(o) tab3[3 * (size_t)(o)]
+#define FT(o) tab3[3 * (size_t)(o) + 1]
+#define FK(o) tab3[3 * (size_t)(o) + 2]
     int32_t *touch = touch_all + (size_t)blockIdx.x * n;
     u128 sums[3] = {0, 0, 0};
     for (;;) {
@@ -170,11 +178,11 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 int32_t pk = base + s;
                 int32_t k = adj[pk];
                 int32_t o = adj[q];
-                uint32_t old = atomicAdd(&cnt[o], 1u);
+                uint32_t old = atomicAdd(&CNT(o), 1u);
                 nvis++;
                 if (old == 0) touch[atomicAdd(&s_nt, 1)] = o;
-                atomicAdd(&ft[o], te[arc_eid[pk]] + te[arc_eid[q]]);
-                atomicAdd(&fk[o], (uint32_t)(off[k + 1] - off[k]));
+                atomicAdd(&FT(o), tarc[pk] + tarc[q]);
+                atomicAdd(&FK(o), (uint32_t)(off[k + 1] - off[k]));
             });
         }
         __syncthreads();
@@ -187,7 +195,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 if (p < sh) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
                 lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
                     int32_t pk = base + s;
-                    uint32_t cc = cnt[adj[q]];
+                    uint32_t cc = CNT(adj[q]);
                     if (cc >= 2) {
                         atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
                         atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
@@ -197,17 +205,20 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
         }
         for (int i = threadIdx.x; i < nt; i += blockDim.x) {
             int32_t o = touch[i];
-            uint64_t cc = cnt[o];
+            uint64_t cc = CNT(o);
             if (cc >= 2) {
-                int64_t dsum = (int64_t)cc * (dh + (off[o + 1] - off[o]) - 8) + 2 * (int64_t)fk[o];
+                int64_t dsum = (int64_t)cc * (dh + (off[o + 1] - off[o]) - 8) + 2 * (int64_t)FK(o);
                 sums[0] += c2(cc);
-                sums[1] += (u128)(cc - 1) * ft[o];
+                sums[1] += (u128)(cc - 1) * FT(o);
                 sums[2] += (u128)(cc - 1) * (uint64_t)dsum;
             }
-            cnt[o] = 0; ft[o] = 0; fk[o] = 0;
+            CNT(o) = 0; FT(o) = 0; FK(o) = 0;
         }
         __syncthreads();
     }
+#undef CNT
+#undef FT
+#undef FK
     const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
     block_flush_u128<3>(sums, red, acc, ids);
     flush_count(nvis, visits);
@@ -232,8 +243,8 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     }
     k_four_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
-                                       (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TE],
-                                       tab, tab + (size_t)n * nwg, tab + 2 * (size_t)n * nwg, touch, task,
+                                       (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
+                                       tab, nullptr, nullptr, touch, task,
                                        (unsigned long long *)c->buf[B_ACC], c4e,
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
     HIP_TRY(hipGetLastError());

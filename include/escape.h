@@ -109,6 +109,83 @@ esc_status esc_count_fragments(esc_ctx *ctx, int32_t n, const int32_t *row_ptr,
                                uint64_t *tri_e, uint64_t *c4_e, uint64_t *k4_e,
                                void *stream);
 
+/* Count all induced k-vertex patterns of each of G independent graphs in one
+ * call (the method applied to every graph; Sec. 2.1 defines the counts).
+ *   G        number of graphs, G >= 0 (G = 0 returns ESC_OK and does nothing)
+ *   vtx_off  host, G+1 int64: graph g has vtx_off[g+1] - vtx_off[g] vertices;
+ *            vtx_off[0] = 0, non-decreasing
+ *   arc_off  host, G+1 int64: graph g owns col[arc_off[g] .. arc_off[g+1]),
+ *            an even count (both arcs of every edge); arc_off[0] = 0
+ *   row_ptr  vtx_off[G] + G int32: graph g's n_g + 1 local offsets start at
+ *            row_ptr[vtx_off[g] + g], run from 0 to arc_off[g+1] - arc_off[g]
+ *   col      arc_off[G] int32 local neighbour ids in [0, n_g), each graph's
+ *            CSR as in esc_count_subgraphs
+ *   k, flags as in esc_count_subgraphs (ESC_F_INPUT_ON_DEVICE: row_ptr and
+ *            col are device pointers; vtx_off / arc_off are always host)
+ *   out      host, G x (11 | 45) uint64, row g = the counts of graph g in the
+ *            documented order
+ *   overflow host, G bytes or NULL: overflow[g] = 1 when a count of graph g
+ *            exceeds 2^64 - 1 (row g then holds the low 64 bits); with NULL,
+ *            such a graph makes the call return ESC_EOVERFLOW after every row
+ *            has been written
+ * The sums vtx_off[G] + G and arc_off[G] must stay below 2^31.  Row offsets and
+ * ids are always checked against each graph's own sizes (ESC_ERANGE); the
+ * other checks follow ESC_F_VALIDATE.  Inputs are read-only and not retained;
+ * the call returns after the counts are on the host.  esc_last_work then
+ * reports totals over the graphs; esc_last_noninduced is not set. */
+esc_status esc_count_batched(esc_ctx *ctx, int32_t G, const int64_t *vtx_off,
+                             const int64_t *arc_off, const int32_t *row_ptr,
+                             const int32_t *col, int k, uint32_t flags,
+                             uint64_t *out, uint8_t *overflow, void *stream);
+
+/* ------------------------------------------------------------- serving
+ *
+ * A request loop over the same method: jobs of any size arrive while others
+ * run.  The server owns max_inflight contexts (one stream and one set of
+ * device buffers each) and a worker thread per context.  A free worker takes
+ * the oldest queued request and, if it has at most 20000 vertices, the
+ * following queued requests of the same k up to 256 in all, and runs them as
+ * one batched launch (esc_count_batched's pipeline); larger requests run
+ * alone.  A launch starts only when its estimated device footprint (CSR and
+ * arc arrays, triangle lists bounded by the wedge count, per-workgroup tables)
+ * fits in the admission budget beside the launches in flight, so launches
+ * overlap on the device as workers and memory free up.  Results are exact and
+ * do not depend on which other requests shared a launch. */
+typedef struct esc_server esc_server;
+
+/* Start a server on ctx's device.  The admission budget is ctx's
+ * hbm_budget_bytes, or half the device's free memory when that is 0.  ctx is
+ * only read here; the server creates its own contexts.  max_inflight in
+ * [1, 64]. */
+esc_status esc_server_start(esc_ctx *ctx, int max_inflight, esc_server **out);
+
+/* Queue a count request.  The CSR (host memory, layout as in
+ * esc_count_subgraphs) is copied before return; offsets are checked here
+ * (ESC_ERANGE / ESC_ENOTSIMPLE / ESC_EINVAL), the rest on the device when the
+ * request runs.  *ticket identifies the request in esc_poll / esc_wait. */
+esc_status esc_submit(esc_server *srv, int32_t n, const int32_t *row_ptr,
+                      const int32_t *col, int k, uint64_t *ticket);
+
+/* Non-blocking: *done = 0 while the request is queued or running.  Once
+ * *done = 1 the request's counts (11 or 45 esc_u128, as esc_count_subgraphs)
+ * are in `out`, `seconds` (nullable) holds submit-to-completion time, the
+ * return value is the request's own status, and the ticket is released. */
+esc_status esc_poll(esc_server *srv, uint64_t ticket, esc_u128 *out, int *done,
+                    double *seconds);
+
+/* Blocking form of esc_poll: returns when the request has completed. */
+esc_status esc_wait(esc_server *srv, uint64_t ticket, esc_u128 *out, double *seconds);
+
+/* Server counters, 8 uint64: [0] completed requests, [1] launches,
+ * [2] requests that ran in batched launches, [3] peak launches in flight,
+ * [4] peak estimated footprint in flight (bytes), [5] admission budget
+ * (bytes), [6] requests queued now, [7] worker contexts. */
+esc_status esc_server_stats(esc_server *srv, uint64_t *out);
+
+/* Finish every queued request, stop the workers and release the server and
+ * its contexts.  Tickets not yet collected are dropped. */
+esc_status esc_server_stop(esc_server *srv);
+
 /* Work counters of the last successful call on this context (Thm fourvertex
  * and Thm fivevertex state the running time in these terms):
  *   [0] W++  out-wedges of the DAG      [1] W+-  in-out wedges

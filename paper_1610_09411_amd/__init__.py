@@ -29,7 +29,8 @@ ESC_F_INPUT_ON_DEVICE = 4
 ESC_F_RANDOM_ORDER = 8
 
 ABI_FUNCTIONS = [
-    "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments",
+    "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments", "esc_count_batched",
+    "esc_server_start", "esc_submit", "esc_poll", "esc_wait", "esc_server_stats", "esc_server_stop",
     "esc_last_work", "esc_last_profile", "esc_last_noninduced", "esc_inverse_matrix", "esc_strerror",
 ]
 
@@ -77,6 +78,20 @@ def _load():
         lib.esc_count_subgraphs.restype = ctypes.c_int
         lib.esc_count_fragments.argtypes = [vp, i32, vp, vp, ctypes.c_int, u32, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.esc_count_fragments.restype = ctypes.c_int
+        lib.esc_count_batched.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.c_int, u32, vp, vp, vp]
+        lib.esc_count_batched.restype = ctypes.c_int
+        lib.esc_server_start.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
+        lib.esc_server_start.restype = ctypes.c_int
+        lib.esc_submit.argtypes = [vp, i32, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+        lib.esc_submit.restype = ctypes.c_int
+        lib.esc_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        lib.esc_poll.restype = ctypes.c_int
+        lib.esc_wait.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_double)]
+        lib.esc_wait.restype = ctypes.c_int
+        lib.esc_server_stats.argtypes = [vp, vp]
+        lib.esc_server_stats.restype = ctypes.c_int
+        lib.esc_server_stop.argtypes = [vp]
+        lib.esc_server_stop.restype = ctypes.c_int
         lib.esc_last_work.argtypes = [vp, vp]
         lib.esc_last_work.restype = ctypes.c_int
         lib.esc_last_profile.argtypes = [vp, vp, vp]
@@ -128,6 +143,11 @@ class Context:
 
     def fragments(self, graph, k=5, flags=0, stream=None):
         return esc_count_fragments(self.ptr, graph.n, graph.row_ptr, graph.col, k, flags, stream)
+
+    def count_batched(self, graphs, k=5, flags=0, stream=None):
+        """Counts of every graph in `graphs` (objects with n, row_ptr, col) in
+        one call: a G x (11|45) uint64 array and the per-graph overflow flags."""
+        return esc_count_batched(self.ptr, *pack_batch(graphs), k=k, flags=flags, stream=stream)
 
     def last_work(self):
         return esc_last_work(self.ptr)
@@ -201,6 +221,102 @@ def esc_count_fragments(ctx, n, row_ptr, col, k=5, flags=0, stream=None):
     _check(st, "esc_count_fragments")
     del keep
     return _ints(out, 11 if k == 4 else 45), arrs
+
+
+def pack_batch(graphs):
+    """Concatenate graphs into the batched layout: (vtx_off, arc_off, row_ptr,
+    col) with vtx_off/arc_off int64 of G+1 entries, every graph's n+1 local row
+    offsets back to back and its local column ids back to back."""
+    G = len(graphs)
+    vtx_off = np.zeros(G + 1, dtype=np.int64)
+    arc_off = np.zeros(G + 1, dtype=np.int64)
+    for g, x in enumerate(graphs):
+        vtx_off[g + 1] = vtx_off[g] + int(x.n)
+        arc_off[g + 1] = arc_off[g] + int(len(x.col))
+    rps = [np.asarray(x.row_ptr, dtype=np.int32) for x in graphs]
+    cols = [np.asarray(x.col, dtype=np.int32) for x in graphs]
+    row_ptr = np.concatenate(rps) if G else np.zeros(0, np.int32)
+    col = np.concatenate(cols) if G else np.zeros(0, np.int32)
+    return vtx_off, arc_off, row_ptr, col
+
+
+def esc_count_batched(ctx, vtx_off, arc_off, row_ptr, col, k=5, flags=0, stream=None):
+    """Per-graph induced counts of a batch (layout of pack_batch): returns a
+    (G, 11|45) uint64 array and a (G,) uint8 array of overflow flags."""
+    vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    ao = np.ascontiguousarray(arc_off, dtype=np.int64)
+    G = len(vo) - 1
+    if G < 0 or len(ao) != len(vo):
+        raise ValueError("vtx_off and arc_off need G+1 entries each")
+    rp, ci, flags, keep = _csr_args(row_ptr, col, flags)
+    cnt = 11 if k == 4 else 45
+    out = np.zeros((max(G, 0), cnt), dtype=np.uint64)
+    ovf = np.zeros(max(G, 0), dtype=np.uint8)
+    st = _load().esc_count_batched(ctx, int(G), vo.ctypes.data_as(ctypes.c_void_p),
+                                   ao.ctypes.data_as(ctypes.c_void_p), rp, ci, int(k), flags,
+                                   out.ctypes.data_as(ctypes.c_void_p), ovf.ctypes.data_as(ctypes.c_void_p),
+                                   _stream_ptr(stream))
+    _check(st, "esc_count_batched")
+    del keep
+    return out, ovf
+
+
+class Server:
+    """Request loop (esc_server_*): submit graphs, collect exact counts.
+
+    ``submit`` copies the CSR and returns a ticket at once; ``poll`` returns
+    None while the request is pending, else ``(counts, seconds)``; ``wait``
+    blocks.  A failed request raises EscapeError from poll / wait."""
+
+    def __init__(self, ctx, max_inflight=4):
+        self._keep_ctx = ctx
+        ptr = ctypes.c_void_p()
+        _check(_load().esc_server_start(ctx.ptr if isinstance(ctx, Context) else ctx, int(max_inflight),
+                                        ctypes.byref(ptr)), "esc_server_start")
+        self.ptr = ptr
+
+    def submit(self, graph, k=5):
+        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(graph.col, dtype=np.int32)
+        t = ctypes.c_uint64()
+        _check(_load().esc_submit(self.ptr, int(graph.n), rp.ctypes.data_as(ctypes.c_void_p),
+                                  ci.ctypes.data_as(ctypes.c_void_p), int(k), ctypes.byref(t)), "esc_submit")
+        return (int(t.value), int(k))
+
+    def poll(self, ticket):
+        t, k = ticket
+        out = (_U128 * 45)()
+        done = ctypes.c_int()
+        sec = ctypes.c_double()
+        _check(_load().esc_poll(self.ptr, t, out, ctypes.byref(done), ctypes.byref(sec)), "esc_poll")
+        if not done.value:
+            return None
+        return _ints(out, 11 if k == 4 else 45), float(sec.value)
+
+    def wait(self, ticket):
+        t, k = ticket
+        out = (_U128 * 45)()
+        sec = ctypes.c_double()
+        _check(_load().esc_wait(self.ptr, t, out, ctypes.byref(sec)), "esc_wait")
+        return _ints(out, 11 if k == 4 else 45), float(sec.value)
+
+    def stats(self):
+        out = (ctypes.c_uint64 * 8)()
+        _check(_load().esc_server_stats(self.ptr, out), "esc_server_stats")
+        keys = ["completed", "launches", "batched_requests", "peak_inflight", "peak_reserved_bytes",
+                "budget_bytes", "queued", "workers"]
+        return dict(zip(keys, [int(x) for x in out]))
+
+    def stop(self):
+        if self.ptr:
+            _check(_load().esc_server_stop(self.ptr), "esc_server_stop")
+            self.ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
 
 
 def esc_last_work(ctx):

@@ -24,7 +24,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 into one shared library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
            # packed FP32 instructions stay off (no float math here, but keep the
            # code generator from ever emitting them)
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,5 +1,6 @@
 // C ABI entry points (include/escape.h): context, memory, pipeline order.
 #include <stdlib.h>
+#include <limits.h>
 #include <string.h>
 #include "device.h"
 #include "ctx.h"
@@ -120,6 +121,67 @@ __global__ void k_fragments_out(int32_t n, const int32_t *rp, const int32_t *col
     }
 }
 
+// The stages of one call on the graph (or disjoint union) held in c, each
+// bracketed by events on the call's stream (see esc_last_profile).
+static esc_status pipeline(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col, bool per_edge_c4) {
+    hipStream_t st = c->stream;
+    const int k = c->k;
+    uint64_t *work = (uint64_t *)ctx_buf(c, B_WORK, sizeof(uint64_t) * WORK_WORDS);
+    if (!work) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(work, 0, sizeof(uint64_t) * WORK_WORDS, st));
+    if (!c->scratch_clean && c->buf[B_WG_SCRATCH]) {
+        HIP_TRY(hipMemsetAsync(c->buf[B_WG_SCRATCH], 0, c->cap[B_WG_SCRATCH], st));
+    }
+    c->scratch_clean = false;   // until the pipeline completes
+    int ev = 0;
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_orient(c, d_rp, d_col));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_triangles(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_four(c, per_edge_c4));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_k4_triangles(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_k5(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    ESC_TRY(stage_reduce(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_pairs(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_wheels(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    if (k == 5) ESC_TRY(stage_cycles(c));
+    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    return ESC_OK;
+}
+
+// after the combine stage: per-stage times and visit counts, work counters
+esc_status call_finish(esc_ctx *c, uint64_t w, uint64_t t3, uint64_t d) {
+    hipStream_t st = c->stream;
+    HIP_TRY(hipEventRecord(c->ev[NSTAGES], st));
+    uint64_t hw[WORK_WORDS];
+    HIP_TRY(hipMemcpyAsync(hw, c->buf[B_WORK], sizeof(hw), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (c->G) { w = hw[12]; t3 = hw[13]; d = hw[14]; }
+    c->work[0] = hw[0];
+    c->work[1] = hw[1];
+    c->work[2] = w;
+    c->work[3] = t3 / 3;
+    c->work[4] = d;
+    c->work[5] = (uint64_t)c->maxdplus;
+    c->work[6] = (uint64_t)c->n;
+    c->work[7] = (uint64_t)c->m;
+    for (int i = 0; i < NSTAGES; i++) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+        c->stage_ms[i] = ms;
+        c->visits[i] = hw[WORK_VISITS + i];
+    }
+    c->scratch_clean = true;
+    return ESC_OK;
+}
+
 static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags,
                       esc_u128 *out, uint64_t **frag, void *stream) {
     if (!c || !out || (k != 4 && k != 5) || n < 0) return ESC_EINVAL;
@@ -147,6 +209,9 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
     c->m = m2 / 2;
     c->k = k;
     c->flags = flags;
+    c->G = 0;
+    c->tab_n = n > 0 ? n : 1;
+    c->task_chunk = 1;
     const int32_t *d_rp = row_ptr, *d_col = col;
     if (!on_dev) {
         int32_t *brp = (int32_t *)ctx_buf(c, B_RP_IN, sizeof(int32_t) * ((size_t)n + 1));
@@ -157,38 +222,14 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
         d_rp = brp;
         d_col = bcol;
     }
-    unsigned long long *acc = (unsigned long long *)ctx_buf(c, B_ACC, sizeof(uint64_t) * 2 * AC_COUNT);
-    uint64_t *work = (uint64_t *)ctx_buf(c, B_WORK, sizeof(uint64_t) * WORK_WORDS);
-    if (!acc || !work) return ESC_ENOMEM;
-    HIP_TRY(hipMemsetAsync(acc, 0, sizeof(uint64_t) * 2 * AC_COUNT, st));
-    HIP_TRY(hipMemsetAsync(work, 0, sizeof(uint64_t) * WORK_WORDS, st));
-    if (!c->scratch_clean && c->buf[B_WG_SCRATCH]) {
-        HIP_TRY(hipMemsetAsync(c->buf[B_WG_SCRATCH], 0, c->cap[B_WG_SCRATCH], st));
-    }
-    c->scratch_clean = false;   // until the pipeline completes
-    // stages, each bracketed by events on the call's stream (see esc_last_profile)
-    int ev = 0;
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_orient(c, d_rp, d_col));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_triangles(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_four(c, frag != nullptr));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_k4_triangles(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_k5(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_reduce(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_pairs(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_wheels(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_cycles(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    unsigned long long *acc = (unsigned long long *)ctx_buf(c, B_ACC, sizeof(uint64_t) * ACC_STRIDE);
+    if (!acc) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(acc, 0, sizeof(uint64_t) * ACC_STRIDE, st));
+    ESC_TRY(pipeline(c, d_rp, d_col, frag != nullptr));
     ESC_TRY(stage_combine(c, out, c->d_inv4, c->d_inv5));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    unsigned long long hacc[ACC_STRIDE];
+    HIP_TRY(hipMemcpyAsync(hacc, acc, sizeof(hacc), hipMemcpyDeviceToHost, st));
+    ESC_TRY(call_finish(c, hacc[2 * AC_W], hacc[2 * AC_T3], hacc[2 * AC_D]));
     if (frag) {
         size_t nn = (size_t)n, aa = (size_t)m2;
         uint64_t *fb = (uint64_t *)ctx_buf(c, B_FRAG, sizeof(uint64_t) * (3 * nn + 3 * aa + 8));
@@ -212,27 +253,107 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
             if (frag[i] && cnt[i]) HIP_TRY(hipMemcpyAsync(frag[i], src[i], sizeof(uint64_t) * cnt[i], hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
-    // work counters
-    uint64_t hw[WORK_WORDS];
-    unsigned long long hacc[2 * AC_COUNT];
-    HIP_TRY(hipMemcpyAsync(hw, work, sizeof(hw), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hacc, acc, sizeof(hacc), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    c->work[0] = hw[0];
-    c->work[1] = hw[1];
-    c->work[2] = hacc[2 * AC_W];
-    c->work[3] = hacc[2 * AC_T3] / 3;
-    c->work[4] = hacc[2 * AC_D];
-    c->work[5] = (uint64_t)c->maxdplus;
-    c->work[6] = (uint64_t)n;
-    c->work[7] = (uint64_t)c->m;
-    for (int i = 0; i < NSTAGES; i++) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
-        c->stage_ms[i] = ms;
-        c->visits[i] = hw[WORK_VISITS + i];
+    return ESC_OK;
+}
+
+// One workgroup per graph of a batch: union vertex id = first id of the
+// graph + local id, arcs keep their positions.  Rows and ids are checked
+// against the graph's own sizes, so no edge can leave its graph.
+__global__ void k_union(int32_t G, int32_t N, int32_t A, const int64_t *voff, const int64_t *aoff,
+                        const int32_t *rp, const int32_t *col, int32_t *urp, int32_t *ucol, int32_t *vgraph,
+                        int *err) {
+    for (int32_t g = blockIdx.x; g < G; g += gridDim.x) {
+        const int64_t v0 = voff[g], ng = voff[g + 1] - v0, a0 = aoff[g], na = aoff[g + 1] - a0;
+        const int32_t *r = rp + v0 + g;   // the graph's ng + 1 local offsets
+        for (int64_t v = threadIdx.x; v < ng; v += blockDim.x) {
+            const int32_t a = r[v], b = r[v + 1];
+            if (a < 0 || b < a || b > na || (v == 0 && a != 0) || (v == ng - 1 && b != na))
+                atomicCAS(err, 0, (int)ESC_ERANGE);
+            urp[v0 + v] = (int32_t)(a0 + a);
+            vgraph[v0 + v] = g;
+        }
+        for (int64_t p = threadIdx.x; p < na; p += blockDim.x) {
+            const int32_t x = col[a0 + p];
+            if (x < 0 || x >= ng) atomicCAS(err, 0, (int)ESC_ERANGE);
+            ucol[a0 + p] = (int32_t)(v0 + x);
+        }
     }
-    c->scratch_clean = true;
+    if (blockIdx.x == 0 && threadIdx.x == 0) urp[N] = A;
+}
+
+esc_status run_batched_device(esc_ctx *c, int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                              const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags, void *stream) {
+    if (!c || (k != 4 && k != 5) || G <= 0 || !vtx_off || !arc_off) return ESC_EINVAL;
+    if (vtx_off[0] != 0 || arc_off[0] != 0) return ESC_ERANGE;
+    int64_t max_n = 0;
+    for (int32_t g = 0; g < G; g++) {
+        const int64_t ng = vtx_off[g + 1] - vtx_off[g], na = arc_off[g + 1] - arc_off[g];
+        if (ng < 0 || na < 0) return ESC_ERANGE;
+        if (na & 1) return ESC_ENOTSIMPLE;
+        if (ng == 0 && na != 0) return ESC_ERANGE;
+        if (ng > max_n) max_n = ng;
+    }
+    const int64_t N = vtx_off[G], A = arc_off[G];
+    if (N + G >= INT32_MAX || A >= INT32_MAX) return ESC_ERANGE;   // int32 union CSR
+    if (k == 5 && max_n > 100000000) return ESC_EOVERFLOW;         // C(n,5) must fit 128 bits
+    if (N > 0 && !row_ptr) return ESC_EINVAL;
+    if (A > 0 && !col) return ESC_EINVAL;
+    HIP_TRY(hipSetDevice(c->device));
+    c->stream = stream ? (hipStream_t)stream : c->own_stream;
+    hipStream_t st = c->stream;
+    c->n = (int32_t)N;
+    c->m2 = A;
+    c->m = A / 2;
+    c->k = k;
+    c->flags = flags;
+    c->G = G;
+    c->tab_n = max_n > 0 ? (int32_t)max_n : 1;
+    c->task_chunk = 8;
+    int64_t *goff = (int64_t *)ctx_buf(c, B_GOFF, sizeof(int64_t) * 2 * ((size_t)G + 1));
+    int32_t *urp = (int32_t *)ctx_buf(c, B_URP, sizeof(int32_t) * ((size_t)N + 1));
+    int32_t *ucol = (int32_t *)ctx_buf(c, B_UCOL, sizeof(int32_t) * ((size_t)A + 1));
+    int32_t *vg = (int32_t *)ctx_buf(c, B_VGRAPH, sizeof(int32_t) * ((size_t)N + 1));
+    int *err = (int *)ctx_buf(c, B_ERR, sizeof(int) * 4);
+    if (!goff || !urp || !ucol || !vg || !err) return ESC_ENOMEM;
+    HIP_TRY(hipMemcpyAsync(goff, vtx_off, sizeof(int64_t) * ((size_t)G + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(goff + G + 1, arc_off, sizeof(int64_t) * ((size_t)G + 1), hipMemcpyHostToDevice, st));
+    const int32_t *d_rp = row_ptr, *d_col = col;
+    if (!(flags & ESC_F_INPUT_ON_DEVICE)) {
+        int32_t *brp = (int32_t *)ctx_buf(c, B_RP_IN, sizeof(int32_t) * ((size_t)N + G));
+        int32_t *bcol = (int32_t *)ctx_buf(c, B_COL_IN, sizeof(int32_t) * ((size_t)A + 1));
+        if (!brp || !bcol) return ESC_ENOMEM;
+        HIP_TRY(hipMemcpyAsync(brp, row_ptr, sizeof(int32_t) * ((size_t)N + G), hipMemcpyHostToDevice, st));
+        if (A) HIP_TRY(hipMemcpyAsync(bcol, col, sizeof(int32_t) * (size_t)A, hipMemcpyHostToDevice, st));
+        d_rp = brp;
+        d_col = bcol;
+    }
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(int) * 4, st));
+    int blocks = G < c->num_cu * 16 ? G : c->num_cu * 16;
+    k_union<<<blocks, 256, 0, st>>>(G, (int32_t)N, (int32_t)A, goff, goff + G + 1, d_rp, d_col, urp, ucol, vg, err);
+    HIP_TRY(hipGetLastError());
+    int h_err = 0;
+    HIP_TRY(hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h_err) return (esc_status)h_err;
+    unsigned long long *acc = (unsigned long long *)ctx_buf(c, B_ACC, sizeof(uint64_t) * ACC_STRIDE * (size_t)G);
+    if (!acc) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(acc, 0, sizeof(uint64_t) * ACC_STRIDE * (size_t)G, st));
+    c->flags = flags & ~(uint32_t)ESC_F_INPUT_ON_DEVICE;
+    ESC_TRY(pipeline(c, urp, ucol, false));
+    return stage_combine_batched(c);
+}
+
+static esc_status run_batched(esc_ctx *c, int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                              const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags, uint64_t *out,
+                              uint8_t *overflow, void *stream) {
+    if (!c || (k != 4 && k != 5) || G < 0) return ESC_EINVAL;
+    if (G == 0) return ESC_OK;
+    if (!out) return ESC_EINVAL;
+    ESC_TRY(run_batched_device(c, G, vtx_off, arc_off, row_ptr, col, k, flags, stream));
+    int any = 0;
+    ESC_TRY(batched_copy_u64(c, out, overflow, &any));
+    ESC_TRY(call_finish(c, 0, 0, 0));
+    if (any && !overflow) return ESC_EOVERFLOW;
     return ESC_OK;
 }
 
@@ -247,6 +368,12 @@ extern "C" esc_status esc_count_fragments(esc_ctx *ctx, int32_t n, const int32_t
                                           void *stream) {
     uint64_t *frag[6] = {tri_v, c4_v, k4_v, tri_e, c4_e, k4_e};
     return run(ctx, n, row_ptr, col, k, flags, out, frag, stream);
+}
+
+extern "C" esc_status esc_count_batched(esc_ctx *ctx, int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                                        const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags,
+                                        uint64_t *out, uint8_t *overflow, void *stream) {
+    return run_batched(ctx, G, vtx_off, arc_off, row_ptr, col, k, flags, out, overflow, stream);
 }
 
 extern "C" esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out) {

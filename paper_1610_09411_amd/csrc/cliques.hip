@@ -54,19 +54,35 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
                                                       const int32_t *arc_eid, const int32_t *earc,
                                                       const int32_t *elo, const uint32_t *te, const int64_t *aoff,
                                                       const uint32_t *aa, const int32_t *av,
-                                                      unsigned long long *k4e, unsigned long long *acc,
+                                                      unsigned long long *k4e, GMap gm, unsigned long long *acc,
                                                       unsigned long long *visits) {
     __shared__ uint32_t bm_all[4][BM_WORDS];
     __shared__ u128 red[5 * 4];
+    const int ids[5] = {AC_K4X4, AC_N20, AC_N10, AC_N16, AC_Z};
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t *bm = bm_all[wid];
     for (int w = lane; w < BM_WORDS; w += 64) bm[w] = 0;
     wave_sync();
     const int64_t wave = (int64_t)blockIdx.x * 4 + wid;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
+    // one graph: edges strided over the waves; a batch: one contiguous block
+    // of edges per wave, so that its per-graph sums change graph rarely
+    const bool batched = gm.vg != nullptr;
+    const int64_t per = (m + nwaves - 1) / nwaves;
+    const int64_t e_first = batched ? wave * per : wave;
+    const int64_t e_end = batched ? (e_first + per < m ? e_first + per : m) : m;
+    const int64_t e_step = batched ? 1 : nwaves;
     u128 s[5] = {0, 0, 0, 0, 0};
+    int gcur = -1;
     uint64_t nvis = 0;
-    for (int64_t e = wave; e < m; e += nwaves) {
+    for (int64_t e = e_first; e < e_end; e += e_step) {
+        if (batched) {
+            const int g = gm.graph(elo[e]);   // wave-uniform
+            if (g != gcur) {
+                if (gcur >= 0) wave_flush_runs<5>(s, gcur, acc, ACC_STRIDE, ids);
+                gcur = g;
+            }
+        }
         const int32_t p = earc[e];
         const int64_t l0 = aoff[p], l1 = aoff[p + 1];
         if (l1 == l0) continue;
@@ -126,8 +142,8 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
             wave_sync();
         }
     }
-    const int ids[5] = {AC_K4X4, AC_N20, AC_N10, AC_N16, AC_Z};
-    block_flush_u128<5>(s, red, acc, ids);
+    if (batched) wave_flush_runs<5>(s, gcur, acc, ACC_STRIDE, ids);
+    else block_flush_u128<5>(s, red, acc, ids);
     flush_count(nvis, visits);
 }
 
@@ -182,20 +198,27 @@ __device__ inline int nth_set_bit(const unsigned long long *row, int words, int 
 // one workgroup per vertex a; items = pairs (b, c) with c in row(a,b)
 __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const int32_t *split,
                                             const int64_t *ob_off, const unsigned long long *ob, int *task,
-                                            unsigned long long *acc, unsigned long long *visits) {
+                                            int chunk, GMap gm, unsigned long long *acc,
+                                            unsigned long long *visits) {
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
     __shared__ int s_a;
     __shared__ u128 red[4];
-    u128 k5 = 0;
+    const int ids[1] = {AC_K5};
+    u128 k5[1] = {0};
+    int gcur = -1;
     uint64_t nvis = 0;
     for (;;) {
         if (threadIdx.x == 0) s_a = atomicAdd(task, 1);
         __syncthreads();
-        const int32_t a = s_a;
-        if (a >= n) break;
+        const int64_t a0 = (int64_t)s_a * chunk;
+        if (a0 >= n) break;
+        const int32_t a1 = (int32_t)(a0 + chunk < n ? a0 + chunk : n);
+        __syncthreads();   // s_a is read by every thread before it is taken again
+        for (int32_t a = (int32_t)a0; a < a1; a++) {
+        block_switch_graph<1>(k5, gcur, gm.graph(a), red, acc, ACC_STRIDE, ids);
         const int32_t dpa = off[a + 1] - split[a];
-        if (dpa < 4) { __syncthreads(); continue; }
+        if (dpa < 4) continue;
         const int wa = (dpa + 63) >> 6;
         const unsigned long long *rows = ob + ob_off[a];
         for (int ib = 0; ib < dpa; ib += blockDim.x) {
@@ -213,16 +236,15 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
                         const int x = w * 64 + __ffsll((long long)sw) - 1;
                         sw &= sw - 1;
                         const unsigned long long *rx = rows + (int64_t)x * wa;
-                        for (int w2 = 0; w2 < wa; w2++) k5 += __popcll(rb[w2] & rc[w2] & rx[w2]);
+                        for (int w2 = 0; w2 < wa; w2++) k5[0] += __popcll(rb[w2] & rc[w2] & rx[w2]);
                         nvis += wa;
                     }
                 }
             });
         }
+        }
     }
-    const int ids[1] = {AC_K5};
-    u128 v[1] = {k5};
-    block_flush_u128<1>(v, red, acc, ids);
+    if (gcur >= 0) block_flush_u128<1>(k5, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
 
@@ -239,7 +261,8 @@ esc_status stage_k4_triangles(esc_ctx *c) {
         m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
         (const int32_t *)c->buf[B_REV], (const int32_t *)c->buf[B_ARC_EID], (const int32_t *)c->buf[B_EARC],
         (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], (const int64_t *)c->buf[B_AOFF],
-        (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], k4e, (unsigned long long *)c->buf[B_ACC],
+        (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], k4e, gmap_of(c),
+        (unsigned long long *)c->buf[B_ACC],
         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
@@ -268,7 +291,8 @@ esc_status stage_k5(esc_ctx *c) {
         n, off, split, (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV],
         (const int32_t *)c->buf[B_ADJ], ob_off, ob);
     HIP_TRY(hipGetLastError());
-    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, task + 3, (unsigned long long *)c->buf[B_ACC],
+    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, task + 3, c->task_chunk, gmap_of(c),
+                                        (unsigned long long *)c->buf[B_ACC],
                                         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4);
     HIP_TRY(hipGetLastError());
     return ESC_OK;

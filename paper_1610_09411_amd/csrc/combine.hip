@@ -9,6 +9,7 @@
 #include <string.h>
 #include <vector>
 #include <algorithm>
+#include <stdlib.h>
 #include "device.h"
 #include "ctx.h"
 
@@ -162,9 +163,10 @@ __device__ inline u128 apply_inv(const int32_t *inv, int count, int row, const u
     return s;
 }
 
-__global__ void k_combine(const unsigned long long *acc, const int32_t *inv4, const int32_t *inv5, int64_t nv,
-                          int64_t me, int k, u128 *out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One graph: its AC_COUNT sums, n and m -> out[0..44] induced counts,
+// out[45..89] non-induced counts (the first 11 of each when k = 4).
+__device__ void combine_one(const unsigned long long *acc, const int32_t *inv4, const int32_t *inv5, int64_t nv,
+                            int64_t me, int k, u128 *out) {
     u128 S[AC_COUNT];
     for (int s = 0; s < AC_COUNT; s++) S[s] = ((u128)acc[2 * s + 1] << 64) | acc[2 * s];
     const u128 n = (u128)nv, m = (u128)me;
@@ -229,6 +231,35 @@ __global__ void k_combine(const unsigned long long *acc, const int32_t *inv4, co
     for (int i = 0; i < 34; i++) out[56 + i] = N5[i];
 }
 
+__global__ void k_combine(const unsigned long long *acc, const int32_t *inv4, const int32_t *inv5, int64_t nv,
+                          int64_t me, int k, u128 *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    combine_one(acc, inv4, inv5, nv, me, k, out);
+}
+
+// One thread per graph of a batch: exact 128-bit combination, then the
+// induced counts as uint64 with a per-graph flag when one does not fit.
+// Also adds the graphs' W, 3T and D into the work counters.
+__global__ void k_combine_batched(int32_t G, const unsigned long long *acc, const int32_t *inv4, const int32_t *inv5,
+                                  const int64_t *voff, const int64_t *aoff, int k, u128 *tmp, uint64_t *out,
+                                  uint8_t *ovf, unsigned long long *work) {
+    const int cnt = k == 4 ? 11 : 45;
+    for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+        const unsigned long long *a = acc + (size_t)g * ACC_STRIDE;
+        u128 *o = tmp + (size_t)g * 90;
+        combine_one(a, inv4, inv5, voff[g + 1] - voff[g], (aoff[g + 1] - aoff[g]) / 2, k, o);
+        uint8_t f = 0;
+        for (int i = 0; i < cnt; i++) {
+            out[(size_t)g * cnt + i] = (uint64_t)o[i];
+            f |= (o[i] >> 64) != 0;
+        }
+        ovf[g] = f;
+        atomicAdd(&work[12], a[2 * AC_W]);
+        atomicAdd(&work[13], a[2 * AC_T3]);
+        atomicAdd(&work[14], a[2 * AC_D]);
+    }
+}
+
 esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, const int32_t *d_inv5) {
     u128 *dout = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * 96);
     if (!dout) return ESC_ENOMEM;
@@ -246,4 +277,69 @@ esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, 
         c->noninduced[i].hi = (uint64_t)(h[45 + i] >> 64);
     }
     return ESC_OK;
+}
+
+// Device side of a batched combine: exact rows (90 u128 per graph: 45 induced
+// then 45 non-induced) in B_OUT, uint64 rows and overflow flags in B_BOUT.
+esc_status stage_combine_batched(esc_ctx *c) {
+    const int32_t G = c->G;
+    const int cnt = c->k == 4 ? 11 : 45;
+    u128 *tmp = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * 90 * (size_t)G);
+    uint8_t *bout = (uint8_t *)ctx_buf(c, B_BOUT, (sizeof(uint64_t) * cnt + 1) * (size_t)G);
+    if (!tmp || !bout) return ESC_ENOMEM;
+    uint64_t *dout = (uint64_t *)bout;
+    uint8_t *dovf = bout + sizeof(uint64_t) * cnt * (size_t)G;
+    const int64_t *voff = (const int64_t *)c->buf[B_GOFF];
+    int blocks = (G + 63) / 64;
+    if (blocks > c->num_cu * 8) blocks = c->num_cu * 8;
+    k_combine_batched<<<blocks, 64, 0, c->stream>>>(G, (const unsigned long long *)c->buf[B_ACC], c->d_inv4, c->d_inv5,
+                                                    voff, voff + G + 1, c->k, tmp, dout, dovf,
+                                                    (unsigned long long *)c->buf[B_WORK]);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
+esc_status batched_copy_u64(esc_ctx *c, uint64_t *host_out, uint8_t *host_overflow, int *any_overflow) {
+    const int32_t G = c->G;
+    const int cnt = c->k == 4 ? 11 : 45;
+    const uint64_t *dout = (const uint64_t *)c->buf[B_BOUT];
+    const uint8_t *dovf = (const uint8_t *)c->buf[B_BOUT] + sizeof(uint64_t) * cnt * (size_t)G;
+    HIP_TRY(hipMemcpyAsync(host_out, dout, sizeof(uint64_t) * cnt * (size_t)G, hipMemcpyDeviceToHost, c->stream));
+    uint8_t *flags = host_overflow;
+    uint8_t *own = nullptr;
+    if (!flags) {
+        own = (uint8_t *)malloc((size_t)G);
+        if (!own) return ESC_ENOMEM;
+        flags = own;
+    }
+    esc_status st = ESC_OK;
+    if (hipMemcpyAsync(flags, dovf, (size_t)G, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        st = ESC_EDEVICE;
+    int any = 0;
+    if (st == ESC_OK)
+        for (int32_t g = 0; g < G; g++) any |= flags[g];
+    free(own);
+    *any_overflow = any;
+    return st;
+}
+
+esc_status batched_copy_u128(esc_ctx *c, esc_u128 *host_out) {
+    const int32_t G = c->G;
+    const int cnt = c->k == 4 ? 11 : 45;
+    u128 *h = (u128 *)malloc(sizeof(u128) * 90 * (size_t)G);
+    if (!h) return ESC_ENOMEM;
+    esc_status st = ESC_OK;
+    if (hipMemcpyAsync(h, c->buf[B_OUT], sizeof(u128) * 90 * (size_t)G, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        st = ESC_EDEVICE;
+    if (st == ESC_OK)
+        for (int32_t g = 0; g < G; g++)
+            for (int i = 0; i < cnt; i++) {
+                const u128 x = h[(size_t)g * 90 + i];
+                host_out[(size_t)g * cnt + i].lo = (uint64_t)x;
+                host_out[(size_t)g * cnt + i].hi = (uint64_t)(x >> 64);
+            }
+    free(h);
+    return st;
 }

@@ -62,10 +62,29 @@ enum Buf {
     B_TASK,
     B_FRAG,                     // fragment outputs in input order
     B_OB, B_OB_OFF,             // out-neighbourhood bitmaps for 5-cliques
+    B_GOFF,                     // batched: vertex and arc offsets of the graphs (int64, 2 x (G+1))
+    B_VGRAPH,                   // batched: graph of each union vertex id (= of each rank)
+    B_URP, B_UCOL,              // batched: CSR of the disjoint union
+    B_BOUT,                     // batched: per-graph counts and overflow flags
     B_COUNT
 };
 
 #define NSTAGES 10
+
+// Per-graph sums: graph g's slots start at acc + g * ACC_STRIDE.
+#define ACC_STRIDE (2 * AC_COUNT)
+
+// Which graph an item of the union belongs to: vg maps a rank (equivalently
+// a union vertex id) to its graph, voff holds the first rank of every graph.
+// A single-graph call passes vg = nullptr: graph 0 spans [0, n).
+struct GMap {
+    const int32_t *vg;
+    const int64_t *voff;
+    int32_t n;
+    __device__ int graph(int32_t r) const { return vg ? vg[r] : 0; }
+    __device__ int32_t begin(int g) const { return vg ? (int32_t)voff[g] : 0; }
+    __device__ int32_t end(int g) const { return vg ? (int32_t)voff[g + 1] : n; }
+};
 
 struct esc_ctx;
 inline int pair_wgs(const esc_ctx *c);
@@ -95,18 +114,32 @@ struct esc_ctx {
     int k;
     uint32_t flags;
     bool scratch_clean;        // per-workgroup tables are all zero
+    // batched calls: the graphs form one disjoint union whose rank order is
+    // (graph, degree, id), so every graph owns a contiguous range of ranks
+    int32_t G;                 // number of graphs; 0 for a single-graph call
+    int32_t tab_n;             // extent of a per-workgroup dense table (largest graph)
+    int task_chunk;            // sources taken per grab by the per-source kernels
     int32_t *d_inv4, *d_inv5;  // signed inverse matrices (Appendix B), device copies
 };
 
 // Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):
-// two per CU; each owns dense n-entry tables in B_WG_SCRATCH.
+// two per CU; each owns dense tables of tab_n entries in B_WG_SCRATCH.
 inline int pair_wgs(const esc_ctx *c) { return 2 * c->num_cu; }
+
+inline GMap gmap_of(const esc_ctx *c) {
+    GMap g;
+    g.vg = c->G ? (const int32_t *)c->buf[B_VGRAPH] : nullptr;
+    g.voff = c->G ? (const int64_t *)c->buf[B_GOFF] : nullptr;
+    g.n = c->n;
+    return g;
+}
 
 // Grow-only device buffer; returns nullptr on failure (status set by caller).
 void *ctx_buf(esc_ctx *c, Buf b, size_t bytes);
 esc_status ctx_check(hipError_t e);
 
-// B_WORK layout: [0] W++, [1] W+-, [2 + s] visits of stage s (see esc_last_profile)
+// B_WORK layout: [0] W++, [1] W+-, [2 + s] visits of stage s (see esc_last_profile),
+// [12] W, [13] 3T, [14] D summed over the graphs of a batched call
 #define WORK_VISITS 2
 #define WORK_WORDS 16
 
@@ -124,6 +157,18 @@ esc_status stage_k4_triangles(esc_ctx *c);
 esc_status stage_k5(esc_ctx *c);
 esc_status stage_reduce(esc_ctx *c);
 esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, const int32_t *d_inv5);
+esc_status stage_combine_batched(esc_ctx *c);
+esc_status batched_copy_u64(esc_ctx *c, uint64_t *host_out, uint8_t *host_overflow, int *any_overflow);
+esc_status batched_copy_u128(esc_ctx *c, esc_u128 *host_out);
+
+// End of a call (api.hip): stage times, work counters, scratch marked clean.
+// w, t3, d are the single-graph totals; a batch reads them from B_WORK.
+esc_status call_finish(esc_ctx *c, uint64_t w, uint64_t t3, uint64_t d);
+
+// A batch through the pipeline up to the device-side combine (api.hip); the
+// rows are then copied out with batched_copy_u64 / batched_copy_u128.
+esc_status run_batched_device(esc_ctx *c, int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                              const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags, void *stream);
 esc_status combine_tables(int32_t *host_inv4, int32_t *host_inv5);
 esc_status stage_fragments_out(esc_ctx *c, uint64_t *tri_v, uint64_t *c4_v, uint64_t *k4_v,
                                uint64_t *tri_e, uint64_t *c4_e, uint64_t *k4_e);

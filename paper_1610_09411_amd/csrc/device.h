@@ -56,6 +56,54 @@ __device__ inline void block_flush_u128(u128 (&v)[NV], u128 *scratch, unsigned l
     __syncthreads();
 }
 
+__device__ inline u128 shfl_up_u128(u128 x, int d) {
+    unsigned long long lo = (unsigned long long)x, hi = (unsigned long long)(x >> 64);
+    lo = __shfl_up(lo, d);
+    hi = __shfl_up(hi, d);
+    return ((u128)hi << 64) | lo;
+}
+
+// Batched calls keep one set of sums per graph (graph g at slots + g*stride).
+// Each lane adds its NV values to the sums of its graph g; runs of adjacent
+// lanes with the same g are summed first (segmented scan), so a wave whose
+// lanes all hold one graph issues one atomic per value.  Lanes with g < 0
+// hold nothing.  Zeroes v.  All 64 lanes of the wave must take part.
+template <int NV>
+__device__ inline void wave_flush_runs(u128 (&v)[NV], int g, unsigned long long *slots, size_t stride,
+                                       const int *slot_ids) {
+    const int lane = threadIdx.x & (ESC_WAVE - 1);
+    const int gp = __shfl_up(g, 1);
+    const uint64_t heads = __ballot(lane == 0 || gp != g);
+    const uint64_t upto = heads & ((2ull << lane) - 1);       // run heads at or below this lane
+    const int run0 = 63 - __clzll((long long)upto);
+    const bool last = lane == ESC_WAVE - 1 || ((heads >> (lane + 1)) & 1);
+#pragma unroll
+    for (int s = 0; s < NV; s++) {
+        u128 x = v[s];
+        for (int o = 1; o < ESC_WAVE; o <<= 1) {
+            u128 y = shfl_up_u128(x, o);
+            if (lane - o >= run0) x += y;
+        }
+        if (last && g >= 0 && x) atomic_add_u128(slots + (size_t)g * stride + 2 * slot_ids[s], x);
+        v[s] = 0;
+    }
+}
+
+// Per-source kernels take whole sources per workgroup, so the graph of the
+// current source is block-uniform: when it changes, the block's partial sums
+// go to the graph they were gathered for.  Every thread of the block calls it.
+template <int NV>
+__device__ inline void block_switch_graph(u128 (&v)[NV], int &gcur, int gnew, u128 *scratch,
+                                          unsigned long long *slots, size_t stride, const int *slot_ids) {
+    if (gnew == gcur) return;
+    if (gcur >= 0) {
+        block_flush_u128<NV>(v, scratch, slots + (size_t)gcur * stride, slot_ids);
+#pragma unroll
+        for (int s = 0; s < NV; s++) v[s] = 0;
+    }
+    gcur = gnew;
+}
+
 __device__ inline uint64_t wave_sum_u64(uint64_t x) {
     for (int o = ESC_WAVE / 2; o > 0; o >>= 1) x += __shfl_xor((unsigned long long)x, o);
     return x;

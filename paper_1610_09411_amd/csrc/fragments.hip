@@ -147,27 +147,36 @@ esc_status stage_triangles(esc_ctx *c) {
 __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, const int32_t *rev,
                                                      const int32_t *arc_eid, const uint32_t *tarc,
-                                                     uint32_t *tab_c, uint32_t *tab_t, uint32_t *tab_k,
-                                                     int32_t *touch_all, int *task, unsigned long long *acc,
+                                                     uint32_t *tab_c, int32_t *touch_all, int32_t tab_n,
+                                                     int chunk, GMap gm, int *task, unsigned long long *acc,
                                                      unsigned long long *c4e, unsigned long long *visits) {
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_h, s_nt;
     __shared__ u128 red[3 * 8];
-    // the three counters of a key sit side by side (one cache line per key)
-    uint32_t *tab3 = tab_c + (size_t)blockIdx.x * 3 * n;
-#define CNT(o) tab3[3 * (size_t)(o)]
-#define FT(o) tab3[3 * (size_t)(o) + 1]
-#define FK(o) tab3[3 * (size_t)(o) + 2]
-    int32_t *touch = touch_all + (size_t)blockIdx.x * n;
+    // the three counters of a key sit side by side (one cache line per key);
+    // keys are ranks relative to the first rank of the source's graph
+    uint32_t *tab3 = tab_c + (size_t)blockIdx.x * 3 * tab_n;
+#define CNT(o) tab3[3 * (size_t)((o) - gb)]
+#define FT(o) tab3[3 * (size_t)((o) - gb) + 1]
+#define FK(o) tab3[3 * (size_t)((o) - gb) + 2]
+    int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
+    const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
     u128 sums[3] = {0, 0, 0};
+    int gcur = -1;
+    if (threadIdx.x == 0) s_nt = 0;
     for (;;) {
-        if (threadIdx.x == 0) { s_h = atomicAdd(task, 1); s_nt = 0; }
+        if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
         __syncthreads();
-        const int32_t t = s_h;
-        if (t >= n) break;
+        const int64_t t0 = (int64_t)s_h * chunk;
+        if (t0 >= n) break;
+        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t h = n - 1 - t;
+        const int g = gm.graph(h);
+        block_switch_graph<3>(sums, gcur, g, red, acc, ACC_STRIDE, ids);
+        const int32_t gb = gm.begin(g);
         const int32_t oh = off[h], sh = split[h];
         // wedges h - k - o with k, o before h: k in N-(h), o in the prefix of N(k) below h
         for (int32_t base = oh; base < sh; base += blockDim.x) {
@@ -215,12 +224,13 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
             CNT(o) = 0; FT(o) = 0; FK(o) = 0;
         }
         __syncthreads();
+        if (threadIdx.x == 0) s_nt = 0;   // next read of s_nt is behind a barrier
+        }
     }
 #undef CNT
 #undef FT
 #undef FK
-    const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
-    block_flush_u128<3>(sums, red, acc, ids);
+    if (gcur >= 0) block_flush_u128<3>(sums, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
 
@@ -229,7 +239,7 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     hipStream_t st = c->stream;
     if (n == 0) return ESC_OK;
     int nwg = pair_wgs(c);
-    size_t per = (size_t)n * sizeof(uint32_t);
+    size_t per = (size_t)c->tab_n * sizeof(uint32_t);
     uint32_t *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
     int32_t *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * 2 * nwg);
     int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
@@ -244,7 +254,7 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     k_four_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
                                        (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
-                                       tab, nullptr, nullptr, touch, task,
+                                       tab, touch, c->tab_n, c->task_chunk, gmap_of(c), task,
                                        (unsigned long long *)c->buf[B_ACC], c4e,
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
     HIP_TRY(hipGetLastError());
@@ -253,16 +263,55 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
 
 // -------------------------------------------------------------- reductions
 
+// Item ranges of the flat per-vertex / per-edge kernels.  A single graph
+// strides the whole grid over the items; a batch gives every wave one
+// contiguous block of items, so a wave meets few graph boundaries and keeps
+// its per-graph sums in registers in between.
+struct WaveRange {
+    int64_t base, end, step;
+};
+
+__device__ inline WaveRange wave_range(int64_t items, bool blocked) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    WaveRange r;
+    if (blocked) {
+        const int64_t per = ((items + nwaves - 1) / nwaves + 63) & ~(int64_t)63;
+        r.base = wave * per;
+        r.end = r.base + per < items ? r.base + per : items;
+        r.step = 64;
+    } else {
+        r.base = wave * 64;
+        r.end = items;
+        r.step = nwaves * 64;
+    }
+    return r;
+}
+
 // per vertex r (rank ids): t(v) = half the sum of t(e) over its edges,
 // K4(v) = a third of the sum of K4(e) = a sixth of the sum of k4e.
 __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t *off, const int32_t *adj,
                                                        const int32_t *split, const int32_t *arc_eid,
                                                        const uint32_t *te, const unsigned long long *k4e,
-                                                       uint64_t *tv, unsigned long long *acc, uint64_t *work) {
-    __shared__ u128 red[12 * 4];
-    u128 s[12] = {0};
+                                                       uint64_t *tv, GMap gm, unsigned long long *acc,
+                                                       uint64_t *work) {
+    __shared__ u128 red[10 * 4];
+    const int ids[10] = {AC_W, AC_S3, AC_S4, AC_TT, AC_N3, AC_N4, AC_N9, AC_N15, AC_SW, AC_TD};
+    u128 s[10] = {0};
     uint64_t wpp = 0, wpm = 0, nvis = 0;
-    for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const bool batched = gm.vg != nullptr;
+    const WaveRange wr = wave_range(n, batched);
+    int gcur = -1;
+    for (int64_t base = wr.base; base < wr.end; base += wr.step) {
+        const int32_t r = (int32_t)(base + lane);
+        const bool ok = base + lane < wr.end;
+        if (batched) {
+            const int g = ok ? gm.graph(r) : gcur;
+            if (__ballot(g != gcur && gcur >= 0)) wave_flush_runs<10>(s, gcur, acc, ACC_STRIDE, ids);
+            gcur = g;
+        }
+        if (!ok) continue;
         const int32_t a = off[r], b = off[r + 1];
         const uint64_t d = b - a;
         nvis += d;
@@ -294,9 +343,8 @@ __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t 
         wpp += c2(dp);
         wpm += dp * dm;
     }
-    const int ids[10] = {AC_W, AC_S3, AC_S4, AC_TT, AC_N3, AC_N4, AC_N9, AC_N15, AC_SW, AC_TD};
-    u128 v[10] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8], s[9]};
-    block_flush_u128<10>(v, red, acc, ids);
+    if (batched) wave_flush_runs<10>(s, gcur, acc, ACC_STRIDE, ids);
+    else block_flush_u128<10>(s, red, acc, ids);
     wpp = wave_sum_u64(wpp);
     wpm = wave_sum_u64(wpm);
     if ((threadIdx.x & 63) == 0) {
@@ -308,12 +356,26 @@ __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t 
 
 __global__ void __launch_bounds__(256) k_edge_reduce(int64_t m, const int32_t *off, const int32_t *adj,
                                                      const int32_t *earc, const int32_t *elo, const uint32_t *te,
-                                                     const uint64_t *tv, const unsigned long long *k4e,
+                                                     const uint64_t *tv, const unsigned long long *k4e, GMap gm,
                                                      unsigned long long *acc) {
-    __shared__ u128 red[10 * 4];
-    u128 s[10] = {0};
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t u = elo[e], v = adj[earc[e]];
+    __shared__ u128 red[9 * 4];
+    const int ids[9] = {AC_T3, AC_D, AC_EP, AC_N2, AC_N5, AC_N6, AC_N11, AC_N14, AC_N19};
+    u128 s[9] = {0};
+    const int lane = threadIdx.x & 63;
+    const bool batched = gm.vg != nullptr;
+    const WaveRange wr = wave_range(m, batched);
+    int gcur = -1;
+    for (int64_t base = wr.base; base < wr.end; base += wr.step) {
+        const int64_t e = base + lane;
+        const bool ok = e < wr.end;
+        const int32_t u = ok ? elo[e] : 0;
+        if (batched) {
+            const int g = ok ? gm.graph(u) : gcur;
+            if (__ballot(g != gcur && gcur >= 0)) wave_flush_runs<9>(s, gcur, acc, ACC_STRIDE, ids);
+            gcur = g;
+        }
+        if (!ok) continue;
+        const int32_t v = adj[earc[e]];
         const uint64_t du = off[u + 1] - off[u], dv = off[v + 1] - off[v];
         const uint64_t t = te[e], tu = tv[u], tw = tv[v], k4 = k4e[e] / 2;
         s[0] += t;
@@ -326,9 +388,8 @@ __global__ void __launch_bounds__(256) k_edge_reduce(int64_t m, const int32_t *o
         s[7] += c3(t);
         if (t >= 2) s[8] += (u128)k4 * (t - 2);
     }
-    const int ids[9] = {AC_T3, AC_D, AC_EP, AC_N2, AC_N5, AC_N6, AC_N11, AC_N14, AC_N19};
-    u128 v[9] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8]};
-    block_flush_u128<9>(v, red, acc, ids);
+    if (batched) wave_flush_runs<9>(s, gcur, acc, ACC_STRIDE, ids);
+    else block_flush_u128<9>(s, red, acc, ids);
 }
 
 esc_status stage_reduce(esc_ctx *c) {
@@ -342,14 +403,14 @@ esc_status stage_reduce(esc_ctx *c) {
         k_vertex_reduce<<<grid_cap(c, n, 256), 256, 0, st>>>(
             n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
             (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TE],
-            (const unsigned long long *)c->buf[B_K4E], tv, acc, (uint64_t *)c->buf[B_WORK]);
+            (const unsigned long long *)c->buf[B_K4E], tv, gmap_of(c), acc, (uint64_t *)c->buf[B_WORK]);
         HIP_TRY(hipGetLastError());
     }
     if (m > 0) {
         k_edge_reduce<<<grid_cap(c, m, 256), 256, 0, st>>>(
             m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_EARC],
             (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], tv,
-            (const unsigned long long *)c->buf[B_K4E], acc);
+            (const unsigned long long *)c->buf[B_K4E], gmap_of(c), acc);
         HIP_TRY(hipGetLastError());
     }
     return ESC_OK;

@@ -131,6 +131,12 @@ __global__ void k_init_keys(int32_t n, const int32_t *deg, uint32_t *keys, uint3
     }
 }
 
+// batched calls: second sort key = graph of the vertex (stable on the first)
+__global__ void k_graph_keys(int32_t n, const uint32_t *vals, const int32_t *vgraph, uint32_t *keys) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        keys[i] = (uint32_t)vgraph[vals[i]];
+}
+
 __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint32_t *keys, int32_t n, int shift, int32_t *hist,
                                                         int32_t ntiles) {
     __shared__ int32_t h[256];
@@ -424,33 +430,33 @@ esc_status stage_orient(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col) {
     int random_order = (c->flags & ESC_F_RANDOM_ORDER) ? 1 : 0;
     k_init_keys<<<grid_for(c, n, 256), 256, 0, st>>>(n, deg, ka, va, random_order);
     HIP_TRY(hipGetLastError());
-    int bits = 0;
-    uint32_t maxkey = random_order ? 0x7FFFFFFFu : (uint32_t)c->maxdeg;
-    while (bits < 32 && (maxkey >> bits)) bits += 8;
-    if (bits == 0) bits = 8;
-    int passes = bits / 8;
-    uint32_t *kin = ka, *vin = va, *kout = kb, *vout = vb;
-    // make sure the final output lands in B_PERM (vb): with an even number of
-    // passes start by copying into the pair that ends in vb
-    if (passes % 2 == 0) {
-        HIP_TRY(hipMemcpyAsync(kb, ka, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(vb, va, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st));
-        kin = kb; vin = vb; kout = ka; vout = va;
-    }
     int32_t *hs = (int32_t *)ctx_buf(c, B_TASK, sizeof(int32_t) * (size_t)(256 * (int64_t)ntiles + 2));
     if (!hs) return ESC_ENOMEM;
-    for (int pass = 0; pass < passes && n > 0; pass++) {
-        int shift = pass * 8;
-        k_rs_hist<<<ntiles, RS_THREADS, 0, st>>>(kin, n, shift, hist, ntiles);
-        HIP_TRY(hipGetLastError());
-        ESC_TRY(dev_scan<int32_t>(c, hist, hs, 256 * (int64_t)ntiles));
-        k_rs_scatter<<<ntiles, RS_THREADS, 0, st>>>(kin, vin, kout, vout, n, shift, hs, ntiles);
-        HIP_TRY(hipGetLastError());
-        uint32_t *t;
-        t = kin; kin = kout; kout = t;
-        t = vin; vin = vout; vout = t;
+    // LSD radix sort, 8 bits per pass, ping-ponging between the two pairs:
+    // first by degree (ties keep id order), then, for a batch, stably by graph
+    uint32_t *kin = ka, *vin = va, *kout = kb, *vout = vb;
+    for (int round = 0; round < (c->G ? 2 : 1) && n > 0; round++) {
+        uint32_t maxkey = round ? (uint32_t)(c->G - 1) : random_order ? 0x7FFFFFFFu : (uint32_t)c->maxdeg;
+        if (round) {
+            k_graph_keys<<<grid_for(c, n, 256), 256, 0, st>>>(n, vin, (const int32_t *)c->buf[B_VGRAPH], kin);
+            HIP_TRY(hipGetLastError());
+        }
+        int bits = 0;
+        while (bits < 32 && (maxkey >> bits)) bits += 8;
+        if (bits == 0) bits = 8;
+        for (int pass = 0; pass < bits / 8; pass++) {
+            int shift = pass * 8;
+            k_rs_hist<<<ntiles, RS_THREADS, 0, st>>>(kin, n, shift, hist, ntiles);
+            HIP_TRY(hipGetLastError());
+            ESC_TRY(dev_scan<int32_t>(c, hist, hs, 256 * (int64_t)ntiles));
+            k_rs_scatter<<<ntiles, RS_THREADS, 0, st>>>(kin, vin, kout, vout, n, shift, hs, ntiles);
+            HIP_TRY(hipGetLastError());
+            uint32_t *t;
+            t = kin; kin = kout; kout = t;
+            t = vin; vin = vout; vout = t;
+        }
     }
-    const uint32_t *perm = vin;   // == vb by construction
+    const uint32_t *perm = vin;   // B_VALS_A or B_PERM; the segmented sort below uses neither
     k_rank<<<grid_for(c, n, 256), 256, 0, st>>>(n, perm, rank);
     HIP_TRY(hipGetLastError());
 

@@ -31,24 +31,35 @@
 __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off, const int32_t *adj,
                                                   const int32_t *rev, const int64_t *aoff, const uint32_t *aa,
                                                   const int32_t *av, uint32_t *tab_all, int32_t *touch_all,
-                                                  int *task, int32_t slab, unsigned long long *acc,
-                                                  unsigned long long *visits) {
+                                                  int32_t tab_n, int chunk, GMap gm, int *task, int32_t slab,
+                                                  unsigned long long *acc, unsigned long long *visits) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
-    const int32_t hi0 = n - slab;   // first key held in LDS
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_i, s_nt;
     __shared__ u128 red[2 * 8];
-    uint32_t *W = tab_all + (size_t)blockIdx.x * n;
-    int32_t *touch = touch_all + (size_t)blockIdx.x * n;
-    u128 s13 = 0, s17 = 0;
+    const int ids[2] = {AC_N13, AC_N17};
+    uint32_t *Wt = tab_all + (size_t)blockIdx.x * tab_n;
+    int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
+    u128 sv[2] = {0, 0};   // pattern 13, pattern 17
+    int gcur = -1;
+    if (threadIdx.x == 0) s_nt = 0;
     for (;;) {
-        if (threadIdx.x == 0) { s_i = atomicAdd(task, 1); s_nt = 0; }
+        if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
         __syncthreads();
-        const int32_t t = s_i;
-        if (t >= n) break;
+        const int64_t t0 = (int64_t)s_i * chunk;
+        if (t0 >= n) break;
+        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t i = n - 1 - t;
+        const int g = gm.graph(i);
+        block_switch_graph<2>(sv, gcur, g, red, acc, ACC_STRIDE, ids);
+        // keys are ranks of the source's graph: the latest `slab` of them sit
+        // in LDS, the rest in the workgroup's table, relative to the graph's start
+        const int32_t gb = gm.begin(g), ge = gm.end(g);
+        const int32_t hi0 = ge - slab > gb ? ge - slab : gb;   // first key held in LDS
+        uint32_t *W = Wt - gb;
         const int32_t oi = off[i], ei = off[i + 1];
         const int32_t nsl = i > hi0 ? i - hi0 : 0;   // LDS keys [hi0, i)
         for (int q = threadIdx.x; q < nsl; q += blockDim.x) sl[q] = 0;
@@ -110,7 +121,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                             acc17 += (uint64_t)(j >= hi0 ? sl[j - hi0] : W[j]) - 2;
                         }
                     }
-                    s17 += acc17;
+                    sv[1] += acc17;
                 }
             }
             __syncthreads();
@@ -118,15 +129,15 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         const int nt = s_nt;
         for (int q = threadIdx.x; q < nt; q += blockDim.x) {
             int32_t j = touch[q];
-            s13 += c3(W[j]);
+            sv[0] += c3(W[j]);
             W[j] = 0;
         }
-        for (int q = threadIdx.x; q < nsl; q += blockDim.x) s13 += c3(sl[q]);
+        for (int q = threadIdx.x; q < nsl; q += blockDim.x) sv[0] += c3(sl[q]);
         __syncthreads();
+        if (threadIdx.x == 0) s_nt = 0;   // next read of s_nt is behind a barrier
+        }
     }
-    const int ids[2] = {AC_N13, AC_N17};
-    u128 v[2] = {s13, s17};
-    block_flush_u128<2>(v, red, acc, ids);
+    if (gcur >= 0) block_flush_u128<2>(sv, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
 
@@ -138,25 +149,32 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // lives in LDS when d(h) fits, else in the workgroup's global scratch.
 __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
-                                                uint32_t *gtab_all, int32_t *gtouch_all, int32_t lds_cap,
-                                                int *task, unsigned long long *acc, unsigned long long *visits) {
+                                                uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
+                                                int32_t lds_cap, int chunk, GMap gm, int *task,
+                                                unsigned long long *acc, unsigned long long *visits) {
     uint64_t nvis = 0;
     extern __shared__ uint32_t dyn[];
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
     __shared__ int s_h, s_nt;
     __shared__ u128 red[4];
-    u128 s18 = 0;
+    const int ids[1] = {AC_N18};
+    u128 s18[1] = {0};
+    int gcur = -1;
     for (;;) {
         if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
         __syncthreads();
-        const int32_t t = s_h;
-        if (t >= n) break;
+        const int64_t t0 = (int64_t)s_h * chunk;
+        if (t0 >= n) break;
+        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        __syncthreads();   // s_h is read by every thread before it is taken again
+        for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t h = n - 1 - t;
+        block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
         const int32_t oh = off[h], dh = off[h + 1] - oh;
         const bool in_lds = dh <= lds_cap;
-        uint32_t *cnt_ = in_lds ? dyn : gtab_all + (size_t)blockIdx.x * n;
-        int32_t *tch = in_lds ? (int32_t *)(dyn + lds_cap) : gtouch_all + (size_t)blockIdx.x * n;
+        uint32_t *cnt_ = in_lds ? dyn : gtab_all + (size_t)blockIdx.x * tab_n;
+        int32_t *tch = in_lds ? (int32_t *)(dyn + lds_cap) : gtouch_all + (size_t)blockIdx.x * tab_n;
         if (in_lds)
             for (int q = threadIdx.x; q < dh; q += blockDim.x) cnt_[q] = 0;
         __syncthreads();
@@ -209,15 +227,14 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
             const int nt = s_nt;
             for (int q = threadIdx.x; q < nt; q += blockDim.x) {
                 int32_t key = tch[q];
-                s18 += c2(cnt_[key]);
+                s18[0] += c2(cnt_[key]);
                 cnt_[key] = 0;
             }
             __syncthreads();
         }
+        }
     }
-    const int ids[1] = {AC_N18};
-    u128 v[1] = {s18};
-    block_flush_u128<1>(v, red, acc, ids);
+    if (gcur >= 0) block_flush_u128<1>(s18, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
 
@@ -225,24 +242,35 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
 
 __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, uint32_t *tabX_all, uint32_t *tabW_all,
-                                                     int32_t *touchX_all, int32_t *touchW_all, int *task,
-                                                     unsigned long long *acc, unsigned long long *visits) {
+                                                     int32_t *touchX_all, int32_t *touchW_all, int32_t tab_n,
+                                                     int chunk, GMap gm, int *task, unsigned long long *acc,
+                                                     unsigned long long *visits) {
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_i, s_nx, s_nw;
     __shared__ u128 red[8];
-    uint32_t *X = tabX_all + (size_t)blockIdx.x * n;
-    uint32_t *Wn = tabW_all + (size_t)blockIdx.x * n;
-    int32_t *tx = touchX_all + (size_t)blockIdx.x * n;
-    int32_t *tw = touchW_all + (size_t)blockIdx.x * n;
-    u128 sc = 0;
+    const int ids[1] = {AC_CYC};
+    uint32_t *Xt = tabX_all + (size_t)blockIdx.x * tab_n;
+    uint32_t *Wt = tabW_all + (size_t)blockIdx.x * tab_n;
+    int32_t *tx = touchX_all + (size_t)blockIdx.x * tab_n;
+    int32_t *tw = touchW_all + (size_t)blockIdx.x * tab_n;
+    u128 sc[1] = {0};
+    int gcur = -1;
+    if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }
     for (;;) {
-        if (threadIdx.x == 0) { s_i = atomicAdd(task, 1); s_nx = 0; s_nw = 0; }
+        if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
         __syncthreads();
-        const int32_t t = s_i;
-        if (t >= n) break;
+        const int64_t t0 = (int64_t)s_i * chunk;
+        if (t0 >= n) break;
+        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t i = n - 1 - t;
+        const int g = gm.graph(i);
+        block_switch_graph<1>(sc, gcur, g, red, acc, ACC_STRIDE, ids);
+        // tables are indexed by rank relative to the start of i's graph
+        const int32_t gb = gm.begin(g);
+        uint32_t *X = Xt - gb, *Wn = Wt - gb;
         const int32_t oi = off[i], si = split[i], ei = off[i + 1];
         // X(i,b): a in N-(i), b in N+(a), b != i
         for (int32_t base = oi; base < si; base += blockDim.x) {
@@ -256,7 +284,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             });
         }
         __syncthreads();
-        if (s_nx == 0) { __syncthreads(); continue; }
+        if (s_nx == 0) continue;   // s_nw is still zero; the next write of s_nx is behind a barrier
         // Wnt(i,j): c in N(i); all of N(c) when c is before i, else only N+(c)
         for (int32_t base = oi; base < ei; base += blockDim.x) {
             int32_t p = base + threadIdx.x;
@@ -282,7 +310,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
                 int32_t b = tx[base + s];
                 nvis++;
-                sc += (u128)X[b] * Wn[adj[q]];
+                sc[0] += (u128)X[b] * Wn[adj[q]];
             });
         }
         __syncthreads();
@@ -290,17 +318,17 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         const int nw = s_nw;
         for (int q = threadIdx.x; q < nw; q += blockDim.x) Wn[tw[q]] = 0;
         __syncthreads();
+        if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }   // next reads are behind a barrier
+        }
     }
-    const int ids[1] = {AC_CYC};
-    u128 v[1] = {sc};
-    block_flush_u128<1>(v, red, acc, ids);
+    if (gcur >= 0) block_flush_u128<1>(sc, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
 
 // ------------------------------------------------------------------- stages
 
 static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int **task) {
-    size_t per = (size_t)c->n * sizeof(uint32_t);
+    size_t per = (size_t)c->tab_n * sizeof(uint32_t);
     int nwg = pair_wgs(c);
     *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
     *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * 2 * nwg);
@@ -318,16 +346,17 @@ esc_status stage_pairs(esc_ctx *c) {
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
-    // LDS slab for the latest keys, leaving room for the static arrays
+    // LDS slab for the latest keys of a graph, leaving room for the static arrays
     int32_t slab = (c->max_lds - 16384) / 4;
     if (slab > 16384) slab = 16384;
-    if (slab > n) slab = n;
+    if (slab > c->tab_n) slab = c->tab_n;
     if (slab < 0) slab = 0;
     k_pairs_wd<<<pair_wgs(c), 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                           n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
                                           (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], tab, touch,
-                                          task, slab, (unsigned long long *)c->buf[B_ACC],
+                                          c->tab_n, c->task_chunk, gmap_of(c), task, slab,
+                                          (unsigned long long *)c->buf[B_ACC],
                                           (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
@@ -348,8 +377,8 @@ esc_status stage_wheels(esc_ctx *c) {
     size_t lds = sizeof(uint32_t) * 2 * (size_t)lds_cap;
     k_wheels<<<pair_wgs(c), 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
-                                              (const int32_t *)c->buf[B_AV], tab, touch, lds_cap, task + 1,
-                                              (unsigned long long *)c->buf[B_ACC],
+                                              (const int32_t *)c->buf[B_AV], tab, touch, c->tab_n, lds_cap,
+                                              c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],
                                               (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
@@ -365,8 +394,9 @@ esc_status stage_cycles(esc_ctx *c) {
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     int nwg = pair_wgs(c);
     k_five_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
-                                       (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)n * nwg, touch,
-                                       touch + (size_t)n * nwg, task + 2, (unsigned long long *)c->buf[B_ACC],
+                                       (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,
+                                       touch + (size_t)c->tab_n * nwg, c->tab_n, c->task_chunk, gmap_of(c),
+                                       task + 2, (unsigned long long *)c->buf[B_ACC],
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 8);
     HIP_TRY(hipGetLastError());
     return ESC_OK;

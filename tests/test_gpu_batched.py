@@ -1,0 +1,165 @@
+"""Parity of esc_count_batched (many independent graphs in one call) with the
+CPU oracle, graph by graph, and with one-graph calls of the same library.
+
+Exact integer counts: every row must equal the oracle's 45 (or 11) counts.
+"""
+import ctypes
+import random
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1610_09411_amd as esc
+    c = esc.Context(0)
+    yield c
+    c.close()
+
+
+def _special_graphs():
+    fe = synth.from_edges
+    return [
+        fe(0, []), fe(1, []), fe(2, [(0, 1)]), fe(3, [(0, 1), (1, 2), (0, 2)]), fe(4, []),
+        fe(5, [(u, v) for u in range(5) for v in range(u + 1, 5)]),                      # K5
+        fe(7, [(u, v) for u in range(7) for v in range(u + 1, 7)]),                      # K7
+        fe(12, [(0, v) for v in range(1, 12)]),                                          # star
+        fe(9, [(i, (i + 1) % 9) for i in range(9)]),                                     # C9
+        fe(10, [(u, 5 + v) for u in range(5) for v in range(5)]),                        # K5,5
+        fe(30, []),                                                                      # isolated vertices only
+    ]
+
+
+def _mixed_batch(seed, count):
+    """Ragged batch: special cases interleaved with graphs of the batched
+    workload recipe (n log-uniform in [20, 2000], half ER, half Chung-Lu)."""
+    out = []
+    special = _special_graphs()
+    for i, sp in enumerate(synth.batch_specs(count, seed)):
+        out.append(synth.from_spec(sp))
+        if i < len(special):
+            out.append(special[i])
+    return out
+
+
+def _oracle_rows(graphs, k):
+    return [oracle.count(g, k, threads=8) for g in graphs]
+
+
+@pytest.mark.parametrize("k", [5, 4])
+def test_batched_equals_oracle(ctx, k):
+    graphs = _mixed_batch(11, 40)
+    print("batch of", len(graphs), "graphs, sum n", sum(g.n for g in graphs), flush=True)
+    got, ovf = ctx.count_batched(graphs, k)
+    assert got.shape == (len(graphs), 45 if k == 5 else 11)
+    assert not ovf.any()
+    want = _oracle_rows(graphs, k)
+    for g, (row, w) in enumerate(zip(got, want)):
+        assert [int(x) for x in row] == w, (g, graphs[g].name, graphs[g].n)
+
+
+def test_batched_equals_single_calls(ctx):
+    graphs = [synth.from_spec(s) for s in synth.batch_specs(24, 5)]
+    got, _ = ctx.count_batched(graphs, 5)
+    for g, x in enumerate(graphs):
+        assert [int(v) for v in got[g]] == ctx.count(x, 5), (g, x.name)
+
+
+def test_batched_random_order_and_repeat(ctx):
+    import paper_1610_09411_amd as esc
+    graphs = _mixed_batch(3, 20)
+    a, _ = ctx.count_batched(graphs, 5)
+    b, _ = ctx.count_batched(graphs, 5, flags=esc.ESC_F_RANDOM_ORDER)
+    ctx.count_batched(_mixed_batch(4, 7), 5)          # a different batch in between
+    c, _ = ctx.count_batched(graphs, 5, flags=esc.ESC_F_VALIDATE)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+    # a single-graph call in between leaves batched results unchanged
+    ctx.count(synth.er_small(0), 5)
+    d, _ = ctx.count_batched(graphs, 5)
+    assert np.array_equal(a, d)
+
+
+def test_batched_device_input(ctx):
+    import torch
+    import paper_1610_09411_amd as esc
+    graphs = _mixed_batch(8, 12)
+    vo, ao, rp, ci = esc.pack_batch(graphs)
+    host, _ = esc.esc_count_batched(ctx.ptr, vo, ao, rp, ci, 5)
+    dev, _ = esc.esc_count_batched(ctx.ptr, vo, ao, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), 5)
+    assert np.array_equal(host, dev)
+
+
+def test_batched_overflow_flag(ctx):
+    import paper_1610_09411_amd as esc
+    big = synth.from_edges(20000, [])               # C(20000,5) > 2^64 - 1
+    small = synth.from_edges(6, [(0, 1), (1, 2)])
+    got, ovf = ctx.count_batched([small, big, small], 5)
+    assert list(ovf) == [0, 1, 0]
+    assert int(got[1][32]) == comb(20000, 5) % (1 << 64)      # 5-vertex independent sets, low 64 bits
+    assert [int(x) for x in got[0]] == oracle.count(small, 5)
+    # without the flag array the call reports the overflow after writing every row
+    vo, ao, rp, ci = esc.pack_batch([small, big])
+    out = np.zeros((2, 45), dtype=np.uint64)
+    lib = esc._load()
+    st = lib.esc_count_batched(ctx.ptr, 2, vo.ctypes.data_as(ctypes.c_void_p), ao.ctypes.data_as(ctypes.c_void_p),
+                               rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p), 5, 0,
+                               out.ctypes.data_as(ctypes.c_void_p), None, None)
+    assert st == esc.ESC_EOVERFLOW
+    assert [int(x) for x in out[0]] == oracle.count(small, 5)
+
+
+def test_batched_invalid_input(ctx):
+    import paper_1610_09411_amd as esc
+    good = synth.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    vo, ao, rp, ci = esc.pack_batch([good, good])
+    bad = ci.copy()
+    bad[-1] = 4                                        # id outside its own graph
+    with pytest.raises(esc.EscapeError) as e:
+        esc.esc_count_batched(ctx.ptr, vo, ao, rp, bad, 5)
+    assert e.value.status == esc.ESC_ERANGE
+    odd = ao.copy()
+    odd[1] -= 1
+    with pytest.raises(esc.EscapeError) as e:
+        esc.esc_count_batched(ctx.ptr, vo, odd, rp, ci, 5)
+    assert e.value.status in (esc.ESC_ENOTSIMPLE, esc.ESC_ERANGE)
+    shifted = vo.copy()
+    shifted[0] = 1
+    with pytest.raises(esc.EscapeError) as e:
+        esc.esc_count_batched(ctx.ptr, shifted, ao, rp, ci, 5)
+    assert e.value.status == esc.ESC_ERANGE
+    with pytest.raises(esc.EscapeError) as e:
+        esc.esc_count_batched(ctx.ptr, vo, ao, rp, ci, 3)
+    assert e.value.status == esc.ESC_EINVAL
+    empty, _ = esc.esc_count_batched(ctx.ptr, np.zeros(1, np.int64), np.zeros(1, np.int64),
+                                     np.zeros(0, np.int32), np.zeros(0, np.int32), 5)
+    assert empty.shape == (0, 45)
+    # the context still works afterwards
+    got, _ = ctx.count_batched([good], 5)
+    assert [int(x) for x in got[0]] == oracle.count(good, 5)
+
+
+def test_batched_workload_full_size(ctx):
+    """The batched workload at full size (10^4 graphs, n log-uniform in
+    [20, 2000]): every row sums to C(n,4) / C(n,5), and sampled graphs (the
+    largest ones and a random sample) equal the oracle."""
+    specs = synth.batch_specs(10_000, 0)
+    graphs = [synth.from_spec(s) for s in specs]
+    print("full batch: sum n", sum(g.n for g in graphs), "sum m", sum(g.m for g in graphs), flush=True)
+    got, ovf = ctx.count_batched(graphs, 5)
+    assert not ovf.any()
+    for g, x in enumerate(graphs):
+        assert int(got[g][:11].sum(dtype=object)) == comb(x.n, 4), g
+        assert int(got[g][11:].sum(dtype=object)) == comb(x.n, 5), g
+    rng = random.Random(0)
+    sizes = np.array([x.m for x in graphs])
+    sample = list(np.argsort(-sizes)[:4]) + [rng.randrange(len(graphs)) for _ in range(24)]
+    for g in sample:
+        assert [int(v) for v in got[g]] == oracle.count(graphs[g], 5, threads=8), int(g)

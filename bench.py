@@ -39,6 +39,17 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also measure the 10^4-graph batched workload against one graph per launch (0 = skip)")
+    ap.add_argument("--plain-sample", type=int, default=500,
+                    help="graphs of the batched workload timed one graph per launch")
+    ap.add_argument("--serving-rate", type=float, default=200.0,
+                    help="Poisson arrival rate (requests/s) of the serving latency measurement (0 = skip serving)")
+    ap.add_argument("--serving-seconds", type=float, default=4.0)
+    ap.add_argument("--serving-inflight", type=int, default=8)
+    ap.add_argument("--workload", choices=["single", "serving-sweep"], default="single",
+                    help="serving-sweep: only the serving loop, one JSON line per rate in --rates")
+    ap.add_argument("--rates", default="100,200,500,1000,2000,5000")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -58,6 +69,17 @@ def main():
         return
     import synth
     import paper_1610_09411_amd as esc
+
+    if args.workload == "serving-sweep":
+        ctx = esc.Context(0)
+        pool = serving_pool(synth, args.seed)
+        cap = bench_serving_capacity(esc, ctx, pool, args.serving_inflight)
+        print(json.dumps(dict(cap, metric="serving capacity (burst)", n_gpus=1)), flush=True)
+        for rate in [float(x) for x in args.rates.split(",")]:
+            res = bench_serving(esc, ctx, pool, rate, args.serving_seconds, args.serving_inflight, args.seed)
+            print(json.dumps(dict(res, metric="serving latency and throughput", n_gpus=1)), flush=True)
+        ctx.close()
+        return
 
     g = synth.chung_lu_1m(args.seed)
     n, m = g.n, g.m
@@ -104,6 +126,16 @@ def main():
                          "(%.1f s, scaled x%d); estimated whole-job %.0f s"
                          % (setup_s, args.cpu_sample, sampled_s, args.cpu_sample, est)}
 
+    batched = None
+    if args.batched:
+        batched = bench_batched(esc, ctx, synth, torch, stream, args.steps, args.seed, args.plain_sample)
+    serving = None
+    if args.serving_rate > 0:
+        pool = serving_pool(synth, args.seed)
+        serving = bench_serving(esc, ctx, pool, args.serving_rate, args.serving_seconds, args.serving_inflight,
+                                args.seed)
+        serving["capacity"] = bench_serving_capacity(esc, ctx, pool, args.serving_inflight)
+
     line = {
         "metric": "edges/sec for all induced 4+5-vertex counts (bit-exact)",
         "value": value,
@@ -127,10 +159,136 @@ def main():
         "work": work,
         "checksum": {"sum_5": str(sum(counts[11:])), "p8_5cycles": str(counts[11 + 7]),
                      "p21_5cliques": str(counts[31])},
+        "batched": batched,
+        "serving": serving,
     }
     if rank == 0:
         print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def bench_batched(esc, ctx, synth, torch, stream, steps, seed, plain_sample):
+    """The batched workload: 10^4 graphs, n log-uniform in [20, 2000], half
+    Erdos-Renyi (mean degree 4-30), half Chung-Lu (exponent 2.0-2.8), in one
+    esc_count_batched call with the concatenated CSR resident in HBM; against
+    the same graphs one esc_count_subgraphs call each (a sample of them)."""
+    specs = synth.batch_specs(10_000, seed)
+    graphs = [synth.from_spec(x) for x in specs]
+    vo, ao, rp, ci = esc.pack_batch(graphs)
+    rp_d = torch.from_numpy(rp).cuda()
+    ci_d = torch.from_numpy(ci).cuda()
+    esc.esc_count_batched(ctx.ptr, vo, ao, rp_d, ci_d, 5, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rows, ovf = esc.esc_count_batched(ctx.ptr, vo, ao, rp_d, ci_d, 5, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    prof = {k: round(v[0], 3) for k, v in esc.esc_last_profile(ctx.ptr).items()}
+    sums_ok = all(int(rows[i][11:].sum(dtype=object)) == _comb5(graphs[i].n) for i in range(len(graphs)))
+    sample = graphs[:plain_sample]
+    dev = [(x.n, torch.from_numpy(x.row_ptr).cuda(), torch.from_numpy(x.col).cuda()) for x in sample]
+    esc.esc_count_subgraphs(ctx.ptr, dev[0][0], dev[0][1], dev[0][2], 5, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_rows = [esc.esc_count_subgraphs(ctx.ptr, n, r, c, 5, stream=stream) for n, r, c in dev]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = all([int(v) for v in rows[i]] == plain_rows[i] for i in range(len(sample)))
+    m_total = int(ao[-1]) // 2
+    return {"workload": "batched: 10000 graphs, n log-uniform [20,2000], half ER mean degree 4-30, "
+                        "half Chung-Lu exponent 2.0-2.8, seed %d" % seed,
+            "graphs": len(graphs), "sum_n": int(vo[-1]), "sum_m": m_total,
+            "graphs_per_s": len(graphs) / t_batch, "edges_per_s": m_total / t_batch, "ms_per_batch": t_batch * 1e3,
+            "stages_ms": prof,
+            "plain_graphs_per_s": len(sample) / t_plain, "plain_sample": len(sample),
+            "speedup_vs_plain": (len(graphs) / t_batch) / (len(sample) / t_plain),
+            "rows_sum_to_C(n,5)": sums_ok, "sample_equal_to_plain": same}
+
+
+def _comb5(n):
+    from math import comb
+    return comb(n, 5)
+
+
+def serving_pool(synth, seed, size=400):
+    """Request graphs: Chung-Lu, n log-uniform in [50, 50000], exponent
+    2.0-2.5, mean degree 8-32; arrivals draw from this pool."""
+    return [synth.from_spec(x) for x in synth.request_specs(size, seed)]
+
+
+def bench_serving_capacity(esc, ctx, pool, inflight, count=2000):
+    """Saturated throughput: `count` requests submitted at once."""
+    srv = esc.Server(ctx, max_inflight=inflight)
+    for t in [srv.submit(g, 5) for g in pool[:16]]:
+        srv.wait(t)
+    st0 = srv.stats()
+    t0 = time.perf_counter()
+    tickets = [srv.submit(pool[i % len(pool)], 5) for i in range(count)]
+    for t in tickets:
+        srv.wait(t)
+    t1 = time.perf_counter()
+    st = srv.stats()
+    srv.stop()
+    edges = sum(pool[i % len(pool)].m for i in range(count))
+    return {"requests": count, "graphs_per_s": count / (t1 - t0), "edges_per_s": edges / (t1 - t0),
+            "launches": st["launches"] - st0["launches"], "peak_inflight": st["peak_inflight"]}
+
+
+def bench_serving(esc, ctx, pool, rate, seconds, inflight, seed):
+    """Poisson arrivals at `rate` for `seconds`; latency = submit to result,
+    measured by the server; throughput = completed requests / elapsed."""
+    import random
+    import threading
+    rng = random.Random(seed)
+    srv = esc.Server(ctx, max_inflight=inflight)
+    for t in [srv.submit(g, 5) for g in pool[:16]]:     # warm the worker contexts
+        srv.wait(t)
+    st0 = srv.stats()
+    tickets = []
+    lat = []
+    done_evt = threading.Event()
+
+    def collect():
+        i = 0
+        while True:
+            if i < len(tickets):
+                lat.append(srv.wait(tickets[i])[1])
+                i += 1
+            elif done_evt.is_set():
+                break
+            else:
+                time.sleep(0.0005)
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    nxt = t0
+    edges = 0
+    while True:
+        nxt += rng.expovariate(rate)
+        if nxt - t0 > seconds:
+            break
+        d = nxt - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        g = pool[rng.randrange(len(pool))]
+        tickets.append(srv.submit(g, 5))
+        edges += g.m
+    done_evt.set()
+    th.join()
+    t1 = time.perf_counter()
+    st = srv.stats()
+    srv.stop()
+    lat.sort()
+    q = lambda p: lat[min(len(lat) - 1, int(p * len(lat)))] * 1e3 if lat else None
+    return {"workload": "serving: Chung-Lu requests, n log-uniform [50,50000], exponent 2.0-2.5, mean degree 8-32 "
+                        "(pool of %d graphs), Poisson arrivals" % len(pool),
+            "rate_req_s": rate, "seconds": seconds, "requests": len(tickets),
+            "graphs_per_s": len(tickets) / (t1 - t0), "edges_per_s": edges / (t1 - t0),
+            "p50_ms": q(0.50), "p99_ms": q(0.99), "max_inflight": inflight,
+            "launches": st["launches"] - st0["launches"],
+            "batched_requests": st["batched_requests"] - st0["batched_requests"],
+            "peak_inflight": st["peak_inflight"]}
 
 
 if __name__ == "__main__":

@@ -143,7 +143,7 @@ esc_status esc_count_batched(esc_ctx *ctx, int32_t G, const int64_t *vtx_off,
  * A request loop over the same method: jobs of any size arrive while others
  * run.  The server owns max_inflight contexts (one stream and one set of
  * device buffers each) and a worker thread per context.  A free worker takes
- * the oldest queued request and, if it has at most 20000 vertices, the
+ * the oldest queued request and, if it has at most 2^20 vertices, the
  * following queued requests of the same k up to 256 in all, and runs them as
  * one batched launch (esc_count_batched's pipeline); larger requests run
  * alone.  A launch starts only when its estimated device footprint (CSR and

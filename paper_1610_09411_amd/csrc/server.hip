@@ -160,6 +160,17 @@ void worker(esc_server *s, esc_ctx *c) {
                 est = e2;
             }
         }
+        if (grp.size() == 1 && est > s->budget) {
+            // cannot fit even alone: fail it without holding up the queue
+            Req *r = grp[0];
+            s->queue.pop_front();
+            r->status = ESC_ENOMEM;
+            r->t_done = now_s();
+            r->done = true;
+            s->completed++;
+            s->cv_done.notify_all();
+            continue;
+        }
         if (s->reserved > 0 && s->reserved + est > s->budget) {
             s->cv.wait(lk);   // until a launch in flight releases its memory
             continue;
@@ -171,8 +182,7 @@ void worker(esc_server *s, esc_ctx *c) {
         if (s->reserved > s->peak_reserved) s->peak_reserved = s->reserved;
         s->launches++;
         lk.unlock();
-        if (grp.size() == 1 && est > s->budget) grp[0]->status = ESC_ENOMEM;   // cannot fit even alone
-        else run_group(s, c, grp);
+        run_group(s, c, grp);
         const double t = now_s();
         lk.lock();
         s->reserved -= est;
@@ -205,7 +215,7 @@ extern "C" esc_status esc_server_start(esc_ctx *ctx, int max_inflight, esc_serve
     if (!s) return ESC_ENOMEM;
     s->device = ctx->device;
     s->nwg = pair_wgs(ctx);
-    s->small_n = 20000;
+    s->small_n = 1 << 20;
     s->max_group = 256;
     size_t budget = ctx->budget;
     if (budget == 0) {

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
-#include "../../include/escape.h"
+#include "escape.h"
 
 // Indices of the exact 128-bit sums produced on the device.  Each stage adds
 // its terms into acc[2*slot] (lo) / acc[2*slot+1] (hi).

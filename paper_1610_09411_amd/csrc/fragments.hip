@@ -136,31 +136,31 @@ esc_status stage_triangles(esc_ctx *c) {
 // ------------------------------------------------------------------ 4-cycles
 
 // One workgroup per top vertex h (latest vertex of the 4-cycle), taken from a
-// shared counter, heaviest (latest) vertices first.  A dense per-workgroup
-// table over all vertices accumulates, for every o before h, c(h,o) = number
-// of middles k (k before h, adjacent to h and o), plus the sums over those
-// middles of t(hk)+t(ko) and of d(k).  Then every (h,o) pair contributes
-//   C(c,2)                                    4-cycles
-//   (c-1) * sum_k [t(hk) + t(ko)]             to sum_e C4(e) t(e)
-//   (c-1) * sum_k [d(h)+2d(k)+d(o)-8]         to sum_e C4(e)(d(u)+d(v)-4)
-// With per_edge set, a second pass also adds c-1 to C4 of edges hk and ko.
+// shared counter, latest vertices first.  For every o before h the table
+// holds c(h,o) = number of middles k (k before h, adjacent to h and o).
+// Pass 1 counts, pass 2 revisits the wedges and reads c, pass 3 walks the
+// touched keys:
+//   C(c,2)                                       4-cycles
+//   (c-1) * [t(hk) + t(ko)]   per wedge          sum_e C4(e) t(e)
+//   (c-1) * (2 d(k) - 4)      per wedge   } sum_e C4(e)(d(u)+d(v)-4)
+//   (c-1) * c * (d(h) + d(o) - 4)  per key }
+// With per_edge set, pass 2 also adds c-1 to C4 of edges hk and ko.
+// Keys in the latest `slab` ranks of h's graph are counted in LDS, the rest
+// in the workgroup's dense table (relative to the graph's first rank).
 __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, const int32_t *rev,
                                                      const int32_t *arc_eid, const uint32_t *tarc,
-                                                     uint32_t *tab_c, int32_t *touch_all, int32_t tab_n,
-                                                     int chunk, GMap gm, int *task, unsigned long long *acc,
-                                                     unsigned long long *c4e, unsigned long long *visits) {
+                                                     uint32_t *tab_all, int32_t *touch_all, int32_t tab_n,
+                                                     int chunk, GMap gm, int *task, int32_t slab,
+                                                     unsigned long long *acc, unsigned long long *c4e,
+                                                     unsigned long long *visits) {
+    extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_h, s_nt;
     __shared__ u128 red[3 * 8];
-    // the three counters of a key sit side by side (one cache line per key);
-    // keys are ranks relative to the first rank of the source's graph
-    uint32_t *tab3 = tab_c + (size_t)blockIdx.x * 3 * tab_n;
-#define CNT(o) tab3[3 * (size_t)((o) - gb)]
-#define FT(o) tab3[3 * (size_t)((o) - gb) + 1]
-#define FK(o) tab3[3 * (size_t)((o) - gb) + 2]
+    uint32_t *Ct = tab_all + (size_t)blockIdx.x * tab_n;
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
     const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
     u128 sums[3] = {0, 0, 0};
@@ -173,63 +173,66 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
         if (t0 >= n) break;
         const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {
-        const int32_t h = n - 1 - t;
-        const int g = gm.graph(h);
-        block_switch_graph<3>(sums, gcur, g, red, acc, ACC_STRIDE, ids);
-        const int32_t gb = gm.begin(g);
-        const int32_t oh = off[h], sh = split[h];
-        // wedges h - k - o with k, o before h: k in N-(h), o in the prefix of N(k) below h
-        for (int32_t base = oh; base < sh; base += blockDim.x) {
-            int32_t p = base + threadIdx.x;
-            int start = 0, len = 0;
-            if (p < sh) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
-            lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
-                int32_t pk = base + s;
-                int32_t k = adj[pk];
-                int32_t o = adj[q];
-                uint32_t old = atomicAdd(&CNT(o), 1u);
-                nvis++;
-                if (old == 0) touch[atomicAdd(&s_nt, 1)] = o;
-                atomicAdd(&FT(o), tarc[pk] + tarc[q]);
-                atomicAdd(&FK(o), (uint32_t)(off[k + 1] - off[k]));
-            });
-        }
-        __syncthreads();
-        const int nt = s_nt;
-        const int64_t dh = off[h + 1] - oh;
-        if (c4e) {
+            const int32_t h = n - 1 - t;
+            const int g = gm.graph(h);
+            block_switch_graph<3>(sums, gcur, g, red, acc, ACC_STRIDE, ids);
+            const int32_t gb = gm.begin(g), ge = gm.end(g);
+            const int32_t hi0 = ge - slab > gb ? ge - slab : gb;   // first key held in LDS
+            const int32_t nsl = h > hi0 ? h - hi0 : 0;
+            uint32_t *C = Ct - gb;
+            const int32_t oh = off[h], sh = split[h];
+            const int64_t dh = off[h + 1] - oh;
+            for (int q = threadIdx.x; q < nsl; q += blockDim.x) sl[q] = 0;
+            __syncthreads();
+            // pass 1: wedges h - k - o, k in N-(h), o in the prefix of N(k) below h
+            for (int32_t base = oh; base < sh; base += blockDim.x) {
+                int32_t p = base + threadIdx.x;
+                int start = 0, len = 0;
+                if (p < sh) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
+                lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
+                    const int32_t o = adj[q];
+                    nvis++;
+                    if (o >= hi0) atomicAdd(&sl[o - hi0], 1u);
+                    else if (atomicAdd(&C[o], 1u) == 0) touch[atomicAdd(&s_nt, 1)] = o;
+                });
+            }
+            __syncthreads();
+            // pass 2: per-wedge terms
             for (int32_t base = oh; base < sh; base += blockDim.x) {
                 int32_t p = base + threadIdx.x;
                 int start = 0, len = 0;
                 if (p < sh) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
                 lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
-                    int32_t pk = base + s;
-                    uint32_t cc = CNT(adj[q]);
+                    const int32_t pk = base + s;
+                    const int32_t o = adj[q];
+                    const uint32_t cc = o >= hi0 ? sl[o - hi0] : C[o];
                     if (cc >= 2) {
-                        atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
-                        atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
+                        const int32_t k = adj[pk];
+                        sums[1] += (uint64_t)(cc - 1) * (tarc[pk] + tarc[q]);
+                        sums[2] += (uint64_t)(cc - 1) * (uint64_t)(2 * (off[k + 1] - off[k]) - 4);
+                        if (c4e) {
+                            atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
+                            atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
+                        }
                     }
                 });
             }
-        }
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-            int32_t o = touch[i];
-            uint64_t cc = CNT(o);
-            if (cc >= 2) {
-                int64_t dsum = (int64_t)cc * (dh + (off[o + 1] - off[o]) - 8) + 2 * (int64_t)FK(o);
-                sums[0] += c2(cc);
-                sums[1] += (u128)(cc - 1) * FT(o);
-                sums[2] += (u128)(cc - 1) * (uint64_t)dsum;
+            // pass 3: per-key terms, tables back to zero
+            const int nt = s_nt;
+            for (int i = threadIdx.x; i < nt + nsl; i += blockDim.x) {
+                int32_t o;
+                uint64_t cc;
+                if (i < nt) { o = touch[i]; cc = C[o]; C[o] = 0; }
+                else { o = hi0 + (i - nt); cc = sl[i - nt]; }
+                if (cc >= 2) {
+                    sums[0] += c2(cc);
+                    sums[2] += (u128)(cc - 1) * cc * (uint64_t)(dh + (off[o + 1] - off[o]) - 4);
+                }
             }
-            CNT(o) = 0; FT(o) = 0; FK(o) = 0;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) s_nt = 0;   // next read of s_nt is behind a barrier
+            __syncthreads();
+            if (threadIdx.x == 0) s_nt = 0;   // next read of s_nt is behind a barrier
         }
     }
-#undef CNT
-#undef FT
-#undef FK
     if (gcur >= 0) block_flush_u128<3>(sums, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
@@ -251,10 +254,16 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
         if (!c4e) return ESC_ENOMEM;
         HIP_TRY(hipMemsetAsync(c4e, 0, sizeof(uint64_t) * (size_t)(c->m + 1), st));
     }
-    k_four_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    // LDS slab for the latest keys of a graph, leaving room for the static arrays
+    int32_t slab = (c->max_lds - 16384) / 4;
+    if (slab > 16384) slab = 16384;
+    if (slab > c->tab_n) slab = c->tab_n;
+    if (slab < 0) slab = 0;
+    k_four_cycles<<<nwg, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
+                                       n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
                                        (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
-                                       tab, touch, c->tab_n, c->task_chunk, gmap_of(c), task,
+                                       tab, touch, c->tab_n, c->task_chunk, gmap_of(c), task, slab,
                                        (unsigned long long *)c->buf[B_ACC], c4e,
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
     HIP_TRY(hipGetLastError());

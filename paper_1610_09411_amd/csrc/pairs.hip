@@ -1,7 +1,7 @@
 // Pair-level sums (Thm 5cutwed with the algorithm of Thm 5formula) and
 // 5-cycles (Thm 5cycle).
 //
-//  * pattern 13 and 17: for every source i and every j before i,
+//  * pattern 13 and 17: for every source i and every j after i,
 //      W(i,j) = common neighbours (2-step search from i),
 //      D(i,j) = edges inside the common neighbourhood, generated from a
 //               triangle (i,k,l) followed by a triangle (k,l,j);
@@ -16,17 +16,20 @@
 //      sum_b X(i,b) * sum_{j in N+(b)} Wnt(i,j),   X(i,b) = |N-(i) & N-(b)|,
 //    which visits each distinct (i,b) once instead of every 3-path.
 //
-// Every per-source table is a dense per-workgroup array over all vertices,
-// reset through a list of touched keys.
+// Every per-source table is a dense per-workgroup array over the ranks of
+// the source's graph, reset through a list of touched keys.
 #include "device.h"
 #include "ctx.h"
 
 // ------------------------------------------------------- patterns 13 and 17
 //
-// Keys j in the top `slab` ranks [n - slab, n) are counted in an LDS array:
-// the latest sources (hubs) carry almost all diamonds, and the tips of their
-// diamonds are mostly other hubs, so the diamond gathers stay in LDS.  Lower
-// keys use the workgroup's dense global table.
+// Every unordered pair {i, j} is taken from its earlier vertex i (the source)
+// and keyed by the later one, j > i: the later endpoint of a wedge is a hub
+// far more often than the earlier one, so most keys fall in the latest ranks.
+// Keys in the latest `slab` ranks of the graph are counted in an LDS array,
+// the rest in the workgroup's dense table (relative to the graph's start).
+// The tips of diamonds are mostly hubs as well, so the diamond gathers stay
+// in LDS too.
 
 __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off, const int32_t *adj,
                                                   const int32_t *rev, const int64_t *aoff, const uint32_t *aa,
@@ -55,20 +58,18 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         const int32_t i = n - 1 - t;
         const int g = gm.graph(i);
         block_switch_graph<2>(sv, gcur, g, red, acc, ACC_STRIDE, ids);
-        // keys are ranks of the source's graph: the latest `slab` of them sit
-        // in LDS, the rest in the workgroup's table, relative to the graph's start
         const int32_t gb = gm.begin(g), ge = gm.end(g);
         const int32_t hi0 = ge - slab > gb ? ge - slab : gb;   // first key held in LDS
         uint32_t *W = Wt - gb;
         const int32_t oi = off[i], ei = off[i + 1];
-        const int32_t nsl = i > hi0 ? i - hi0 : 0;   // LDS keys [hi0, i)
-        for (int q = threadIdx.x; q < nsl; q += blockDim.x) sl[q] = 0;
+        const int32_t ls = i + 1 > hi0 ? i + 1 : hi0;          // LDS keys [ls, ge)
+        for (int q = ls - hi0 + threadIdx.x; q < ge - hi0; q += blockDim.x) sl[q] = 0;
         __syncthreads();
-        // W(i,j) for j before i: k in N(i), j in the prefix of N(k) below i
+        // W(i,j) for j after i: k in N(i), j in the suffix of N(k) after i
         for (int32_t base = oi; base < ei; base += blockDim.x) {
             int32_t p = base + threadIdx.x;
             int start = 0, len = 0;
-            if (p < ei) { int32_t k = adj[p]; start = off[k]; len = rev[p] - off[k]; }
+            if (p < ei) { int32_t k = adj[p]; start = rev[p] + 1; len = off[k + 1] - start; }
             lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
                 int32_t j = adj[q];
                 nvis++;
@@ -77,18 +78,18 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             });
         }
         __syncthreads();
-        // diamonds with tips i and j (j before i): triangles (i,k,l), k<l, then
-        // apexes j of edge (k,l) below i.  Each wave takes arcs (i,k); for
+        // diamonds with tips i and j (j after i): triangles (i,k,l), k<l, then
+        // apexes j of edge (k,l) after i.  Each wave takes arcs (i,k); for
         // every entry l of the arc's triangle list the lanes stride over the
-        // prefix of the list of (k,l) below i.
+        // suffix of the list of (k,l) after i.
         {
             const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
             for (int32_t pk = oi + wid; pk < ei; pk += nw) {
                 const int32_t k = adj[pk];
                 const int64_t e0 = aoff[pk], e1 = aoff[pk + 1];
                 const int64_t r0 = aoff[rev[pk]];
-                // 64 entries at a time: each lane finds one segment (the prefix
-                // of the list of (k,l) below i), then the wave walks them
+                // 64 entries at a time: each lane finds one segment (the suffix
+                // of the list of (k,l) after i), then the wave walks them
                 for (int64_t xb = e0; xb < e1; xb += 64) {
                     const int64_t x = xb + lane;
                     int64_t a0 = 0, a1 = 0;
@@ -96,10 +97,10 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                         const int32_t l = av[x];
                         if (l > k) {
                             const int32_t qkl = (int32_t)aa[r0 + (x - e0)];   // arc (k,l) in row k
-                            a0 = aoff[qkl];
-                            int64_t lo2 = a0, hi2 = aoff[qkl + 1];
-                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
-                            a1 = lo2;
+                            int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
+                            a1 = hi2;
+                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] <= i) lo2 = mid + 1; else hi2 = mid; }
+                            a0 = lo2;
                         }
                     }
                     nvis += (uint64_t)(a1 - a0);
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             sv[0] += c3(W[j]);
             W[j] = 0;
         }
-        for (int q = threadIdx.x; q < nsl; q += blockDim.x) sv[0] += c3(sl[q]);
+        for (int q = ls - hi0 + threadIdx.x; q < ge - hi0; q += blockDim.x) sv[0] += c3(sl[q]);
         __syncthreads();
         if (threadIdx.x == 0) s_nt = 0;   // next read of s_nt is behind a barrier
         }

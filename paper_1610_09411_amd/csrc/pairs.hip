@@ -241,11 +241,16 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
 
 // ---------------------------------------------------------------- 5-cycles
 
+// Keys in the latest `slab` ranks of the graph (mostly hubs: X keys are
+// out-neighbours, the 3-path ends j are out-neighbours of them) use two LDS
+// arrays, one for X and one for Wnt; the rest use the workgroup's tables.
+// Both are reset through the touched-key lists.
 __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, uint32_t *tabX_all, uint32_t *tabW_all,
                                                      int32_t *touchX_all, int32_t *touchW_all, int32_t tab_n,
-                                                     int chunk, GMap gm, int *task, unsigned long long *acc,
-                                                     unsigned long long *visits) {
+                                                     int chunk, GMap gm, int *task, int32_t slab,
+                                                     unsigned long long *acc, unsigned long long *visits) {
+    extern __shared__ uint32_t dyn[];   // [0, slab) X, [slab, 2 slab) Wnt
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
@@ -256,8 +261,10 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     uint32_t *Wt = tabW_all + (size_t)blockIdx.x * tab_n;
     int32_t *tx = touchX_all + (size_t)blockIdx.x * tab_n;
     int32_t *tw = touchW_all + (size_t)blockIdx.x * tab_n;
+    uint32_t *sX = dyn, *sW = dyn + slab;
     u128 sc[1] = {0};
     int gcur = -1;
+    for (int q = threadIdx.x; q < 2 * slab; q += blockDim.x) dyn[q] = 0;
     if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }
     for (;;) {
         if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
@@ -270,7 +277,8 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         const int g = gm.graph(i);
         block_switch_graph<1>(sc, gcur, g, red, acc, ACC_STRIDE, ids);
         // tables are indexed by rank relative to the start of i's graph
-        const int32_t gb = gm.begin(g);
+        const int32_t gb = gm.begin(g), ge = gm.end(g);
+        const int32_t hi0 = ge - slab > gb ? ge - slab : gb;   // first key held in LDS
         uint32_t *X = Xt - gb, *Wn = Wt - gb;
         const int32_t oi = off[i], si = split[i], ei = off[i + 1];
         // X(i,b): a in N-(i), b in N+(a), b != i
@@ -281,7 +289,9 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
                 int32_t b = adj[q];
                 nvis++;
-                if (b != i && atomicAdd(&X[b], 1u) == 0) tx[atomicAdd(&s_nx, 1)] = b;
+                if (b == i) return;
+                const uint32_t old = b >= hi0 ? atomicAdd(&sX[b - hi0], 1u) : atomicAdd(&X[b], 1u);
+                if (old == 0) tx[atomicAdd(&s_nx, 1)] = b;
             });
         }
         __syncthreads();
@@ -298,7 +308,9 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
                 int32_t j = adj[q];
                 nvis++;
-                if (j != i && atomicAdd(&Wn[j], 1u) == 0) tw[atomicAdd(&s_nw, 1)] = j;
+                if (j == i) return;
+                const uint32_t old = j >= hi0 ? atomicAdd(&sW[j - hi0], 1u) : atomicAdd(&Wn[j], 1u);
+                if (old == 0) tw[atomicAdd(&s_nw, 1)] = j;
             });
         }
         __syncthreads();
@@ -309,15 +321,24 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             int start = 0, len = 0;
             if (xi < nx) { int32_t b = tx[xi]; start = split[b]; len = off[b + 1] - split[b]; }
             lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
-                int32_t b = tx[base + s];
+                const int32_t b = tx[base + s];
+                const int32_t j = adj[q];
                 nvis++;
-                sc[0] += (u128)X[b] * Wn[adj[q]];
+                const uint32_t xb = b >= hi0 ? sX[b - hi0] : X[b];
+                const uint32_t wj = j >= hi0 ? sW[j - hi0] : Wn[j];
+                sc[0] += (uint64_t)xb * wj;
             });
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < nx; q += blockDim.x) X[tx[q]] = 0;
+        for (int q = threadIdx.x; q < nx; q += blockDim.x) {
+            const int32_t b = tx[q];
+            if (b >= hi0) sX[b - hi0] = 0; else X[b] = 0;
+        }
         const int nw = s_nw;
-        for (int q = threadIdx.x; q < nw; q += blockDim.x) Wn[tw[q]] = 0;
+        for (int q = threadIdx.x; q < nw; q += blockDim.x) {
+            const int32_t j = tw[q];
+            if (j >= hi0) sW[j - hi0] = 0; else Wn[j] = 0;
+        }
         __syncthreads();
         if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }   // next reads are behind a barrier
         }
@@ -394,10 +415,16 @@ esc_status stage_cycles(esc_ctx *c) {
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     int nwg = pair_wgs(c);
-    k_five_cycles<<<nwg, 512, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays
+    int32_t slab = (c->max_lds - 16384) / 8;
+    if (slab > 8192) slab = 8192;
+    if (slab > c->tab_n) slab = c->tab_n;
+    if (slab < 0) slab = 0;
+    k_five_cycles<<<nwg, 512, sizeof(uint32_t) * (size_t)(2 * slab > 0 ? 2 * slab : 1), st>>>(
+                                       n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,
                                        touch + (size_t)c->tab_n * nwg, c->tab_n, c->task_chunk, gmap_of(c),
-                                       task + 2, (unsigned long long *)c->buf[B_ACC],
+                                       task + 2, slab, (unsigned long long *)c->buf[B_ACC],
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 8);
     HIP_TRY(hipGetLastError());
     return ESC_OK;

@@ -19,12 +19,6 @@
 #include "device.h"
 #include "ctx.h"
 
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 #define BM_WORDS 512   // LDS bitmap per wave: rows of up to 16384 vertices
 
 static int grid_cap(esc_ctx *c, int64_t items, int threads, int per_cu = 16) {

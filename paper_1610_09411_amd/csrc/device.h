@@ -163,6 +163,57 @@ __device__ inline void flush_count(uint64_t x, unsigned long long *dst) {
     if ((threadIdx.x & (ESC_WAVE - 1)) == 0 && x) atomicAdd(dst, (unsigned long long)x);
 }
 
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Walk the concatenation of up to 64 segments held one per lane (lane y
+// holds segment y = [a0, a1)), 64 consecutive elements per step, so that one
+// step spans as many short segments as it needs; four steps are issued
+// before their results are used.  load(pos) reads the element at position
+// pos, use(value) consumes it.  sa/se/si are 64-entry LDS arrays private to
+// the calling wave (the segments of one call hold fewer than 2^31 elements
+// in all).  Every lane of the wave must call it.
+template <class L, class U>
+__device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
+    const int lane = threadIdx.x & (ESC_WAVE - 1);
+    const int32_t len = (int32_t)(a1 - a0);
+    int32_t incl = len;
+    for (int o = 1; o < ESC_WAVE; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int32_t total = __shfl(incl, ESC_WAVE - 1);
+    sa[lane] = a0;
+    se[lane] = incl - len;
+    si[lane] = incl;
+    wave_sync();
+    int y = 0;
+    int32_t e = lane;
+    for (; e + 3 * ESC_WAVE < total; e += 4 * ESC_WAVE) {
+        while (si[y] <= e) y++;
+        const int64_t q0 = sa[y] + (e - se[y]);
+        while (si[y] <= e + ESC_WAVE) y++;
+        const int64_t q1 = sa[y] + (e + ESC_WAVE - se[y]);
+        while (si[y] <= e + 2 * ESC_WAVE) y++;
+        const int64_t q2 = sa[y] + (e + 2 * ESC_WAVE - se[y]);
+        while (si[y] <= e + 3 * ESC_WAVE) y++;
+        const int64_t q3 = sa[y] + (e + 3 * ESC_WAVE - se[y]);
+        const auto v0 = load(q0), v1 = load(q1), v2 = load(q2), v3 = load(q3);
+        use(v0);
+        use(v1);
+        use(v2);
+        use(v3);
+    }
+    for (; e < total; e += ESC_WAVE) {
+        while (si[y] <= e) y++;
+        use(load(sa[y] + (e - se[y])));
+    }
+    wave_sync();   // the arrays are reused by the next call
+}
+
 __device__ inline uint64_t c2(uint64_t x) { return x < 2 ? 0 : x * (x - 1) / 2; }
 __device__ inline u128 c3(uint64_t x) { return x < 3 ? 0 : (u128)x * (x - 1) * (x - 2) / 6; }
 __device__ inline u128 c4(uint64_t x) { return x < 4 ? 0 : (u128)x * (x - 1) * (x - 2) / 6 * (x - 3) / 4; }

@@ -42,6 +42,8 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
     __shared__ int64_t beg[513];
     __shared__ int s_i, s_nt;
     __shared__ u128 red[2 * 8];
+    __shared__ int64_t wsa[8][64];
+    __shared__ int32_t wse[8][64], wsi[8][64];
     const int ids[2] = {AC_N13, AC_N17};
     uint32_t *Wt = tab_all + (size_t)blockIdx.x * tab_n;
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
@@ -104,24 +106,10 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                         }
                     }
                     nvis += (uint64_t)(a1 - a0);
-                    const int cnt = (int)((e1 - xb) < 64 ? (e1 - xb) : 64);
                     uint64_t acc17 = 0;
-                    for (int y = 0; y < cnt; y++) {
-                        const int64_t b0 = __shfl(a0, y), b1 = __shfl(a1, y);
-                        int64_t q = b0 + lane;
-                        for (; q + 192 < b1; q += 256) {   // four loads in flight per lane
-                            const int32_t j0 = av[q], j1 = av[q + 64], j2 = av[q + 128], j3 = av[q + 192];
-                            const uint32_t w0 = j0 >= hi0 ? sl[j0 - hi0] : W[j0];
-                            const uint32_t w1 = j1 >= hi0 ? sl[j1 - hi0] : W[j1];
-                            const uint32_t w2 = j2 >= hi0 ? sl[j2 - hi0] : W[j2];
-                            const uint32_t w3 = j3 >= hi0 ? sl[j3 - hi0] : W[j3];
-                            acc17 += (uint64_t)w0 + w1 + w2 + w3 - 8;
-                        }
-                        for (; q < b1; q += 64) {
-                            const int32_t j = av[q];
-                            acc17 += (uint64_t)(j >= hi0 ? sl[j - hi0] : W[j]) - 2;
-                        }
-                    }
+                    wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid],
+                              [&](int64_t q) { return av[q]; },
+                              [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? sl[j - hi0] : W[j]) - 2; });
                     sv[1] += acc17;
                 }
             }
@@ -147,7 +135,10 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // One workgroup per hub h.  For each neighbour i of h (latest rim vertex):
 // l runs over the triangle list of arc (h,i) below i, j over the triangle
 // list of arc (h,l) below i; key = position of j in the row of h.  The table
-// lives in LDS when d(h) fits, else in the workgroup's global scratch.
+// lives in LDS when d(h) fits, else in the workgroup's global scratch.  In
+// LDS a count is below d(h) <= lds_cap < 2^16, so two counts share a word
+// (16 bits each; one 32-bit atomic adds 1 << 16 for odd keys) and the
+// touched keys are 16-bit.
 __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
@@ -159,6 +150,8 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
     __shared__ int64_t beg[257];
     __shared__ int s_h, s_nt;
     __shared__ u128 red[4];
+    __shared__ int64_t wsa[4][64];
+    __shared__ int32_t wse[4][64], wsi[4][64];
     const int ids[1] = {AC_N18};
     u128 s18[1] = {0};
     int gcur = -1;
@@ -174,10 +167,12 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
         block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
         const int32_t oh = off[h], dh = off[h + 1] - oh;
         const bool in_lds = dh <= lds_cap;
-        uint32_t *cnt_ = in_lds ? dyn : gtab_all + (size_t)blockIdx.x * tab_n;
-        int32_t *tch = in_lds ? (int32_t *)(dyn + lds_cap) : gtouch_all + (size_t)blockIdx.x * tab_n;
+        uint32_t *gcnt = gtab_all + (size_t)blockIdx.x * tab_n;
+        int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
+        uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
+        uint16_t *ltch = (uint16_t *)(dyn + (lds_cap + 1) / 2);      // lds_cap keys
         if (in_lds)
-            for (int q = threadIdx.x; q < dh; q += blockDim.x) cnt_[q] = 0;
+            for (int q = threadIdx.x; q < (dh + 1) / 2; q += blockDim.x) lcnt[q] = 0;
         __syncthreads();
         for (int32_t pi = oh; pi < oh + dh; pi++) {
             const int32_t i = adj[pi];
@@ -205,31 +200,35 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
                         b1 = lo2;
                     }
                     nvis += (uint64_t)(b1 - b0);
-                    const int cnt = (nl - xb) < 64 ? (nl - xb) : 64;
-                    for (int y = 0; y < cnt; y++) {
-                        const int64_t c0 = __shfl(b0, y), c1 = __shfl(b1, y);
-                        int64_t q = c0 + lane;
-                        for (; q + 192 < c1; q += 256) {   // four loads in flight per lane
-                            const int32_t k0 = (int32_t)aa[q] - oh, k1 = (int32_t)aa[q + 64] - oh;
-                            const int32_t k2 = (int32_t)aa[q + 128] - oh, k3 = (int32_t)aa[q + 192] - oh;
-                            if (atomicAdd(&cnt_[k0], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k0;
-                            if (atomicAdd(&cnt_[k1], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k1;
-                            if (atomicAdd(&cnt_[k2], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k2;
-                            if (atomicAdd(&cnt_[k3], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = k3;
-                        }
-                        for (; q < c1; q += 64) {
-                            const int32_t key = (int32_t)aa[q] - oh;
-                            if (atomicAdd(&cnt_[key], 1u) == 0) tch[atomicAdd(&s_nt, 1)] = key;
-                        }
-                    }
+                    if (in_lds)
+                        wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                                  [&](int32_t key) {
+                                      const uint32_t sh = (uint32_t)(key & 1) << 4;
+                                      const uint32_t old = atomicAdd(&lcnt[key >> 1], 1u << sh);
+                                      if (((old >> sh) & 0xFFFFu) == 0) ltch[atomicAdd(&s_nt, 1)] = (uint16_t)key;
+                                  });
+                    else
+                        wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                                  [&](int32_t key) {
+                                      if (atomicAdd(&gcnt[key], 1u) == 0) gtch[atomicAdd(&s_nt, 1)] = key;
+                                  });
                 }
             }
             __syncthreads();
             const int nt = s_nt;
             for (int q = threadIdx.x; q < nt; q += blockDim.x) {
-                int32_t key = tch[q];
-                s18[0] += c2(cnt_[key]);
-                cnt_[key] = 0;
+                if (in_lds) {
+                    const int32_t key = ltch[q];
+                    const uint32_t sh = (uint32_t)(key & 1) << 4;
+                    const uint32_t old = atomicAnd(&lcnt[key >> 1], ~(0xFFFFu << sh));   // the other half may be reset concurrently
+                    s18[0] += c2((old >> sh) & 0xFFFFu);
+                } else {
+                    const int32_t key = gtch[q];
+                    s18[0] += c2(gcnt[key]);
+                    gcnt[key] = 0;
+                }
             }
             __syncthreads();
         }
@@ -392,11 +391,12 @@ esc_status stage_wheels(esc_ctx *c) {
     int32_t *touch;
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
-    // table + touched list in LDS, leaving room for the kernel's static arrays
-    int lds_cap = (c->max_lds - 8192) / 8;
-    if (lds_cap > 16384) lds_cap = 16384;
+    // 16-bit counts and touched keys in LDS, two workgroups per CU, leaving
+    // room for the kernel's static arrays
+    int lds_cap = (c->max_lds / 2 - 8192) / 4;
+    if (lds_cap > 32768) lds_cap = 32768;
     if (c->maxdeg + 1 < lds_cap) lds_cap = c->maxdeg + 1;
-    size_t lds = sizeof(uint32_t) * 2 * (size_t)lds_cap;
+    size_t lds = sizeof(uint32_t) * ((size_t)(lds_cap + 1) / 2) + sizeof(uint16_t) * (size_t)lds_cap + 16;
     k_wheels<<<pair_wgs(c), 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               (const int32_t *)c->buf[B_AV], tab, touch, c->tab_n, lds_cap,

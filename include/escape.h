@@ -201,6 +201,12 @@ esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out);
  * `out` is a host array of that many esc_u128. */
 esc_status esc_last_noninduced(const esc_ctx *ctx, esc_u128 *out);
 
+/* Induced 3-vertex counts of the last successful esc_count_subgraphs /
+ * esc_count_fragments call (the method's 3-vertex by-products, Sec. 1):
+ * [0] no edge, [1] exactly one edge, [2] path (wedge), [3] triangle; they sum
+ * to C(n,3).  `out` is a host array of 4 esc_u128.  Not set by batched calls. */
+esc_status esc_last_three(const esc_ctx *ctx, esc_u128 *out);
+
 /* Per-stage profile of the last successful call.  Stages, in order:
  *   [0] degree order and relabelled CSR      [1] triangles, per-arc lists
  *   [2] 4-cycles                             [3] 4-cliques per triangle and

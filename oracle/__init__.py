@@ -212,3 +212,30 @@ def vertex_triangles(graph, v):
     for x in nv:
         s += len(np.intersect1d(_row(graph, int(x)), nv, assume_unique=True))
     return s // 2
+
+
+def three_vertex_brute(graph):
+    """Induced 3-vertex counts by definition: classify every 3-subset by its
+    number of edges.  [no edge, one edge, path, triangle].  Small graphs only."""
+    n = graph.n
+    adj = [set(int(x) for x in graph.col[graph.row_ptr[v]:graph.row_ptr[v + 1]]) for v in range(n)]
+    out = [0, 0, 0, 0]
+    for a in range(n):
+        for b in range(a + 1, n):
+            ab = b in adj[a]
+            for c in range(b + 1, n):
+                out[int(ab) + int(c in adj[a]) + int(c in adj[b])] += 1
+    return out
+
+
+def three_vertex(graph):
+    """Induced 3-vertex counts from the oracle's triangle and wedge totals
+    (the method's 3-vertex by-products): triangles T, paths W - 3T, one-edge
+    sets m (n-2) - 2 (W - 3T) - 3T, and the rest of the C(n,3) sets.  Pinned
+    to three_vertex_brute in the CPU tests."""
+    S = sums(graph, 4)
+    n, m, W, T = S["n"], S["m"], S["W"], S["T"]
+    P3 = W - 3 * T
+    E1 = m * (n - 2) - 2 * P3 - 3 * T if n >= 2 else 0
+    from math import comb
+    return [comb(n, 3) - E1 - P3 - T, E1, P3, T]

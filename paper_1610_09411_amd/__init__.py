@@ -31,7 +31,7 @@ ESC_F_RANDOM_ORDER = 8
 ABI_FUNCTIONS = [
     "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments", "esc_count_batched",
     "esc_server_start", "esc_submit", "esc_poll", "esc_wait", "esc_server_stats", "esc_server_stop",
-    "esc_last_work", "esc_last_profile", "esc_last_noninduced", "esc_inverse_matrix", "esc_strerror",
+    "esc_last_work", "esc_last_profile", "esc_last_noninduced", "esc_last_three", "esc_inverse_matrix", "esc_strerror",
 ]
 
 PATTERN_NAMES = [
@@ -98,6 +98,8 @@ def _load():
         lib.esc_last_profile.restype = ctypes.c_int
         lib.esc_last_noninduced.argtypes = [vp, vp]
         lib.esc_last_noninduced.restype = ctypes.c_int
+        lib.esc_last_three.argtypes = [vp, vp]
+        lib.esc_last_three.restype = ctypes.c_int
         lib.esc_inverse_matrix.argtypes = [ctypes.c_int, vp]
         lib.esc_inverse_matrix.restype = ctypes.c_int
         lib.esc_strerror.argtypes = [ctypes.c_int]
@@ -157,6 +159,9 @@ class Context:
 
     def last_noninduced(self, k=5):
         return esc_last_noninduced(self.ptr, k)
+
+    def last_three(self):
+        return esc_last_three(self.ptr)
 
 
 def esc_create(device: int = 0, hbm_budget_bytes: int = 0):
@@ -331,6 +336,13 @@ def esc_last_noninduced(ctx, k=5):
     out = (_U128 * 45)()
     _check(_load().esc_last_noninduced(ctx, out), "esc_last_noninduced")
     return _ints(out, 11 if k == 4 else 45)
+
+
+def esc_last_three(ctx):
+    """Induced 3-vertex counts of the last call: [no edge, one edge, path, triangle]."""
+    out = (_U128 * 4)()
+    _check(_load().esc_last_three(ctx, out), "esc_last_three")
+    return _ints(out, 4)
 
 
 STAGES = ["orient", "triangles", "four_cycles", "k4_triangles", "five_cliques", "reduce", "pairs_13_17",

@@ -388,6 +388,12 @@ extern "C" esc_status esc_last_noninduced(const esc_ctx *ctx, esc_u128 *out) {
     return ESC_OK;
 }
 
+extern "C" esc_status esc_last_three(const esc_ctx *ctx, esc_u128 *out) {
+    if (!ctx || !out) return ESC_EINVAL;
+    memcpy(out, ctx->three, sizeof(esc_u128) * 4);
+    return ESC_OK;
+}
+
 extern "C" esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64_t *visits_out) {
     if (!ctx) return ESC_EINVAL;
     if (ms_out) memcpy(ms_out, ctx->stage_ms, sizeof(float) * NSTAGES);

@@ -52,6 +52,9 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
                                                       unsigned long long *visits) {
     __shared__ uint32_t bm_all[4][BM_WORDS];
     __shared__ u128 red[5 * 4];
+    __shared__ int64_t wsa[4][64];
+    __shared__ int32_t wse[4][64], wsi[4][64];
+    __shared__ uint32_t wcn[4][64];
     const int ids[5] = {AC_K4X4, AC_N20, AC_N10, AC_N16, AC_Z};
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t *bm = bm_all[wid];
@@ -98,24 +101,34 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
         const uint64_t da = da_i, db = off[b + 1] - off[b];
         const uint64_t dpa = off[a + 1] - split[a], dpb = off[b + 1] - split[b];
         const uint64_t tab = te[e];
-        for (int64_t k = lo + lane; k < l1; k += 64) {
-            const int32_t cc = av[k];
-            const int32_t pac = (int32_t)aa[k];             // arc (a,c) in row a
-            const int32_t pbc = (int32_t)aa[r0 + (k - l0)]; // arc (b,c) in row b
+        // 64 triangles (a,b,c), c after b, at a time: lane = triangle; K4 of
+        // the triangle = entries of list(a,c) marked in the bitmap, counted
+        // by the whole wave across the 64 lists
+        for (int64_t kb = lo; kb < l1; kb += 64) {
+            const int64_t k = kb + lane;
+            const bool ok = k < l1;
+            int32_t cc = 0, pac = 0, pbc = 0;
+            int64_t q0 = 0, q1 = 0;
+            if (ok) {
+                cc = av[k];
+                pac = (int32_t)aa[k];                  // arc (a,c) in row a
+                pbc = (int32_t)aa[r0 + (k - l0)];      // arc (b,c) in row b
+                q0 = aoff[pac];
+                q1 = aoff[pac + 1];
+            }
+            uint32_t k4 = 0;
+            if (use_bm) {
+                k4 = wave_count(q0, q1, wsa[wid], wse[wid], wsi[wid], wcn[wid],
+                                [&](int64_t q) { return (int32_t)aa[q] - oa; },
+                                [&](int32_t pos) { return (bm[pos >> 5] >> (pos & 31)) & 1u; });
+                nvis += q1 - q0;
+            } else if (ok) {
+                k4 = count_common(av + l0, l1 - l0, av + q0, q1 - q0, nvis);
+            }
+            if (!ok) continue;
             const int32_t eac = arc_eid[pac], ebc = arc_eid[pbc];
             const uint64_t tac = te[eac], tbc = te[ebc];
             const uint64_t dc = off[cc + 1] - off[cc], dpc = off[cc + 1] - split[cc];
-            uint32_t k4 = 0;
-            const int64_t q0 = aoff[pac], q1 = aoff[pac + 1];
-            if (use_bm) {
-                for (int64_t q = q0; q < q1; q++) {
-                    int32_t pos = (int32_t)aa[q] - oa;
-                    k4 += (bm[pos >> 5] >> (pos & 31)) & 1u;
-                }
-                nvis += q1 - q0;
-            } else {
-                k4 = count_common(av + l0, l1 - l0, av + q0, q1 - q0, nvis);
-            }
             if (k4) {
                 atomicAdd(&k4e[e], (unsigned long long)k4);
                 atomicAdd(&k4e[eac], (unsigned long long)k4);

@@ -164,7 +164,9 @@ __device__ inline u128 apply_inv(const int32_t *inv, int count, int row, const u
 }
 
 // One graph: its AC_COUNT sums, n and m -> out[0..44] induced counts,
-// out[45..89] non-induced counts (the first 11 of each when k = 4).
+// out[45..89] non-induced counts (the first 11 of each when k = 4),
+// out[90..93] induced 3-vertex counts (no edge, one edge, path, triangle).
+#define COMBINE_ROW 96
 __device__ void combine_one(const unsigned long long *acc, const int32_t *inv4, const int32_t *inv5, int64_t nv,
                             int64_t me, int k, u128 *out) {
     u128 S[AC_COUNT];
@@ -189,6 +191,15 @@ __device__ void combine_one(const unsigned long long *acc, const int32_t *inv4, 
     N4[10] = n >= 3 ? T * (n - 3) : 0;
     for (int i = 0; i < 11; i++) out[i] = apply_inv(inv4, 11, i, N4);
     for (int i = 0; i < 11; i++) out[45 + i] = N4[i];
+    // 3-vertex subsets: triangles T, induced paths W - 3T; the m (n-2) pairs
+    // (edge, third vertex) meet a one-edge set once, a path twice, a
+    // triangle three times
+    const u128 P3 = W - 3 * T;
+    const u128 E1 = n >= 2 ? m * (n - 2) - 2 * P3 - 3 * T : 0;
+    out[90] = binom(n, 3) - E1 - P3 - T;
+    out[91] = E1;
+    out[92] = P3;
+    out[93] = T;
     if (k < 5) return;
     u128 N5[34];
     N5[0] = S[AC_S4];
@@ -246,7 +257,7 @@ __global__ void k_combine_batched(int32_t G, const unsigned long long *acc, cons
     const int cnt = k == 4 ? 11 : 45;
     for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
         const unsigned long long *a = acc + (size_t)g * ACC_STRIDE;
-        u128 *o = tmp + (size_t)g * 90;
+        u128 *o = tmp + (size_t)g * COMBINE_ROW;
         combine_one(a, inv4, inv5, voff[g + 1] - voff[g], (aoff[g + 1] - aoff[g]) / 2, k, o);
         uint8_t f = 0;
         for (int i = 0; i < cnt; i++) {
@@ -261,14 +272,14 @@ __global__ void k_combine_batched(int32_t G, const unsigned long long *acc, cons
 }
 
 esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, const int32_t *d_inv5) {
-    u128 *dout = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * 96);
+    u128 *dout = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * COMBINE_ROW);
     if (!dout) return ESC_ENOMEM;
     k_combine<<<1, 64, 0, c->stream>>>((const unsigned long long *)c->buf[B_ACC], d_inv4, d_inv5, c->n, c->m, c->k,
                                        dout);
     HIP_TRY(hipGetLastError());
-    u128 h[90];
+    u128 h[COMBINE_ROW];
     int cnt = c->k == 4 ? 11 : 45;
-    HIP_TRY(hipMemcpyAsync(h, dout, sizeof(u128) * 90, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(h, dout, sizeof(u128) * COMBINE_ROW, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (int i = 0; i < cnt; i++) {
         host_out[i].lo = (uint64_t)h[i];
@@ -276,15 +287,20 @@ esc_status stage_combine(esc_ctx *c, esc_u128 *host_out, const int32_t *d_inv4, 
         c->noninduced[i].lo = (uint64_t)h[45 + i];
         c->noninduced[i].hi = (uint64_t)(h[45 + i] >> 64);
     }
+    for (int i = 0; i < 4; i++) {
+        c->three[i].lo = (uint64_t)h[90 + i];
+        c->three[i].hi = (uint64_t)(h[90 + i] >> 64);
+    }
     return ESC_OK;
 }
 
-// Device side of a batched combine: exact rows (90 u128 per graph: 45 induced
-// then 45 non-induced) in B_OUT, uint64 rows and overflow flags in B_BOUT.
+// Device side of a batched combine: exact rows (COMBINE_ROW u128 per graph:
+// 45 induced, 45 non-induced, 4 three-vertex) in B_OUT, uint64 rows and
+// overflow flags in B_BOUT.
 esc_status stage_combine_batched(esc_ctx *c) {
     const int32_t G = c->G;
     const int cnt = c->k == 4 ? 11 : 45;
-    u128 *tmp = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * 90 * (size_t)G);
+    u128 *tmp = (u128 *)ctx_buf(c, B_OUT, sizeof(u128) * COMBINE_ROW * (size_t)G);
     uint8_t *bout = (uint8_t *)ctx_buf(c, B_BOUT, (sizeof(uint64_t) * cnt + 1) * (size_t)G);
     if (!tmp || !bout) return ESC_ENOMEM;
     uint64_t *dout = (uint64_t *)bout;
@@ -327,16 +343,16 @@ esc_status batched_copy_u64(esc_ctx *c, uint64_t *host_out, uint8_t *host_overfl
 esc_status batched_copy_u128(esc_ctx *c, esc_u128 *host_out) {
     const int32_t G = c->G;
     const int cnt = c->k == 4 ? 11 : 45;
-    u128 *h = (u128 *)malloc(sizeof(u128) * 90 * (size_t)G);
+    u128 *h = (u128 *)malloc(sizeof(u128) * COMBINE_ROW * (size_t)G);
     if (!h) return ESC_ENOMEM;
     esc_status st = ESC_OK;
-    if (hipMemcpyAsync(h, c->buf[B_OUT], sizeof(u128) * 90 * (size_t)G, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+    if (hipMemcpyAsync(h, c->buf[B_OUT], sizeof(u128) * COMBINE_ROW * (size_t)G, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         st = ESC_EDEVICE;
     if (st == ESC_OK)
         for (int32_t g = 0; g < G; g++)
             for (int i = 0; i < cnt; i++) {
-                const u128 x = h[(size_t)g * 90 + i];
+                const u128 x = h[(size_t)g * COMBINE_ROW + i];
                 host_out[(size_t)g * cnt + i].lo = (uint64_t)x;
                 host_out[(size_t)g * cnt + i].hi = (uint64_t)(x >> 64);
             }

@@ -103,6 +103,7 @@ struct esc_ctx {
     float stage_ms[NSTAGES];
     uint64_t visits[NSTAGES];
     esc_u128 noninduced[45];
+    esc_u128 three[4];         // induced 3-vertex counts of the last single-graph call
     hipEvent_t ev[NSTAGES + 1];
     // current graph
     int32_t n;

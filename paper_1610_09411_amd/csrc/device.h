@@ -171,7 +171,7 @@ __device__ inline void wave_sync() {
 
 // Walk the concatenation of up to 64 segments held one per lane (lane y
 // holds segment y = [a0, a1)), 64 consecutive elements per step, so that one
-// step spans as many short segments as it needs; four steps are issued
+// step spans as many short segments as it needs; eight steps are issued
 // before their results are used.  load(pos) reads the element at position
 // pos, use(value) consumes it.  sa/se/si are 64-entry LDS arrays private to
 // the calling wave (the segments of one call hold fewer than 2^31 elements
@@ -192,26 +192,82 @@ __device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *s
     wave_sync();
     int y = 0;
     int32_t e = lane;
-    for (; e + 3 * ESC_WAVE < total; e += 4 * ESC_WAVE) {
-        while (si[y] <= e) y++;
-        const int64_t q0 = sa[y] + (e - se[y]);
-        while (si[y] <= e + ESC_WAVE) y++;
-        const int64_t q1 = sa[y] + (e + ESC_WAVE - se[y]);
-        while (si[y] <= e + 2 * ESC_WAVE) y++;
-        const int64_t q2 = sa[y] + (e + 2 * ESC_WAVE - se[y]);
-        while (si[y] <= e + 3 * ESC_WAVE) y++;
-        const int64_t q3 = sa[y] + (e + 3 * ESC_WAVE - se[y]);
-        const auto v0 = load(q0), v1 = load(q1), v2 = load(q2), v3 = load(q3);
-        use(v0);
-        use(v1);
-        use(v2);
-        use(v3);
+    constexpr int NU = 8;   // steps in flight
+    for (; e + (NU - 1) * ESC_WAVE < total; e += NU * ESC_WAVE) {
+        int64_t q[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) {
+            while (si[y] <= e + u * ESC_WAVE) y++;
+            q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
+        }
+        decltype(load(q[0])) v[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) v[u] = load(q[u]);
+#pragma unroll
+        for (int u = 0; u < NU; u++) use(v[u]);
     }
     for (; e < total; e += ESC_WAVE) {
         while (si[y] <= e) y++;
         use(load(sa[y] + (e - se[y])));
     }
     wave_sync();   // the arrays are reused by the next call
+}
+
+// Same walk as wave_walk, counting for every segment the elements x with
+// pred(load(pos)) true; returns the count of the calling lane's segment.
+// cnt is a 64-entry LDS array private to the wave.
+template <class L, class P>
+__device__ inline uint32_t wave_count(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, uint32_t *cnt,
+                                      L load, P pred) {
+    const int lane = threadIdx.x & (ESC_WAVE - 1);
+    const int32_t len = (int32_t)(a1 - a0);
+    int32_t incl = len;
+    for (int o = 1; o < ESC_WAVE; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int32_t total = __shfl(incl, ESC_WAVE - 1);
+    sa[lane] = a0;
+    se[lane] = incl - len;
+    si[lane] = incl;
+    cnt[lane] = 0;
+    wave_sync();
+    int y = 0, ycur = 0;
+    uint32_t run = 0;
+    int32_t e = lane;
+    for (; e + 3 * ESC_WAVE < total; e += 4 * ESC_WAVE) {
+        int yy[4];
+        int64_t q[4];
+        for (int u = 0; u < 4; u++) {
+            while (si[y] <= e + u * ESC_WAVE) y++;
+            yy[u] = y;
+            q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
+        }
+        const auto v0 = load(q[0]), v1 = load(q[1]), v2 = load(q[2]), v3 = load(q[3]);
+        const uint32_t b[4] = {(uint32_t)pred(v0), (uint32_t)pred(v1), (uint32_t)pred(v2), (uint32_t)pred(v3)};
+        for (int u = 0; u < 4; u++) {
+            if (yy[u] != ycur) {
+                if (run) atomicAdd(&cnt[ycur], run);
+                run = 0;
+                ycur = yy[u];
+            }
+            run += b[u];
+        }
+    }
+    for (; e < total; e += ESC_WAVE) {
+        while (si[y] <= e) y++;
+        if (y != ycur) {
+            if (run) atomicAdd(&cnt[ycur], run);
+            run = 0;
+            ycur = y;
+        }
+        run += (uint32_t)pred(load(sa[y] + (e - se[y])));
+    }
+    if (run) atomicAdd(&cnt[ycur], run);
+    wave_sync();
+    const uint32_t r = cnt[lane];
+    wave_sync();   // the arrays are reused by the next call
+    return r;
 }
 
 __device__ inline uint64_t c2(uint64_t x) { return x < 2 ? 0 : x * (x - 1) / 2; }

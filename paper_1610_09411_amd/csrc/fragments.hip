@@ -243,7 +243,7 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     if (n == 0) return ESC_OK;
     int nwg = pair_wgs(c);
     size_t per = (size_t)c->tab_n * sizeof(uint32_t);
-    uint32_t *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
+    uint32_t *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 2 * nwg);
     int32_t *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * 2 * nwg);
     int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
     if (!tab || !touch || !task) return ESC_ENOMEM;

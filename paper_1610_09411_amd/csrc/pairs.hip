@@ -61,12 +61,21 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         const int g = gm.graph(i);
         block_switch_graph<2>(sv, gcur, g, red, acc, ACC_STRIDE, ids);
         const int32_t gb = gm.begin(g), ge = gm.end(g);
-        const int32_t hi0 = ge - slab > gb ? ge - slab : gb;   // first key held in LDS
         uint32_t *W = Wt - gb;
         const int32_t oi = off[i], ei = off[i + 1];
-        const int32_t ls = i + 1 > hi0 ? i + 1 : hi0;          // LDS keys [ls, ge)
-        for (int q = ls - hi0 + threadIdx.x; q < ge - hi0; q += blockDim.x) sl[q] = 0;
+        // W(i,j) <= d(i): counts of a low-degree source are packed 4 or 2 to
+        // an LDS word, so the slab covers 4x or 2x as many latest ranks
+        const int shift = ei - oi < 256 ? 2 : (ei - oi < 65536 ? 1 : 0);   // log2(counts per word)
+        const int cb = 32 >> shift;                                        // bits per count
+        const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
+        const int32_t sranks = slab << shift;
+        const int32_t hi0 = ge - sranks > gb ? ge - sranks : gb;           // first key held in LDS
+        const int32_t ls = i + 1 > hi0 ? i + 1 : hi0;                       // LDS keys [ls, ge)
+        const int32_t w_lo = (ls - hi0) >> shift, w_hi = ge > ls ? ((ge - 1 - hi0) >> shift) + 1 : w_lo;
+        for (int q = w_lo + threadIdx.x; q < w_hi; q += blockDim.x) sl[q] = 0;
         __syncthreads();
+#define SLAB_INC(j) atomicAdd(&sl[((j) - hi0) >> shift], 1u << ((((j) - hi0) & ((1 << shift) - 1)) * cb))
+#define SLAB_GET(j) ((sl[((j) - hi0) >> shift] >> ((((j) - hi0) & ((1 << shift) - 1)) * cb)) & cmask)
         // W(i,j) for j after i: k in N(i), j in the suffix of N(k) after i
         for (int32_t base = oi; base < ei; base += blockDim.x) {
             int32_t p = base + threadIdx.x;
@@ -75,7 +84,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
                 int32_t j = adj[q];
                 nvis++;
-                if (j >= hi0) atomicAdd(&sl[j - hi0], 1u);
+                if (j >= hi0) SLAB_INC(j);
                 else if (atomicAdd(&W[j], 1u) == 0) touch[atomicAdd(&s_nt, 1)] = j;
             });
         }
@@ -109,7 +118,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                     uint64_t acc17 = 0;
                     wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid],
                               [&](int64_t q) { return av[q]; },
-                              [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? sl[j - hi0] : W[j]) - 2; });
+                              [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? SLAB_GET(j) : W[j]) - 2; });
                     sv[1] += acc17;
                 }
             }
@@ -121,7 +130,13 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             sv[0] += c3(W[j]);
             W[j] = 0;
         }
-        for (int q = ls - hi0 + threadIdx.x; q < ge - hi0; q += blockDim.x) sv[0] += c3(sl[q]);
+        for (int q = w_lo + threadIdx.x; q < w_hi; q += blockDim.x) {
+            const uint32_t x = sl[q];
+            if (x == 0) continue;
+            for (int f = 0; f < (1 << shift); f++) sv[0] += c3((x >> (f * cb)) & cmask);
+        }
+#undef SLAB_INC
+#undef SLAB_GET
         __syncthreads();
         if (threadIdx.x == 0) s_nt = 0;   // next read of s_nt is behind a barrier
         }
@@ -138,7 +153,9 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // lives in LDS when d(h) fits, else in the workgroup's global scratch.  In
 // LDS a count is below d(h) <= lds_cap < 2^16, so two counts share a word
 // (16 bits each; one 32-bit atomic adds 1 << 16 for odd keys) and the
-// touched keys are 16-bit.
+// touched keys are 16-bit.  A hub with d(h) <= lds_cap / 4 gives each of
+// the four waves its own table and rim vertices, with no workgroup barrier
+// per rim vertex.
 __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
@@ -148,7 +165,7 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
     extern __shared__ uint32_t dyn[];
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
-    __shared__ int s_h, s_nt;
+    __shared__ int s_h, s_nt, s_ntw[4];
     __shared__ u128 red[4];
     __shared__ int64_t wsa[4][64];
     __shared__ int32_t wse[4][64], wsi[4][64];
@@ -171,6 +188,57 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
         int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
         uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
         uint16_t *ltch = (uint16_t *)(dyn + (lds_cap + 1) / 2);      // lds_cap keys
+        const int32_t wq = lds_cap / 4;   // largest d(h) of the one-wave-per-rim-vertex mode
+        if (dh <= wq) {
+            // small hub: each wave takes its own rim vertices i with its own
+            // table, so no workgroup barrier is needed per i
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+            const int32_t rw = (wq + 1) / 2;   // words of a table, and of a touched list
+            uint32_t *wc = dyn + (size_t)wid * 2 * rw;
+            uint16_t *wt = (uint16_t *)(wc + rw);
+            for (int q = lane; q < (dh + 1) / 2; q += 64) wc[q] = 0;
+            wave_sync();
+            for (int32_t pi = oh + wid; pi < oh + dh; pi += nw) {
+                const int32_t i = adj[pi];
+                const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
+                if (l1 - l0 < 2) continue;
+                int64_t lo = l0, hi = l1;
+                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] < i) lo = mid + 1; else hi = mid; }
+                const int nl = (int)(lo - l0);
+                if (nl == 0) continue;
+                if (lane == 0) s_ntw[wid] = 0;
+                wave_sync();
+                for (int xb = 0; xb < nl; xb += 64) {
+                    const int x = xb + lane;
+                    int64_t b0 = 0, b1 = 0;
+                    if (x < nl) {
+                        const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
+                        b0 = aoff[qhl];
+                        int64_t lo2 = b0, hi2 = aoff[qhl + 1];
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
+                        b1 = lo2;
+                    }
+                    nvis += (uint64_t)(b1 - b0);
+                    wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                              [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                              [&](int32_t key) {
+                                  const uint32_t sh = (uint32_t)(key & 1) << 4;
+                                  const uint32_t old = atomicAdd(&wc[key >> 1], 1u << sh);
+                                  if (((old >> sh) & 0xFFFFu) == 0) wt[atomicAdd(&s_ntw[wid], 1)] = (uint16_t)key;
+                              });
+                }
+                const int nt = s_ntw[wid];
+                for (int q = lane; q < nt; q += 64) {
+                    const int32_t key = wt[q];
+                    const uint32_t sh = (uint32_t)(key & 1) << 4;
+                    const uint32_t old = atomicAnd(&wc[key >> 1], ~(0xFFFFu << sh));
+                    s18[0] += c2((old >> sh) & 0xFFFFu);
+                }
+                wave_sync();
+            }
+            __syncthreads();   // a later hub in the workgroup mode reuses the whole array
+            continue;
+        }
         if (in_lds)
             for (int q = threadIdx.x; q < (dh + 1) / 2; q += blockDim.x) lcnt[q] = 0;
         __syncthreads();
@@ -351,7 +419,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
 static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int **task) {
     size_t per = (size_t)c->tab_n * sizeof(uint32_t);
     int nwg = pair_wgs(c);
-    *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 4 * nwg);
+    *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 2 * nwg);
     *touch = (int32_t *)ctx_buf(c, B_WG_TOUCH, per * 2 * nwg);
     *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
     if (!*tab || !*touch || !*task) return ESC_ENOMEM;
@@ -397,7 +465,15 @@ esc_status stage_wheels(esc_ctx *c) {
     if (lds_cap > 32768) lds_cap = 32768;
     if (c->maxdeg + 1 < lds_cap) lds_cap = c->maxdeg + 1;
     size_t lds = sizeof(uint32_t) * ((size_t)(lds_cap + 1) / 2) + sizeof(uint16_t) * (size_t)lds_cap + 16;
-    k_wheels<<<pair_wgs(c), 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    size_t lds_waves = sizeof(uint32_t) * 4 * 2 * (size_t)((lds_cap / 4 + 1) / 2) + 16;   // four one-wave tables
+    if (lds_waves > lds) lds = lds_waves;
+    // as many 4-wave workgroups per CU as LDS holds (up to 4): the walk is
+    // bound by load latency, so resident waves matter; the global tables
+    // have room for 4 per CU
+    int per_cu = (int)(c->max_lds / (lds + 10240));
+    if (per_cu > 4) per_cu = 4;
+    if (per_cu < 1) per_cu = 1;
+    k_wheels<<<c->num_cu * per_cu, 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               (const int32_t *)c->buf[B_AV], tab, touch, c->tab_n, lds_cap,
                                               c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],

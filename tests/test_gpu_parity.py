@@ -100,6 +100,19 @@ def test_power_law_graphs_equal_oracle(ctx, n, gamma, dbar, dmax, seed):
     _check_equal(ctx, g, 5)
 
 
+def test_three_vertex_counts(ctx):
+    """The 3-vertex by-products of a call equal the oracle's, and the
+    classification of every 3-subset on a 200-vertex graph."""
+    g = synth.er_small(0)
+    ctx.count(g, 5)
+    assert ctx.last_three() == oracle.three_vertex_brute(g)
+    for g in _cases_small()[:8] + [synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2), synth.from_edges(2, [(0, 1)])]:
+        ctx.count(g, 4)
+        got = ctx.last_three()
+        assert got == oracle.three_vertex(g), g.name
+        assert sum(got) == comb(g.n, 3)
+
+
 def test_random_order_gives_same_counts(ctx):
     import paper_1610_09411_amd as esc
     g = synth.chung_lu(5000, 2.1, 15.0, 600.0, 9)

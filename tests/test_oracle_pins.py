@@ -276,3 +276,24 @@ def test_sum_of_induced_counts_is_binomial():
     assert sum(got[:11]) == comb(g.n, 4)
     assert sum(got[11:]) == comb(g.n, 5)
     assert min(got) >= 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_three_vertex_closed_form_equals_definition(seed):
+    """3-vertex by-products (triangles, paths, one edge, none) against the
+    classification of every 3-subset."""
+    for g in (synth.erdos_renyi(40 + 10 * seed, 0.15, 900 + seed),
+              synth.chung_lu(60, 2.1, 6.0, 20.0, 910 + seed)):
+        assert oracle.three_vertex(g) == oracle.three_vertex_brute(g)
+
+
+def test_three_vertex_special_graphs():
+    from math import comb
+    k6 = synth.from_edges(6, [(u, v) for u in range(6) for v in range(u + 1, 6)])
+    assert oracle.three_vertex_brute(k6) == [0, 0, 0, comb(6, 3)]
+    star = synth.from_edges(7, [(0, v) for v in range(1, 7)])
+    assert oracle.three_vertex_brute(star) == [comb(6, 3), 0, comb(6, 2), 0]
+    path = synth.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    # {0,1,2},{1,2,3} paths; {0,1,3},{0,2,3} one edge
+    assert oracle.three_vertex_brute(path) == [0, 2, 2, 0]
+    assert oracle.three_vertex(path) == [0, 2, 2, 0]

@@ -61,10 +61,10 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         const int g = gm.graph(i);
         block_switch_graph<2>(sv, gcur, g, red, acc, ACC_STRIDE, ids);
         const int32_t gb = gm.begin(g), ge = gm.end(g);
-        uint32_t *W = Wt - gb;
         const int32_t oi = off[i], ei = off[i + 1];
         // W(i,j) <= d(i): counts of a low-degree source are packed 4 or 2 to
-        // an LDS word, so the slab covers 4x or 2x as many latest ranks
+        // a word, so the LDS slab covers 4x or 2x as many latest ranks and
+        // the workgroup table touches 4x or 2x fewer cache lines
         const int shift = ei - oi < 256 ? 2 : (ei - oi < 65536 ? 1 : 0);   // log2(counts per word)
         const int cb = 32 >> shift;                                        // bits per count
         const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
@@ -76,6 +76,9 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         __syncthreads();
 #define SLAB_INC(j) atomicAdd(&sl[((j) - hi0) >> shift], 1u << ((((j) - hi0) & ((1 << shift) - 1)) * cb))
 #define SLAB_GET(j) ((sl[((j) - hi0) >> shift] >> ((((j) - hi0) & ((1 << shift) - 1)) * cb)) & cmask)
+#define TAB_SH(j) ((uint32_t)((((j) - gb) & ((1 << shift) - 1)) * cb))
+#define TAB_INC(j) ((atomicAdd(&Wt[((j) - gb) >> shift], 1u << TAB_SH(j)) >> TAB_SH(j)) & cmask)
+#define TAB_GET(j) ((Wt[((j) - gb) >> shift] >> TAB_SH(j)) & cmask)
         // W(i,j) for j after i: k in N(i), j in the suffix of N(k) after i
         for (int32_t base = oi; base < ei; base += blockDim.x) {
             int32_t p = base + threadIdx.x;
@@ -85,7 +88,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                 int32_t j = adj[q];
                 nvis++;
                 if (j >= hi0) SLAB_INC(j);
-                else if (atomicAdd(&W[j], 1u) == 0) touch[atomicAdd(&s_nt, 1)] = j;
+                else if (TAB_INC(j) == 0) touch[atomicAdd(&s_nt, 1)] = j;
             });
         }
         __syncthreads();
@@ -118,7 +121,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                     uint64_t acc17 = 0;
                     wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid],
                               [&](int64_t q) { return av[q]; },
-                              [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? SLAB_GET(j) : W[j]) - 2; });
+                              [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? SLAB_GET(j) : TAB_GET(j)) - 2; });
                     sv[1] += acc17;
                 }
             }
@@ -126,9 +129,10 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         }
         const int nt = s_nt;
         for (int q = threadIdx.x; q < nt; q += blockDim.x) {
-            int32_t j = touch[q];
-            sv[0] += c3(W[j]);
-            W[j] = 0;
+            const int32_t j = touch[q];
+            // other counts of the word may be reset concurrently
+            const uint32_t old = atomicAnd(&Wt[(j - gb) >> shift], ~(cmask << TAB_SH(j)));
+            sv[0] += c3((old >> TAB_SH(j)) & cmask);
         }
         for (int q = w_lo + threadIdx.x; q < w_hi; q += blockDim.x) {
             const uint32_t x = sl[q];
@@ -137,6 +141,9 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         }
 #undef SLAB_INC
 #undef SLAB_GET
+#undef TAB_SH
+#undef TAB_INC
+#undef TAB_GET
         __syncthreads();
         if (threadIdx.x == 0) s_nt = 0;   // next read of s_nt is behind a barrier
         }

@@ -177,13 +177,29 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
             const int g = gm.graph(h);
             block_switch_graph<3>(sums, gcur, g, red, acc, ACC_STRIDE, ids);
             const int32_t gb = gm.begin(g), ge = gm.end(g);
-            const int32_t hi0 = ge - slab > gb ? ge - slab : gb;   // first key held in LDS
-            const int32_t nsl = h > hi0 ? h - hi0 : 0;
-            uint32_t *C = Ct - gb;
             const int32_t oh = off[h], sh = split[h];
             const int64_t dh = off[h + 1] - oh;
-            for (int q = threadIdx.x; q < nsl; q += blockDim.x) sl[q] = 0;
+            // c(h,o) <= d(h): a low-degree top vertex packs 4 or 2 counts per
+            // word, in LDS (4x or 2x more latest ranks) and in the table
+            const int shift = dh < 256 ? 2 : (dh < 65536 ? 1 : 0);
+            const int cb = 32 >> shift;
+            const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
+            const int32_t hi0 = ge - (slab << shift) > gb ? ge - (slab << shift) : gb;   // first key held in LDS
+            const int32_t nsl = h > hi0 ? h - hi0 : 0;                                  // LDS keys [hi0, h)
+            const int32_t nslw = (nsl + (1 << shift) - 1) >> shift;
+            for (int q = threadIdx.x; q < nslw; q += blockDim.x) sl[q] = 0;
             __syncthreads();
+            auto inc = [&](int32_t o) -> uint32_t {
+                const int32_t idx = o >= hi0 ? o - hi0 : o - gb;
+                const uint32_t s = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+                const uint32_t old = o >= hi0 ? atomicAdd(&sl[idx >> shift], 1u << s) : atomicAdd(&Ct[idx >> shift], 1u << s);
+                return (old >> s) & cmask;
+            };
+            auto get = [&](int32_t o) -> uint32_t {
+                const int32_t idx = o >= hi0 ? o - hi0 : o - gb;
+                const uint32_t s = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+                return ((o >= hi0 ? sl[idx >> shift] : Ct[idx >> shift]) >> s) & cmask;
+            };
             // pass 1: wedges h - k - o, k in N-(h), o in the prefix of N(k) below h
             for (int32_t base = oh; base < sh; base += blockDim.x) {
                 int32_t p = base + threadIdx.x;
@@ -192,8 +208,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
                     const int32_t o = adj[q];
                     nvis++;
-                    if (o >= hi0) atomicAdd(&sl[o - hi0], 1u);
-                    else if (atomicAdd(&C[o], 1u) == 0) touch[atomicAdd(&s_nt, 1)] = o;
+                    if (inc(o) == 0 && o < hi0) touch[atomicAdd(&s_nt, 1)] = o;
                 });
             }
             __syncthreads();
@@ -205,7 +220,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
                     const int32_t pk = base + s;
                     const int32_t o = adj[q];
-                    const uint32_t cc = o >= hi0 ? sl[o - hi0] : C[o];
+                    const uint32_t cc = get(o);
                     if (cc >= 2) {
                         const int32_t k = adj[pk];
                         sums[1] += (uint64_t)(cc - 1) * (tarc[pk] + tarc[q]);
@@ -222,8 +237,16 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
             for (int i = threadIdx.x; i < nt + nsl; i += blockDim.x) {
                 int32_t o;
                 uint64_t cc;
-                if (i < nt) { o = touch[i]; cc = C[o]; C[o] = 0; }
-                else { o = hi0 + (i - nt); cc = sl[i - nt]; }
+                if (i < nt) {
+                    o = touch[i];
+                    const int32_t idx = o - gb;
+                    const uint32_t s = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+                    // other counts of the word may be cleared concurrently
+                    cc = (atomicAnd(&Ct[idx >> shift], ~(cmask << s)) >> s) & cmask;
+                } else {
+                    o = hi0 + (i - nt);
+                    cc = get(o);
+                }
                 if (cc >= 2) {
                     sums[0] += c2(cc);
                     sums[2] += (u128)(cc - 1) * cc * (uint64_t)(dh + (off[o + 1] - off[o]) - 4);

@@ -352,9 +352,34 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         block_switch_graph<1>(sc, gcur, g, red, acc, ACC_STRIDE, ids);
         // tables are indexed by rank relative to the start of i's graph
         const int32_t gb = gm.begin(g), ge = gm.end(g);
-        const int32_t hi0 = ge - slab > gb ? ge - slab : gb;   // first key held in LDS
-        uint32_t *X = Xt - gb, *Wn = Wt - gb;
         const int32_t oi = off[i], si = split[i], ei = off[i + 1];
+        // X(i,b) and Wnt(i,j) never exceed d(i): a low-degree source packs 4
+        // or 2 counts per word, in LDS and in the workgroup tables
+        const int shift = ei - oi < 256 ? 2 : (ei - oi < 65536 ? 1 : 0);
+        const int cb = 32 >> shift;
+        const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
+        const int32_t hi0 = ge - (slab << shift) > gb ? ge - (slab << shift) : gb;   // first key held in LDS
+        // count of key x in the LDS array s (latest keys) or the table t: add
+        // one (returns the old count), read, clear; separate branches keep
+        // LDS and global accesses apart
+        auto inc = [&](uint32_t *s, uint32_t *t, int32_t x) -> uint32_t {
+            const int32_t idx = x >= hi0 ? x - hi0 : x - gb;
+            const uint32_t sh = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+            const uint32_t old = x >= hi0 ? atomicAdd(&s[idx >> shift], 1u << sh) : atomicAdd(&t[idx >> shift], 1u << sh);
+            return (old >> sh) & cmask;
+        };
+        auto get = [&](const uint32_t *s, const uint32_t *t, int32_t x) -> uint32_t {
+            const int32_t idx = x >= hi0 ? x - hi0 : x - gb;
+            const uint32_t sh = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+            return ((x >= hi0 ? s[idx >> shift] : t[idx >> shift]) >> sh) & cmask;
+        };
+        auto clr = [&](uint32_t *s, uint32_t *t, int32_t x) {
+            const int32_t idx = x >= hi0 ? x - hi0 : x - gb;
+            const uint32_t sh = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+            // other counts of the word may be cleared concurrently
+            if (x >= hi0) atomicAnd(&s[idx >> shift], ~(cmask << sh));
+            else atomicAnd(&t[idx >> shift], ~(cmask << sh));
+        };
         // X(i,b): a in N-(i), b in N+(a), b != i
         for (int32_t base = oi; base < si; base += blockDim.x) {
             int32_t p = base + threadIdx.x;
@@ -364,8 +389,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                 int32_t b = adj[q];
                 nvis++;
                 if (b == i) return;
-                const uint32_t old = b >= hi0 ? atomicAdd(&sX[b - hi0], 1u) : atomicAdd(&X[b], 1u);
-                if (old == 0) tx[atomicAdd(&s_nx, 1)] = b;
+                if (inc(sX, Xt, b) == 0) tx[atomicAdd(&s_nx, 1)] = b;
             });
         }
         __syncthreads();
@@ -383,8 +407,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                 int32_t j = adj[q];
                 nvis++;
                 if (j == i) return;
-                const uint32_t old = j >= hi0 ? atomicAdd(&sW[j - hi0], 1u) : atomicAdd(&Wn[j], 1u);
-                if (old == 0) tw[atomicAdd(&s_nw, 1)] = j;
+                if (inc(sW, Wt, j) == 0) tw[atomicAdd(&s_nw, 1)] = j;
             });
         }
         __syncthreads();
@@ -398,20 +421,20 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                 const int32_t b = tx[base + s];
                 const int32_t j = adj[q];
                 nvis++;
-                const uint32_t xb = b >= hi0 ? sX[b - hi0] : X[b];
-                const uint32_t wj = j >= hi0 ? sW[j - hi0] : Wn[j];
+                const uint32_t xb = get(sX, Xt, b);
+                const uint32_t wj = get(sW, Wt, j);
                 sc[0] += (uint64_t)xb * wj;
             });
         }
         __syncthreads();
         for (int q = threadIdx.x; q < nx; q += blockDim.x) {
             const int32_t b = tx[q];
-            if (b >= hi0) sX[b - hi0] = 0; else X[b] = 0;
+            clr(sX, Xt, b);
         }
         const int nw = s_nw;
         for (int q = threadIdx.x; q < nw; q += blockDim.x) {
             const int32_t j = tw[q];
-            if (j >= hi0) sW[j - hi0] = 0; else Wn[j] = 0;
+            clr(sW, Wt, j);
         }
         __syncthreads();
         if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }   // next reads are behind a barrier

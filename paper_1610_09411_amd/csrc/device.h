@@ -173,11 +173,12 @@ __device__ inline void wave_sync() {
 // holds segment y = [a0, a1)), 64 consecutive elements per step, so that one
 // step spans as many short segments as it needs; eight steps are issued
 // before their results are used.  load(pos) reads the element at position
-// pos, use(value) consumes it.  sa/se/si are 64-entry LDS arrays private to
-// the calling wave (the segments of one call hold fewer than 2^31 elements
-// in all).  Every lane of the wave must call it.
+// pos, use(y, pos, value) consumes it (y = the lane holding the segment).
+// sa/se/si are 64-entry LDS arrays private to the calling wave (the
+// segments of one call hold fewer than 2^31 elements in all).  Every lane
+// of the wave must call it.
 template <class L, class U>
-__device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
+__device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
     const int lane = threadIdx.x & (ESC_WAVE - 1);
     const int32_t len = (int32_t)(a1 - a0);
     int32_t incl = len;
@@ -195,22 +196,31 @@ __device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *s
     constexpr int NU = 8;   // steps in flight
     for (; e + (NU - 1) * ESC_WAVE < total; e += NU * ESC_WAVE) {
         int64_t q[NU];
+        int yy[NU];
 #pragma unroll
         for (int u = 0; u < NU; u++) {
             while (si[y] <= e + u * ESC_WAVE) y++;
+            yy[u] = y;
             q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
         }
         decltype(load(q[0])) v[NU];
 #pragma unroll
         for (int u = 0; u < NU; u++) v[u] = load(q[u]);
 #pragma unroll
-        for (int u = 0; u < NU; u++) use(v[u]);
+        for (int u = 0; u < NU; u++) use(yy[u], q[u], v[u]);
     }
     for (; e < total; e += ESC_WAVE) {
         while (si[y] <= e) y++;
-        use(load(sa[y] + (e - se[y])));
+        const int64_t q = sa[y] + (e - se[y]);
+        use(y, q, load(q));
     }
     wave_sync();   // the arrays are reused by the next call
+}
+
+// wave_walk_seg with use(value) only
+template <class L, class U>
+__device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
+    wave_walk_seg(a0, a1, sa, se, si, load, [&](int, int64_t, decltype(load(a0)) v) { use(v); });
 }
 
 // Same walk as wave_walk, counting for every segment the elements x with

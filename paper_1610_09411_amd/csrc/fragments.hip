@@ -22,52 +22,127 @@ static int grid_cap(esc_ctx *c, int64_t items, int threads, int per_cu = 16) {
 
 // ---------------------------------------------------------------- triangles
 
-// One wave per vertex u; lanes take the out-arcs u->v and intersect N+(u)
-// with N+(v).  Every triangle u<v<w is found once, from its first arc.
-// mode 0: count t(e) (atomics on the two arcs other than u->v)
+// One wave per vertex u.  N+(u) goes into a hash set in the wave's LDS
+// (key: rank, value: position of the arc in u's row); the lanes take 64
+// out-arcs u->v at a time and the wave walks the 64 lists N+(v) together,
+// probing every entry x: a hit is the triangle u<v<x, found once, from its
+// first arc.  Vertices whose N+ does not fit the table fall back to one
+// merge per lane.
+// mode 0: count t(e) (atomics on the three edges)
 // mode 1: write the six per-arc list entries through per-arc cursors
+__device__ inline uint32_t hash_slot(uint32_t x, int bits) { return (x * 2654435761u) >> (32 - bits); }
+
 __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off, const int32_t *adj,
                                                    const int32_t *split, const int32_t *arc_eid,
                                                    const int32_t *rev, uint32_t *te, int mode,
-                                                   unsigned long long *cur, uint32_t *aa,
+                                                   unsigned long long *cur, uint32_t *aa, int hbits,
                                                    unsigned long long *visits) {
+    extern __shared__ uint32_t hdyn[];   // per wave: keys[H] then values[H]
+    __shared__ int64_t wsa[4][64];
+    __shared__ int32_t wse[4][64], wsi[4][64];
+    __shared__ uint32_t wcn[4][64];
     uint64_t nvis = 0;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int H = 1 << hbits;
+    uint32_t *hk = hdyn + (size_t)wid * 2 * H, *hv = hk + H;
+    for (int q = lane; q < H; q += 64) hk[q] = 0;
+    wcn[wid][lane] = 0;
+    wave_sync();
     const int32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    // the six list entries of triangle u<v<w from arcs p=(u,v) x=(u,w) y=(v,w)
+    auto fill6 = [&](int32_t p, int32_t x, int32_t y) {
+        int32_t rp = rev[p], rx = rev[x], ry = rev[y];
+        aa[atomicAdd(&cur[p], 1ull)] = (uint32_t)x;    // list(u->v): apex w -> (u,w)
+        aa[atomicAdd(&cur[rp], 1ull)] = (uint32_t)y;   // list(v->u): apex w -> (v,w)
+        aa[atomicAdd(&cur[x], 1ull)] = (uint32_t)p;    // list(u->w): apex v -> (u,v)
+        aa[atomicAdd(&cur[rx], 1ull)] = (uint32_t)ry;  // list(w->u): apex v -> (w,v)
+        aa[atomicAdd(&cur[y], 1ull)] = (uint32_t)rp;   // list(v->w): apex u -> (v,u)
+        aa[atomicAdd(&cur[ry], 1ull)] = (uint32_t)rx;  // list(w->v): apex u -> (w,u)
+    };
     for (int32_t u = wave; u < n; u += nwaves) {
         const int32_t su = split[u], eu = off[u + 1];
-        for (int32_t p = su + lane; p < eu; p += 64) {
-            const int32_t v = adj[p];
-            int32_t x = p + 1, y = split[v];
-            const int32_t ev = off[v + 1];
-            uint32_t cnt = 0;
-            while (x < eu && y < ev) {
-                int32_t a = adj[x], b = adj[y];
-                nvis += 2;
-                if (a < b) x++;
-                else if (a > b) y++;
-                else {
-                    if (mode == 0) {
-                        atomicAdd(&te[arc_eid[x]], 1u);
-                        atomicAdd(&te[arc_eid[y]], 1u);
-                    } else {
-                        // arcs: p=(u,v) x=(u,w) y=(v,w) and reverses
-                        int32_t rp = rev[p], rx = rev[x], ry = rev[y];
-                        aa[atomicAdd(&cur[p], 1ull)] = (uint32_t)x;    // list(u->v): apex w -> (u,w)
-                        aa[atomicAdd(&cur[rp], 1ull)] = (uint32_t)y;   // list(v->u): apex w -> (v,w)
-                        aa[atomicAdd(&cur[x], 1ull)] = (uint32_t)p;    // list(u->w): apex v -> (u,v)
-                        aa[atomicAdd(&cur[rx], 1ull)] = (uint32_t)ry;  // list(w->u): apex v -> (w,v)
-                        aa[atomicAdd(&cur[y], 1ull)] = (uint32_t)rp;   // list(v->w): apex u -> (v,u)
-                        aa[atomicAdd(&cur[ry], 1ull)] = (uint32_t)rx;  // list(w->v): apex u -> (w,u)
+        const int32_t dp = eu - su;
+        if (dp < 2) continue;
+        if (2 * dp > H) {
+            // merge fallback: lanes take the out-arcs u->v
+            for (int32_t p = su + lane; p < eu; p += 64) {
+                const int32_t v = adj[p];
+                int32_t x = p + 1, y = split[v];
+                const int32_t ev = off[v + 1];
+                uint32_t cnt = 0;
+                while (x < eu && y < ev) {
+                    int32_t a = adj[x], b = adj[y];
+                    nvis += 2;
+                    if (a < b) x++;
+                    else if (a > b) y++;
+                    else {
+                        if (mode == 0) {
+                            atomicAdd(&te[arc_eid[x]], 1u);
+                            atomicAdd(&te[arc_eid[y]], 1u);
+                        } else {
+                            fill6(p, x, y);
+                        }
+                        cnt++;
+                        x++;
+                        y++;
                     }
-                    cnt++;
-                    x++;
-                    y++;
                 }
+                if (mode == 0 && cnt) atomicAdd(&te[arc_eid[p]], cnt);
             }
-            if (mode == 0 && cnt) atomicAdd(&te[arc_eid[p]], cnt);
+            continue;
         }
+        int lb = 1;
+        while ((1 << lb) < 2 * dp) lb++;
+        const uint32_t lm = (1u << lb) - 1;
+        for (int32_t p = su + lane; p < eu; p += 64) {
+            const uint32_t x = (uint32_t)adj[p];
+            uint32_t h = hash_slot(x, lb);
+            while (atomicCAS(&hk[h], 0u, x + 1) != 0u) h = (h + 1) & lm;
+            hv[h] = (uint32_t)p;
+        }
+        wave_sync();
+        auto find = [&](uint32_t x) -> int32_t {
+            uint32_t h = hash_slot(x, lb);
+            for (;;) {
+                const uint32_t k = hk[h];
+                if (k == x + 1) return (int32_t)hv[h];
+                if (k == 0) return -1;
+                h = (h + 1) & lm;
+            }
+        };
+        for (int32_t pb = su; pb < eu; pb += 64) {
+            const int32_t p = pb + lane;
+            int64_t a0 = 0, a1 = 0;
+            if (p < eu) {
+                const int32_t v = adj[p];
+                a0 = split[v];
+                a1 = off[v + 1];
+            }
+            nvis += (uint64_t)(a1 - a0);
+            wave_walk_seg(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return (uint32_t)adj[q]; },
+                          [&](int yl, int64_t q, uint32_t w) {
+                              const int32_t xw = find(w);   // arc (u,w) in u's row
+                              if (xw < 0) return;
+                              if (mode == 0) {
+                                  atomicAdd(&te[arc_eid[xw]], 1u);
+                                  atomicAdd(&te[arc_eid[q]], 1u);
+                                  atomicAdd(&wcn[wid][yl], 1u);
+                              } else {
+                                  fill6(pb + yl, xw, (int32_t)q);
+                              }
+                          });
+            if (mode == 0) {
+                const uint32_t c = wcn[wid][lane];
+                if (c) {
+                    atomicAdd(&te[arc_eid[p]], c);
+                    wcn[wid][lane] = 0;
+                }
+                wave_sync();
+            }
+        }
+        for (int q = lane; q <= (int)lm; q += 64) hk[q] = 0;
+        wave_sync();
     }
     if (visits) flush_count(nvis, visits);
 }
@@ -109,8 +184,12 @@ esc_status stage_triangles(esc_ctx *c) {
     if (n == 0) { c->narcs_apex = 0; return ESC_OK; }
     int g = grid_cap(c, (int64_t)n * 64, 256);
     unsigned long long *work = (unsigned long long *)c->buf[B_WORK];
-    k_triangles<<<g, 256, 0, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr,
-                                   work + WORK_VISITS + 1);
+    // per-wave hash sets of twice the largest out-degree, at most 2048 slots
+    int hbits = 1;
+    while ((1 << hbits) < 2 * c->maxdplus && hbits < 11) hbits++;
+    const size_t hlds = sizeof(uint32_t) * 2 * 4 * ((size_t)1 << hbits);
+    k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr, hbits,
+                                      work + WORK_VISITS + 1);
     HIP_TRY(hipGetLastError());
     k_arc_len<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, arc_eid, te, len, tarc);
     HIP_TRY(hipGetLastError());
@@ -125,7 +204,7 @@ esc_status stage_triangles(esc_ctx *c) {
     if (total == 0) return ESC_OK;
     k_copy_cursor<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, aoff, cur);
     HIP_TRY(hipGetLastError());
-    k_triangles<<<g, 256, 0, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, nullptr);
+    k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, hbits, nullptr);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_segsort_u32(c, aa, aoff, m2, c->maxdeg));
     k_apex_ids<<<grid_cap(c, total, 256), 256, 0, st>>>(total, aa, adj, av);

@@ -26,6 +26,35 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_VISIT = 4     # one int32 neighbour / triangle-list entry per visited element
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chung_lu_1m.json")
+
+
+def kernel_sources_sha():
+    """sha256 over the kernel sources (name and bytes of csrc/*.hip, *.h)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1610_09411_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when the kernels have changed
+    since it was taken (or it does not cover the stage)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sources_sha256") != kernel_sources_sha() or stage not in t.get("stages", {}):
+        return None
+    e = t["stages"][stage]
+    return e["fetch_bytes"] + e["write_bytes"]
 
 
 def main():
@@ -113,6 +142,8 @@ def main():
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_vis = prof[dom]
     achieved = dom_vis * BYTES_PER_VISIT / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
+    tbytes = measured_traffic(dom)
+    traffic = tbytes / (dom_ms / 1000.0) / 1e9 if (tbytes is not None and dom_ms > 0) else None
 
     cpu = None
     if rank == 0 and args.cpu_sample > 0:
@@ -152,7 +183,8 @@ def main():
         "config": {"workload": "chung_lu n=1000000 gamma=2.1 mean_degree=20 max_expected_degree=10000 seed=%d"
                                % args.seed, "n": n, "m": m, "k": 5, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": tbytes,
+                     "algorithmic_bytes_per_launch": dom_vis * BYTES_PER_VISIT},
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v[0], 3) for k, v in prof.items()},
         "stages_visits": {k: int(v[1]) for k, v in prof.items()},

@@ -248,6 +248,7 @@ __global__ void k_edges(int32_t n, const int32_t *off, const int32_t *adj, const
 // --------------------------------------------------------- segmented sort
 
 #define SEG_SMALL 32
+#define SEG_WAVE 1024   // segments up to this length are sorted by one wave
 
 __global__ void k_seg_classify(const int64_t *seg_off, int64_t nseg, int32_t *q, int32_t *counts, int64_t qcap,
                                int64_t lds_keys) {
@@ -261,9 +262,9 @@ __global__ void k_seg_classify(const int64_t *seg_off, int64_t nseg, int32_t *q,
         int cls = -1;
         if (s < nseg) {
             int64_t len = seg_off[s + 1] - seg_off[s];
-            if (len > 1) cls = len <= SEG_SMALL ? 0 : (len <= lds_keys ? 1 : 2);
+            if (len > 1) cls = len <= SEG_SMALL ? 0 : (len <= SEG_WAVE ? 1 : (len <= lds_keys ? 2 : 3));
         }
-        for (int c = 0; c < 3; c++) {
+        for (int c = 0; c < 4; c++) {
             const uint64_t m = __ballot(cls == c);
             if (!m) continue;
             const int leader = __ffsll((long long)m) - 1;
@@ -293,12 +294,45 @@ __global__ void k_seg_small(uint32_t *keys, const int64_t *seg_off, const int32_
     }
 }
 
+// medium segments: one wave sorts one segment (bitonic in its LDS region,
+// wave-level barriers only)
+__global__ void __launch_bounds__(256) k_seg_wave(uint32_t *keys, const int64_t *seg_off, const int32_t *q,
+                                                  const int32_t *counts, int64_t qcap) {
+    __shared__ uint32_t sk_all[4][SEG_WAVE];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t *sk = sk_all[wid];
+    const int32_t cnt = counts[1];
+    for (int32_t i = blockIdx.x * 4 + wid; i < cnt; i += gridDim.x * 4) {
+        const int64_t s = q[qcap + i];
+        const int64_t a = seg_off[s];
+        const int len = (int)(seg_off[s + 1] - a);
+        int N = 64;
+        while (N < len) N <<= 1;
+        for (int j = lane; j < N; j += 64) sk[j] = j < len ? keys[a + j] : 0xFFFFFFFFu;
+        wave_sync();
+        for (int k = 2; k <= N; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < N; t += 64) {
+                    const int x = t ^ j;
+                    if (x > t) {
+                        const uint32_t p = sk[t], r = sk[x];
+                        const bool asc = (t & k) == 0;
+                        if ((p > r) == asc) { sk[t] = r; sk[x] = p; }
+                    }
+                }
+                wave_sync();
+            }
+        for (int j = lane; j < len; j += 64) keys[a + j] = sk[j];
+        wave_sync();
+    }
+}
+
 __global__ void __launch_bounds__(256) k_seg_lds(uint32_t *keys, const int64_t *seg_off, const int32_t *q,
                                                  const int32_t *counts, int64_t qcap) {
     extern __shared__ uint32_t sk[];
-    int32_t cnt = counts[1];
+    int32_t cnt = counts[2];
     for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-        int64_t s = q[qcap + i];
+        int64_t s = q[2 * qcap + i];
         int64_t a = seg_off[s];
         int len = (int)(seg_off[s + 1] - a);
         int N = 1;
@@ -325,9 +359,9 @@ __global__ void __launch_bounds__(256) k_seg_lds(uint32_t *keys, const int64_t *
 // rare very long segments: bitonic sort in a padded global buffer, one segment at a time
 __global__ void __launch_bounds__(1024) k_seg_global(uint32_t *keys, const int64_t *seg_off, const int32_t *q,
                                                      const int32_t *counts, int64_t qcap, uint32_t *tmp) {
-    int32_t cnt = counts[2];
+    int32_t cnt = counts[3];
     for (int32_t i = 0; i < cnt; i++) {
-        int64_t s = q[2 * qcap + i];
+        int64_t s = q[3 * qcap + i];
         int64_t a = seg_off[s];
         int64_t len = seg_off[s + 1] - a;
         int64_t N = 1;
@@ -353,7 +387,7 @@ __global__ void __launch_bounds__(1024) k_seg_global(uint32_t *keys, const int64
 
 esc_status dev_segsort_u32(esc_ctx *c, uint32_t *keys, const int64_t *seg_off, int64_t nseg, int32_t maxlen) {
     if (nseg <= 0 || maxlen <= 1) return ESC_OK;
-    int32_t *q = (int32_t *)ctx_buf(c, B_SEGQ, sizeof(int32_t) * (size_t)(3 * nseg + 16));
+    int32_t *q = (int32_t *)ctx_buf(c, B_SEGQ, sizeof(int32_t) * (size_t)(4 * nseg + 16));
     int32_t *counts = (int32_t *)ctx_buf(c, B_SEGCLS, sizeof(int32_t) * 16);
     if (!q || !counts) return ESC_ENOMEM;
     hipStream_t st = c->stream;
@@ -368,6 +402,10 @@ esc_status dev_segsort_u32(esc_ctx *c, uint32_t *keys, const int64_t *seg_off, i
     k_seg_small<<<blocks, 256, 0, st>>>(keys, seg_off, q, counts);
     HIP_TRY(hipGetLastError());
     if (maxlen > SEG_SMALL) {
+        k_seg_wave<<<c->num_cu * 8, 256, 0, st>>>(keys, seg_off, q, counts, nseg);
+        HIP_TRY(hipGetLastError());
+    }
+    if (maxlen > SEG_WAVE) {
         int lds_n = 1;
         while (lds_n < maxlen && lds_n < lds_keys) lds_n <<= 1;
         int g = c->num_cu * 4;

@@ -29,29 +29,29 @@ BYTES_PER_VISIT = 4     # one int32 neighbour / triangle-list entry per visited 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chung_lu_1m.json")
 
 
-def kernel_sources_sha():
-    """sha256 over the kernel sources (name and bytes of csrc/*.hip, *.h)."""
-    import glob
+def kernel_sources_sha(source_file):
+    """sha256 over (name, bytes) of ctx.h, device.h and the kernel's file."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1610_09411_amd", "csrc")
-    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
+    for name in ("ctx.h", "device.h", source_file):
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
 def measured_traffic(stage):
     """HBM bytes per launch of a stage's kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None when the kernels have changed
-    since it was taken (or it does not cover the stage)."""
+    FETCH_SIZE/WRITE_SIZE summary, or None when that kernel's sources have
+    changed since it was taken (or the summary does not cover the stage)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_sources_sha256") != kernel_sources_sha() or stage not in t.get("stages", {}):
+        e = t["stages"][stage]
+        if e["sources_sha256"] != kernel_sources_sha(e["source_file"]):
+            return None
+    except (OSError, ValueError, KeyError):
         return None
     e = t["stages"][stage]
     return e["fetch_bytes"] + e["write_bytes"]

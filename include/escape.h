@@ -62,9 +62,14 @@ enum {
                                   ESC_ERANGE on failure); without it the input
                                   must already be simple, sorted and symmetric */
     ESC_F_INPUT_ON_DEVICE = 4, /* row_ptr / col are device pointers */
-    ESC_F_RANDOM_ORDER = 8     /* orient by a seeded pseudo-random total order
+    ESC_F_RANDOM_ORDER = 8,    /* orient by a seeded pseudo-random total order
                                   instead of the degree order (test hook: counts
                                   do not depend on the order, work does) */
+    ESC_F_COMPACT_LISTS = 16   /* keep the per-edge triangle lists as arc
+                                  positions only (4 B per entry instead of 8;
+                                  apex ids are read through the adjacency).
+                                  Chosen automatically when device memory
+                                  cannot hold both; same counts, slower */
 };
 
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the

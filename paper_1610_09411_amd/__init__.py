@@ -27,6 +27,7 @@ ESC_OK, ESC_EINVAL, ESC_ENOTSIMPLE, ESC_ERANGE, ESC_ENOMEM, ESC_EDEVICE, ESC_EOV
 ESC_F_VALIDATE = 1
 ESC_F_INPUT_ON_DEVICE = 4
 ESC_F_RANDOM_ORDER = 8
+ESC_F_COMPACT_LISTS = 16
 
 ABI_FUNCTIONS = [
     "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments", "esc_count_batched",

@@ -1,4 +1,5 @@
 // C ABI entry points (include/escape.h): context, memory, pipeline order.
+#include <stdio.h>
 #include <stdlib.h>
 #include <limits.h>
 #include <string.h>
@@ -31,6 +32,24 @@ void *ctx_buf(esc_ctx *c, Buf b, size_t bytes) {
         if (hipMemsetAsync(p, 0, want, c->stream) != hipSuccess) return nullptr;
     }
     return p;
+}
+
+size_t ctx_held(const esc_ctx *c, Buf b) { return c->buf[b] ? c->cap[b] : 0; }
+
+void ctx_release(esc_ctx *c, Buf b) {
+    if (!c->buf[b]) return;
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->buf[b]);
+    c->held -= c->cap[b];
+    c->buf[b] = nullptr;
+    c->cap[b] = 0;
+}
+
+// Per-source kernels run two workgroups per CU unless their dense tables
+// (two tables and two touched lists of tab_n entries each) would pass 8 GiB.
+static void set_pair_wgs(esc_ctx *c) {
+    c->wg_per_cu = 2;
+    if (16 * (size_t)c->tab_n * (size_t)(2 * c->num_cu) > ((size_t)8 << 30)) c->wg_per_cu = 1;
 }
 
 extern "C" const char *esc_strerror(esc_status s) {
@@ -75,6 +94,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hipMemcpy(c->d_inv4, h4, sizeof(h4), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_inv5, h5, sizeof(h5), hipMemcpyHostToDevice) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     c->scratch_clean = true;
+    c->wg_per_cu = 2;
     *out = c;
     return ESC_OK;
 }
@@ -123,6 +143,31 @@ __global__ void k_fragments_out(int32_t n, const int32_t *rp, const int32_t *col
 
 // The stages of one call on the graph (or disjoint union) held in c, each
 // bracketed by events on the call's stream (see esc_last_profile).
+// ESC_TRACE=1 in the environment: after every stage, wait for it and print
+// its name and time to stderr (long runs report their progress).
+static bool trace_on() {
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("ESC_TRACE");
+        on = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+static esc_status trace_stage(esc_ctx *c, int ev) {
+    static const char *names[NSTAGES] = {"orient", "triangles", "four_cycles", "k4_triangles", "five_cliques",
+                                         "reduce", "pairs_13_17", "wheels", "five_cycles", "combine"};
+    if (!trace_on() || ev < 1 || ev > NSTAGES) return ESC_OK;
+    HIP_TRY(hipEventSynchronize(c->ev[ev]));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev[ev - 1], c->ev[ev]);
+    fprintf(stderr, "esc: %s done in %.1f ms\n", names[ev - 1], ms);
+    fflush(stderr);
+    return ESC_OK;
+}
+
+// The stages of one call on the graph (or disjoint union) held in c, each
+// bracketed by events on the call's stream (see esc_last_profile).
 static esc_status pipeline(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col, bool per_edge_c4) {
     hipStream_t st = c->stream;
     const int k = c->k;
@@ -134,25 +179,23 @@ static esc_status pipeline(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col
     }
     c->scratch_clean = false;   // until the pipeline completes
     int ev = 0;
+#define STAGE(call)                                  \
+    do {                                             \
+        ESC_TRY(call);                               \
+        HIP_TRY(hipEventRecord(c->ev[ev++], st));    \
+        ESC_TRY(trace_stage(c, ev - 1));             \
+    } while (0)
     HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_orient(c, d_rp, d_col));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_triangles(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_four(c, per_edge_c4));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_k4_triangles(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_k5(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    ESC_TRY(stage_reduce(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_pairs(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_wheels(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
-    if (k == 5) ESC_TRY(stage_cycles(c));
-    HIP_TRY(hipEventRecord(c->ev[ev++], st));
+    STAGE(stage_orient(c, d_rp, d_col));
+    STAGE(stage_triangles(c));
+    STAGE(stage_four(c, per_edge_c4));
+    STAGE(stage_k4_triangles(c));
+    STAGE(k == 5 ? stage_k5(c) : ESC_OK);
+    STAGE(stage_reduce(c));
+    STAGE(k == 5 ? stage_pairs(c) : ESC_OK);
+    STAGE(k == 5 ? stage_wheels(c) : ESC_OK);
+    STAGE(k == 5 ? stage_cycles(c) : ESC_OK);
+#undef STAGE
     return ESC_OK;
 }
 
@@ -212,6 +255,7 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
     c->G = 0;
     c->tab_n = n > 0 ? n : 1;
     c->task_chunk = 1;
+    set_pair_wgs(c);
     const int32_t *d_rp = row_ptr, *d_col = col;
     if (!on_dev) {
         int32_t *brp = (int32_t *)ctx_buf(c, B_RP_IN, sizeof(int32_t) * ((size_t)n + 1));
@@ -309,6 +353,7 @@ esc_status run_batched_device(esc_ctx *c, int32_t G, const int64_t *vtx_off, con
     c->G = G;
     c->tab_n = max_n > 0 ? (int32_t)max_n : 1;
     c->task_chunk = 8;
+    set_pair_wgs(c);
     int64_t *goff = (int64_t *)ctx_buf(c, B_GOFF, sizeof(int64_t) * 2 * ((size_t)G + 1));
     int32_t *urp = (int32_t *)ctx_buf(c, B_URP, sizeof(int32_t) * ((size_t)N + 1));
     int32_t *ucol = (int32_t *)ctx_buf(c, B_UCOL, sizeof(int32_t) * ((size_t)A + 1));

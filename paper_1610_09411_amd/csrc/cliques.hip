@@ -30,16 +30,17 @@ static int grid_cap(esc_ctx *c, int64_t items, int threads, int per_cu = 16) {
 }
 
 // merge-count of two sorted id lists (rows too long for the bitmap)
-__device__ inline uint32_t count_common(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, uint64_t &nvis) {
-    int64_t x = 0, y = 0;
+__device__ inline uint32_t count_common(const int32_t *av, const int32_t *adj, const uint32_t *aa, int64_t x,
+                                        int64_t xe, int64_t y, int64_t ye, uint64_t &nvis) {
+    const int64_t x0 = x, y0 = y;
     uint32_t c = 0;
-    while (x < na && y < nb) {
-        int32_t p = a[x], q = b[y];
+    while (x < xe && y < ye) {
+        const int32_t p = apex_at(av, adj, aa, x), q = apex_at(av, adj, aa, y);
         c += (p == q);
         x += (p <= q);
         y += (q <= p);
     }
-    nvis += x + y;
+    nvis += (x - x0) + (y - y0);
     return c;
 }
 
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
         if (l1 == l0) continue;
         const int32_t a = elo[e], b = adj[p];
         int64_t lo = l0, hi = l1;   // first apex after b
-        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] <= b) lo = mid + 1; else hi = mid; }
+        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
         if (lo == l1) continue;
         const int32_t oa = off[a];
         const int32_t da_i = off[a + 1] - oa;
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
             int32_t cc = 0, pac = 0, pbc = 0;
             int64_t q0 = 0, q1 = 0;
             if (ok) {
-                cc = av[k];
+                cc = apex_at(av, adj, aa, k);
                 pac = (int32_t)aa[k];                  // arc (a,c) in row a
                 pbc = (int32_t)aa[r0 + (k - l0)];      // arc (b,c) in row b
                 q0 = aoff[pac];
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
                                 [&](int32_t pos) { return (bm[pos >> 5] >> (pos & 31)) & 1u; });
                 nvis += q1 - q0;
             } else if (ok) {
-                k4 = count_common(av + l0, l1 - l0, av + q0, q1 - q0, nvis);
+                k4 = count_common(av, adj, aa, l0, l1, q0, q1, nvis);
             }
             if (!ok) continue;
             const int32_t eac = arc_eid[pac], ebc = arc_eid[pbc];
@@ -180,7 +181,7 @@ __global__ void k_ob_rows(int32_t n, const int32_t *off, const int32_t *split, c
             unsigned long long *row = ob + ob_off[c] + (int64_t)(p - sc) * wc;
             const int64_t k1 = aoff[p + 1];
             int64_t k = aoff[p];
-            while (k < k1 && av[k] <= x) k++;   // apexes after x only
+            while (k < k1 && apex_at(av, adj, aa, k) <= x) k++;   // apexes after x only
             for (; k < k1; k++) {
                 int32_t pos = (int32_t)aa[k] - sc;
                 row[pos >> 6] |= 1ull << (pos & 63);
@@ -268,7 +269,7 @@ esc_status stage_k4_triangles(esc_ctx *c) {
         m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
         (const int32_t *)c->buf[B_REV], (const int32_t *)c->buf[B_ARC_EID], (const int32_t *)c->buf[B_EARC],
         (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], (const int64_t *)c->buf[B_AOFF],
-        (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], k4e, gmap_of(c),
+        (const uint32_t *)c->buf[B_AA], c->av, k4e, gmap_of(c),
         (unsigned long long *)c->buf[B_ACC],
         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
     HIP_TRY(hipGetLastError());
@@ -295,7 +296,7 @@ esc_status stage_k5(esc_ctx *c) {
     HIP_TRY(hipMemsetAsync(ob, 0, sizeof(uint64_t) * (size_t)(words + 1), st));
     HIP_TRY(hipMemsetAsync(task + 3, 0, sizeof(int), st));
     k_ob_rows<<<grid_cap(c, (int64_t)n * 64, 256), 256, 0, st>>>(
-        n, off, split, (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV],
+        n, off, split, (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av,
         (const int32_t *)c->buf[B_ADJ], ob_off, ob);
     HIP_TRY(hipGetLastError());
     k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, task + 3, c->task_chunk, gmap_of(c),

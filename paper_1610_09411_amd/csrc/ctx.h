@@ -121,11 +121,14 @@ struct esc_ctx {
     int32_t tab_n;             // extent of a per-workgroup dense table (largest graph)
     int task_chunk;            // sources taken per grab by the per-source kernels
     int32_t *d_inv4, *d_inv5;  // signed inverse matrices (Appendix B), device copies
+    const int32_t *av;         // apex ids of the triangle lists, or nullptr (read through aa)
+    int wg_per_cu;             // workgroups per CU of the per-source kernels
 };
 
 // Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):
-// two per CU; each owns dense tables of tab_n entries in B_WG_SCRATCH.
-inline int pair_wgs(const esc_ctx *c) { return 2 * c->num_cu; }
+// wg_per_cu per CU (two, one when the tables of a large graph would take too
+// much memory); each owns dense tables of tab_n entries in B_WG_SCRATCH.
+inline int pair_wgs(const esc_ctx *c) { return c->wg_per_cu * c->num_cu; }
 
 inline GMap gmap_of(const esc_ctx *c) {
     GMap g;
@@ -137,6 +140,9 @@ inline GMap gmap_of(const esc_ctx *c) {
 
 // Grow-only device buffer; returns nullptr on failure (status set by caller).
 void *ctx_buf(esc_ctx *c, Buf b, size_t bytes);
+// Bytes held by a buffer; release one (it is allocated again on next use).
+size_t ctx_held(const esc_ctx *c, Buf b);
+void ctx_release(esc_ctx *c, Buf b);
 esc_status ctx_check(hipError_t e);
 
 // B_WORK layout: [0] W++, [1] W+-, [2 + s] visits of stage s (see esc_last_profile),

@@ -280,6 +280,13 @@ __device__ inline uint32_t wave_count(int64_t a0, int64_t a1, int64_t *sa, int32
     return r;
 }
 
+// Apex id of triangle-list entry q: the stored id, or, when the lists keep
+// arc positions only (graphs whose lists would not fit twice), the
+// neighbour at that position (av == nullptr).
+__device__ inline int32_t apex_at(const int32_t *av, const int32_t *adj, const uint32_t *aa, int64_t q) {
+    return av ? av[q] : adj[aa[q]];
+}
+
 __device__ inline uint64_t c2(uint64_t x) { return x < 2 ? 0 : x * (x - 1) / 2; }
 __device__ inline u128 c3(uint64_t x) { return x < 3 ? 0 : (u128)x * (x - 1) * (x - 2) / 6; }
 __device__ inline u128 c4(uint64_t x) { return x < 4 ? 0 : (u128)x * (x - 1) * (x - 2) / 6 * (x - 3) / 4; }

@@ -180,6 +180,7 @@ esc_status stage_triangles(esc_ctx *c) {
     unsigned long long *cur = (unsigned long long *)ctx_buf(c, B_ACUR, sizeof(uint64_t) * (size_t)(m2 + 1));
     uint32_t *tarc = (uint32_t *)ctx_buf(c, B_TARC, sizeof(uint32_t) * (size_t)(m2 + 1));
     if (!te || !len || !aoff || !cur || !tarc) return ESC_ENOMEM;
+    c->av = nullptr;
     HIP_TRY(hipMemsetAsync(te, 0, sizeof(uint32_t) * (size_t)(m + 1), st));
     if (n == 0) { c->narcs_apex = 0; return ESC_OK; }
     int g = grid_cap(c, (int64_t)n * 64, 256);
@@ -198,17 +199,36 @@ esc_status stage_triangles(esc_ctx *c) {
     HIP_TRY(hipMemcpyAsync(&total, aoff + m2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     c->narcs_apex = total;
-    uint32_t *aa = (uint32_t *)ctx_buf(c, B_AA, sizeof(uint32_t) * (size_t)(total + 1));
-    int32_t *av = (int32_t *)ctx_buf(c, B_AV, sizeof(int32_t) * (size_t)(total + 1));
-    if (!aa || !av) return ESC_ENOMEM;
+    // The lists hold arc positions (aa); the apex ids (av) are a copy for
+    // faster reads, kept only when device memory has room for both beside
+    // what the later stages allocate (per-edge K4, 5-clique bitmaps bounded
+    // by m (max d+ / 64 + 1) words, per-workgroup tables, 4 GiB margin).
+    const size_t list_bytes = sizeof(uint32_t) * (size_t)(total + 1);
+    size_t later = sizeof(uint64_t) * (size_t)(m + 1) + 16 * (size_t)c->tab_n * (size_t)pair_wgs(c) + ((size_t)4 << 30);
+    if (c->k == 5) later += sizeof(uint64_t) * (size_t)m * (size_t)(c->maxdplus / 64 + 1);
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    size_t avail = fr + ctx_held(c, B_AA) + ctx_held(c, B_AV);   // the two list buffers may be reallocated
+    if (c->budget) {
+        const size_t room = c->budget > c->held ? c->budget - c->held + ctx_held(c, B_AA) + ctx_held(c, B_AV) : 0;
+        if (room < avail) avail = room;
+    }
+    const bool keep_av = avail >= 2 * list_bytes + later && !(c->flags & ESC_F_COMPACT_LISTS);
+    if (!keep_av) ctx_release(c, B_AV);
+    uint32_t *aa = (uint32_t *)ctx_buf(c, B_AA, list_bytes);
+    int32_t *av = keep_av ? (int32_t *)ctx_buf(c, B_AV, list_bytes) : nullptr;
+    if (!aa || (keep_av && !av)) return ESC_ENOMEM;
+    c->av = av;
     if (total == 0) return ESC_OK;
     k_copy_cursor<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, aoff, cur);
     HIP_TRY(hipGetLastError());
     k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, hbits, nullptr);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_segsort_u32(c, aa, aoff, m2, c->maxdeg));
-    k_apex_ids<<<grid_cap(c, total, 256), 256, 0, st>>>(total, aa, adj, av);
-    HIP_TRY(hipGetLastError());
+    if (av) {
+        k_apex_ids<<<grid_cap(c, total, 256), 256, 0, st>>>(total, aa, adj, av);
+        HIP_TRY(hipGetLastError());
+    }
     return ESC_OK;
 }
 

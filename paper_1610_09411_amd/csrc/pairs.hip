@@ -108,19 +108,19 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                     const int64_t x = xb + lane;
                     int64_t a0 = 0, a1 = 0;
                     if (x < e1) {
-                        const int32_t l = av[x];
+                        const int32_t l = apex_at(av, adj, aa, x);
                         if (l > k) {
                             const int32_t qkl = (int32_t)aa[r0 + (x - e0)];   // arc (k,l) in row k
                             int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
                             a1 = hi2;
-                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] <= i) lo2 = mid + 1; else hi2 = mid; }
+                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
                             a0 = lo2;
                         }
                     }
                     nvis += (uint64_t)(a1 - a0);
                     uint64_t acc17 = 0;
                     wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid],
-                              [&](int64_t q) { return av[q]; },
+                              [&](int64_t q) { return apex_at(av, adj, aa, q); },
                               [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? SLAB_GET(j) : TAB_GET(j)) - 2; });
                     sv[1] += acc17;
                 }
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
                 const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
                 if (l1 - l0 < 2) continue;
                 int64_t lo = l0, hi = l1;
-                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] < i) lo = mid + 1; else hi = mid; }
+                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
                 const int nl = (int)(lo - l0);
                 if (nl == 0) continue;
                 if (lane == 0) s_ntw[wid] = 0;
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
                         const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
                         b0 = aoff[qhl];
                         int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
                         b1 = lo2;
                     }
                     nvis += (uint64_t)(b1 - b0);
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
             if (l1 - l0 < 2) continue;   // a rim 4-cycle needs two triangles on (h,i)
             // entries l of list(h,i) below i
             int64_t lo = l0, hi = l1;
-            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (av[mid] < i) lo = mid + 1; else hi = mid; }
+            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
             const int nl = (int)(lo - l0);
             if (nl == 0) continue;
             if (threadIdx.x == 0) s_nt = 0;
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
                         const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
                         b0 = aoff[qhl];
                         int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (av[mid] < i) lo2 = mid + 1; else hi2 = mid; }
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
                         b1 = lo2;
                     }
                     nvis += (uint64_t)(b1 - b0);
@@ -473,7 +473,7 @@ esc_status stage_pairs(esc_ctx *c) {
     k_pairs_wd<<<pair_wgs(c), 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                           n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
-                                          (const uint32_t *)c->buf[B_AA], (const int32_t *)c->buf[B_AV], tab, touch,
+                                          (const uint32_t *)c->buf[B_AA], c->av, tab, touch,
                                           c->tab_n, c->task_chunk, gmap_of(c), task, slab,
                                           (unsigned long long *)c->buf[B_ACC],
                                           (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
@@ -497,15 +497,15 @@ esc_status stage_wheels(esc_ctx *c) {
     size_t lds = sizeof(uint32_t) * ((size_t)(lds_cap + 1) / 2) + sizeof(uint16_t) * (size_t)lds_cap + 16;
     size_t lds_waves = sizeof(uint32_t) * 4 * 2 * (size_t)((lds_cap / 4 + 1) / 2) + 16;   // four one-wave tables
     if (lds_waves > lds) lds = lds_waves;
-    // as many 4-wave workgroups per CU as LDS holds (up to 4): the walk is
-    // bound by load latency, so resident waves matter; the global tables
-    // have room for 4 per CU
+    // as many 4-wave workgroups per CU as LDS holds: the walk is bound by
+    // load latency, so resident waves matter; the global tables have room
+    // for 2 * wg_per_cu per CU
     int per_cu = (int)(c->max_lds / (lds + 10240));
-    if (per_cu > 4) per_cu = 4;
+    if (per_cu > 2 * c->wg_per_cu) per_cu = 2 * c->wg_per_cu;
     if (per_cu < 1) per_cu = 1;
     k_wheels<<<c->num_cu * per_cu, 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
-                                              (const int32_t *)c->buf[B_AV], tab, touch, c->tab_n, lds_cap,
+                                              c->av, tab, touch, c->tab_n, lds_cap,
                                               c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],
                                               (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
     HIP_TRY(hipGetLastError());

@@ -119,6 +119,19 @@ def test_random_order_gives_same_counts(ctx):
     assert ctx.count(g, 5, flags=esc.ESC_F_RANDOM_ORDER) == ctx.count(g, 5)
 
 
+def test_compact_lists_give_same_counts(ctx):
+    """Triangle lists without apex ids (read through the adjacency), the
+    layout chosen when device memory is short."""
+    import paper_1610_09411_amd as esc
+    for g in (synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2), synth.chung_lu(12000, 1.9, 30.0, 3000.0, 3)):
+        assert ctx.count(g, 5, flags=esc.ESC_F_COMPACT_LISTS) == ctx.count(g, 5)
+    g = synth.chung_lu(3000, 2.1, 12.0, 400.0, 1)
+    assert ctx.count(g, 5, flags=esc.ESC_F_COMPACT_LISTS) == oracle.count(g, 5, threads=8)
+    counts, fr = ctx.fragments(g, 4, flags=esc.ESC_F_COMPACT_LISTS)
+    S, it = oracle.sums(g, 4, per_item=True)
+    assert np.array_equal(fr["k4_e"], it["k4_e"])
+
+
 def test_repeat_calls_are_identical(ctx):
     g = synth.chung_lu(8000, 2.0, 16.0, 900.0, 4)
     a = ctx.count(g, 5)

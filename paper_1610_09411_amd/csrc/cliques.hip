@@ -203,36 +203,65 @@ __device__ inline int nth_set_bit(const unsigned long long *row, int words, int 
     return -1;
 }
 
-// one workgroup per vertex a; items = pairs (b, c) with c in row(a,b)
+// Work of vertex a grows like d+(a)^3 / 64 word operations, so a is split
+// into units of ch out-neighbours b, ch = min(256, 2^24 / d+(a)^2): a hub
+// spreads over many workgroups.
+__device__ inline int k5_chunk(int32_t dp) {
+    const int64_t q = ((int64_t)1 << 24) / ((int64_t)dp * dp);
+    return q >= 256 ? 256 : (q < 1 ? 1 : (int)q);
+}
+
+__global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, int64_t *len) {
+    for (int32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+        const int32_t dp = off[a + 1] - split[a];
+        len[a] = dp < 4 ? 0 : (dp + k5_chunk(dp) - 1) / k5_chunk(dp);
+    }
+}
+
+// one workgroup per unit (a, block of out-neighbours b); items = pairs
+// (b, c) with c in row(a,b); units are taken latest vertex first
 __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const int32_t *split,
-                                            const int64_t *ob_off, const unsigned long long *ob, int *task,
-                                            int chunk, GMap gm, unsigned long long *acc,
-                                            unsigned long long *visits) {
+                                            const int64_t *ob_off, const unsigned long long *ob,
+                                            const int64_t *uoff, int64_t nunits, int *task, GMap gm,
+                                            unsigned long long *acc, unsigned long long *visits) {
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
-    __shared__ int s_a;
+    __shared__ int64_t s_u;
+    __shared__ int32_t s_a;
     __shared__ u128 red[4];
     const int ids[1] = {AC_K5};
     u128 k5[1] = {0};
     int gcur = -1;
     uint64_t nvis = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_a = atomicAdd(task, 1);
+        if (threadIdx.x == 0) {
+            const int64_t t = atomicAdd(task, 1);
+            s_u = t < nunits ? nunits - 1 - t : -1;
+            if (s_u >= 0) {
+                int32_t lo = 0, hi = n - 1;   // last a with uoff[a] <= u
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (uoff[mid] <= s_u) lo = mid; else hi = mid - 1;
+                }
+                s_a = lo;
+            }
+        }
         __syncthreads();
-        const int64_t a0 = (int64_t)s_a * chunk;
-        if (a0 >= n) break;
-        const int32_t a1 = (int32_t)(a0 + chunk < n ? a0 + chunk : n);
-        __syncthreads();   // s_a is read by every thread before it is taken again
-        for (int32_t a = (int32_t)a0; a < a1; a++) {
+        const int64_t u = s_u;
+        const int32_t a = s_a;
+        __syncthreads();   // s_u, s_a are read by every thread before they are taken again
+        if (u < 0) break;
         block_switch_graph<1>(k5, gcur, gm.graph(a), red, acc, ACC_STRIDE, ids);
         const int32_t dpa = off[a + 1] - split[a];
-        if (dpa < 4) continue;
+        const int ch = k5_chunk(dpa);
+        const int32_t ib0 = (int32_t)(u - uoff[a]) * ch;
+        const int32_t ib1 = ib0 + ch < dpa ? ib0 + ch : dpa;
         const int wa = (dpa + 63) >> 6;
         const unsigned long long *rows = ob + ob_off[a];
-        for (int ib = 0; ib < dpa; ib += blockDim.x) {
+        for (int ib = ib0; ib < ib1; ib += blockDim.x) {
             int i = ib + threadIdx.x;
             int len = 0;
-            if (i < dpa)
+            if (i < ib1)
                 for (int w = 0; w < wa; w++) len += __popcll(rows[(int64_t)i * wa + w]);
             lbs_batch(0, len, pref, beg, tmp, [&](int s, int64_t r) {
                 const unsigned long long *rb = rows + (int64_t)(ib + s) * wa;
@@ -249,7 +278,6 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
                     }
                 }
             });
-        }
         }
     }
     if (gcur >= 0) block_flush_u128<1>(k5, red, acc + (size_t)gcur * ACC_STRIDE, ids);
@@ -299,7 +327,17 @@ esc_status stage_k5(esc_ctx *c) {
         n, off, split, (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av,
         (const int32_t *)c->buf[B_ADJ], ob_off, ob);
     HIP_TRY(hipGetLastError());
-    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, task + 3, c->task_chunk, gmap_of(c),
+    // units of work (see k5_chunk): per-vertex counts, then offsets
+    int64_t *uoff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
+    if (!uoff) return ESC_ENOMEM;
+    k_k5_units<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, len);
+    HIP_TRY(hipGetLastError());
+    ESC_TRY(dev_exclusive_scan_i64(c, len, uoff, n));
+    int64_t nunits = 0;
+    HIP_TRY(hipMemcpyAsync(&nunits, uoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (nunits == 0) return ESC_OK;
+    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, nunits, task + 3, gmap_of(c),
                                         (unsigned long long *)c->buf[B_ACC],
                                         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4);
     HIP_TRY(hipGetLastError());

@@ -62,6 +62,7 @@ enum Buf {
     B_TASK,
     B_FRAG,                     // fragment outputs in input order
     B_OB, B_OB_OFF,             // out-neighbourhood bitmaps for 5-cliques
+    B_K5_UNITS,                 // offsets of the 5-clique work units per vertex
     B_GOFF,                     // batched: vertex and arc offsets of the graphs (int64, 2 x (G+1))
     B_VGRAPH,                   // batched: graph of each union vertex id (= of each rank)
     B_URP, B_UCOL,              // batched: CSR of the disjoint union

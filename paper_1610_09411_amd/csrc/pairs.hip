@@ -160,22 +160,22 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // lives in LDS when d(h) fits, else in the workgroup's global scratch.  In
 // LDS a count is below d(h) <= lds_cap < 2^16, so two counts share a word
 // (16 bits each; one 32-bit atomic adds 1 << 16 for odd keys) and the
-// touched keys are 16-bit.  A hub with d(h) <= lds_cap / 4 gives each of
-// the four waves its own table and rim vertices, with no workgroup barrier
-// per rim vertex.
-__global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
+// touched keys are 16-bit.  A hub with d(h) <= lds_cap / WHEEL_WAVES gives
+// each wave its own table and rim vertices, with no workgroup barrier per
+// rim vertex.
+#define WHEEL_WAVES 8   // waves per workgroup of the wheel pass
+
+__global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
                                                 int32_t lds_cap, int chunk, GMap gm, int *task,
                                                 unsigned long long *acc, unsigned long long *visits) {
     uint64_t nvis = 0;
     extern __shared__ uint32_t dyn[];
-    __shared__ int pref[257], tmp[8];
-    __shared__ int64_t beg[257];
-    __shared__ int s_h, s_nt, s_ntw[4];
+    __shared__ int s_h, s_nt, s_ntw[WHEEL_WAVES];
     __shared__ u128 red[4];
-    __shared__ int64_t wsa[4][64];
-    __shared__ int32_t wse[4][64], wsi[4][64];
+    __shared__ int64_t wsa[WHEEL_WAVES][64];
+    __shared__ int32_t wse[WHEEL_WAVES][64], wsi[WHEEL_WAVES][64];
     const int ids[1] = {AC_N18};
     u128 s18[1] = {0};
     int gcur = -1;
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_wheels(int32_t n, const int32_t *off, c
         int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
         uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
         uint16_t *ltch = (uint16_t *)(dyn + (lds_cap + 1) / 2);      // lds_cap keys
-        const int32_t wq = lds_cap / 4;   // largest d(h) of the one-wave-per-rim-vertex mode
+        const int32_t wq = lds_cap / WHEEL_WAVES;   // largest d(h) of the one-wave-per-rim-vertex mode
         if (dh <= wq) {
             // small hub: each wave takes its own rim vertices i with its own
             // table, so no workgroup barrier is needed per i
@@ -495,15 +495,15 @@ esc_status stage_wheels(esc_ctx *c) {
     if (lds_cap > 32768) lds_cap = 32768;
     if (c->maxdeg + 1 < lds_cap) lds_cap = c->maxdeg + 1;
     size_t lds = sizeof(uint32_t) * ((size_t)(lds_cap + 1) / 2) + sizeof(uint16_t) * (size_t)lds_cap + 16;
-    size_t lds_waves = sizeof(uint32_t) * 4 * 2 * (size_t)((lds_cap / 4 + 1) / 2) + 16;   // four one-wave tables
+    size_t lds_waves = sizeof(uint32_t) * WHEEL_WAVES * 2 * (size_t)((lds_cap / WHEEL_WAVES + 1) / 2) + 16;   // one-wave tables
     if (lds_waves > lds) lds = lds_waves;
-    // as many 4-wave workgroups per CU as LDS holds: the walk is bound by
+    // as many workgroups per CU as LDS holds: the walk is bound by
     // load latency, so resident waves matter; the global tables have room
     // for 2 * wg_per_cu per CU
     int per_cu = (int)(c->max_lds / (lds + 10240));
     if (per_cu > 2 * c->wg_per_cu) per_cu = 2 * c->wg_per_cu;
     if (per_cu < 1) per_cu = 1;
-    k_wheels<<<c->num_cu * per_cu, 256, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    k_wheels<<<c->num_cu * per_cu, 64 * WHEEL_WAVES, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               c->av, tab, touch, c->tab_n, lds_cap,
                                               c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],

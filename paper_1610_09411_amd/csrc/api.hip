@@ -45,11 +45,13 @@ void ctx_release(esc_ctx *c, Buf b) {
     c->cap[b] = 0;
 }
 
-// Per-source kernels run two workgroups per CU unless their dense tables
-// (two tables and two touched lists of tab_n entries each) would pass 8 GiB.
+// Per-source kernels run three workgroups per CU (more resident waves for
+// their latency-bound gathers), fewer when their dense tables (two tables and
+// two touched lists of tab_n entries each) would pass a tenth of the device.
 static void set_pair_wgs(esc_ctx *c) {
-    c->wg_per_cu = 2;
-    if (16 * (size_t)c->tab_n * (size_t)(2 * c->num_cu) > ((size_t)8 << 30)) c->wg_per_cu = 1;
+    c->wg_per_cu = 3;
+    while (c->wg_per_cu > 1 && 16 * (size_t)c->tab_n * (size_t)(c->wg_per_cu * c->num_cu) > c->dev_mem / 10)
+        c->wg_per_cu--;
 }
 
 extern "C" const char *esc_strerror(esc_status s) {
@@ -94,6 +96,9 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hipMemcpy(c->d_inv4, h4, sizeof(h4), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_inv5, h5, sizeof(h5), hipMemcpyHostToDevice) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     c->scratch_clean = true;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = (size_t)64 << 30;
+    c->dev_mem = tot;
     c->wg_per_cu = 2;
     *out = c;
     return ESC_OK;

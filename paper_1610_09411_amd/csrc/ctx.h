@@ -124,12 +124,27 @@ struct esc_ctx {
     int32_t *d_inv4, *d_inv5;  // signed inverse matrices (Appendix B), device copies
     const int32_t *av;         // apex ids of the triangle lists, or nullptr (read through aa)
     int wg_per_cu;             // workgroups per CU of the per-source kernels
+    size_t dev_mem;            // device memory in bytes
 };
 
 // Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):
 // wg_per_cu per CU (two, one when the tables of a large graph would take too
 // much memory); each owns dense tables of tab_n entries in B_WG_SCRATCH.
 inline int pair_wgs(const esc_ctx *c) { return c->wg_per_cu * c->num_cu; }
+// The 4-cycle and pattern 13/17 kernels gain more from a large LDS slab than
+// from a third workgroup per CU: at most two per CU.
+inline int slab_wgs_per_cu(const esc_ctx *c) { return c->wg_per_cu < 2 ? c->wg_per_cu : 2; }
+
+// LDS words per slab for a per-source kernel with `nslabs` slabs, at most
+// `cap`, so that wgs_per_cu workgroups fit in one CU's LDS next to the
+// kernel's static arrays.
+inline int32_t slab_words(const esc_ctx *c, int wgs_per_cu, int nslabs, int32_t cap, int static_bytes) {
+    int64_t w = ((int64_t)c->max_lds / wgs_per_cu - static_bytes) / (4 * nslabs);
+    if (w > cap) w = cap;
+    if (w > c->tab_n) w = c->tab_n;
+    if (w < 0) w = 0;
+    return (int32_t)w;
+}
 
 inline GMap gmap_of(const esc_ctx *c) {
     GMap g;

@@ -377,11 +377,8 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
         HIP_TRY(hipMemsetAsync(c4e, 0, sizeof(uint64_t) * (size_t)(c->m + 1), st));
     }
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
-    int32_t slab = (c->max_lds - 16384) / 4;
-    if (slab > 16384) slab = 16384;
-    if (slab > c->tab_n) slab = c->tab_n;
-    if (slab < 0) slab = 0;
-    k_four_cycles<<<nwg, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
+    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 8192);
+    k_four_cycles<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
                                        (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],

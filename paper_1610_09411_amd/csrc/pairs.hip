@@ -466,11 +466,8 @@ esc_status stage_pairs(esc_ctx *c) {
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
-    int32_t slab = (c->max_lds - 16384) / 4;
-    if (slab > 16384) slab = 16384;
-    if (slab > c->tab_n) slab = c->tab_n;
-    if (slab < 0) slab = 0;
-    k_pairs_wd<<<pair_wgs(c), 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
+    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 16384);
+    k_pairs_wd<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                           n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
                                           (const uint32_t *)c->buf[B_AA], c->av, tab, touch,
@@ -522,10 +519,7 @@ esc_status stage_cycles(esc_ctx *c) {
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     int nwg = pair_wgs(c);
     // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays
-    int32_t slab = (c->max_lds - 16384) / 8;
-    if (slab > 8192) slab = 8192;
-    if (slab > c->tab_n) slab = c->tab_n;
-    if (slab < 0) slab = 0;
+    const int32_t slab = slab_words(c, c->wg_per_cu, 2, 8192, 8192);
     k_five_cycles<<<nwg, 512, sizeof(uint32_t) * (size_t)(2 * slab > 0 ? 2 * slab : 1), st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,

@@ -287,6 +287,13 @@ __device__ inline int32_t apex_at(const int32_t *av, const int32_t *adj, const u
     return av ? av[q] : adj[aa[q]];
 }
 
+// Counts bounded by d pack 32 / 2^shift to a 32-bit word: 2-bit fields for
+// d < 4, 4-bit for d < 16, 8-bit for d < 256, 16-bit for d < 2^16.
+// Returns shift = log2(fields per word).
+__device__ inline int count_shift(int64_t d) {
+    return d < 4 ? 4 : (d < 16 ? 3 : (d < 256 ? 2 : (d < 65536 ? 1 : 0)));
+}
+
 __device__ inline uint64_t c2(uint64_t x) { return x < 2 ? 0 : x * (x - 1) / 2; }
 __device__ inline u128 c3(uint64_t x) { return x < 3 ? 0 : (u128)x * (x - 1) * (x - 2) / 6; }
 __device__ inline u128 c4(uint64_t x) { return x < 4 ? 0 : (u128)x * (x - 1) * (x - 2) / 6 * (x - 3) / 4; }

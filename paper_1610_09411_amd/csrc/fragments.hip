@@ -278,9 +278,10 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
             const int32_t gb = gm.begin(g), ge = gm.end(g);
             const int32_t oh = off[h], sh = split[h];
             const int64_t dh = off[h + 1] - oh;
-            // c(h,o) <= d(h): a low-degree top vertex packs 4 or 2 counts per
-            // word, in LDS (4x or 2x more latest ranks) and in the table
-            const int shift = dh < 256 ? 2 : (dh < 65536 ? 1 : 0);
+            // c(h,o) <= d(h): a low-degree top vertex packs 16, 8, 4 or 2
+            // counts per word (count_shift), in LDS (that many times more
+            // latest ranks) and in the table
+            const int shift = count_shift(dh);
             const int cb = 32 >> shift;
             const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
             const int32_t hi0 = ge - (slab << shift) > gb ? ge - (slab << shift) : gb;   // first key held in LDS

@@ -62,10 +62,11 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         block_switch_graph<2>(sv, gcur, g, red, acc, ACC_STRIDE, ids);
         const int32_t gb = gm.begin(g), ge = gm.end(g);
         const int32_t oi = off[i], ei = off[i + 1];
-        // W(i,j) <= d(i): counts of a low-degree source are packed 4 or 2 to
-        // a word, so the LDS slab covers 4x or 2x as many latest ranks and
-        // the workgroup table touches 4x or 2x fewer cache lines
-        const int shift = ei - oi < 256 ? 2 : (ei - oi < 65536 ? 1 : 0);   // log2(counts per word)
+        // W(i,j) <= d(i): counts of a low-degree source are packed 16, 8, 4
+        // or 2 to a word (count_shift), so the LDS slab covers that many
+        // times more latest ranks and the workgroup table touches that many
+        // times fewer cache lines
+        const int shift = count_shift(ei - oi);   // log2(counts per word)
         const int cb = 32 >> shift;                                        // bits per count
         const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
         const int32_t sranks = slab << shift;
@@ -353,9 +354,9 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         // tables are indexed by rank relative to the start of i's graph
         const int32_t gb = gm.begin(g), ge = gm.end(g);
         const int32_t oi = off[i], si = split[i], ei = off[i + 1];
-        // X(i,b) and Wnt(i,j) never exceed d(i): a low-degree source packs 4
-        // or 2 counts per word, in LDS and in the workgroup tables
-        const int shift = ei - oi < 256 ? 2 : (ei - oi < 65536 ? 1 : 0);
+        // X(i,b) and Wnt(i,j) never exceed d(i): a low-degree source packs
+        // several counts per word (count_shift), in LDS and in the tables
+        const int shift = count_shift(ei - oi);
         const int cb = 32 >> shift;
         const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
         const int32_t hi0 = ge - (slab << shift) > gb ? ge - (slab << shift) : gb;   // first key held in LDS

@@ -53,7 +53,8 @@ typedef enum {
     ESC_ERANGE = 3,      /* a column id outside [0, n), or row_ptr not monotone */
     ESC_ENOMEM = 4,      /* device allocation failed or exceeds the context budget */
     ESC_EDEVICE = 5,     /* a HIP runtime call failed */
-    ESC_EOVERFLOW = 6    /* a count does not fit the requested output width */
+    ESC_EOVERFLOW = 6,   /* a count does not fit the requested output width */
+    ESC_EBUSY = 7        /* the server's queue is full (esc_submit); retry later */
 } esc_status;
 
 /* Flags for esc_count_subgraphs. */
@@ -61,6 +62,15 @@ enum {
     ESC_F_VALIDATE = 1,        /* check the CSR on the device (ESC_ENOTSIMPLE /
                                   ESC_ERANGE on failure); without it the input
                                   must already be simple, sorted and symmetric */
+    ESC_F_CANONICALIZE = 2,    /* esc_count_subgraphs only: take any CSR (rows
+                                  unsorted, repeated entries, self-loops, edges
+                                  listed in one row only; row_ptr[n] may be odd)
+                                  and count the simple undirected graph it
+                                  describes: every entry (u,v), u != v, is the
+                                  edge {u,v}.  Done on the device; ids must be
+                                  in [0,n) (else ESC_ERANGE).  Not accepted by
+                                  esc_count_fragments or esc_count_batched
+                                  (ESC_EINVAL) */
     ESC_F_INPUT_ON_DEVICE = 4, /* row_ptr / col are device pointers */
     ESC_F_RANDOM_ORDER = 8,    /* orient by a seeded pseudo-random total order
                                   instead of the degree order (test hook: counts
@@ -167,7 +177,8 @@ esc_status esc_server_start(esc_ctx *ctx, int max_inflight, esc_server **out);
 /* Queue a count request.  The CSR (host memory, layout as in
  * esc_count_subgraphs) is copied before return; offsets are checked here
  * (ESC_ERANGE / ESC_ENOTSIMPLE / ESC_EINVAL), the rest on the device when the
- * request runs.  *ticket identifies the request in esc_poll / esc_wait. */
+ * request runs.  *ticket identifies the request in esc_poll / esc_wait.
+ * ESC_EBUSY: 2^20 requests are already waiting. */
 esc_status esc_submit(esc_server *srv, int32_t n, const int32_t *row_ptr,
                       const int32_t *col, int k, uint64_t *ticket);
 

@@ -23,8 +23,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libescape.so")
 
-ESC_OK, ESC_EINVAL, ESC_ENOTSIMPLE, ESC_ERANGE, ESC_ENOMEM, ESC_EDEVICE, ESC_EOVERFLOW = range(7)
+ESC_OK, ESC_EINVAL, ESC_ENOTSIMPLE, ESC_ERANGE, ESC_ENOMEM, ESC_EDEVICE, ESC_EOVERFLOW, ESC_EBUSY = range(8)
 ESC_F_VALIDATE = 1
+ESC_F_CANONICALIZE = 2
 ESC_F_INPUT_ON_DEVICE = 4
 ESC_F_RANDOM_ORDER = 8
 ESC_F_COMPACT_LISTS = 16

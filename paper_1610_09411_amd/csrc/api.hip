@@ -63,6 +63,7 @@ extern "C" const char *esc_strerror(esc_status s) {
         case ESC_ENOMEM: return "device memory exhausted or over the context budget";
         case ESC_EDEVICE: return "HIP runtime error";
         case ESC_EOVERFLOW: return "count does not fit the output width";
+        case ESC_EBUSY: return "server queue full";
     }
     return "unknown status";
 }
@@ -249,8 +250,10 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
         rp0 = row_ptr[0];
         m2 = row_ptr[n];
     }
+    const bool canon = (flags & ESC_F_CANONICALIZE) != 0;
+    if (canon && frag) return ESC_EINVAL;   // fragments follow the caller's arcs, which canonicalising changes
     if (rp0 != 0 || m2 < 0) return ESC_ERANGE;
-    if (m2 & 1) return ESC_ENOTSIMPLE;
+    if ((m2 & 1) && !canon) return ESC_ENOTSIMPLE;
     if (m2 > 0 && !col) return ESC_EINVAL;
     c->n = n;
     c->m2 = m2;
@@ -270,6 +273,13 @@ static esc_status run(esc_ctx *c, int32_t n, const int32_t *row_ptr, const int32
         if (m2) HIP_TRY(hipMemcpyAsync(bcol, col, sizeof(int32_t) * (size_t)m2, hipMemcpyHostToDevice, st));
         d_rp = brp;
         d_col = bcol;
+    }
+    if (canon) {
+        int64_t cm2 = 0;
+        ESC_TRY(canonicalize(c, n, d_rp, d_col, &d_rp, &d_col, &cm2));
+        c->m2 = cm2;
+        c->m = cm2 / 2;
+        c->flags &= ~(uint32_t)ESC_F_VALIDATE;   // the canonical CSR is simple by construction
     }
     unsigned long long *acc = (unsigned long long *)ctx_buf(c, B_ACC, sizeof(uint64_t) * ACC_STRIDE);
     if (!acc) return ESC_ENOMEM;
@@ -333,6 +343,7 @@ __global__ void k_union(int32_t G, int32_t N, int32_t A, const int64_t *voff, co
 esc_status run_batched_device(esc_ctx *c, int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
                               const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags, void *stream) {
     if (!c || (k != 4 && k != 5) || G <= 0 || !vtx_off || !arc_off) return ESC_EINVAL;
+    if (flags & ESC_F_CANONICALIZE) return ESC_EINVAL;
     if (vtx_off[0] != 0 || arc_off[0] != 0) return ESC_ERANGE;
     int64_t max_n = 0;
     for (int32_t g = 0; g < G; g++) {

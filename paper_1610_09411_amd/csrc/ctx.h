@@ -63,6 +63,8 @@ enum Buf {
     B_FRAG,                     // fragment outputs in input order
     B_OB, B_OB_OFF,             // out-neighbourhood bitmaps for 5-cliques
     B_K5_UNITS,                 // offsets of the 5-clique work units per vertex
+    B_CAN_CNT, B_CAN_LEN, B_CAN_OFF, B_CAN_UOFF, B_CAN_ARCS,   // canonicalisation work
+    B_CAN_RP, B_CAN_COL,        // canonical CSR
     B_GOFF,                     // batched: vertex and arc offsets of the graphs (int64, 2 x (G+1))
     B_VGRAPH,                   // batched: graph of each union vertex id (= of each rank)
     B_URP, B_UCOL,              // batched: CSR of the disjoint union
@@ -195,6 +197,10 @@ esc_status run_batched_device(esc_ctx *c, int32_t G, const int64_t *vtx_off, con
 esc_status combine_tables(int32_t *host_inv4, int32_t *host_inv5);
 esc_status stage_fragments_out(esc_ctx *c, uint64_t *tri_v, uint64_t *c4_v, uint64_t *k4_v,
                                uint64_t *tri_e, uint64_t *c4_e, uint64_t *k4_e);
+
+// simple sorted symmetric CSR from any input CSR (canon.hip)
+esc_status canonicalize(esc_ctx *c, int32_t n, const int32_t *d_rp, const int32_t *d_col, const int32_t **rp_out,
+                        const int32_t **col_out, int64_t *m2_out);
 
 // generic device primitives (orient.hip)
 esc_status dev_exclusive_scan_i64(esc_ctx *c, const int64_t *in, int64_t *out, int64_t n);

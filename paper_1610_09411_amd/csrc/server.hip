@@ -49,6 +49,7 @@ struct esc_server {
     int32_t small_n;           // requests up to this size may share a launch
     int max_group;             // requests per batched launch
     int nwg;                   // workgroups of the per-source kernels (table footprint)
+    size_t max_queue = 1 << 20;   // requests waiting at most; esc_submit returns ESC_EBUSY beyond
     std::mutex mu;
     std::condition_variable cv;        // queue, memory or stop changed
     std::condition_variable cv_done;   // a request finished
@@ -263,6 +264,10 @@ extern "C" esc_status esc_submit(esc_server *s, int32_t n, const int32_t *row_pt
     if (s->stopping) {
         delete r;
         return ESC_EINVAL;
+    }
+    if (s->queue.size() >= s->max_queue) {   // back-pressure
+        delete r;
+        return ESC_EBUSY;
     }
     r->ticket = s->next_ticket++;
     s->reqs[r->ticket] = r;

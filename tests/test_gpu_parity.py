@@ -132,6 +132,51 @@ def test_compact_lists_give_same_counts(ctx):
     assert np.array_equal(fr["k4_e"], it["k4_e"])
 
 
+def _messy_csr(g, seed):
+    """The same graph written carelessly: each edge in one row or both,
+    some entries repeated, self-loops added, rows unsorted."""
+    rng = np.random.default_rng(seed)
+    rows = [[] for _ in range(g.n)]
+    for u in range(g.n):
+        for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]]:
+            v = int(v)
+            if u < v:
+                r = rng.integers(3)
+                if r == 0:
+                    rows[u].append(v)
+                elif r == 1:
+                    rows[v].append(u)
+                else:
+                    rows[u].append(v)
+                    rows[v].append(u)
+                if rng.integers(5) == 0:
+                    rows[u].append(v)
+        if rng.integers(7) == 0:
+            rows[u].append(u)
+    for r in rows:
+        rng.shuffle(r)
+    rp = np.zeros(g.n + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([x for r in rows for x in r], np.int32)
+    return synth.Graph(g.n, rp, col)
+
+
+def test_canonicalize_counts_the_described_graph(ctx):
+    import paper_1610_09411_amd as esc
+    for g in (synth.chung_lu(3000, 2.1, 12.0, 400.0, 1), synth.er_small(2), synth.from_edges(6, [])):
+        messy = _messy_csr(g, 7)
+        got = ctx.count(messy, 5, flags=esc.ESC_F_CANONICALIZE)
+        assert got == oracle.count(g, 5, threads=8), g.name
+        assert ctx.last_work()["m"] == g.m
+    bad = synth.Graph(3, np.array([0, 1, 2, 3], np.int32), np.array([1, 2, 5], np.int32))
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.count(bad, 5, flags=esc.ESC_F_CANONICALIZE)
+    assert e.value.status == esc.ESC_ERANGE
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.fragments(synth.er_small(2), 5, flags=esc.ESC_F_CANONICALIZE)
+    assert e.value.status == esc.ESC_EINVAL
+
+
 def test_repeat_calls_are_identical(ctx):
     g = synth.chung_lu(8000, 2.0, 16.0, 900.0, 4)
     a = ctx.count(g, 5)

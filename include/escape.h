@@ -202,6 +202,46 @@ esc_status esc_server_stats(esc_server *srv, uint64_t *out);
  * its contexts.  Tickets not yet collected are dropped. */
 esc_status esc_server_stop(esc_server *srv);
 
+/* ------------------------------------------------------------- tuning
+ *
+ * Launch parameters of the per-source kernels (4-cycles, pair passes,
+ * wheels, 5-cycles) and of the 5-clique pass.  A context keeps a table of
+ * tuned parameters keyed by the graph's degree statistics (log2 of n, of the
+ * mean degree and of the largest degree, batched or not); a call uses the
+ * parameters set with esc_set_params, else the table's entry for its key,
+ * else the defaults.  Parameters change speed only, never counts. */
+typedef struct {
+    int32_t task_chunk;     /* sources taken per grab by a workgroup, 1..64
+                               (default 1; 8 for batched calls) */
+    int32_t wg_per_cu;      /* workgroups per CU of the per-source kernels, 1..3
+                               (default 3; lowered when their tables would pass a
+                               tenth of device memory) */
+    int32_t k5_work_log2;   /* 5-cliques: a vertex with out-degree d is split
+                               into units of min(256, 2^k5_work_log2 / d^2)
+                               out-neighbours, 16..30 (default 24) */
+    int32_t reserved;       /* 0 */
+} esc_params;
+
+/* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}
+ * x wg_per_cu in {1, 2, 3}, then k5_work_log2 in {22, 24, 26} for k = 5),
+ * keep the fastest (total device time of the call) in the context's table
+ * under the graph's key and return it in *best, its time in *best_ms
+ * (nullable).  Arguments as in esc_count_subgraphs. */
+esc_status esc_tune(esc_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col, int k,
+                    uint32_t flags, esc_params *best, float *best_ms, void *stream);
+
+/* The same for a batch (arguments as in esc_count_batched, without outputs). */
+esc_status esc_tune_batched(esc_ctx *ctx, int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                            const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags,
+                            esc_params *best, float *best_ms, void *stream);
+
+/* Force these parameters on every later call of the context (NULL: back to
+ * the table and the defaults).  ESC_EINVAL when a field is out of range. */
+esc_status esc_set_params(esc_ctx *ctx, const esc_params *params);
+
+/* Parameters the last successful call ran with. */
+esc_status esc_last_params(const esc_ctx *ctx, esc_params *out);
+
 /* Work counters of the last successful call on this context (Thm fourvertex
  * and Thm fivevertex state the running time in these terms):
  *   [0] W++  out-wedges of the DAG      [1] W+-  in-out wedges

@@ -33,6 +33,7 @@ ESC_F_COMPACT_LISTS = 16
 ABI_FUNCTIONS = [
     "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments", "esc_count_batched",
     "esc_server_start", "esc_submit", "esc_poll", "esc_wait", "esc_server_stats", "esc_server_stop",
+    "esc_tune", "esc_tune_batched", "esc_set_params", "esc_last_params",
     "esc_last_work", "esc_last_profile", "esc_last_noninduced", "esc_last_three", "esc_inverse_matrix", "esc_strerror",
 ]
 
@@ -54,6 +55,15 @@ class EscapeError(RuntimeError):
 
 class _U128(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("task_chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("k5_work_log2", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+def _params_dict(p):
+    return {"task_chunk": p.task_chunk, "wg_per_cu": p.wg_per_cu, "k5_work_log2": p.k5_work_log2}
 
 
 _lib = None
@@ -94,6 +104,14 @@ def _load():
         lib.esc_server_stats.restype = ctypes.c_int
         lib.esc_server_stop.argtypes = [vp]
         lib.esc_server_stop.restype = ctypes.c_int
+        lib.esc_tune.argtypes = [vp, i32, vp, vp, ctypes.c_int, u32, vp, vp, vp]
+        lib.esc_tune.restype = ctypes.c_int
+        lib.esc_tune_batched.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.c_int, u32, vp, vp, vp]
+        lib.esc_tune_batched.restype = ctypes.c_int
+        lib.esc_set_params.argtypes = [vp, vp]
+        lib.esc_set_params.restype = ctypes.c_int
+        lib.esc_last_params.argtypes = [vp, vp]
+        lib.esc_last_params.restype = ctypes.c_int
         lib.esc_last_work.argtypes = [vp, vp]
         lib.esc_last_work.restype = ctypes.c_int
         lib.esc_last_profile.argtypes = [vp, vp, vp]
@@ -152,6 +170,42 @@ class Context:
         """Counts of every graph in `graphs` (objects with n, row_ptr, col) in
         one call: a G x (11|45) uint64 array and the per-graph overflow flags."""
         return esc_count_batched(self.ptr, *pack_batch(graphs), k=k, flags=flags, stream=stream)
+
+    def tune(self, graph, k=5, flags=0, stream=None):
+        """Time the candidate launch parameters on this graph; the fastest are
+        kept for graphs with the same degree statistics.  Returns (params, ms)."""
+        rp, ci, flags, keep = _csr_args(graph.row_ptr, graph.col, flags)
+        best = _Params()
+        ms = ctypes.c_float()
+        _check(_load().esc_tune(self.ptr, int(graph.n), rp, ci, int(k), flags, ctypes.byref(best), ctypes.byref(ms),
+                                _stream_ptr(stream)), "esc_tune")
+        del keep
+        return _params_dict(best), float(ms.value)
+
+    def tune_batched(self, graphs, k=5, flags=0, stream=None):
+        vo, ao, rp, ci = pack_batch(graphs)
+        rpp, cip, flags, keep = _csr_args(rp, ci, flags)
+        best = _Params()
+        ms = ctypes.c_float()
+        _check(_load().esc_tune_batched(self.ptr, len(graphs), vo.ctypes.data_as(ctypes.c_void_p),
+                                        ao.ctypes.data_as(ctypes.c_void_p), rpp, cip, int(k), flags,
+                                        ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)), "esc_tune_batched")
+        del keep
+        return _params_dict(best), float(ms.value)
+
+    def set_params(self, params):
+        """Force launch parameters (dict with task_chunk, wg_per_cu,
+        k5_work_log2) on later calls; None returns to the tuned/default ones."""
+        if params is None:
+            _check(_load().esc_set_params(self.ptr, None), "esc_set_params")
+            return
+        p = _Params(int(params["task_chunk"]), int(params["wg_per_cu"]), int(params["k5_work_log2"]), 0)
+        _check(_load().esc_set_params(self.ptr, ctypes.byref(p)), "esc_set_params")
+
+    def last_params(self):
+        p = _Params()
+        _check(_load().esc_last_params(self.ptr, ctypes.byref(p)), "esc_last_params")
+        return _params_dict(p)
 
     def last_work(self):
         return esc_last_work(self.ptr)

@@ -45,13 +45,68 @@ void ctx_release(esc_ctx *c, Buf b) {
     c->cap[b] = 0;
 }
 
-// Per-source kernels run three workgroups per CU (more resident waves for
-// their latency-bound gathers), fewer when their dense tables (two tables and
-// two touched lists of tab_n entries each) would pass a tenth of the device.
+// Per-source kernels run up to three workgroups per CU (more resident waves
+// for their latency-bound gathers), fewer when their dense tables (two tables
+// and two touched lists of tab_n entries each) would pass a tenth of the
+// device: wg_cap.  The parameters proper are chosen after the degree order.
 static void set_pair_wgs(esc_ctx *c) {
-    c->wg_per_cu = 3;
-    while (c->wg_per_cu > 1 && 16 * (size_t)c->tab_n * (size_t)(c->wg_per_cu * c->num_cu) > c->dev_mem / 10)
-        c->wg_per_cu--;
+    c->wg_cap = 3;
+    while (c->wg_cap > 1 && 16 * (size_t)c->tab_n * (size_t)(c->wg_cap * c->num_cu) > c->dev_mem / 10) c->wg_cap--;
+    c->wg_per_cu = c->wg_cap;
+}
+
+static int floor_log2(int64_t x) {
+    int b = 0;
+    while (x > 1) { x >>= 1; b++; }
+    return b;
+}
+
+// key of the tuning table: batched or not, log2 of the (largest) graph's
+// vertex count, of the mean degree and of the largest degree
+static uint32_t degree_key(const esc_ctx *c) {
+    const int64_t nn = c->G ? c->tab_n : c->n;
+    const int64_t mean = c->n > 0 ? 2 * c->m / c->n : 0;
+    return (c->G ? 1u << 24 : 0u) | (uint32_t)floor_log2(nn + 1) << 16 | (uint32_t)floor_log2(mean + 1) << 8 |
+           (uint32_t)floor_log2((int64_t)c->maxdeg + 1);
+}
+
+static esc_params default_params(const esc_ctx *c) {
+    esc_params p;
+    p.task_chunk = c->G ? 8 : 1;
+    p.wg_per_cu = 3;
+    p.k5_work_log2 = 24;
+    p.reserved = 0;
+    return p;
+}
+
+// after the degree order (the key needs the largest degree)
+static void select_params(esc_ctx *c) {
+    esc_params p = default_params(c);
+    c->tune_key = degree_key(c);
+    if (c->forced) {
+        p = c->force;
+    } else {
+        for (int i = 0; i < c->tune_used; i++)
+            if (c->tune_keys[i] == c->tune_key) { p = c->tune_vals[i]; break; }
+    }
+    c->task_chunk = p.task_chunk;
+    c->wg_per_cu = p.wg_per_cu < c->wg_cap ? p.wg_per_cu : c->wg_cap;
+    c->k5_work_log2 = p.k5_work_log2;
+    c->params = p;
+    c->params.wg_per_cu = c->wg_per_cu;
+}
+
+static bool params_valid(const esc_params *p) {
+    return p->task_chunk >= 1 && p->task_chunk <= 64 && p->wg_per_cu >= 1 && p->wg_per_cu <= 3 &&
+           p->k5_work_log2 >= 16 && p->k5_work_log2 <= 30 && p->reserved == 0;
+}
+
+static void store_tuned(esc_ctx *c, uint32_t key, const esc_params &p) {
+    for (int i = 0; i < c->tune_used; i++)
+        if (c->tune_keys[i] == key) { c->tune_vals[i] = p; return; }
+    const int slot = c->tune_used < TUNE_SLOTS ? c->tune_used++ : (int)(key % TUNE_SLOTS);
+    c->tune_keys[slot] = key;
+    c->tune_vals[slot] = p;
 }
 
 extern "C" const char *esc_strerror(esc_status s) {
@@ -97,6 +152,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hipMemcpy(c->d_inv4, h4, sizeof(h4), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_inv5, h5, sizeof(h5), hipMemcpyHostToDevice) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     c->scratch_clean = true;
+    c->k5_work_log2 = 24;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = (size_t)64 << 30;
     c->dev_mem = tot;
@@ -193,6 +249,7 @@ static esc_status pipeline(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col
     } while (0)
     HIP_TRY(hipEventRecord(c->ev[ev++], st));
     STAGE(stage_orient(c, d_rp, d_col));
+    select_params(c);
     STAGE(stage_triangles(c));
     STAGE(stage_four(c, per_edge_c4));
     STAGE(stage_k4_triangles(c));
@@ -435,6 +492,93 @@ extern "C" esc_status esc_count_batched(esc_ctx *ctx, int32_t G, const int64_t *
                                         const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags,
                                         uint64_t *out, uint8_t *overflow, void *stream) {
     return run_batched(ctx, G, vtx_off, arc_off, row_ptr, col, k, flags, out, overflow, stream);
+}
+
+// total device time of the last call (sum of its stages)
+static float last_ms(const esc_ctx *c) {
+    float t = 0.f;
+    for (int i = 0; i < NSTAGES; i++) t += c->stage_ms[i];
+    return t;
+}
+
+// run(g) for every candidate; keep the fastest under the graph's key
+template <class Run>
+static esc_status tune_with(esc_ctx *c, int k, esc_params *best, float *best_ms, Run run_once) {
+    const bool had = c->forced;
+    const esc_params saved = c->force;
+    esc_params bp = default_params(c);
+    float bms = 3.0e38f;
+    uint32_t key = 0;
+    auto restore = [&] { c->forced = had; c->force = saved; };
+    auto try_one = [&](esc_params p) -> esc_status {
+        c->forced = true;
+        c->force = p;
+        esc_status st = run_once();
+        if (st != ESC_OK) return st;
+        key = c->tune_key;
+        const float ms = last_ms(c);
+        if (ms < bms) { bms = ms; bp = c->params; }
+        return ESC_OK;
+    };
+    esc_params p = default_params(c);
+    esc_status st = try_one(p);   // first run also sizes the buffers: not counted
+    bms = 3.0e38f;
+    const int chunks[3] = {1, 4, 16};
+    for (int a = 0; a < 3 && st == ESC_OK; a++)
+        for (int w = 1; w <= 3 && st == ESC_OK; w++) {
+            p.task_chunk = chunks[a];
+            p.wg_per_cu = w;
+            st = try_one(p);
+        }
+    if (k == 5)
+        for (int lg = 22; lg <= 26 && st == ESC_OK; lg += 4) {
+            p = bp;
+            p.k5_work_log2 = lg;
+            st = try_one(p);
+        }
+    restore();
+    if (st != ESC_OK) return st;
+    store_tuned(c, key, bp);
+    *best = bp;
+    if (best_ms) *best_ms = bms;
+    return ESC_OK;
+}
+
+extern "C" esc_status esc_tune(esc_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col, int k,
+                               uint32_t flags, esc_params *best, float *best_ms, void *stream) {
+    if (!ctx || !best) return ESC_EINVAL;
+    esc_u128 out[45];
+    return tune_with(ctx, k, best, best_ms, [&] { return run(ctx, n, row_ptr, col, k, flags, out, nullptr, stream); });
+}
+
+extern "C" esc_status esc_tune_batched(esc_ctx *ctx, int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                                       const int32_t *row_ptr, const int32_t *col, int k, uint32_t flags,
+                                       esc_params *best, float *best_ms, void *stream) {
+    if (!ctx || !best || G <= 0) return ESC_EINVAL;
+    uint64_t *rows = (uint64_t *)malloc(sizeof(uint64_t) * 45 * (size_t)G);
+    uint8_t *ovf = (uint8_t *)malloc((size_t)G);
+    if (!rows || !ovf) { free(rows); free(ovf); return ESC_ENOMEM; }
+    esc_status st = tune_with(ctx, k, best, best_ms, [&] {
+        return run_batched(ctx, G, vtx_off, arc_off, row_ptr, col, k, flags, rows, ovf, stream);
+    });
+    free(rows);
+    free(ovf);
+    return st;
+}
+
+extern "C" esc_status esc_set_params(esc_ctx *ctx, const esc_params *params) {
+    if (!ctx) return ESC_EINVAL;
+    if (!params) { ctx->forced = false; return ESC_OK; }
+    if (!params_valid(params)) return ESC_EINVAL;
+    ctx->forced = true;
+    ctx->force = *params;
+    return ESC_OK;
+}
+
+extern "C" esc_status esc_last_params(const esc_ctx *ctx, esc_params *out) {
+    if (!ctx || !out) return ESC_EINVAL;
+    *out = ctx->params;
+    return ESC_OK;
 }
 
 extern "C" esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out) {

@@ -204,17 +204,17 @@ __device__ inline int nth_set_bit(const unsigned long long *row, int words, int 
 }
 
 // Work of vertex a grows like d+(a)^3 / 64 word operations, so a is split
-// into units of ch out-neighbours b, ch = min(256, 2^24 / d+(a)^2): a hub
-// spreads over many workgroups.
-__device__ inline int k5_chunk(int32_t dp) {
-    const int64_t q = ((int64_t)1 << 24) / ((int64_t)dp * dp);
+// into units of ch out-neighbours b, ch = min(256, 2^lg / d+(a)^2) (lg = 24
+// unless tuned): a hub spreads over many workgroups.
+__device__ inline int k5_chunk(int32_t dp, int lg) {
+    const int64_t q = ((int64_t)1 << lg) / ((int64_t)dp * dp);
     return q >= 256 ? 256 : (q < 1 ? 1 : (int)q);
 }
 
-__global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, int64_t *len) {
+__global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, int lg, int64_t *len) {
     for (int32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
         const int32_t dp = off[a + 1] - split[a];
-        len[a] = dp < 4 ? 0 : (dp + k5_chunk(dp) - 1) / k5_chunk(dp);
+        len[a] = dp < 4 ? 0 : (dp + k5_chunk(dp, lg) - 1) / k5_chunk(dp, lg);
     }
 }
 
@@ -222,7 +222,7 @@ __global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, 
 // (b, c) with c in row(a,b); units are taken latest vertex first
 __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const int32_t *split,
                                             const int64_t *ob_off, const unsigned long long *ob,
-                                            const int64_t *uoff, int64_t nunits, int *task, GMap gm,
+                                            const int64_t *uoff, int64_t nunits, int lg, int *task, GMap gm,
                                             unsigned long long *acc, unsigned long long *visits) {
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
         if (u < 0) break;
         block_switch_graph<1>(k5, gcur, gm.graph(a), red, acc, ACC_STRIDE, ids);
         const int32_t dpa = off[a + 1] - split[a];
-        const int ch = k5_chunk(dpa);
+        const int ch = k5_chunk(dpa, lg);
         const int32_t ib0 = (int32_t)(u - uoff[a]) * ch;
         const int32_t ib1 = ib0 + ch < dpa ? ib0 + ch : dpa;
         const int wa = (dpa + 63) >> 6;
@@ -330,14 +330,14 @@ esc_status stage_k5(esc_ctx *c) {
     // units of work (see k5_chunk): per-vertex counts, then offsets
     int64_t *uoff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
     if (!uoff) return ESC_ENOMEM;
-    k_k5_units<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, len);
+    k_k5_units<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, c->k5_work_log2, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, uoff, n));
     int64_t nunits = 0;
     HIP_TRY(hipMemcpyAsync(&nunits, uoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (nunits == 0) return ESC_OK;
-    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, nunits, task + 3, gmap_of(c),
+    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, nunits, c->k5_work_log2, task + 3, gmap_of(c),
                                         (unsigned long long *)c->buf[B_ACC],
                                         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4);
     HIP_TRY(hipGetLastError());

@@ -92,6 +92,8 @@ struct GMap {
 struct esc_ctx;
 inline int pair_wgs(const esc_ctx *c);
 
+#define TUNE_SLOTS 64   // entries of a context's tuning table
+
 struct esc_ctx {
     int device;
     size_t budget;
@@ -126,7 +128,17 @@ struct esc_ctx {
     int32_t *d_inv4, *d_inv5;  // signed inverse matrices (Appendix B), device copies
     const int32_t *av;         // apex ids of the triangle lists, or nullptr (read through aa)
     int wg_per_cu;             // workgroups per CU of the per-source kernels
+    int wg_cap;                // largest wg_per_cu the tables' memory allows for this call
+    int k5_work_log2;          // 5-clique work units (see k5_chunk)
     size_t dev_mem;            // device memory in bytes
+    // tuning: parameters in use, forced ones, the table
+    esc_params params;
+    bool forced;
+    esc_params force;
+    uint32_t tune_key;
+    int tune_used;
+    uint32_t tune_keys[TUNE_SLOTS];
+    esc_params tune_vals[TUNE_SLOTS];
 };
 
 // Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):

@@ -177,6 +177,33 @@ def test_canonicalize_counts_the_described_graph(ctx):
     assert e.value.status == esc.ESC_EINVAL
 
 
+def test_tuned_and_forced_parameters_give_same_counts(ctx):
+    """The autotuner picks launch parameters per degree-statistics key; any
+    parameters give the same counts."""
+    import paper_1610_09411_amd as esc
+    g = synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2)
+    want = oracle.count(g, 5, threads=8)
+    best, ms = ctx.tune(g, 5)
+    assert ms > 0 and 1 <= best["wg_per_cu"] <= 3 and best["task_chunk"] in (1, 4, 16)
+    assert ctx.count(g, 5) == want
+    assert ctx.last_params() == best             # the table entry is used for this graph
+    for p in ({"task_chunk": 64, "wg_per_cu": 1, "k5_work_log2": 16},
+              {"task_chunk": 3, "wg_per_cu": 3, "k5_work_log2": 30}):
+        ctx.set_params(p)
+        assert ctx.count(g, 5) == want
+        assert ctx.last_params() == p
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.set_params({"task_chunk": 0, "wg_per_cu": 1, "k5_work_log2": 24})
+    assert e.value.status == esc.ESC_EINVAL
+    ctx.set_params(None)
+    graphs = [synth.from_spec(s) for s in synth.batch_specs(40, 3)]
+    bbest, _ = ctx.tune_batched(graphs, 5)
+    rows, _ = ctx.count_batched(graphs, 5)
+    assert ctx.last_params() == bbest
+    for i in (0, 7, 39):
+        assert [int(x) for x in rows[i]] == oracle.count(graphs[i], 5), i
+
+
 def test_repeat_calls_are_identical(ctx):
     g = synth.chung_lu(8000, 2.0, 16.0, 900.0, 4)
     a = ctx.count(g, 5)

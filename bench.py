@@ -189,6 +189,7 @@ def main():
         "stages_ms": {k: round(v[0], 3) for k, v in prof.items()},
         "stages_visits": {k: int(v[1]) for k, v in prof.items()},
         "work": work,
+        "launch_params": ctx.last_params(),
         "checksum": {"sum_5": str(sum(counts[11:])), "p8_5cycles": str(counts[11 + 7]),
                      "p21_5cliques": str(counts[31])},
         "batched": batched,

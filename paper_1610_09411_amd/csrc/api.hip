@@ -74,7 +74,7 @@ static esc_params default_params(const esc_ctx *c) {
     esc_params p;
     p.task_chunk = c->G ? 8 : 1;
     p.wg_per_cu = 3;
-    p.k5_work_log2 = 24;
+    p.k5_work_log2 = 20;
     p.reserved = 0;
     return p;
 }
@@ -152,7 +152,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hipMemcpy(c->d_inv4, h4, sizeof(h4), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_inv5, h5, sizeof(h5), hipMemcpyHostToDevice) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     c->scratch_clean = true;
-    c->k5_work_log2 = 24;
+    c->k5_work_log2 = 20;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = (size_t)64 << 30;
     c->dev_mem = tot;

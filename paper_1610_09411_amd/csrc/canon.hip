@@ -7,14 +7,6 @@
 #include "device.h"
 #include "ctx.h"
 
-static int grid_cap(esc_ctx *c, int64_t items, int threads) {
-    int64_t b = (items + threads - 1) / threads;
-    int64_t cap = (int64_t)c->num_cu * 16;
-    if (b > cap) b = cap;
-    if (b < 1) b = 1;
-    return (int)b;
-}
-
 // one wave per input row: check ids, count both arcs of every non-loop entry
 __global__ void k_can_count(int32_t n, const int32_t *rp, const int32_t *col, int32_t *cnt, int *err) {
     const int lane = threadIdx.x & 63;

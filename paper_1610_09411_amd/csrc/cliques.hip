@@ -21,14 +21,6 @@
 
 #define BM_WORDS 512   // LDS bitmap per wave: rows of up to 16384 vertices
 
-static int grid_cap(esc_ctx *c, int64_t items, int threads, int per_cu = 16) {
-    int64_t b = (items + threads - 1) / threads;
-    int64_t cap = (int64_t)c->num_cu * per_cu;
-    if (b > cap) b = cap;
-    if (b < 1) b = 1;
-    return (int)b;
-}
-
 // merge-count of two sorted id lists (rows too long for the bitmap)
 __device__ inline uint32_t count_common(const int32_t *av, const int32_t *adj, const uint32_t *aa, int64_t x,
                                         int64_t xe, int64_t y, int64_t ye, uint64_t &nvis) {

@@ -160,6 +160,16 @@ inline int32_t slab_words(const esc_ctx *c, int wgs_per_cu, int nslabs, int32_t 
     return (int32_t)w;
 }
 
+// blocks for a grid-stride kernel over `items`: enough to cover them, at most
+// per_cu per compute unit
+inline int grid_cap(const esc_ctx *c, int64_t items, int threads, int per_cu = 16) {
+    int64_t b = (items + threads - 1) / threads;
+    const int64_t cap = (int64_t)c->num_cu * per_cu;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
 inline GMap gmap_of(const esc_ctx *c) {
     GMap g;
     g.vg = c->G ? (const int32_t *)c->buf[B_VGRAPH] : nullptr;

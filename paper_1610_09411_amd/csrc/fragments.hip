@@ -12,14 +12,6 @@
 #include "device.h"
 #include "ctx.h"
 
-static int grid_cap(esc_ctx *c, int64_t items, int threads, int per_cu = 16) {
-    int64_t b = (items + threads - 1) / threads;
-    int64_t cap = (int64_t)c->num_cu * per_cu;
-    if (b > cap) b = cap;
-    if (b < 1) b = 1;
-    return (int)b;
-}
-
 // ---------------------------------------------------------------- triangles
 
 // One wave per vertex u.  N+(u) goes into a hash set in the wave's LDS

@@ -155,31 +155,143 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 
 // ------------------------------------------------------------ pattern 18
 
-// One workgroup per hub h.  For each neighbour i of h (latest rim vertex):
-// l runs over the triangle list of arc (h,i) below i, j over the triangle
-// list of arc (h,l) below i; key = position of j in the row of h.  The table
-// lives in LDS when d(h) fits, else in the workgroup's global scratch.  In
-// LDS a count is below d(h) <= lds_cap < 2^16, so two counts share a word
-// (16 bits each; one 32-bit atomic adds 1 << 16 for odd keys) and the
-// touched keys are 16-bit.  A hub with d(h) <= lds_cap / WHEEL_WAVES gives
-// each wave its own table and rim vertices, with no workgroup barrier per
-// rim vertex.
+// Hub h, each neighbour i of h taken as the latest rim vertex: l runs over
+// the triangle list of arc (h,i) below i, j over the triangle list of arc
+// (h,l) below i; key = position of j in the row of h, and C(count,2) summed
+// over keys counts the rim 4-cycles with latest vertex i.  The table lives in
+// LDS when d(h) fits, else in the workgroup's global scratch.  In LDS a count
+// is below d(h) <= lds_cap < 2^16, so two counts share a word (16 bits each;
+// one 32-bit atomic adds 1 << 16 for odd keys) and the touched keys are
+// 16-bit.
+//
+// Hubs with d(h) > wq = lds_cap / WHEEL_WAVES come first, split into tasks of
+// WHEEL_RIMS rim vertices (task offsets per hub in toff, latest hubs first):
+// every workgroup of the chip works on the same few hubs at a time, so their
+// triangle lists, re-read for every rim vertex, stay in each XCD's L2.  The
+// smaller hubs follow, one per workgroup, each wave taking its own rim
+// vertices with its own table and no workgroup barrier per rim vertex.
 #define WHEEL_WAVES 8   // waves per workgroup of the wheel pass
+#define WHEEL_RIMS 16   // rim vertices per task of a large hub
+
+__global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int64_t *len) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t d = off[v + 1] - off[v];
+        len[v] = d > wq ? (d + WHEEL_RIMS - 1) / WHEEL_RIMS : 0;
+    }
+}
 
 __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
-                                                int32_t lds_cap, int chunk, GMap gm, int *task,
-                                                unsigned long long *acc, unsigned long long *visits) {
+                                                int32_t lds_cap, const int64_t *toff, int *task_big, int chunk,
+                                                GMap gm, int *task, unsigned long long *acc,
+                                                unsigned long long *visits) {
     uint64_t nvis = 0;
     extern __shared__ uint32_t dyn[];
-    __shared__ int s_h, s_nt, s_ntw[WHEEL_WAVES];
-    __shared__ u128 red[4];
+    __shared__ int s_h, s_r, s_nt, s_ntw[WHEEL_WAVES];
+    __shared__ u128 red[WHEEL_WAVES];   // one sum per wave (block_flush_u128)
     __shared__ int64_t wsa[WHEEL_WAVES][64];
     __shared__ int32_t wse[WHEEL_WAVES][64], wsi[WHEEL_WAVES][64];
     const int ids[1] = {AC_N18};
     u128 s18[1] = {0};
     int gcur = -1;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int32_t wq = lds_cap / WHEEL_WAVES;   // largest d(h) of the one-wave-per-rim-vertex mode
+    uint32_t *gcnt = gtab_all + (size_t)blockIdx.x * tab_n;
+    int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
+    uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
+    uint16_t *ltch = (uint16_t *)(dyn + (lds_cap + 1) / 2);      // lds_cap keys
+    const int64_t nbig = toff[n];
+
+    // large hubs: tasks of WHEEL_RIMS rim vertices
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t u = nbig - 1 - atomicAdd(task_big, 1);
+            int32_t v = -1;
+            if (u >= 0) {
+                int32_t lo = 0, hi = n - 1;   // last v with toff[v] <= u: its task count is > 0
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (toff[mid] <= u) lo = mid; else hi = mid - 1;
+                }
+                v = lo;
+                s_r = (int)(u - toff[v]);
+            }
+            s_h = v;
+        }
+        __syncthreads();
+        const int32_t h = s_h;
+        const int32_t r0 = s_r * WHEEL_RIMS;
+        __syncthreads();   // s_h, s_r are read by every thread before they are taken again
+        if (h < 0) break;
+        block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
+        const int32_t oh = off[h], dh = off[h + 1] - oh;
+        const bool in_lds = dh <= lds_cap;
+        const int32_t r1 = r0 + WHEEL_RIMS < dh ? r0 + WHEEL_RIMS : dh;
+        if (in_lds)
+            for (int q = threadIdx.x; q < (dh + 1) / 2; q += blockDim.x) lcnt[q] = 0;
+        __syncthreads();
+        for (int32_t pi = oh + r0; pi < oh + r1; pi++) {
+            const int32_t i = adj[pi];
+            const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
+            if (l1 - l0 < 2) continue;   // a rim 4-cycle needs two triangles on (h,i)
+            // entries l of list(h,i) below i
+            int64_t lo = l0, hi = l1;
+            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
+            const int nl = (int)(lo - l0);
+            if (nl == 0) continue;
+            if (threadIdx.x == 0) s_nt = 0;
+            __syncthreads();
+            // each wave takes entries l; its lanes stride over the list of (h,l) below i
+            for (int xb = wid * 64; xb < nl; xb += nw * 64) {
+                // each lane finds one segment: the list of (h,l) below i
+                const int x = xb + lane;
+                int64_t b0 = 0, b1 = 0;
+                if (x < nl) {
+                    const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
+                    b0 = aoff[qhl];
+                    int64_t lo2 = b0, hi2 = aoff[qhl + 1];
+                    while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
+                    b1 = lo2;
+                }
+                nvis += (uint64_t)(b1 - b0);
+                if (in_lds)
+                    wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                              [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                              [&](int32_t key) {
+                                  const uint32_t sh = (uint32_t)(key & 1) << 4;
+                                  const uint32_t old = atomicAdd(&lcnt[key >> 1], 1u << sh);
+                                  if (((old >> sh) & 0xFFFFu) == 0) ltch[atomicAdd(&s_nt, 1)] = (uint16_t)key;
+                              });
+                else
+                    wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                              [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                              [&](int32_t key) {
+                                  if (atomicAdd(&gcnt[key], 1u) == 0) gtch[atomicAdd(&s_nt, 1)] = key;
+                              });
+            }
+            __syncthreads();
+            const int nt = s_nt;
+            for (int q = threadIdx.x; q < nt; q += blockDim.x) {
+                if (in_lds) {
+                    const int32_t key = ltch[q];
+                    const uint32_t sh = (uint32_t)(key & 1) << 4;
+                    const uint32_t old = atomicAnd(&lcnt[key >> 1], ~(0xFFFFu << sh));   // the other half may be reset concurrently
+                    s18[0] += c2((old >> sh) & 0xFFFFu);
+                } else {
+                    const int32_t key = gtch[q];
+                    s18[0] += c2(gcnt[key]);
+                    gcnt[key] = 0;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // smaller hubs: one per workgroup, one table per wave
+    const int32_t rw = (wq + 1) / 2;   // words of a wave's table, and of its touched list
+    uint32_t *wc = dyn + (size_t)wid * 2 * rw;
+    uint16_t *wt = (uint16_t *)(wc + rw);
     for (;;) {
         if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
         __syncthreads();
@@ -188,22 +300,10 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
         const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
         __syncthreads();   // s_h is read by every thread before it is taken again
         for (int32_t t = (int32_t)t0; t < t1; t++) {
-        const int32_t h = n - 1 - t;
-        block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
-        const int32_t oh = off[h], dh = off[h + 1] - oh;
-        const bool in_lds = dh <= lds_cap;
-        uint32_t *gcnt = gtab_all + (size_t)blockIdx.x * tab_n;
-        int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
-        uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
-        uint16_t *ltch = (uint16_t *)(dyn + (lds_cap + 1) / 2);      // lds_cap keys
-        const int32_t wq = lds_cap / WHEEL_WAVES;   // largest d(h) of the one-wave-per-rim-vertex mode
-        if (dh <= wq) {
-            // small hub: each wave takes its own rim vertices i with its own
-            // table, so no workgroup barrier is needed per i
-            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-            const int32_t rw = (wq + 1) / 2;   // words of a table, and of a touched list
-            uint32_t *wc = dyn + (size_t)wid * 2 * rw;
-            uint16_t *wt = (uint16_t *)(wc + rw);
+            const int32_t h = n - 1 - t;
+            const int32_t oh = off[h], dh = off[h + 1] - oh;
+            if (dh > wq || dh < 3) continue;   // large hubs are done; a wheel hub has 4 neighbours
+            block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
             for (int q = lane; q < (dh + 1) / 2; q += 64) wc[q] = 0;
             wave_sync();
             for (int32_t pi = oh + wid; pi < oh + dh; pi += nw) {
@@ -244,70 +344,6 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                 }
                 wave_sync();
             }
-            __syncthreads();   // a later hub in the workgroup mode reuses the whole array
-            continue;
-        }
-        if (in_lds)
-            for (int q = threadIdx.x; q < (dh + 1) / 2; q += blockDim.x) lcnt[q] = 0;
-        __syncthreads();
-        for (int32_t pi = oh; pi < oh + dh; pi++) {
-            const int32_t i = adj[pi];
-            const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
-            if (l1 - l0 < 2) continue;   // a rim 4-cycle needs two triangles on (h,i)
-            // entries l of list(h,i) below i
-            int64_t lo = l0, hi = l1;
-            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
-            const int nl = (int)(lo - l0);
-            if (nl == 0) continue;
-            if (threadIdx.x == 0) s_nt = 0;
-            __syncthreads();
-            {
-                // each wave takes entries l; its lanes stride over the list of (h,l) below i
-                const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-                for (int xb = wid * 64; xb < nl; xb += nw * 64) {
-                    // each lane finds one segment: the list of (h,l) below i
-                    const int x = xb + lane;
-                    int64_t b0 = 0, b1 = 0;
-                    if (x < nl) {
-                        const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
-                        b0 = aoff[qhl];
-                        int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
-                        b1 = lo2;
-                    }
-                    nvis += (uint64_t)(b1 - b0);
-                    if (in_lds)
-                        wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
-                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
-                                  [&](int32_t key) {
-                                      const uint32_t sh = (uint32_t)(key & 1) << 4;
-                                      const uint32_t old = atomicAdd(&lcnt[key >> 1], 1u << sh);
-                                      if (((old >> sh) & 0xFFFFu) == 0) ltch[atomicAdd(&s_nt, 1)] = (uint16_t)key;
-                                  });
-                    else
-                        wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
-                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
-                                  [&](int32_t key) {
-                                      if (atomicAdd(&gcnt[key], 1u) == 0) gtch[atomicAdd(&s_nt, 1)] = key;
-                                  });
-                }
-            }
-            __syncthreads();
-            const int nt = s_nt;
-            for (int q = threadIdx.x; q < nt; q += blockDim.x) {
-                if (in_lds) {
-                    const int32_t key = ltch[q];
-                    const uint32_t sh = (uint32_t)(key & 1) << 4;
-                    const uint32_t old = atomicAnd(&lcnt[key >> 1], ~(0xFFFFu << sh));   // the other half may be reset concurrently
-                    s18[0] += c2((old >> sh) & 0xFFFFu);
-                } else {
-                    const int32_t key = gtch[q];
-                    s18[0] += c2(gcnt[key]);
-                    gcnt[key] = 0;
-                }
-            }
-            __syncthreads();
-        }
         }
     }
     if (gcur >= 0) block_flush_u128<1>(s18, red, acc + (size_t)gcur * ACC_STRIDE, ids);
@@ -501,9 +537,16 @@ esc_status stage_wheels(esc_ctx *c) {
     int per_cu = (int)(c->max_lds / (lds + 10240));
     if (per_cu > 2 * c->wg_per_cu) per_cu = 2 * c->wg_per_cu;
     if (per_cu < 1) per_cu = 1;
+    // tasks of the hubs with more than lds_cap / WHEEL_WAVES neighbours
+    int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
+    int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
+    if (!len || !toff) return ESC_ENOMEM;
+    k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], lds_cap / WHEEL_WAVES, len);
+    HIP_TRY(hipGetLastError());
+    ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     k_wheels<<<c->num_cu * per_cu, 64 * WHEEL_WAVES, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
-                                              c->av, tab, touch, c->tab_n, lds_cap,
+                                              c->av, tab, touch, c->tab_n, lds_cap, toff, task + 4,
                                               c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],
                                               (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
     HIP_TRY(hipGetLastError());

@@ -236,12 +236,32 @@ esc_status stage_triangles(esc_ctx *c) {
 //   (c-1) * (2 d(k) - 4)      per wedge   } sum_e C4(e)(d(u)+d(v)-4)
 //   (c-1) * c * (d(h) + d(o) - 4)  per key }
 // With per_edge set, pass 2 also adds c-1 to C4 of edges hk and ko.
-// Keys in the latest `slab` ranks of h's graph are counted in LDS, the rest
-// in the workgroup's dense table (relative to the graph's first rank).
+//
+// A top vertex with more than FOUR_RANGE_DEG neighbours is split into tasks by
+// key range: task r counts the keys o in [gb + r*R, gb + (r+1)*R) (R = the
+// LDS slab in keys at h's packing), its pass 1 and 2 reading from every row
+// N(k) only the run of keys in the range (rows are sorted, so two binary
+// searches find it).  All keys of a task are in LDS, and the workgroups of
+// the chip share the few large tops in progress, whose rows stay in L2.
+// Smaller tops go one per workgroup: keys in the latest `slab` ranks of h's
+// graph are counted in LDS, the rest in the workgroup's dense table (relative
+// to the graph's first rank).
+#define FOUR_RANGE_DEG 256
+
+__global__ void k_four_tasks(int32_t n, const int32_t *off, GMap gm, int32_t slab, int64_t *len) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t d = off[v + 1] - off[v];
+        const int64_t keys = v - gm.begin(gm.graph(v));   // keys before v in its graph
+        const int64_t rk = (int64_t)slab << count_shift(d);
+        len[v] = d > FOUR_RANGE_DEG && slab > 0 ? (keys + rk - 1) / rk : 0;
+    }
+}
+
 __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, const int32_t *rev,
                                                      const int32_t *arc_eid, const uint32_t *tarc,
                                                      uint32_t *tab_all, int32_t *touch_all, int32_t tab_n,
+                                                     const int64_t *toff, int *task_big,
                                                      int chunk, GMap gm, int *task, int32_t slab,
                                                      unsigned long long *acc, unsigned long long *c4e,
                                                      unsigned long long *visits) {
@@ -249,13 +269,113 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
-    __shared__ int s_h, s_nt;
+    __shared__ int s_h, s_r, s_nt;
     __shared__ u128 red[3 * 8];
     uint32_t *Ct = tab_all + (size_t)blockIdx.x * tab_n;
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
     const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
     u128 sums[3] = {0, 0, 0};
     int gcur = -1;
+    const int64_t nbig = toff[n];
+
+    // large tops: one key range per task, latest tops first
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t u = nbig - 1 - atomicAdd(task_big, 1);
+            int32_t v = -1;
+            if (u >= 0) {
+                int32_t lo = 0, hi = n - 1;   // last v with toff[v] <= u: its task count is > 0
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (toff[mid] <= u) lo = mid; else hi = mid - 1;
+                }
+                v = lo;
+                s_r = (int)(u - toff[v]);
+            }
+            s_h = v;
+        }
+        __syncthreads();
+        const int32_t h = s_h, r = s_r;
+        __syncthreads();   // s_h, s_r are read by every thread before they are taken again
+        if (h < 0) break;
+        const int g = gm.graph(h);
+        block_switch_graph<3>(sums, gcur, g, red, acc, ACC_STRIDE, ids);
+        const int32_t oh = off[h], sh = split[h];
+        const int64_t dh = off[h + 1] - oh;
+        const int shift = count_shift(dh);
+        const int cb = 32 >> shift;
+        const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
+        const int64_t rk = (int64_t)slab << shift;
+        const int32_t o0 = (int32_t)(gm.begin(g) + r * rk);
+        const int32_t o1 = (int32_t)(o0 + rk < h ? o0 + rk : h);
+        const int32_t nwd = ((o1 - o0) + (1 << shift) - 1) >> shift;
+        for (int q = threadIdx.x; q < nwd; q += blockDim.x) sl[q] = 0;
+        __syncthreads();
+        auto slot = [&](int32_t o, uint32_t &s) -> uint32_t * {
+            const int32_t idx = o - o0;
+            s = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+            return &sl[idx >> shift];
+        };
+        // the run of row k below h with keys in [o0, o1)
+        auto run = [&](int32_t p, int64_t &start, int &len) {
+            start = 0;
+            len = 0;
+            if (p < sh) {
+                const int32_t k = adj[p];
+                const int a = lower_bound_i32(adj, off[k], rev[p], o0);
+                const int b = lower_bound_i32(adj, a, rev[p], o1);
+                start = a;
+                len = b - a;
+            }
+        };
+        // pass 1: counts
+        for (int32_t base = oh; base < sh; base += blockDim.x) {
+            int64_t start;
+            int len;
+            run(base + threadIdx.x, start, len);
+            lbs_batch(start, len, pref, beg, tmp, [&](int, int64_t q) {
+                uint32_t s;
+                uint32_t *w = slot(adj[q], s);
+                nvis++;
+                atomicAdd(w, 1u << s);
+            });
+        }
+        __syncthreads();
+        // pass 2: per-wedge terms
+        for (int32_t base = oh; base < sh; base += blockDim.x) {
+            int64_t start;
+            int len;
+            run(base + threadIdx.x, start, len);
+            lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t q) {
+                const int32_t pk = base + s;
+                uint32_t sb;
+                const uint32_t cc = (*slot(adj[q], sb) >> sb) & cmask;
+                if (cc >= 2) {
+                    const int32_t k = adj[pk];
+                    sums[1] += (uint64_t)(cc - 1) * (tarc[pk] + tarc[q]);
+                    sums[2] += (uint64_t)(cc - 1) * (uint64_t)(2 * (off[k + 1] - off[k]) - 4);
+                    if (c4e) {
+                        atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
+                        atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
+                    }
+                }
+            });
+        }
+        // pass 3: per-key terms (the next task clears the slab behind a barrier)
+        for (int q = threadIdx.x; q < nwd; q += blockDim.x) {
+            const uint32_t x = sl[q];
+            if (x == 0) continue;
+            for (int f = 0; f < (1 << shift); f++) {
+                const uint64_t cc = (x >> (f * cb)) & cmask;
+                if (cc < 2) continue;
+                const int32_t o = o0 + (q << shift) + f;
+                sums[0] += c2(cc);
+                sums[2] += (u128)(cc - 1) * cc * (uint64_t)(dh + (off[o + 1] - off[o]) - 4);
+            }
+        }
+    }
+
+    // smaller tops: one per workgroup
     if (threadIdx.x == 0) s_nt = 0;
     for (;;) {
         if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
@@ -270,6 +390,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
             const int32_t gb = gm.begin(g), ge = gm.end(g);
             const int32_t oh = off[h], sh = split[h];
             const int64_t dh = off[h + 1] - oh;
+            if (dh > FOUR_RANGE_DEG && slab > 0) continue;   // done by key range
             // c(h,o) <= d(h): a low-degree top vertex packs 16, 8, 4 or 2
             // counts per word (count_shift), in LDS (that many times more
             // latest ranks) and in the table
@@ -371,11 +492,18 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     }
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
     const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 8192);
+    // key-range tasks of the tops with more than FOUR_RANGE_DEG neighbours
+    int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
+    int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
+    if (!len || !toff) return ESC_ENOMEM;
+    k_four_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], gmap_of(c), slab, len);
+    HIP_TRY(hipGetLastError());
+    ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     k_four_cycles<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
                                        (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
-                                       tab, touch, c->tab_n, c->task_chunk, gmap_of(c), task, slab,
+                                       tab, touch, c->tab_n, toff, task + 4, c->task_chunk, gmap_of(c), task, slab,
                                        (unsigned long long *)c->buf[B_ACC], c4e,
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
     HIP_TRY(hipGetLastError());

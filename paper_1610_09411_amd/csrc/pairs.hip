@@ -367,6 +367,8 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     __shared__ int64_t beg[513];
     __shared__ int s_i, s_nx, s_nw;
     __shared__ u128 red[8];
+    __shared__ int32_t wsi[8][64];    // wave walks: segment ends (starts alias pref, firsts alias beg)
+    __shared__ uint32_t wxs[8][64];   // X(i,b) of each lane's segment
     const int ids[1] = {AC_CYC};
     uint32_t *Xt = tabX_all + (size_t)blockIdx.x * tab_n;
     uint32_t *Wt = tabW_all + (size_t)blockIdx.x * tab_n;
@@ -448,20 +450,28 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             });
         }
         __syncthreads();
-        // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j)
+        // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j): each wave takes 64 keys b
+        // and walks their out-rows as one flattened run
         const int nx = s_nx;
-        for (int base = 0; base < nx; base += blockDim.x) {
-            int xi = base + threadIdx.x;
-            int start = 0, len = 0;
-            if (xi < nx) { int32_t b = tx[xi]; start = split[b]; len = off[b + 1] - split[b]; }
-            lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
-                const int32_t b = tx[base + s];
-                const int32_t j = adj[q];
-                nvis++;
-                const uint32_t xb = get(sX, Xt, b);
-                const uint32_t wj = get(sW, Wt, j);
-                sc[0] += (uint64_t)xb * wj;
-            });
+        {
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+            int64_t *wsa = beg + wid * 64;
+            int32_t *wse = pref + wid * 64;
+            for (int xb = wid * 64; xb < nx; xb += nwv * 64) {
+                const int xi = xb + lane;
+                int64_t a0 = 0, a1 = 0;
+                uint32_t xv = 0;
+                if (xi < nx) {
+                    const int32_t b = tx[xi];
+                    a0 = split[b];
+                    a1 = off[b + 1];
+                    xv = get(sX, Xt, b);
+                }
+                nvis += (uint64_t)(a1 - a0);
+                wxs[wid][lane] = xv;   // visible to the wave after the walk's own wave_sync
+                wave_walk_seg(a0, a1, wsa, wse, wsi[wid], [&](int64_t q) { return adj[q]; },
+                              [&](int y, int64_t, int32_t j) { sc[0] += (uint64_t)wxs[wid][y] * get(sW, Wt, j); });
+            }
         }
         __syncthreads();
         for (int q = threadIdx.x; q < nx; q += blockDim.x) {
@@ -563,7 +573,7 @@ esc_status stage_cycles(esc_ctx *c) {
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     int nwg = pair_wgs(c);
     // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays
-    const int32_t slab = slab_words(c, c->wg_per_cu, 2, 8192, 8192);
+    const int32_t slab = slab_words(c, c->wg_per_cu, 2, 8192, 12288);
     k_five_cycles<<<nwg, 512, sizeof(uint32_t) * (size_t)(2 * slab > 0 ? 2 * slab : 1), st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,

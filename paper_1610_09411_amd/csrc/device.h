@@ -217,6 +217,47 @@ __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_
     wave_sync();   // the arrays are reused by the next call
 }
 
+// Load-balanced walk over the block's segments like lbs_batch, but coarser:
+// every segment is cut into pieces of at most PIECE elements and each wave
+// walks 64 pieces at a time as one flattened run (wave_walk_seg), so the
+// segment of an element is searched for once per piece, not once per
+// element.  Thread t describes segment t by (start, len).  `pref` holds
+// blockDim+1 ints, `beg` blockDim int64, `lens` blockDim ints, `tmp` as for
+// block_exclusive_scan (block LDS arrays); sa/se/si/sg are 64-entry LDS arrays
+// private to the calling wave.  use(s, q, v): s = the segment's thread index,
+// q = the position, v = load(q).  Every thread of the block must call it.
+template <int PIECE, class L, class U>
+__device__ inline void block_walk(int64_t start, int len, int *pref, int64_t *beg, int *lens, int *tmp,
+                                  int64_t *sa, int32_t *se, int32_t *si, int32_t *sg, L load, U use) {
+    int total;
+    const int ex = block_exclusive_scan((len + PIECE - 1) / PIECE, tmp, &total);
+    pref[threadIdx.x] = ex;
+    beg[threadIdx.x] = start;
+    lens[threadIdx.x] = len;
+    if (threadIdx.x == 0) pref[blockDim.x] = total;
+    __syncthreads();
+    const int lane = threadIdx.x & (ESC_WAVE - 1), wid = threadIdx.x / ESC_WAVE, nw = blockDim.x / ESC_WAVE;
+    for (int pb = wid * ESC_WAVE; pb < total; pb += nw * ESC_WAVE) {
+        const int piece = pb + lane;
+        int64_t a0 = 0, a1 = 0;
+        int s = 0;
+        if (piece < total) {
+            int lo = 0, hi = blockDim.x - 1;   // last segment whose prefix is <= piece
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pref[mid] <= piece) lo = mid; else hi = mid - 1;
+            }
+            s = lo;
+            a0 = beg[s] + (int64_t)(piece - pref[s]) * PIECE;
+            const int64_t e = beg[s] + lens[s];
+            a1 = a0 + PIECE < e ? a0 + PIECE : e;
+        }
+        sg[lane] = s;   // read by the wave after the walk's own wave_sync
+        wave_walk_seg(a0, a1, sa, se, si, load, [&](int y, int64_t q, decltype(load(a0)) v) { use(sg[y], q, v); });
+    }
+    __syncthreads();
+}
+
 // wave_walk_seg with use(value) only
 template <class L, class U>
 __device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
@@ -295,8 +336,26 @@ __device__ inline int count_shift(int64_t d) {
 }
 
 __device__ inline uint64_t c2(uint64_t x) { return x < 2 ? 0 : x * (x - 1) / 2; }
-__device__ inline u128 c3(uint64_t x) { return x < 3 ? 0 : (u128)x * (x - 1) * (x - 2) / 6; }
-__device__ inline u128 c4(uint64_t x) { return x < 4 ? 0 : (u128)x * (x - 1) * (x - 2) / 6 * (x - 3) / 4; }
+// C(x,3) and C(x,4) without a 128-bit division (which compiles to a
+// bit-serial loop): the factors 3 and 2 (resp. 3, 4 and 2) are divided out of
+// the consecutive numbers that hold them, then the quotients are multiplied.
+// Exact whenever the result fits 128 bits.
+__device__ inline u128 c3(uint64_t x) {
+    if (x < 3) return 0;
+    uint64_t a = x, b = x - 1, c = x - 2;
+    if (a % 3 == 0) a /= 3; else if (b % 3 == 0) b /= 3; else c /= 3;
+    if ((a & 1) == 0) a >>= 1; else b >>= 1;   // dividing by 3 keeps the parity
+    return (u128)a * b * c;
+}
+__device__ inline u128 c4(uint64_t x) {
+    if (x < 4) return 0;
+    uint64_t f[4] = {x, x - 1, x - 2, x - 3};
+    const int t = (int)(x % 3);                 // f[t] is a multiple of 3
+    f[t] /= 3;                                  // keeps the residue mod 4 (3 is odd, 3^-1 = 3 mod 4)
+    const int e = (int)(x & 1);                 // f[e] and f[e+2] are the even ones
+    if ((f[e] & 3) == 0) { f[e] >>= 2; f[e + 2] >>= 1; } else { f[e] >>= 1; f[e + 2] >>= 2; }
+    return (u128)f[0] * f[1] * f[2] * f[3];
+}
 
 // first index in sorted a[lo, hi) with a[idx] >= key
 __device__ inline int lower_bound_i32(const int32_t *a, int lo, int hi, int32_t key) {

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
     __shared__ int s_i, s_nt;
     __shared__ u128 red[2 * 8];
     __shared__ int64_t wsa[8][64];
-    __shared__ int32_t wse[8][64], wsi[8][64];
+    __shared__ int32_t wse[8][64], wsi[8][64], wsg[8][64], lens[512];
     const int ids[2] = {AC_N13, AC_N17};
     uint32_t *Wt = tab_all + (size_t)blockIdx.x * tab_n;
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
@@ -82,15 +82,18 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 #define TAB_GET(j) ((Wt[((j) - gb) >> shift] >> TAB_SH(j)) & cmask)
         // W(i,j) for j after i: k in N(i), j in the suffix of N(k) after i
         for (int32_t base = oi; base < ei; base += blockDim.x) {
-            int32_t p = base + threadIdx.x;
-            int start = 0, len = 0;
-            if (p < ei) { int32_t k = adj[p]; start = rev[p] + 1; len = off[k + 1] - start; }
-            lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
-                int32_t j = adj[q];
-                nvis++;
-                if (j >= hi0) SLAB_INC(j);
-                else if (TAB_INC(j) == 0) touch[atomicAdd(&s_nt, 1)] = j;
-            });
+            const int32_t p = base + threadIdx.x;
+            int64_t start = 0;
+            int len = 0;
+            if (p < ei) { const int32_t k = adj[p]; start = rev[p] + 1; len = off[k + 1] - (int32_t)start; }
+            nvis += (uint64_t)len;
+            const int wid = threadIdx.x >> 6;
+            block_walk<64>(start, len, pref, beg, lens, tmp, wsa[wid], wse[wid], wsi[wid], wsg[wid],
+                           [&](int64_t q) { return adj[q]; },
+                           [&](int, int64_t, int32_t j) {
+                               if (j >= hi0) SLAB_INC(j);
+                               else if (TAB_INC(j) == 0) touch[atomicAdd(&s_nt, 1)] = j;
+                           });
         }
         __syncthreads();
         // diamonds with tips i and j (j after i): triangles (i,k,l), k<l, then
@@ -513,7 +516,7 @@ esc_status stage_pairs(esc_ctx *c) {
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
-    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 16384);
+    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 20480);
     k_pairs_wd<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                           n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],

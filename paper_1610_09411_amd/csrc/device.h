@@ -258,6 +258,85 @@ __device__ inline void block_walk(int64_t start, int len, int *pref, int64_t *be
     __syncthreads();
 }
 
+// wave_walk_seg with the use split in two: act(v) runs for the NU loaded
+// elements of a step first and post(v, r) after, with r = act(v).  When act
+// issues an atomic whose result post needs, the NU atomics of a step are in
+// flight together instead of each waiting for the one before.
+template <class L, class A, class P>
+__device__ inline void wave_walk_act(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, A act,
+                                     P post) {
+    const int lane = threadIdx.x & (ESC_WAVE - 1);
+    const int32_t len = (int32_t)(a1 - a0);
+    int32_t incl = len;
+    for (int o = 1; o < ESC_WAVE; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int32_t total = __shfl(incl, ESC_WAVE - 1);
+    sa[lane] = a0;
+    se[lane] = incl - len;
+    si[lane] = incl;
+    wave_sync();
+    int y = 0;
+    int32_t e = lane;
+    constexpr int NU = 8;   // steps in flight
+    for (; e + (NU - 1) * ESC_WAVE < total; e += NU * ESC_WAVE) {
+        int64_t q[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) {
+            while (si[y] <= e + u * ESC_WAVE) y++;
+            q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
+        }
+        decltype(load(q[0])) v[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) v[u] = load(q[u]);
+        decltype(act(v[0])) r[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) r[u] = act(v[u]);
+        // keeps post's reads of r after all NU acts (one wait for the step)
+        asm volatile("" : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]),
+                     "+v"(r[7]));
+#pragma unroll
+        for (int u = 0; u < NU; u++) post(v[u], r[u]);
+    }
+    for (; e < total; e += ESC_WAVE) {
+        while (si[y] <= e) y++;
+        const auto v = load(sa[y] + (e - se[y]));
+        post(v, act(v));
+    }
+    wave_sync();   // the arrays are reused by the next call
+}
+
+// block_walk with wave_walk_act's split use (no segment index)
+template <int PIECE, class L, class A, class P>
+__device__ inline void block_walk_act(int64_t start, int len, int *pref, int64_t *beg, int *lens, int *tmp,
+                                      int64_t *sa, int32_t *se, int32_t *si, L load, A act, P post) {
+    int total;
+    const int ex = block_exclusive_scan((len + PIECE - 1) / PIECE, tmp, &total);
+    pref[threadIdx.x] = ex;
+    beg[threadIdx.x] = start;
+    lens[threadIdx.x] = len;
+    if (threadIdx.x == 0) pref[blockDim.x] = total;
+    __syncthreads();
+    const int lane = threadIdx.x & (ESC_WAVE - 1), wid = threadIdx.x / ESC_WAVE, nw = blockDim.x / ESC_WAVE;
+    for (int pb = wid * ESC_WAVE; pb < total; pb += nw * ESC_WAVE) {
+        const int piece = pb + lane;
+        int64_t a0 = 0, a1 = 0;
+        if (piece < total) {
+            int lo = 0, hi = blockDim.x - 1;   // last segment whose prefix is <= piece
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pref[mid] <= piece) lo = mid; else hi = mid - 1;
+            }
+            a0 = beg[lo] + (int64_t)(piece - pref[lo]) * PIECE;
+            const int64_t e = beg[lo] + lens[lo];
+            a1 = a0 + PIECE < e ? a0 + PIECE : e;
+        }
+        wave_walk_act(a0, a1, sa, se, si, load, act, post);
+    }
+    __syncthreads();
+}
+
 // wave_walk_seg with use(value) only
 template <class L, class U>
 __device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
@@ -346,6 +425,22 @@ __device__ inline u128 c3(uint64_t x) {
     if (a % 3 == 0) a /= 3; else if (b % 3 == 0) b /= 3; else c /= 3;
     if ((a & 1) == 0) a >>= 1; else b >>= 1;   // dividing by 3 keeps the parity
     return (u128)a * b * c;
+}
+// Sum of C(f,3) over the cb-bit fields f of a packed word.  Only fields
+// >= 3 are visited: some bit above the lowest two set, or both of those.
+__device__ inline u128 c3_fields(uint32_t x, int cb, uint32_t cmask) {
+    if (cb == 32) return c3(x);
+    const uint32_t low = cb == 2 ? 0x55555555u : cb == 4 ? 0x11111111u : cb == 8 ? 0x01010101u : 0x00010001u;
+    uint32_t hi = 0;
+    for (int b = 2; b < cb; b++) hi |= x >> b;
+    uint32_t m = (hi | (x & (x >> 1))) & low;
+    u128 s = 0;
+    while (m) {
+        const int b = __builtin_ctz(m);
+        s += c3((x >> b) & cmask);
+        m &= m - 1;
+    }
+    return s;
 }
 __device__ inline u128 c4(uint64_t x) {
     if (x < 4) return 0;

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
     __shared__ int s_i, s_nt;
     __shared__ u128 red[2 * 8];
     __shared__ int64_t wsa[8][64];
-    __shared__ int32_t wse[8][64], wsi[8][64], wsg[8][64], lens[512];
+    __shared__ int32_t wse[8][64], wsi[8][64], lens[512];
     const int ids[2] = {AC_N13, AC_N17};
     uint32_t *Wt = tab_all + (size_t)blockIdx.x * tab_n;
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
@@ -88,12 +88,19 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             if (p < ei) { const int32_t k = adj[p]; start = rev[p] + 1; len = off[k + 1] - (int32_t)start; }
             nvis += (uint64_t)len;
             const int wid = threadIdx.x >> 6;
-            block_walk<64>(start, len, pref, beg, lens, tmp, wsa[wid], wse[wid], wsi[wid], wsg[wid],
-                           [&](int64_t q) { return adj[q]; },
-                           [&](int, int64_t, int32_t j) {
-                               if (j >= hi0) SLAB_INC(j);
-                               else if (TAB_INC(j) == 0) touch[atomicAdd(&s_nt, 1)] = j;
-                           });
+            // act: the count of j goes up (LDS slab, or the table with the
+            // old count back); post: a key new to the table is listed
+            block_walk_act<64>(start, len, pref, beg, lens, tmp, wsa[wid], wse[wid], wsi[wid],
+                               [&](int64_t q) { return adj[q]; },
+                               [&](int32_t j) -> uint32_t {
+                                   uint32_t old = 0xFFFFFFFFu;   // the table word before the add
+                                   if (j >= hi0) SLAB_INC(j);
+                                   else old = atomicAdd(&Wt[(j - gb) >> shift], 1u << TAB_SH(j));
+                                   return old;
+                               },
+                               [&](int32_t j, uint32_t old) {
+                                   if (j < hi0 && ((old >> TAB_SH(j)) & cmask) == 0) touch[atomicAdd(&s_nt, 1)] = j;
+                               });
         }
         __syncthreads();
         // diamonds with tips i and j (j after i): triangles (i,k,l), k<l, then
@@ -138,11 +145,11 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             const uint32_t old = atomicAnd(&Wt[(j - gb) >> shift], ~(cmask << TAB_SH(j)));
             sv[0] += c3((old >> TAB_SH(j)) & cmask);
         }
-        for (int q = w_lo + threadIdx.x; q < w_hi; q += blockDim.x) {
-            const uint32_t x = sl[q];
-            if (x == 0) continue;
-            for (int f = 0; f < (1 << shift); f++) sv[0] += c3((x >> (f * cb)) & cmask);
-        }
+        if (ei - oi >= 3)   // W(i,j) <= d(i): below 3 no pair has C(W,3) > 0
+            for (int q = w_lo + threadIdx.x; q < w_hi; q += blockDim.x) {
+                const uint32_t x = sl[q];
+                if (x != 0) sv[0] += c3_fields(x, cb, cmask);
+            }
 #undef SLAB_INC
 #undef SLAB_GET
 #undef TAB_SH

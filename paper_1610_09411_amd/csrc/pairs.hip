@@ -62,6 +62,9 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         block_switch_graph<2>(sv, gcur, g, red, acc, ACC_STRIDE, ids);
         const int32_t gb = gm.begin(g), ge = gm.end(g);
         const int32_t oi = off[i], ei = off[i + 1];
+        // W(i,j) <= d(i): with d(i) <= 2 every C(W,3) is 0, and a diamond's
+        // tips share both its middles, so its W - 2 is 0 too
+        if (ei - oi < 3) continue;
         // W(i,j) <= d(i): counts of a low-degree source are packed 16, 8, 4
         // or 2 to a word (count_shift), so the LDS slab covers that many
         // times more latest ranks and the workgroup table touches that many

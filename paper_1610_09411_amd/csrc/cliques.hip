@@ -203,10 +203,15 @@ __device__ inline int k5_chunk(int32_t dp, int lg) {
     return q >= 256 ? 256 : (q < 1 ? 1 : (int)q);
 }
 
+// Vertices with at most K5_LIGHT out-neighbours (one-word rows) are counted
+// a wave each, lane = b, after the units of the others.
+#define K5_LIGHT 64
+#define K5_LIGHT_RUN 32   // consecutive light vertices per wave at a time
+
 __global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, int lg, int64_t *len) {
     for (int32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
         const int32_t dp = off[a + 1] - split[a];
-        len[a] = dp < 4 ? 0 : (dp + k5_chunk(dp, lg) - 1) / k5_chunk(dp, lg);
+        len[a] = dp <= K5_LIGHT ? 0 : (dp + k5_chunk(dp, lg) - 1) / k5_chunk(dp, lg);
     }
 }
 
@@ -214,7 +219,8 @@ __global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, 
 // (b, c) with c in row(a,b); units are taken latest vertex first
 __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const int32_t *split,
                                             const int64_t *ob_off, const unsigned long long *ob,
-                                            const int64_t *uoff, int64_t nunits, int lg, int *task, GMap gm,
+                                            const int64_t *uoff, const int32_t *uown, int64_t nunits, int lg,
+                                            int *task, GMap gm,
                                             unsigned long long *acc, unsigned long long *visits) {
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
@@ -229,14 +235,7 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
         if (threadIdx.x == 0) {
             const int64_t t = atomicAdd(task, 1);
             s_u = t < nunits ? nunits - 1 - t : -1;
-            if (s_u >= 0) {
-                int32_t lo = 0, hi = n - 1;   // last a with uoff[a] <= u
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (uoff[mid] <= s_u) lo = mid; else hi = mid - 1;
-                }
-                s_a = lo;
-            }
+            if (s_u >= 0) s_a = uown[s_u];
         }
         __syncthreads();
         const int64_t u = s_u;
@@ -273,6 +272,44 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
         }
     }
     if (gcur >= 0) block_flush_u128<1>(k5, red, acc + (size_t)gcur * ACC_STRIDE, ids);
+    // light vertices: runs of K5_LIGHT_RUN consecutive vertices dealt to the
+    // waves in turn; lane b walks the c after b adjacent to b, then the x
+    // after c adjacent to both, and counts the y adjacent to all three
+    const int lane = threadIdx.x & 63;
+    const int64_t nwv = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t wv = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    u128 s = 0;
+    int wg = -1;
+    for (int64_t r0 = wv * K5_LIGHT_RUN; r0 < n; r0 += nwv * K5_LIGHT_RUN) {
+        const int32_t r1 = (int32_t)(r0 + K5_LIGHT_RUN < n ? r0 + K5_LIGHT_RUN : n);
+        for (int32_t a = (int32_t)r0; a < r1; a++) {
+            const int32_t dp = off[a + 1] - split[a];
+            if (dp < 4 || dp > K5_LIGHT) continue;
+            const int g = gm.graph(a);
+            if (g != wg) {
+                if (wg >= 0) wave_flush_u128(s, acc + (size_t)wg * ACC_STRIDE + 2 * AC_K5);
+                wg = g;
+            }
+            const unsigned long long *rows = ob + ob_off[a];   // one word per row
+            if (lane < dp) {
+                const unsigned long long rb = rows[lane];
+                unsigned long long cs = rb;
+                while (cs) {
+                    const int ci = __ffsll((long long)cs) - 1;
+                    cs &= cs - 1;
+                    const unsigned long long sw = rb & rows[ci];
+                    unsigned long long xs = sw;
+                    while (xs) {
+                        const int x = __ffsll((long long)xs) - 1;
+                        xs &= xs - 1;
+                        s += (uint64_t)__popcll(sw & rows[x]);
+                        nvis++;
+                    }
+                }
+            }
+        }
+    }
+    if (wg >= 0) wave_flush_u128(s, acc + (size_t)wg * ACC_STRIDE + 2 * AC_K5);
     flush_count(nvis, visits);
 }
 
@@ -326,10 +363,10 @@ esc_status stage_k5(esc_ctx *c) {
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, uoff, n));
     int64_t nunits = 0;
-    HIP_TRY(hipMemcpyAsync(&nunits, uoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (nunits == 0) return ESC_OK;
-    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, nunits, c->k5_work_log2, task + 3, gmap_of(c),
+    int32_t *uown = nullptr;
+    ESC_TRY(dev_task_owner(c, n, uoff, &nunits, &uown));
+    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, uown, nunits, c->k5_work_log2, task + 3,
+                                        gmap_of(c),
                                         (unsigned long long *)c->buf[B_ACC],
                                         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4);
     HIP_TRY(hipGetLastError());

@@ -69,6 +69,7 @@ enum Buf {
     B_VGRAPH,                   // batched: graph of each union vertex id (= of each rank)
     B_URP, B_UCOL,              // batched: CSR of the disjoint union
     B_BOUT,                     // batched: per-graph counts and overflow flags
+    B_TASK_OWNER,               // vertex of each task of a split per-vertex pass
     B_COUNT
 };
 
@@ -226,5 +227,9 @@ esc_status canonicalize(esc_ctx *c, int32_t n, const int32_t *d_rp, const int32_
 
 // generic device primitives (orient.hip)
 esc_status dev_exclusive_scan_i64(esc_ctx *c, const int64_t *in, int64_t *out, int64_t n);
+// Tasks of a per-vertex pass numbered by the offsets toff (n + 1 entries,
+// vertex v owns tasks [toff[v], toff[v+1])): *ntasks = toff[n] (read back to
+// the host) and *owner[u] = the vertex of task u, on the device.
+esc_status dev_task_owner(esc_ctx *c, int32_t n, const int64_t *toff, int64_t *ntasks, int32_t **owner);
 esc_status dev_segsort_u32(esc_ctx *c, uint32_t *keys, const int64_t *seg_off, int64_t nseg,
                            int32_t maxlen);

@@ -104,6 +104,14 @@ __device__ inline void block_switch_graph(u128 (&v)[NV], int &gcur, int gnew, u1
     gcur = gnew;
 }
 
+// add the wave's sum of v to the 128-bit slot (one atomic, lane 0); zeroes v.
+// Every lane of the wave must call it.
+__device__ inline void wave_flush_u128(u128 &v, unsigned long long *slot) {
+    const u128 x = wave_sum_u128(v);
+    if ((threadIdx.x & (ESC_WAVE - 1)) == 0 && x) atomic_add_u128(slot, x);
+    v = 0;
+}
+
 __device__ inline uint64_t wave_sum_u64(uint64_t x) {
     for (int o = ESC_WAVE / 2; o > 0; o >>= 1) x += __shfl_xor((unsigned long long)x, o);
     return x;
@@ -215,126 +223,6 @@ __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_
         use(y, q, load(q));
     }
     wave_sync();   // the arrays are reused by the next call
-}
-
-// Load-balanced walk over the block's segments like lbs_batch, but coarser:
-// every segment is cut into pieces of at most PIECE elements and each wave
-// walks 64 pieces at a time as one flattened run (wave_walk_seg), so the
-// segment of an element is searched for once per piece, not once per
-// element.  Thread t describes segment t by (start, len).  `pref` holds
-// blockDim+1 ints, `beg` blockDim int64, `lens` blockDim ints, `tmp` as for
-// block_exclusive_scan (block LDS arrays); sa/se/si/sg are 64-entry LDS arrays
-// private to the calling wave.  use(s, q, v): s = the segment's thread index,
-// q = the position, v = load(q).  Every thread of the block must call it.
-template <int PIECE, class L, class U>
-__device__ inline void block_walk(int64_t start, int len, int *pref, int64_t *beg, int *lens, int *tmp,
-                                  int64_t *sa, int32_t *se, int32_t *si, int32_t *sg, L load, U use) {
-    int total;
-    const int ex = block_exclusive_scan((len + PIECE - 1) / PIECE, tmp, &total);
-    pref[threadIdx.x] = ex;
-    beg[threadIdx.x] = start;
-    lens[threadIdx.x] = len;
-    if (threadIdx.x == 0) pref[blockDim.x] = total;
-    __syncthreads();
-    const int lane = threadIdx.x & (ESC_WAVE - 1), wid = threadIdx.x / ESC_WAVE, nw = blockDim.x / ESC_WAVE;
-    for (int pb = wid * ESC_WAVE; pb < total; pb += nw * ESC_WAVE) {
-        const int piece = pb + lane;
-        int64_t a0 = 0, a1 = 0;
-        int s = 0;
-        if (piece < total) {
-            int lo = 0, hi = blockDim.x - 1;   // last segment whose prefix is <= piece
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pref[mid] <= piece) lo = mid; else hi = mid - 1;
-            }
-            s = lo;
-            a0 = beg[s] + (int64_t)(piece - pref[s]) * PIECE;
-            const int64_t e = beg[s] + lens[s];
-            a1 = a0 + PIECE < e ? a0 + PIECE : e;
-        }
-        sg[lane] = s;   // read by the wave after the walk's own wave_sync
-        wave_walk_seg(a0, a1, sa, se, si, load, [&](int y, int64_t q, decltype(load(a0)) v) { use(sg[y], q, v); });
-    }
-    __syncthreads();
-}
-
-// wave_walk_seg with the use split in two: act(v) runs for the NU loaded
-// elements of a step first and post(v, r) after, with r = act(v).  When act
-// issues an atomic whose result post needs, the NU atomics of a step are in
-// flight together instead of each waiting for the one before.
-template <class L, class A, class P>
-__device__ inline void wave_walk_act(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, A act,
-                                     P post) {
-    const int lane = threadIdx.x & (ESC_WAVE - 1);
-    const int32_t len = (int32_t)(a1 - a0);
-    int32_t incl = len;
-    for (int o = 1; o < ESC_WAVE; o <<= 1) {
-        const int32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    const int32_t total = __shfl(incl, ESC_WAVE - 1);
-    sa[lane] = a0;
-    se[lane] = incl - len;
-    si[lane] = incl;
-    wave_sync();
-    int y = 0;
-    int32_t e = lane;
-    constexpr int NU = 8;   // steps in flight
-    for (; e + (NU - 1) * ESC_WAVE < total; e += NU * ESC_WAVE) {
-        int64_t q[NU];
-#pragma unroll
-        for (int u = 0; u < NU; u++) {
-            while (si[y] <= e + u * ESC_WAVE) y++;
-            q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
-        }
-        decltype(load(q[0])) v[NU];
-#pragma unroll
-        for (int u = 0; u < NU; u++) v[u] = load(q[u]);
-        decltype(act(v[0])) r[NU];
-#pragma unroll
-        for (int u = 0; u < NU; u++) r[u] = act(v[u]);
-        // keeps post's reads of r after all NU acts (one wait for the step)
-        asm volatile("" : "+v"(r[0]), "+v"(r[1]), "+v"(r[2]), "+v"(r[3]), "+v"(r[4]), "+v"(r[5]), "+v"(r[6]),
-                     "+v"(r[7]));
-#pragma unroll
-        for (int u = 0; u < NU; u++) post(v[u], r[u]);
-    }
-    for (; e < total; e += ESC_WAVE) {
-        while (si[y] <= e) y++;
-        const auto v = load(sa[y] + (e - se[y]));
-        post(v, act(v));
-    }
-    wave_sync();   // the arrays are reused by the next call
-}
-
-// block_walk with wave_walk_act's split use (no segment index)
-template <int PIECE, class L, class A, class P>
-__device__ inline void block_walk_act(int64_t start, int len, int *pref, int64_t *beg, int *lens, int *tmp,
-                                      int64_t *sa, int32_t *se, int32_t *si, L load, A act, P post) {
-    int total;
-    const int ex = block_exclusive_scan((len + PIECE - 1) / PIECE, tmp, &total);
-    pref[threadIdx.x] = ex;
-    beg[threadIdx.x] = start;
-    lens[threadIdx.x] = len;
-    if (threadIdx.x == 0) pref[blockDim.x] = total;
-    __syncthreads();
-    const int lane = threadIdx.x & (ESC_WAVE - 1), wid = threadIdx.x / ESC_WAVE, nw = blockDim.x / ESC_WAVE;
-    for (int pb = wid * ESC_WAVE; pb < total; pb += nw * ESC_WAVE) {
-        const int piece = pb + lane;
-        int64_t a0 = 0, a1 = 0;
-        if (piece < total) {
-            int lo = 0, hi = blockDim.x - 1;   // last segment whose prefix is <= piece
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pref[mid] <= piece) lo = mid; else hi = mid - 1;
-            }
-            a0 = beg[lo] + (int64_t)(piece - pref[lo]) * PIECE;
-            const int64_t e = beg[lo] + lens[lo];
-            a1 = a0 + PIECE < e ? a0 + PIECE : e;
-        }
-        wave_walk_act(a0, a1, sa, se, si, load, act, post);
-    }
-    __syncthreads();
 }
 
 // wave_walk_seg with use(value) only

@@ -261,7 +261,8 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                                                      const int32_t *split, const int32_t *rev,
                                                      const int32_t *arc_eid, const uint32_t *tarc,
                                                      uint32_t *tab_all, int32_t *touch_all, int32_t tab_n,
-                                                     const int64_t *toff, int *task_big,
+                                                     const int64_t *toff, const int32_t *town, int64_t nbig,
+                                                     int *task_big,
                                                      int chunk, GMap gm, int *task, int32_t slab,
                                                      unsigned long long *acc, unsigned long long *c4e,
                                                      unsigned long long *visits) {
@@ -276,7 +277,6 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
     u128 sums[3] = {0, 0, 0};
     int gcur = -1;
-    const int64_t nbig = toff[n];
 
     // large tops: one key range per task, latest tops first
     for (;;) {
@@ -284,12 +284,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
             const int64_t u = nbig - 1 - atomicAdd(task_big, 1);
             int32_t v = -1;
             if (u >= 0) {
-                int32_t lo = 0, hi = n - 1;   // last v with toff[v] <= u: its task count is > 0
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (toff[mid] <= u) lo = mid; else hi = mid - 1;
-                }
-                v = lo;
+                v = town[u];
                 s_r = (int)(u - toff[v]);
             }
             s_h = v;
@@ -499,11 +494,15 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     k_four_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], gmap_of(c), slab, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
+    int64_t nbig = 0;
+    int32_t *town = nullptr;
+    ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
     k_four_cycles<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
                                        (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
-                                       tab, touch, c->tab_n, toff, task + 4, c->task_chunk, gmap_of(c), task, slab,
+                                       tab, touch, c->tab_n, toff, town, nbig, task + 4, c->task_chunk, gmap_of(c),
+                                       task, slab,
                                        (unsigned long long *)c->buf[B_ACC], c4e,
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
     HIP_TRY(hipGetLastError());

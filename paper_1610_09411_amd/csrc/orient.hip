@@ -85,6 +85,22 @@ esc_status dev_exclusive_scan_i64(esc_ctx *c, const int64_t *in, int64_t *out, i
     return dev_scan<int64_t>(c, in, out, n);
 }
 
+__global__ void k_task_owner(int32_t n, const int64_t *toff, int32_t *owner) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        for (int64_t u = toff[v]; u < toff[v + 1]; u++) owner[u] = v;
+}
+
+esc_status dev_task_owner(esc_ctx *c, int32_t n, const int64_t *toff, int64_t *ntasks, int32_t **owner) {
+    HIP_TRY(hipMemcpyAsync(ntasks, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *owner = (int32_t *)ctx_buf(c, B_TASK_OWNER, sizeof(int32_t) * (size_t)(*ntasks + 1));
+    if (!*owner) return ESC_ENOMEM;
+    if (*ntasks == 0) return ESC_OK;
+    k_task_owner<<<grid_cap(c, n, 256), 256, 0, c->stream>>>(n, toff, *owner);
+    HIP_TRY(hipGetLastError());
+    return ESC_OK;
+}
+
 // ----------------------------------------------------- validation, degrees
 
 __global__ void k_degrees(int32_t n, const int32_t *rp, const int32_t *col, int32_t *deg, int *err,

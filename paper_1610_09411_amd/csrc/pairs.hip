@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
     __shared__ int s_i, s_nt;
     __shared__ u128 red[2 * 8];
     __shared__ int64_t wsa[8][64];
-    __shared__ int32_t wse[8][64], wsi[8][64], lens[512];
+    __shared__ int32_t wse[8][64], wsi[8][64];
     const int ids[2] = {AC_N13, AC_N17};
     uint32_t *Wt = tab_all + (size_t)blockIdx.x * tab_n;
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
@@ -85,25 +85,15 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 #define TAB_GET(j) ((Wt[((j) - gb) >> shift] >> TAB_SH(j)) & cmask)
         // W(i,j) for j after i: k in N(i), j in the suffix of N(k) after i
         for (int32_t base = oi; base < ei; base += blockDim.x) {
-            const int32_t p = base + threadIdx.x;
-            int64_t start = 0;
-            int len = 0;
-            if (p < ei) { const int32_t k = adj[p]; start = rev[p] + 1; len = off[k + 1] - (int32_t)start; }
+            int32_t p = base + threadIdx.x;
+            int start = 0, len = 0;
+            if (p < ei) { int32_t k = adj[p]; start = rev[p] + 1; len = off[k + 1] - start; }
             nvis += (uint64_t)len;
-            const int wid = threadIdx.x >> 6;
-            // act: the count of j goes up (LDS slab, or the table with the
-            // old count back); post: a key new to the table is listed
-            block_walk_act<64>(start, len, pref, beg, lens, tmp, wsa[wid], wse[wid], wsi[wid],
-                               [&](int64_t q) { return adj[q]; },
-                               [&](int32_t j) -> uint32_t {
-                                   uint32_t old = 0xFFFFFFFFu;   // the table word before the add
-                                   if (j >= hi0) SLAB_INC(j);
-                                   else old = atomicAdd(&Wt[(j - gb) >> shift], 1u << TAB_SH(j));
-                                   return old;
-                               },
-                               [&](int32_t j, uint32_t old) {
-                                   if (j < hi0 && ((old >> TAB_SH(j)) & cmask) == 0) touch[atomicAdd(&s_nt, 1)] = j;
-                               });
+            lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
+                int32_t j = adj[q];
+                if (j >= hi0) SLAB_INC(j);
+                else if (TAB_INC(j) == 0) touch[atomicAdd(&s_nt, 1)] = j;
+            });
         }
         __syncthreads();
         // diamonds with tips i and j (j after i): triangles (i,k,l), k<l, then
@@ -177,26 +167,31 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // one 32-bit atomic adds 1 << 16 for odd keys) and the touched keys are
 // 16-bit.
 //
-// Hubs with d(h) > wq = lds_cap / WHEEL_WAVES come first, split into tasks of
-// WHEEL_RIMS rim vertices (task offsets per hub in toff, latest hubs first):
+// Hubs with d(h) > wq = lds_cap / WHEEL_WAVES come first, those above
+// WHEEL_SPLIT_DEG split into tasks of WHEEL_RIMS rim vertices, the others one
+// task each (task offsets per hub in toff, latest hubs first):
 // every workgroup of the chip works on the same few hubs at a time, so their
 // triangle lists, re-read for every rim vertex, stay in each XCD's L2.  The
 // smaller hubs follow, one per workgroup, each wave taking its own rim
 // vertices with its own table and no workgroup barrier per rim vertex.
-#define WHEEL_WAVES 8   // waves per workgroup of the wheel pass
-#define WHEEL_RIMS 16   // rim vertices per task of a large hub
+#define WHEEL_WAVES 8          // waves per workgroup of the wheel pass
+#define WHEEL_RIMS 16          // rim vertices per task of a large hub
+#define WHEEL_SPLIT_DEG 1024   // hubs up to this degree are one task
+
+__device__ inline int32_t wheel_rims(int32_t d) { return d > WHEEL_SPLIT_DEG ? WHEEL_RIMS : d; }
 
 __global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int64_t *len) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t d = off[v + 1] - off[v];
-        len[v] = d > wq ? (d + WHEEL_RIMS - 1) / WHEEL_RIMS : 0;
+        len[v] = d > wq ? (d + wheel_rims(d) - 1) / wheel_rims(d) : 0;
     }
 }
 
 __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
-                                                int32_t lds_cap, const int64_t *toff, int *task_big, int chunk,
+                                                int32_t lds_cap, const int64_t *toff, const int32_t *town,
+                                                int64_t nbig, int *task_big, int chunk,
                                                 GMap gm, int *task, unsigned long long *acc,
                                                 unsigned long long *visits) {
     uint64_t nvis = 0;
@@ -214,7 +209,6 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
     uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
     uint16_t *ltch = (uint16_t *)(dyn + (lds_cap + 1) / 2);      // lds_cap keys
-    const int64_t nbig = toff[n];
 
     // large hubs: tasks of WHEEL_RIMS rim vertices
     for (;;) {
@@ -222,25 +216,21 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
             const int64_t u = nbig - 1 - atomicAdd(task_big, 1);
             int32_t v = -1;
             if (u >= 0) {
-                int32_t lo = 0, hi = n - 1;   // last v with toff[v] <= u: its task count is > 0
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (toff[mid] <= u) lo = mid; else hi = mid - 1;
-                }
-                v = lo;
+                v = town[u];
                 s_r = (int)(u - toff[v]);
             }
             s_h = v;
         }
         __syncthreads();
         const int32_t h = s_h;
-        const int32_t r0 = s_r * WHEEL_RIMS;
+        const int rtask = s_r;
         __syncthreads();   // s_h, s_r are read by every thread before they are taken again
         if (h < 0) break;
         block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
         const int32_t oh = off[h], dh = off[h + 1] - oh;
         const bool in_lds = dh <= lds_cap;
-        const int32_t r1 = r0 + WHEEL_RIMS < dh ? r0 + WHEEL_RIMS : dh;
+        const int32_t r0 = rtask * wheel_rims(dh);
+        const int32_t r1 = r0 + wheel_rims(dh) < dh ? r0 + wheel_rims(dh) : dh;
         if (in_lds)
             for (int q = threadIdx.x; q < (dh + 1) / 2; q += blockDim.x) lcnt[q] = 0;
         __syncthreads();
@@ -365,6 +355,8 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
 
 // ---------------------------------------------------------------- 5-cycles
 
+#define FIVE_WAVE_KEYS 256   // keys b from which the final sum runs as wave walks
+
 // Keys in the latest `slab` ranks of the graph (mostly hubs: X keys are
 // out-neighbours, the 3-path ends j are out-neighbours of them) use two LDS
 // arrays, one for X and one for Wnt; the rest use the workgroup's tables.
@@ -463,10 +455,22 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             });
         }
         __syncthreads();
-        // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j): each wave takes 64 keys b
-        // and walks their out-rows as one flattened run
+        // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j).  With enough keys b each
+        // wave takes 64 of them and walks their out-rows as one flattened
+        // run; with few, the block shares their elements (lbs_batch)
         const int nx = s_nx;
-        {
+        if (nx < FIVE_WAVE_KEYS) {
+            for (int base = 0; base < nx; base += blockDim.x) {
+                const int xi = base + threadIdx.x;
+                int start = 0, len = 0;
+                if (xi < nx) { const int32_t b = tx[xi]; start = split[b]; len = off[b + 1] - split[b]; }
+                nvis += (uint64_t)len;
+                lbs_batch(start, len, pref, beg, tmp, [&](int s, int q) {
+                    const int32_t b = tx[base + s];
+                    sc[0] += (uint64_t)get(sX, Xt, b) * get(sW, Wt, adj[q]);
+                });
+            }
+        } else {
             const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
             int64_t *wsa = beg + wid * 64;
             int32_t *wse = pref + wid * 64;
@@ -526,7 +530,7 @@ esc_status stage_pairs(esc_ctx *c) {
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
-    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 20480);
+    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 16384);
     k_pairs_wd<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
                                           n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
@@ -567,9 +571,12 @@ esc_status stage_wheels(esc_ctx *c) {
     k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], lds_cap / WHEEL_WAVES, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
+    int64_t nbig = 0;
+    int32_t *town = nullptr;
+    ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
     k_wheels<<<c->num_cu * per_cu, 64 * WHEEL_WAVES, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
-                                              c->av, tab, touch, c->tab_n, lds_cap, toff, task + 4,
+                                              c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
                                               c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],
                                               (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
     HIP_TRY(hipGetLastError());

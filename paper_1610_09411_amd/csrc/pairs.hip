@@ -167,14 +167,14 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // one 32-bit atomic adds 1 << 16 for odd keys) and the touched keys are
 // 16-bit.
 //
-// Hubs with d(h) > wq = lds_cap / WHEEL_WAVES come first, those above
+// Hubs with d(h) > wq = lds_cap / (waves per workgroup) come first, those above
 // WHEEL_SPLIT_DEG split into tasks of WHEEL_RIMS rim vertices, the others one
 // task each (task offsets per hub in toff, latest hubs first):
 // every workgroup of the chip works on the same few hubs at a time, so their
 // triangle lists, re-read for every rim vertex, stay in each XCD's L2.  The
 // smaller hubs follow, one per workgroup, each wave taking its own rim
 // vertices with its own table and no workgroup barrier per rim vertex.
-#define WHEEL_WAVES 8          // waves per workgroup of the wheel pass
+#define WHEEL_WAVES 8          // most waves per workgroup of the wheel pass (a launch may use fewer)
 #define WHEEL_RIMS 16          // rim vertices per task of a large hub
 #define WHEEL_SPLIT_DEG 1024   // hubs up to this degree are one task
 
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     u128 s18[1] = {0};
     int gcur = -1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int32_t wq = lds_cap / WHEEL_WAVES;   // largest d(h) of the one-wave-per-rim-vertex mode
+    const int32_t wq = lds_cap / nw;   // largest d(h) of the one-wave-per-rim-vertex mode
     uint32_t *gcnt = gtab_all + (size_t)blockIdx.x * tab_n;
     int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
     uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
@@ -361,6 +361,10 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
 // out-neighbours, the 3-path ends j are out-neighbours of them) use two LDS
 // arrays, one for X and one for Wnt; the rest use the workgroup's tables.
 // Both are reset through the touched-key lists.
+// WALK: the final sum may run as wave walks; the kernel without them needs
+// half the registers, so more workgroups stay resident (batches of small
+// graphs, where few sources have FIVE_WAVE_KEYS keys)
+template <bool WALK>
 __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, uint32_t *tabX_all, uint32_t *tabW_all,
                                                      int32_t *touchX_all, int32_t *touchW_all, int32_t tab_n,
@@ -459,7 +463,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         // wave takes 64 of them and walks their out-rows as one flattened
         // run; with few, the block shares their elements (lbs_batch)
         const int nx = s_nx;
-        if (nx < FIVE_WAVE_KEYS) {
+        if (!WALK || nx < FIVE_WAVE_KEYS) {
             for (int base = 0; base < nx; base += blockDim.x) {
                 const int xi = base + threadIdx.x;
                 int start = 0, len = 0;
@@ -556,7 +560,10 @@ esc_status stage_wheels(esc_ctx *c) {
     if (lds_cap > 32768) lds_cap = 32768;
     if (c->maxdeg + 1 < lds_cap) lds_cap = c->maxdeg + 1;
     size_t lds = sizeof(uint32_t) * ((size_t)(lds_cap + 1) / 2) + sizeof(uint16_t) * (size_t)lds_cap + 16;
-    size_t lds_waves = sizeof(uint32_t) * WHEEL_WAVES * 2 * (size_t)((lds_cap / WHEEL_WAVES + 1) / 2) + 16;   // one-wave tables
+    // eight waves per workgroup for one graph; four for a batch of small
+    // graphs, whose hubs have few rim vertices to share among the waves
+    const int waves = c->G ? 4 : WHEEL_WAVES;
+    size_t lds_waves = sizeof(uint32_t) * waves * 2 * (size_t)((lds_cap / waves + 1) / 2) + 16;   // one-wave tables
     if (lds_waves > lds) lds = lds_waves;
     // as many workgroups per CU as LDS holds: the walk is bound by
     // load latency, so resident waves matter; the global tables have room
@@ -564,17 +571,17 @@ esc_status stage_wheels(esc_ctx *c) {
     int per_cu = (int)(c->max_lds / (lds + 10240));
     if (per_cu > 2 * c->wg_per_cu) per_cu = 2 * c->wg_per_cu;
     if (per_cu < 1) per_cu = 1;
-    // tasks of the hubs with more than lds_cap / WHEEL_WAVES neighbours
+    // tasks of the hubs with more than lds_cap / waves neighbours
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
     if (!len || !toff) return ESC_ENOMEM;
-    k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], lds_cap / WHEEL_WAVES, len);
+    k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], lds_cap / waves, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     int64_t nbig = 0;
     int32_t *town = nullptr;
     ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
-    k_wheels<<<c->num_cu * per_cu, 64 * WHEEL_WAVES, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    k_wheels<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
                                               c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],
@@ -594,7 +601,8 @@ esc_status stage_cycles(esc_ctx *c) {
     int nwg = pair_wgs(c);
     // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays
     const int32_t slab = slab_words(c, c->wg_per_cu, 2, 8192, 12288);
-    k_five_cycles<<<nwg, 512, sizeof(uint32_t) * (size_t)(2 * slab > 0 ? 2 * slab : 1), st>>>(
+    auto kern = c->G ? k_five_cycles<false> : k_five_cycles<true>;
+    kern<<<nwg, 512, sizeof(uint32_t) * (size_t)(2 * slab > 0 ? 2 * slab : 1), st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,
                                        touch + (size_t)c->tab_n * nwg, c->tab_n, c->task_chunk, gmap_of(c),

@@ -598,9 +598,13 @@ esc_status stage_cycles(esc_ctx *c) {
     int32_t *touch;
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
-    int nwg = pair_wgs(c);
+    // the kernel with wave walks holds 103 VGPRs, so two 8-wave workgroups
+    // per CU are resident: launch two, each with the larger LDS slab; the
+    // one without (batches) keeps wg_per_cu of them
+    const int per_cu = c->G ? c->wg_per_cu : slab_wgs_per_cu(c);
+    int nwg = per_cu * c->num_cu;
     // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays
-    const int32_t slab = slab_words(c, c->wg_per_cu, 2, 8192, 12288);
+    const int32_t slab = slab_words(c, per_cu, 2, 8192, 12288);
     auto kern = c->G ? k_five_cycles<false> : k_five_cycles<true>;
     kern<<<nwg, 512, sizeof(uint32_t) * (size_t)(2 * slab > 0 ? 2 * slab : 1), st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],

@@ -225,6 +225,52 @@ __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_
     wave_sync();   // the arrays are reused by the next call
 }
 
+// wave_walk_seg with the use split in two: act(v) for the NU elements of a
+// step first, then post(v, r) with r = act(v).  With an act that is one
+// atomic and no branch, the NU atomics of a step are in flight together
+// instead of each waiting for the branch of the one before.
+template <class L, class A, class P>
+__device__ inline void wave_walk_act(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, A act,
+                                     P post) {
+    const int lane = threadIdx.x & (ESC_WAVE - 1);
+    const int32_t len = (int32_t)(a1 - a0);
+    int32_t incl = len;
+    for (int o = 1; o < ESC_WAVE; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int32_t total = __shfl(incl, ESC_WAVE - 1);
+    sa[lane] = a0;
+    se[lane] = incl - len;
+    si[lane] = incl;
+    wave_sync();
+    int y = 0;
+    int32_t e = lane;
+    constexpr int NU = 8;   // steps in flight
+    for (; e + (NU - 1) * ESC_WAVE < total; e += NU * ESC_WAVE) {
+        int64_t q[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) {
+            while (si[y] <= e + u * ESC_WAVE) y++;
+            q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
+        }
+        decltype(load(q[0])) v[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) v[u] = load(q[u]);
+        decltype(act(v[0])) r[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) r[u] = act(v[u]);
+#pragma unroll
+        for (int u = 0; u < NU; u++) post(v[u], r[u]);
+    }
+    for (; e < total; e += ESC_WAVE) {
+        while (si[y] <= e) y++;
+        const auto v = load(sa[y] + (e - se[y]));
+        post(v, act(v));
+    }
+    wave_sync();   // the arrays are reused by the next call
+}
+
 // wave_walk_seg with use(value) only
 template <class L, class U>
 __device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {

@@ -161,7 +161,8 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // Hub h, each neighbour i of h taken as the latest rim vertex: l runs over
 // the triangle list of arc (h,i) below i, j over the triangle list of arc
 // (h,l) below i; key = position of j in the row of h, and C(count,2) summed
-// over keys counts the rim 4-cycles with latest vertex i.  The table lives in
+// over keys counts the rim 4-cycles with latest vertex i (summed as the
+// count before each increment).  The table lives in
 // LDS when d(h) fits, else in the workgroup's global scratch.  In LDS a count
 // is below d(h) <= lds_cap < 2^16, so two counts share a word (16 bits each;
 // one 32-bit atomic adds 1 << 16 for odd keys) and the touched keys are
@@ -258,33 +259,37 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                     b1 = lo2;
                 }
                 nvis += (uint64_t)(b1 - b0);
+                // sum over keys of C(count,2) = sum over increments of the
+                // count before it
+                uint64_t olds = 0;
                 if (in_lds)
-                    wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
-                              [&](int64_t q) { return (int32_t)aa[q] - oh; },
-                              [&](int32_t key) {
-                                  const uint32_t sh = (uint32_t)(key & 1) << 4;
-                                  const uint32_t old = atomicAdd(&lcnt[key >> 1], 1u << sh);
-                                  if (((old >> sh) & 0xFFFFu) == 0) ltch[atomicAdd(&s_nt, 1)] = (uint16_t)key;
-                              });
+                    wave_walk_act(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                                  [&](int32_t key) { return atomicAdd(&lcnt[key >> 1], 1u << ((key & 1) << 4)); },
+                                  [&](int32_t key, uint32_t old) {
+                                      const uint32_t c = (old >> ((key & 1) << 4)) & 0xFFFFu;
+                                      olds += c;
+                                      if (c == 0) ltch[atomicAdd(&s_nt, 1)] = (uint16_t)key;
+                                  });
                 else
-                    wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
-                              [&](int64_t q) { return (int32_t)aa[q] - oh; },
-                              [&](int32_t key) {
-                                  if (atomicAdd(&gcnt[key], 1u) == 0) gtch[atomicAdd(&s_nt, 1)] = key;
-                              });
+                    wave_walk_act(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                                  [&](int32_t key) { return atomicAdd(&gcnt[key], 1u); },
+                                  [&](int32_t key, uint32_t old) {
+                                      olds += old;
+                                      if (old == 0) gtch[atomicAdd(&s_nt, 1)] = key;
+                                  });
+                s18[0] += olds;
             }
             __syncthreads();
+            // tables back to zero
             const int nt = s_nt;
             for (int q = threadIdx.x; q < nt; q += blockDim.x) {
                 if (in_lds) {
                     const int32_t key = ltch[q];
-                    const uint32_t sh = (uint32_t)(key & 1) << 4;
-                    const uint32_t old = atomicAnd(&lcnt[key >> 1], ~(0xFFFFu << sh));   // the other half may be reset concurrently
-                    s18[0] += c2((old >> sh) & 0xFFFFu);
+                    atomicAnd(&lcnt[key >> 1], ~(0xFFFFu << ((key & 1) << 4)));   // the other half may be reset concurrently
                 } else {
-                    const int32_t key = gtch[q];
-                    s18[0] += c2(gcnt[key]);
-                    gcnt[key] = 0;
+                    gcnt[gtch[q]] = 0;
                 }
             }
             __syncthreads();
@@ -330,20 +335,21 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                         b1 = lo2;
                     }
                     nvis += (uint64_t)(b1 - b0);
-                    wave_walk(b0, b1, wsa[wid], wse[wid], wsi[wid],
-                              [&](int64_t q) { return (int32_t)aa[q] - oh; },
-                              [&](int32_t key) {
-                                  const uint32_t sh = (uint32_t)(key & 1) << 4;
-                                  const uint32_t old = atomicAdd(&wc[key >> 1], 1u << sh);
-                                  if (((old >> sh) & 0xFFFFu) == 0) wt[atomicAdd(&s_ntw[wid], 1)] = (uint16_t)key;
-                              });
+                    uint64_t olds = 0;   // as above: the counts before each increment
+                    wave_walk_act(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                                  [&](int32_t key) { return atomicAdd(&wc[key >> 1], 1u << ((key & 1) << 4)); },
+                                  [&](int32_t key, uint32_t old) {
+                                      const uint32_t c = (old >> ((key & 1) << 4)) & 0xFFFFu;
+                                      olds += c;
+                                      if (c == 0) wt[atomicAdd(&s_ntw[wid], 1)] = (uint16_t)key;
+                                  });
+                    s18[0] += olds;
                 }
                 const int nt = s_ntw[wid];
                 for (int q = lane; q < nt; q += 64) {
                     const int32_t key = wt[q];
-                    const uint32_t sh = (uint32_t)(key & 1) << 4;
-                    const uint32_t old = atomicAnd(&wc[key >> 1], ~(0xFFFFu << sh));
-                    s18[0] += c2((old >> sh) & 0xFFFFu);
+                    atomicAnd(&wc[key >> 1], ~(0xFFFFu << ((key & 1) << 4)));
                 }
                 wave_sync();
             }

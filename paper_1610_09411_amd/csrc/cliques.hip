@@ -207,6 +207,7 @@ __device__ inline int k5_chunk(int32_t dp, int lg) {
 // a wave each, lane = b, after the units of the others.
 #define K5_LIGHT 64
 #define K5_LIGHT_RUN 32   // consecutive light vertices per wave at a time
+#define K5_WAVE_WORDS 8   // heavy vertices with rows of at most this many words: a wave per b
 
 __global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, int lg, int64_t *len) {
     for (int32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
@@ -249,6 +250,43 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
         const int32_t ib1 = ib0 + ch < dpa ? ib0 + ch : dpa;
         const int wa = (dpa + 63) >> 6;
         const unsigned long long *rows = ob + ob_off[a];
+        if (wa <= K5_WAVE_WORDS) {
+            // rows of at most K5_WAVE_WORDS words: one wave per b, the row of
+            // b in registers; lane l takes the c = 64 w + l of row(a,b), ANDs
+            // the two rows once and counts, for each x of the result, the y
+            // adjacent to all of b, c, x
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+            for (int ib = ib0 + wid; ib < ib1; ib += nwv) {
+                const unsigned long long *rb = rows + (int64_t)ib * wa;
+                unsigned long long bw[K5_WAVE_WORDS];
+#pragma unroll
+                for (int w = 0; w < K5_WAVE_WORDS; w++) bw[w] = w < wa ? rb[w] : 0ull;
+                uint64_t cnt = 0;
+#pragma unroll
+                for (int w = 0; w < K5_WAVE_WORDS; w++) {
+                    if (w >= wa || !((bw[w] >> lane) & 1ull)) continue;
+                    const unsigned long long *rc = rows + (int64_t)(w * 64 + lane) * wa;
+                    unsigned long long sc[K5_WAVE_WORDS];
+#pragma unroll
+                    for (int w2 = 0; w2 < K5_WAVE_WORDS; w2++) sc[w2] = w2 < wa ? (bw[w2] & rc[w2]) : 0ull;
+#pragma unroll
+                    for (int w2 = 0; w2 < K5_WAVE_WORDS; w2++) {
+                        unsigned long long xs = sc[w2];
+                        while (xs) {
+                            const int x = w2 * 64 + __ffsll((long long)xs) - 1;
+                            xs &= xs - 1;
+                            const unsigned long long *rx = rows + (int64_t)x * wa;
+#pragma unroll
+                            for (int w3 = 0; w3 < K5_WAVE_WORDS; w3++)
+                                if (w3 < wa) cnt += (uint64_t)__popcll(sc[w3] & rx[w3]);
+                            nvis += wa;
+                        }
+                    }
+                }
+                k5[0] += cnt;
+            }
+            continue;
+        }
         for (int ib = ib0; ib < ib1; ib += blockDim.x) {
             int i = ib + threadIdx.x;
             int len = 0;

@@ -207,6 +207,35 @@ def test_tuned_and_forced_parameters_give_same_counts(ctx):
         assert [int(x) for x in rows[i]] == oracle.count(graphs[i], 5), i
 
 
+def test_dense_graphs_closed_forms(ctx):
+    """Dense graphs with closed-form counts.  K_600: every k-subset is a
+    clique (its out-degrees run from 0 to 599, so the 5-clique pass takes
+    its light, wave and block paths).  K_{300,300}: only stars, 4-cycles,
+    4-stars and K_{2,3} are induced (Thm 5clique and the bipartite cases of
+    the brute-force pins)."""
+    from math import comb
+    n = 600
+    kn = synth.from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+    got5 = ctx.count(kn, 5)
+    want5 = [0] * 45
+    want5[5] = comb(n, 4)
+    want5[31] = comb(n, 5)
+    assert got5 == want5
+    got4 = ctx.count(kn, 4)
+    assert got4 == want5[:11]
+    a = b = 300
+    kab = synth.from_edges(a + b, [(u, a + v) for u in range(a) for v in range(b)])
+    got = ctx.count(kab, 5)
+    want = [0] * 45
+    want[0] = a * comb(b, 3) + b * comb(a, 3)          # 3-stars
+    want[3] = comb(a, 2) * comb(b, 2)                  # 4-cycles
+    want[6] = comb(a, 4) + comb(b, 4)                  # 4 independent vertices
+    want[11] = a * comb(b, 4) + b * comb(a, 4)         # 4-stars
+    want[11 + 12] = comb(a, 2) * comb(b, 3) + comb(a, 3) * comb(b, 2)   # K_{2,3}
+    want[32] = comb(a, 5) + comb(b, 5)                 # 5 independent vertices
+    assert got == want
+
+
 def test_repeat_calls_are_identical(ctx):
     g = synth.chung_lu(8000, 2.0, 16.0, 900.0, 4)
     a = ctx.count(g, 5)

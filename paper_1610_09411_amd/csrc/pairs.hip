@@ -247,9 +247,11 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
             if (threadIdx.x == 0) s_nt = 0;
             __syncthreads();
             // each wave takes entries l; its lanes stride over the list of (h,l) below i
-            for (int xb = wid * 64; xb < nl; xb += nw * 64) {
-                // each lane finds one segment: the list of (h,l) below i
-                const int x = xb + lane;
+            for (int xb = 0; xb < nl; xb += nw * 64) {
+                // each lane finds one segment: the list of (h,l) below i;
+                // entries are dealt to the waves in turn, so a short list
+                // of l still keeps every wave busy
+                const int x = xb + lane * nw + wid;
                 int64_t b0 = 0, b1 = 0;
                 if (x < nl) {
                     const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h

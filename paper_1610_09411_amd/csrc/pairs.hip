@@ -97,24 +97,37 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         }
         __syncthreads();
         // diamonds with tips i and j (j after i): triangles (i,k,l), k<l, then
-        // apexes j of edge (k,l) after i.  Each wave takes arcs (i,k); for
-        // every entry l of the arc's triangle list the lanes stride over the
-        // suffix of the list of (k,l) after i.
+        // apexes j of edge (k,l) after i.  The entries l of the triangle
+        // lists of the arcs (i,k), up to blockDim arcs at a time, are
+        // numbered in one run and dealt to the waves in turn (so a source
+        // with few arcs or short lists still keeps every wave busy); each
+        // lane finds one segment, the suffix of the list of (k,l) after i,
+        // and the wave walks its 64 segments together.
         {
             const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-            for (int32_t pk = oi + wid; pk < ei; pk += nw) {
-                const int32_t k = adj[pk];
-                const int64_t e0 = aoff[pk], e1 = aoff[pk + 1];
-                const int64_t r0 = aoff[rev[pk]];
-                // 64 entries at a time: each lane finds one segment (the suffix
-                // of the list of (k,l) after i), then the wave walks them
-                for (int64_t xb = e0; xb < e1; xb += 64) {
-                    const int64_t x = xb + lane;
+            for (int32_t base = oi; base < ei; base += blockDim.x) {
+                const int32_t pt = base + threadIdx.x;
+                const int cnt = pt < ei ? (int)(aoff[pt + 1] - aoff[pt]) : 0;
+                int total;
+                const int ex = block_exclusive_scan(cnt, tmp, &total);
+                pref[threadIdx.x] = ex;
+                if (threadIdx.x == 0) pref[blockDim.x] = total;
+                __syncthreads();
+                for (int fb = 0; fb < total; fb += nw * 64) {
+                    const int f = fb + lane * nw + wid;
                     int64_t a0 = 0, a1 = 0;
-                    if (x < e1) {
+                    if (f < total) {
+                        int lo = 0, hi = blockDim.x - 1;   // the arc whose entries hold f
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (pref[mid] <= f) lo = mid; else hi = mid - 1;
+                        }
+                        const int32_t pk = base + lo;
+                        const int64_t e0 = aoff[pk];
+                        const int64_t x = e0 + (f - pref[lo]);
                         const int32_t l = apex_at(av, adj, aa, x);
-                        if (l > k) {
-                            const int32_t qkl = (int32_t)aa[r0 + (x - e0)];   // arc (k,l) in row k
+                        if (l > adj[pk]) {
+                            const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - e0)];   // arc (k,l) in row k
                             int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
                             a1 = hi2;
                             while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
@@ -128,8 +141,8 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                               [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? SLAB_GET(j) : TAB_GET(j)) - 2; });
                     sv[1] += acc17;
                 }
+                __syncthreads();   // pref is rewritten by the next batch of arcs
             }
-            __syncthreads();
         }
         const int nt = s_nt;
         for (int q = threadIdx.x; q < nt; q += blockDim.x) {

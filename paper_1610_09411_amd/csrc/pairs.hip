@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
 
 // ---------------------------------------------------------------- 5-cycles
 
-#define FIVE_WAVE_KEYS 256   // keys b from which the final sum runs as wave walks
+#define FIVE_WAVE_KEYS 64    // keys b from which the final sum runs as wave walks
 
 // Keys in the latest `slab` ranks of the graph (mostly hubs: X keys are
 // out-neighbours, the 3-path ends j are out-neighbours of them) use two LDS
@@ -480,9 +480,10 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             });
         }
         __syncthreads();
-        // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j).  With enough keys b each
-        // wave takes 64 of them and walks their out-rows as one flattened
-        // run; with few, the block shares their elements (lbs_batch)
+        // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j).  With enough keys b they are
+        // dealt to the waves in turn and each wave walks the out-rows of its
+        // 64 as one flattened run; with few, the block shares their elements
+        // (lbs_batch)
         const int nx = s_nx;
         if (!WALK || nx < FIVE_WAVE_KEYS) {
             for (int base = 0; base < nx; base += blockDim.x) {
@@ -499,8 +500,8 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
             int64_t *wsa = beg + wid * 64;
             int32_t *wse = pref + wid * 64;
-            for (int xb = wid * 64; xb < nx; xb += nwv * 64) {
-                const int xi = xb + lane;
+            for (int xb = 0; xb < nx; xb += nwv * 64) {
+                const int xi = xb + lane * nwv + wid;   // keys dealt to the waves in turn
                 int64_t a0 = 0, a1 = 0;
                 uint32_t xv = 0;
                 if (xi < nx) {

@@ -323,11 +323,18 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 len = b - a;
             }
         };
+        // pass 1 keeps the runs in the workgroup's touched-key array (free
+        // until the smaller tops), two ints per in-neighbour, for pass 2
+        const bool keep = 2 * (int64_t)(sh - oh) <= tab_n;
         // pass 1: counts
         for (int32_t base = oh; base < sh; base += blockDim.x) {
             int64_t start;
             int len;
             run(base + threadIdx.x, start, len);
+            if (keep && base + (int32_t)threadIdx.x < sh) {
+                touch[2 * (base + threadIdx.x - oh)] = (int32_t)start;
+                touch[2 * (base + threadIdx.x - oh) + 1] = len;
+            }
             lbs_batch(start, len, pref, beg, tmp, [&](int, int64_t q) {
                 uint32_t s;
                 uint32_t *w = slot(adj[q], s);
@@ -338,9 +345,14 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
         __syncthreads();
         // pass 2: per-wedge terms
         for (int32_t base = oh; base < sh; base += blockDim.x) {
-            int64_t start;
-            int len;
-            run(base + threadIdx.x, start, len);
+            int64_t start = 0;
+            int len = 0;
+            if (!keep) {
+                run(base + threadIdx.x, start, len);
+            } else if (base + (int32_t)threadIdx.x < sh) {
+                start = touch[2 * (base + threadIdx.x - oh)];
+                len = touch[2 * (base + threadIdx.x - oh) + 1];
+            }
             lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t q) {
                 const int32_t pk = base + s;
                 uint32_t sb;

@@ -70,6 +70,8 @@ enum Buf {
     B_URP, B_UCOL,              // batched: CSR of the disjoint union
     B_BOUT,                     // batched: per-graph counts and overflow flags
     B_TASK_OWNER,               // vertex of each task of a split per-vertex pass
+    B_TRIREC,                   // triangles found by the count pass: 3 arcs and 3 slots each
+    B_TRICNT,                   // count of B_TRIREC entries, bound of oriented wedges
     B_COUNT
 };
 

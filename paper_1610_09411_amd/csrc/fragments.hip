@@ -24,10 +24,23 @@
 // mode 1: write the six per-arc list entries through per-arc cursors
 __device__ inline uint32_t hash_slot(uint32_t x, int bits) { return (x * 2654435761u) >> (32 - bits); }
 
+// With rec (mode 0), every triangle found is also recorded as its three
+// arcs (u->v, u->w, v->w); the lists are then filled from the records
+// (k_fill_records) instead of a second intersection.  The records go to
+// TRI_REGIONS regions of rec_cap entries, one counter each (a single counter
+// for the whole chip serialises its atomics); a record past its region's end
+// sets the overflow word and is dropped (the caller then runs mode 1).
+struct TriRec {
+    int32_t p, x, y;
+};
+#define TRI_REGIONS 256
+#define TRI_CSTRIDE 16   // u64 words between region counters (own cache lines)
+
 __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off, const int32_t *adj,
                                                    const int32_t *split, const int32_t *arc_eid,
                                                    const int32_t *rev, uint32_t *te, int mode,
                                                    unsigned long long *cur, uint32_t *aa, int hbits,
+                                                   TriRec *rec, unsigned long long *rec_n, int64_t rec_cap,
                                                    unsigned long long *visits) {
     extern __shared__ uint32_t hdyn[];   // per wave: keys[H] then values[H]
     __shared__ int64_t wsa[4][64];
@@ -52,6 +65,18 @@ __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off
         aa[atomicAdd(&cur[y], 1ull)] = (uint32_t)rp;   // list(v->w): apex u -> (v,u)
         aa[atomicAdd(&cur[ry], 1ull)] = (uint32_t)rx;  // list(w->v): apex u -> (w,u)
     };
+    const int region = blockIdx.x % TRI_REGIONS;
+    auto record = [&](int32_t p, int32_t x, int32_t y) {
+        const unsigned long long k = atomicAdd(&rec_n[region * TRI_CSTRIDE], 1ull);
+        if ((int64_t)k < rec_cap) {
+            TriRec *r = rec + (int64_t)region * rec_cap + (int64_t)k;
+            r->p = p;
+            r->x = x;
+            r->y = y;
+        } else {
+            atomicMax(&rec_n[TRI_REGIONS * TRI_CSTRIDE], 1ull);
+        }
+    };
     for (int32_t u = wave; u < n; u += nwaves) {
         const int32_t su = split[u], eu = off[u + 1];
         const int32_t dp = eu - su;
@@ -72,10 +97,11 @@ __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off
                         if (mode == 0) {
                             atomicAdd(&te[arc_eid[x]], 1u);
                             atomicAdd(&te[arc_eid[y]], 1u);
+                            cnt++;
+                            if (rec) record(p, x, y);
                         } else {
                             fill6(p, x, y);
                         }
-                        cnt++;
                         x++;
                         y++;
                     }
@@ -120,6 +146,7 @@ __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off
                                   atomicAdd(&te[arc_eid[xw]], 1u);
                                   atomicAdd(&te[arc_eid[q]], 1u);
                                   atomicAdd(&wcn[wid][yl], 1u);
+                                  if (rec) record(pb + yl, xw, (int32_t)q);
                               } else {
                                   fill6(pb + yl, xw, (int32_t)q);
                               }
@@ -137,6 +164,38 @@ __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off
         wave_sync();
     }
     if (visits) flush_count(nvis, visits);
+}
+
+// the six list entries of every recorded triangle u<v<w: it takes a slot on
+// each of its three edges (a per-edge cursor; an arc and its reverse share
+// their edge's slot), the lists are sorted afterwards
+__global__ void k_fill_records(int64_t rec_cap, const TriRec *rec, const unsigned long long *rec_n,
+                               const int32_t *rev, const int32_t *arc_eid, const int64_t *aoff, uint32_t *ecur,
+                               uint32_t *aa) {
+    const int64_t slots = rec_cap * TRI_REGIONS;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < slots; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t region = k / rec_cap;
+        if (k - region * rec_cap >= (int64_t)rec_n[region * TRI_CSTRIDE]) continue;   // past the region's records
+        const TriRec r = rec[k];
+        const uint32_t sp = atomicAdd(&ecur[arc_eid[r.p]], 1u);
+        const uint32_t sx = atomicAdd(&ecur[arc_eid[r.x]], 1u);
+        const uint32_t sy = atomicAdd(&ecur[arc_eid[r.y]], 1u);
+        const int32_t rp = rev[r.p], rx = rev[r.x], ry = rev[r.y];
+        aa[aoff[r.p] + sp] = (uint32_t)r.x;    // list(u->v): apex w -> (u,w)
+        aa[aoff[rp] + sp] = (uint32_t)r.y;     // list(v->u): apex w -> (v,w)
+        aa[aoff[r.x] + sx] = (uint32_t)r.p;    // list(u->w): apex v -> (u,v)
+        aa[aoff[rx] + sx] = (uint32_t)ry;      // list(w->u): apex v -> (w,v)
+        aa[aoff[r.y] + sy] = (uint32_t)rp;     // list(v->w): apex u -> (v,u)
+        aa[aoff[ry] + sy] = (uint32_t)rx;      // list(w->v): apex u -> (w,u)
+    }
+}
+
+// sum over vertices of C(d+(v), 2): a bound on the triangle count
+__global__ void k_wpp(int32_t n, const int32_t *off, const int32_t *split, unsigned long long *out) {
+    uint64_t s = 0;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        s += c2((uint64_t)(off[v + 1] - split[v]));
+    flush_count(s, out);
 }
 
 // per arc: list length (= t of its edge) for the offsets, and t itself as a
@@ -181,8 +240,30 @@ esc_status stage_triangles(esc_ctx *c) {
     int hbits = 1;
     while ((1 << hbits) < 2 * c->maxdplus && hbits < 11) hbits++;
     const size_t hlds = sizeof(uint32_t) * 2 * 4 * ((size_t)1 << hbits);
-    k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr, hbits,
-                                      work + WORK_VISITS + 1);
+    // Triangle records (12 B each, room for the bound sum C(d+(v),2)) when
+    // they take at most an eighth of the free device memory and the lists
+    // are not kept compact; otherwise the fill pass intersects again.
+    const size_t ncnt = TRI_REGIONS * TRI_CSTRIDE + TRI_CSTRIDE + 1;   // region counters, overflow word, bound
+    unsigned long long *rcnt = (unsigned long long *)ctx_buf(c, B_TRICNT, sizeof(uint64_t) * ncnt);
+    if (!rcnt) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(rcnt, 0, sizeof(uint64_t) * ncnt, st));
+    k_wpp<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, rcnt + ncnt - 1);
+    HIP_TRY(hipGetLastError());
+    uint64_t wpp = 0;
+    HIP_TRY(hipMemcpyAsync(&wpp, rcnt + ncnt - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    TriRec *rec = nullptr;
+    // each region holds its share of the bound twice over (workgroups take
+    // vertices in turn, so the regions fill about evenly)
+    const int64_t rcap = (int64_t)(2 * wpp / TRI_REGIONS + 64);
+    if (wpp > 0 && !(c->flags & ESC_F_COMPACT_LISTS)) {
+        size_t fr = 0, tot = 0;
+        HIP_TRY(hipMemGetInfo(&fr, &tot));
+        const size_t want = sizeof(TriRec) * (size_t)rcap * TRI_REGIONS;
+        if (want <= (fr + ctx_held(c, B_TRIREC)) / 8) rec = (TriRec *)ctx_buf(c, B_TRIREC, want);
+    }
+    k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr, hbits, rec, rcnt,
+                                      rec ? rcap : 0, work + WORK_VISITS + 1);
     HIP_TRY(hipGetLastError());
     k_arc_len<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, arc_eid, te, len, tarc);
     HIP_TRY(hipGetLastError());
@@ -212,10 +293,25 @@ esc_status stage_triangles(esc_ctx *c) {
     if (!aa || (keep_av && !av)) return ESC_ENOMEM;
     c->av = av;
     if (total == 0) return ESC_OK;
-    k_copy_cursor<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, aoff, cur);
-    HIP_TRY(hipGetLastError());
-    k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, hbits, nullptr);
-    HIP_TRY(hipGetLastError());
+    uint64_t overflow = 1;
+    if (rec) {
+        HIP_TRY(hipMemcpyAsync(&overflow, rcnt + TRI_REGIONS * TRI_CSTRIDE, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                               st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (rec && overflow == 0) {
+        uint32_t *ecur = (uint32_t *)cur;   // m per-edge cursors in the per-arc cursor buffer
+        HIP_TRY(hipMemsetAsync(ecur, 0, sizeof(uint32_t) * (size_t)(m + 1), st));
+        k_fill_records<<<grid_cap(c, rcap * TRI_REGIONS, 256), 256, 0, st>>>(rcap, rec, rcnt, rev, arc_eid, aoff,
+                                                                            ecur, aa);
+        HIP_TRY(hipGetLastError());
+    } else {
+        k_copy_cursor<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, aoff, cur);
+        HIP_TRY(hipGetLastError());
+        k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, hbits, nullptr,
+                                          nullptr, 0, nullptr);
+        HIP_TRY(hipGetLastError());
+    }
     ESC_TRY(dev_segsort_u32(c, aa, aoff, m2, c->maxdeg));
     if (av) {
         k_apex_ids<<<grid_cap(c, total, 256), 256, 0, st>>>(total, aa, adj, av);

@@ -463,7 +463,15 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         }
         __syncthreads();
         if (s_nx == 0) continue;   // s_nw is still zero; the next write of s_nx is behind a barrier
-        // Wnt(i,j): c in N(i); all of N(c) when c is before i, else only N+(c)
+        // Wnt(i,j): c in N(i); all of N(c) when c is before i, else only N+(c).
+        // Its LDS keys are only read afterwards, never listed: the array is
+        // cleared here and counted without return values; table keys are
+        // listed for their reset.
+        {
+            const int32_t swn = ((ge - hi0) + (1 << shift) - 1) >> shift;   // words holding keys [hi0, ge)
+            for (int q = threadIdx.x; q < swn; q += blockDim.x) sW[q] = 0;
+            __syncthreads();
+        }
         for (int32_t base = oi; base < ei; base += blockDim.x) {
             int32_t p = base + threadIdx.x;
             int start = 0, len = 0;
@@ -476,7 +484,12 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                 int32_t j = adj[q];
                 nvis++;
                 if (j == i) return;
-                if (inc(sW, Wt, j) == 0) tw[atomicAdd(&s_nw, 1)] = j;
+                if (j >= hi0) {
+                    const int32_t idx = j - hi0;
+                    atomicAdd(&sW[idx >> shift], 1u << ((idx & ((1 << shift) - 1)) * cb));
+                } else if (inc(sW, Wt, j) == 0) {
+                    tw[atomicAdd(&s_nw, 1)] = j;
+                }
             });
         }
         __syncthreads();

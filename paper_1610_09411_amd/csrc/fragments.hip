@@ -646,6 +646,8 @@ __device__ inline WaveRange wave_range(int64_t items, bool blocked) {
 
 // per vertex r (rank ids): t(v) = half the sum of t(e) over its edges,
 // K4(v) = a third of the sum of K4(e) = a sixth of the sum of k4e.
+#define VR_BIG 256   // rows walked by a whole wave in the vertex sums
+
 __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t *off, const int32_t *adj,
                                                        const int32_t *split, const int32_t *arc_eid,
                                                        const uint32_t *te, const unsigned long long *k4e,
@@ -667,22 +669,40 @@ __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t 
             if (__ballot(g != gcur && gcur >= 0)) wave_flush_runs<10>(s, gcur, acc, ACC_STRIDE, ids);
             gcur = g;
         }
-        if (!ok) continue;
-        const int32_t a = off[r], b = off[r + 1];
+        const int32_t a = ok ? off[r] : 0, b = ok ? off[r + 1] : 0;
         const uint64_t d = b - a;
-        nvis += d;
         uint64_t t2 = 0, k3 = 0, A = 0, sd = 0;
         u128 B = 0;
-        for (int32_t p = a; p < b; p++) {
-            int32_t e = arc_eid[p];
-            t2 += te[e];
-            k3 += k4e[e];
-            int32_t j = adj[p];
-            uint64_t dj = off[j + 1] - off[j];
-            A += dj - 1;
-            B += (u128)(dj - 1) * (dj - 1);
-            sd += dj;
+        auto arc_terms = [&](int32_t p, uint64_t &xt2, uint64_t &xk3, uint64_t &xA, u128 &xB, uint64_t &xsd) {
+            const int32_t e = arc_eid[p];
+            xt2 += te[e];
+            xk3 += k4e[e];
+            const int32_t j = adj[p];
+            const uint64_t dj = off[j + 1] - off[j];
+            xA += dj - 1;
+            xB += (u128)(dj - 1) * (dj - 1);
+            xsd += dj;
+        };
+        // a lane walks the row of its vertex; rows longer than VR_BIG are
+        // walked by the whole wave (one lane alone would hold up the grid)
+        const bool big = d > VR_BIG;
+        if (ok && !big)
+            for (int32_t p = a; p < b; p++) arc_terms(p, t2, k3, A, B, sd);
+        for (uint64_t bm = __ballot(ok && big); bm; bm &= bm - 1) {
+            const int L = __ffsll((long long)bm) - 1;
+            const int32_t aL = __shfl(a, L), bL = __shfl(b, L);
+            uint64_t pt2 = 0, pk3 = 0, pA = 0, psd = 0;
+            u128 pB = 0;
+            for (int32_t p = aL + lane; p < bL; p += 64) arc_terms(p, pt2, pk3, pA, pB, psd);
+            pt2 = wave_sum_u64(pt2);
+            pk3 = wave_sum_u64(pk3);
+            pA = wave_sum_u64(pA);
+            psd = wave_sum_u64(psd);
+            pB = wave_sum_u128(pB);
+            if (lane == L) { t2 = pt2; k3 = pk3; A = pA; B = pB; sd = psd; }
         }
+        if (!ok) continue;
+        nvis += d;
         const uint64_t t = t2 / 2, k4v = k3 / 6;
         tv[r] = t;
         s[0] += c2(d);

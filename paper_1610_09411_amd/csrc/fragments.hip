@@ -646,7 +646,7 @@ __device__ inline WaveRange wave_range(int64_t items, bool blocked) {
 
 // per vertex r (rank ids): t(v) = half the sum of t(e) over its edges,
 // K4(v) = a third of the sum of K4(e) = a sixth of the sum of k4e.
-#define VR_BIG 256   // rows walked by a whole wave in the vertex sums
+#define VR_BIG 32    // rows walked by a whole wave in the vertex sums
 
 __global__ void __launch_bounds__(256) k_vertex_reduce(int32_t n, const int32_t *off, const int32_t *adj,
                                                        const int32_t *split, const int32_t *arc_eid,

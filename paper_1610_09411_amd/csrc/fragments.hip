@@ -360,14 +360,16 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                                                      const int64_t *toff, const int32_t *town, int64_t nbig,
                                                      int *task_big,
                                                      int chunk, GMap gm, int *task, int32_t slab,
-                                                     unsigned long long *acc, unsigned long long *c4e,
-                                                     unsigned long long *visits) {
+                                                     int32_t pw_words, unsigned long long *acc,
+                                                     unsigned long long *c4e, unsigned long long *visits) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_h, s_r, s_nt;
     __shared__ u128 red[3 * 8];
+    __shared__ int64_t wsa[8][64];
+    __shared__ int32_t wse[8][64], wsi[8][64];
     uint32_t *Ct = tab_all + (size_t)blockIdx.x * tab_n;
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
     const int ids[3] = {AC_C4, AC_N12, AC_N7X2};
@@ -476,6 +478,95 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 sums[2] += (u128)(cc - 1) * cc * (uint64_t)(dh + (off[o + 1] - off[o]) - 4);
             }
         }
+    }
+
+    if (pw_words > 0) {
+        // a batch of small graphs: one top per wave, its counts in the wave's
+        // own LDS table over the keys of its graph (pw_words words), so no
+        // workgroup barrier per top
+        if (gcur >= 0) {
+            block_flush_u128<3>(sums, red, acc + (size_t)gcur * ACC_STRIDE, ids);
+            sums[0] = sums[1] = sums[2] = 0;
+        }
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+        uint32_t *wt = sl + (size_t)wid * pw_words;
+        int wgc = -1;   // graph of the wave's sums
+        for (;;) {
+            if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
+            __syncthreads();
+            const int64_t t0 = (int64_t)s_h * chunk * nwv;
+            __syncthreads();   // s_h is read by every thread before it is taken again
+            if (t0 >= n) break;
+            const int64_t t1 = t0 + (int64_t)chunk * nwv < n ? t0 + (int64_t)chunk * nwv : n;
+            for (int64_t t = t0 + wid; t < t1; t += nwv) {
+                const int32_t h = n - 1 - (int32_t)t;
+                const int32_t oh = off[h], sh = split[h];
+                const int64_t dh = off[h + 1] - oh;
+                if (dh > FOUR_RANGE_DEG && slab > 0) continue;   // done by key range
+                if (sh - oh < 2) continue;                        // c(h,o) >= 2 needs two middles
+                const int g = gm.graph(h);
+                if (g != wgc) {
+                    if (wgc >= 0) wave_flush_runs<3>(sums, wgc, acc, ACC_STRIDE, ids);
+                    wgc = g;
+                }
+                const int32_t gb = gm.begin(g);
+                const int shift = count_shift(dh);
+                const int cb = 32 >> shift;
+                const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
+                const int32_t nwd = ((h - gb) + (1 << shift) - 1) >> shift;   // words of keys [gb, h)
+                for (int q = lane; q < nwd; q += 64) wt[q] = 0;
+                wave_sync();
+                // pass 1: counts
+                for (int32_t pb = oh; pb < sh; pb += 64) {
+                    const int32_t p = pb + lane;
+                    int64_t a0 = 0, a1 = 0;
+                    if (p < sh) { a0 = off[adj[p]]; a1 = rev[p]; }
+                    nvis += (uint64_t)(a1 - a0);
+                    wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return adj[q]; },
+                              [&](int32_t o) {
+                                  const int32_t idx = o - gb;
+                                  atomicAdd(&wt[idx >> shift], 1u << ((idx & ((1 << shift) - 1)) * cb));
+                              });
+                }
+                wave_sync();
+                // pass 2: per-wedge terms
+                for (int32_t pb = oh; pb < sh; pb += 64) {
+                    const int32_t p = pb + lane;
+                    int64_t a0 = 0, a1 = 0;
+                    if (p < sh) { a0 = off[adj[p]]; a1 = rev[p]; }
+                    wave_walk_seg(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return adj[q]; },
+                                  [&](int y, int64_t q, int32_t o) {
+                                      const int32_t idx = o - gb;
+                                      const uint32_t cc = (wt[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask;
+                                      if (cc < 2) return;
+                                      const int32_t pk = pb + y;
+                                      const int32_t k = adj[pk];
+                                      sums[1] += (uint64_t)(cc - 1) * (tarc[pk] + tarc[q]);
+                                      sums[2] += (uint64_t)(cc - 1) * (uint64_t)(2 * (off[k + 1] - off[k]) - 4);
+                                      if (c4e) {
+                                          atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
+                                          atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
+                                      }
+                                  });
+                }
+                // pass 3: per-key terms
+                for (int q = lane; q < nwd; q += 64) {
+                    const uint32_t x = wt[q];
+                    if (x == 0) continue;
+                    for (int f = 0; f < (1 << shift); f++) {
+                        const uint64_t cc = (x >> (f * cb)) & cmask;
+                        if (cc < 2) continue;
+                        const int32_t o = gb + (q << shift) + f;
+                        sums[0] += c2(cc);
+                        sums[2] += (u128)(cc - 1) * cc * (uint64_t)(dh + (off[o + 1] - off[o]) - 4);
+                    }
+                }
+                wave_sync();   // the table is cleared by the wave's next top
+            }
+        }
+        if (wgc >= 0) wave_flush_runs<3>(sums, wgc, acc, ACC_STRIDE, ids);
+        flush_count(nvis, visits);
+        return;
     }
 
     // smaller tops: one per workgroup
@@ -594,7 +685,11 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
         HIP_TRY(hipMemsetAsync(c4e, 0, sizeof(uint64_t) * (size_t)(c->m + 1), st));
     }
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
-    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 8192);
+    const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 16384);
+    // a batch whose graphs are small counts its smaller tops a wave each, in
+    // per-wave LDS tables over a graph's keys (16-bit counts at most)
+    const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
+    const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
     // key-range tasks of the tops with more than FOUR_RANGE_DEG neighbours
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
@@ -605,12 +700,12 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     int64_t nbig = 0;
     int32_t *town = nullptr;
     ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
-    k_four_cycles<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
+    k_four_cycles<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
                                        (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
                                        tab, touch, c->tab_n, toff, town, nbig, task + 4, c->task_chunk, gmap_of(c),
-                                       task, slab,
+                                       task, slab, pw_words,
                                        (unsigned long long *)c->buf[B_ACC], c4e,
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
     HIP_TRY(hipGetLastError());

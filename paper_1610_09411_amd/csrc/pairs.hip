@@ -35,7 +35,8 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                                                   const int32_t *rev, const int64_t *aoff, const uint32_t *aa,
                                                   const int32_t *av, uint32_t *tab_all, int32_t *touch_all,
                                                   int32_t tab_n, int chunk, GMap gm, int *task, int32_t slab,
-                                                  unsigned long long *acc, unsigned long long *visits) {
+                                                  int32_t pw_words, unsigned long long *acc,
+                                                  unsigned long long *visits) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
@@ -49,6 +50,87 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
     int32_t *touch = touch_all + (size_t)blockIdx.x * tab_n;
     u128 sv[2] = {0, 0};   // pattern 13, pattern 17
     int gcur = -1;
+    if (pw_words > 0) {
+        // a batch of small graphs: one source per wave, W(i,.) in the wave's
+        // own LDS table over the keys after i in its graph (pw_words words),
+        // cleared per source, so no touched list and no workgroup barrier
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+        uint32_t *wt = sl + (size_t)wid * pw_words;
+        int wgc = -1;   // graph of the wave's sums
+        for (;;) {
+            if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
+            __syncthreads();
+            const int64_t t0 = (int64_t)s_i * chunk * nwv;
+            __syncthreads();   // s_i is read by every thread before it is taken again
+            if (t0 >= n) break;
+            const int64_t t1 = t0 + (int64_t)chunk * nwv < n ? t0 + (int64_t)chunk * nwv : n;
+            for (int64_t t = t0 + wid; t < t1; t += nwv) {
+                const int32_t i = n - 1 - (int32_t)t;
+                const int32_t oi = off[i], ei = off[i + 1];
+                if (ei - oi < 3) continue;   // d(i) <= 2 adds nothing (as below)
+                const int g = gm.graph(i);
+                if (g != wgc) {
+                    if (wgc >= 0) wave_flush_runs<2>(sv, wgc, acc, ACC_STRIDE, ids);
+                    wgc = g;
+                }
+                const int32_t ge = gm.end(g);
+                const int shift = count_shift(ei - oi);
+                const int cb = 32 >> shift;
+                const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
+                const int32_t nwd = ((ge - i - 1) + (1 << shift) - 1) >> shift;   // words of keys (i, ge)
+                for (int q = lane; q < nwd; q += 64) wt[q] = 0;
+                wave_sync();
+                // W(i,j), j after i: k in N(i), j in the suffix of N(k) after i
+                for (int32_t pb = oi; pb < ei; pb += 64) {
+                    const int32_t p = pb + lane;
+                    int64_t a0 = 0, a1 = 0;
+                    if (p < ei) { a0 = rev[p] + 1; a1 = off[adj[p] + 1]; }
+                    nvis += (uint64_t)(a1 - a0);
+                    wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return adj[q]; },
+                              [&](int32_t j) {
+                                  const int32_t idx = j - i - 1;
+                                  atomicAdd(&wt[idx >> shift], 1u << ((idx & ((1 << shift) - 1)) * cb));
+                              });
+                }
+                wave_sync();
+                // diamonds with tips i and j: for each arc (i,k), the entries l
+                // after k of its list, then the suffix of the list of (k,l) after i
+                uint64_t acc17 = 0;
+                for (int32_t pk = oi; pk < ei; pk++) {
+                    const int32_t k = adj[pk];
+                    const int64_t e0 = aoff[pk], e1 = aoff[pk + 1];
+                    const int64_t r0 = aoff[rev[pk]];
+                    for (int64_t xb = e0; xb < e1; xb += 64) {
+                        const int64_t x = xb + lane;
+                        int64_t a0 = 0, a1 = 0;
+                        if (x < e1 && apex_at(av, adj, aa, x) > k) {
+                            const int32_t qkl = (int32_t)aa[r0 + (x - e0)];   // arc (k,l) in row k
+                            int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
+                            a1 = hi2;
+                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
+                            a0 = lo2;
+                        }
+                        nvis += (uint64_t)(a1 - a0);
+                        wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return apex_at(av, adj, aa, q); },
+                                  [&](int32_t j) {
+                                      const int32_t idx = j - i - 1;
+                                      acc17 += (uint64_t)((wt[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask) - 2;
+                                  });
+                    }
+                }
+                sv[1] += acc17;
+                // sum of C(W,3) over the keys
+                for (int q = lane; q < nwd; q += 64) {
+                    const uint32_t x = wt[q];
+                    if (x != 0) sv[0] += c3_fields(x, cb, cmask);
+                }
+                wave_sync();   // the table is cleared by the wave's next source
+            }
+        }
+        if (wgc >= 0) wave_flush_runs<2>(sv, wgc, acc, ACC_STRIDE, ids);
+        flush_count(nvis, visits);
+        return;
+    }
     if (threadIdx.x == 0) s_nt = 0;
     for (;;) {
         if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
@@ -570,11 +652,15 @@ esc_status stage_pairs(esc_ctx *c) {
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
     const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 16384);
-    k_pairs_wd<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)(slab > 0 ? slab : 1), st>>>(
+    // a batch whose graphs are small takes a source per wave, with per-wave
+    // LDS tables over a graph's keys (16-bit counts at most)
+    const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
+    const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
+    k_pairs_wd<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
                                           n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
                                           (const uint32_t *)c->buf[B_AA], c->av, tab, touch,
-                                          c->tab_n, c->task_chunk, gmap_of(c), task, slab,
+                                          c->tab_n, c->task_chunk, gmap_of(c), task, slab, pw_words,
                                           (unsigned long long *)c->buf[B_ACC],
                                           (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
     HIP_TRY(hipGetLastError());

@@ -472,7 +472,8 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                                                      const int32_t *split, uint32_t *tabX_all, uint32_t *tabW_all,
                                                      int32_t *touchX_all, int32_t *touchW_all, int32_t tab_n,
                                                      int chunk, GMap gm, int *task, int32_t slab,
-                                                     unsigned long long *acc, unsigned long long *visits) {
+                                                     int32_t pw_words, unsigned long long *acc,
+                                                     unsigned long long *visits) {
     extern __shared__ uint32_t dyn[];   // [0, slab) X, [slab, 2 slab) Wnt
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
@@ -489,6 +490,92 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     uint32_t *sX = dyn, *sW = dyn + slab;
     u128 sc[1] = {0};
     int gcur = -1;
+    if (pw_words > 0) {
+        // a batch of small graphs: one source per wave, X(i,.) and Wnt(i,.)
+        // in the wave's own LDS tables over the keys of its graph (pw_words
+        // words each), cleared per source; the final sum scans the X table
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+        uint32_t *wx = dyn + (size_t)wid * 2 * pw_words, *ww = wx + pw_words;
+        int64_t *wsa = beg + wid * 64;
+        int32_t *wse = pref + wid * 64;
+        int wgc = -1;   // graph of the wave's sums
+        for (;;) {
+            if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
+            __syncthreads();
+            const int64_t t0 = (int64_t)s_i * chunk * nwv;
+            __syncthreads();   // s_i is read by every thread before it is taken again
+            if (t0 >= n) break;
+            const int64_t t1 = t0 + (int64_t)chunk * nwv < n ? t0 + (int64_t)chunk * nwv : n;
+            for (int64_t t = t0 + wid; t < t1; t += nwv) {
+                const int32_t i = n - 1 - (int32_t)t;
+                const int32_t oi = off[i], si = split[i], ei = off[i + 1];
+                if (si == oi) continue;   // no in-neighbour: no X key
+                const int g = gm.graph(i);
+                if (g != wgc) {
+                    if (wgc >= 0) wave_flush_runs<1>(sc, wgc, acc, ACC_STRIDE, ids);
+                    wgc = g;
+                }
+                const int32_t gb = gm.begin(g), ge = gm.end(g);
+                const int shift = count_shift(ei - oi);
+                const int cb = 32 >> shift;
+                const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
+                const int32_t nwd = ((ge - gb) + (1 << shift) - 1) >> shift;   // words of the graph's keys
+                for (int q = lane; q < nwd; q += 64) { wx[q] = 0; ww[q] = 0; }
+                wave_sync();
+                auto add = [&](uint32_t *tb, int32_t x) {
+                    const int32_t idx = x - gb;
+                    atomicAdd(&tb[idx >> shift], 1u << ((idx & ((1 << shift) - 1)) * cb));
+                };
+                // X(i,b): a in N-(i), b in N+(a), b != i
+                for (int32_t pb = oi; pb < si; pb += 64) {
+                    const int32_t p = pb + lane;
+                    int64_t a0 = 0, a1 = 0;
+                    if (p < si) { const int32_t a = adj[p]; a0 = split[a]; a1 = off[a + 1]; }
+                    nvis += (uint64_t)(a1 - a0);
+                    wave_walk(a0, a1, wsa, wse, wsi[wid], [&](int64_t q) { return adj[q]; },
+                              [&](int32_t b) { if (b != i) add(wx, b); });
+                }
+                // Wnt(i,j): c in N(i); all of N(c) when c is before i, else only N+(c)
+                for (int32_t pb = oi; pb < ei; pb += 64) {
+                    const int32_t p = pb + lane;
+                    int64_t a0 = 0, a1 = 0;
+                    if (p < ei) {
+                        const int32_t cv = adj[p];
+                        a0 = cv < i ? off[cv] : split[cv];
+                        a1 = off[cv + 1];
+                    }
+                    nvis += (uint64_t)(a1 - a0);
+                    wave_walk(a0, a1, wsa, wse, wsi[wid], [&](int64_t q) { return adj[q]; },
+                              [&](int32_t j) { if (j != i) add(ww, j); });
+                }
+                wave_sync();
+                // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j): each lane takes words
+                // of the X table and walks the out-rows of their keys
+                u128 part = 0;
+                for (int q = lane; q < nwd; q += 64) {
+                    const uint32_t x = wx[q];
+                    if (x == 0) continue;
+                    for (int f = 0; f < (1 << shift); f++) {
+                        const uint32_t xv = (x >> (f * cb)) & cmask;
+                        if (xv == 0) continue;
+                        const int32_t b = gb + (q << shift) + f;
+                        uint64_t sw = 0;
+                        for (int32_t r = split[b]; r < off[b + 1]; r++) {
+                            const int32_t idx = adj[r] - gb;
+                            sw += (ww[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask;
+                        }
+                        nvis += (uint64_t)(off[b + 1] - split[b]);
+                        part += (u128)xv * sw;
+                    }
+                }
+                sc[0] += part;
+                wave_sync();   // the tables are cleared by the wave's next source
+            }
+        }
+        if (wgc >= 0) wave_flush_runs<1>(sc, wgc, acc, ACC_STRIDE, ids);
+        flush_count(nvis, visits);
+        return;
+    }
     for (int q = threadIdx.x; q < 2 * slab; q += blockDim.x) dyn[q] = 0;
     if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }
     for (;;) {
@@ -726,12 +813,16 @@ esc_status stage_cycles(esc_ctx *c) {
     int nwg = per_cu * c->num_cu;
     // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays
     const int32_t slab = slab_words(c, per_cu, 2, 8192, 12288);
+    // a batch whose graphs are small takes a source per wave, with two
+    // per-wave LDS tables over a graph's keys (16-bit counts at most)
+    const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
+    const int32_t lds_words = 16 * pw_words > 2 * slab ? 16 * pw_words : (2 * slab > 0 ? 2 * slab : 1);
     auto kern = c->G ? k_five_cycles<false> : k_five_cycles<true>;
-    kern<<<nwg, 512, sizeof(uint32_t) * (size_t)(2 * slab > 0 ? 2 * slab : 1), st>>>(
+    kern<<<nwg, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,
                                        touch + (size_t)c->tab_n * nwg, c->tab_n, c->task_chunk, gmap_of(c),
-                                       task + 2, slab, (unsigned long long *)c->buf[B_ACC],
+                                       task + 2, slab, pw_words, (unsigned long long *)c->buf[B_ACC],
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 8);
     HIP_TRY(hipGetLastError());
     return ESC_OK;

@@ -41,8 +41,8 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
                                                       const int32_t *arc_eid, const int32_t *earc,
                                                       const int32_t *elo, const uint32_t *te, const int64_t *aoff,
                                                       const uint32_t *aa, const int32_t *av,
-                                                      unsigned long long *k4e, GMap gm, unsigned long long *acc,
-                                                      unsigned long long *visits) {
+                                                      unsigned long long *k4e, GMap gm, int small,
+                                                      unsigned long long *acc, unsigned long long *visits) {
     __shared__ uint32_t bm_all[4][BM_WORDS];
     __shared__ u128 red[5 * 4];
     __shared__ int64_t wsa[4][64];
@@ -65,6 +65,89 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
     u128 s[5] = {0, 0, 0, 0, 0};
     int gcur = -1;
     uint64_t nvis = 0;
+    // the terms of triangle (a,b,c) whose list entry is k in the list of edge
+    // e = (a,b) (c after b), given K4 of the triangle
+    auto triangle_terms = [&](int64_t e, int32_t a, int32_t b, int64_t l0, int64_t r0, int64_t k, uint32_t k4) {
+        const int32_t cc = apex_at(av, adj, aa, k);
+        const int32_t pac = (int32_t)aa[k];                  // arc (a,c) in row a
+        const int32_t pbc = (int32_t)aa[r0 + (k - l0)];      // arc (b,c) in row b
+        const int32_t eac = arc_eid[pac], ebc = arc_eid[pbc];
+        const uint64_t tab = te[e], tac = te[eac], tbc = te[ebc];
+        const uint64_t da = off[a + 1] - off[a], db = off[b + 1] - off[b], dc = off[cc + 1] - off[cc];
+        const uint64_t dpa = off[a + 1] - split[a], dpb = off[b + 1] - split[b], dpc = off[cc + 1] - split[cc];
+        if (k4) {
+            atomicAdd(&k4e[e], (unsigned long long)k4);
+            atomicAdd(&k4e[eac], (unsigned long long)k4);
+            atomicAdd(&k4e[ebc], (unsigned long long)k4);
+        }
+        s[0] += k4;
+        s[1] += c2(k4);
+        s[2] += (u128)(tbc - 1) * (da - 2) + (u128)(tac - 1) * (db - 2) + (u128)(tab - 1) * (dc - 2);
+        s[3] += (u128)(tab - 1) * (tac - 1) + (u128)(tab - 1) * (tbc - 1) + (u128)(tac - 1) * (tbc - 1);
+        s[4] += dpa + dpb + dpc - 3;
+    };
+    if (small) {
+        // a batch of small graphs, whose lists are short: the triangles of 64
+        // consecutive edges of one graph are numbered in one run, a lane
+        // takes one and merges the two sorted lists (a,b) and (a,c) for K4
+        for (int64_t eb = e_first; eb < e_end;) {
+            const int g0 = gm.graph(elo[eb]);
+            const int64_t e = eb + lane;
+            const bool in = e < e_end && gm.graph(elo[e < e_end ? e : eb]) == g0;
+            const uint64_t inb = __ballot(in);
+            const int nb = inb == ~0ull ? 64 : __ffsll((long long)~inb) - 1;   // edges of this run
+            if (g0 != gcur) {
+                if (gcur >= 0) wave_flush_runs<5>(s, gcur, acc, ACC_STRIDE, ids);
+                gcur = g0;
+            }
+            int cnt = 0;
+            int64_t lo = 0;
+            if (lane < nb) {
+                const int32_t p = earc[e];
+                const int64_t l0 = aoff[p], l1 = aoff[p + 1];
+                const int32_t b = adj[p];
+                int64_t hi = l1;   // first apex after b
+                lo = l0;
+                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
+                cnt = (int)(l1 - lo);
+            }
+            int incl = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            const int total = __shfl(incl, 63);
+            wsa[wid][lane] = lo;
+            wsi[wid][lane] = incl;
+            wave_sync();
+            int y = 0;
+            for (int t = lane; t < total; t += 64) {
+                while (wsi[wid][y] <= t) y++;
+                const int64_t ey = eb + y;
+                const int32_t p = earc[ey];
+                const int32_t a = elo[ey], b = adj[p];
+                const int64_t l0 = aoff[p], l1 = aoff[p + 1];
+                const int64_t k = wsa[wid][y] + (t - (wsi[wid][y] - (int)(l1 - wsa[wid][y])));
+                const int32_t pac = (int32_t)aa[k];
+                int64_t x = l0, q = aoff[pac];
+                const int64_t qe = aoff[pac + 1];
+                uint32_t k4 = 0;
+                while (x < l1 && q < qe) {   // positions in the row of a, both sorted
+                    const uint32_t u = aa[x], v = aa[q];
+                    k4 += u == v;
+                    x += u <= v;
+                    q += v <= u;
+                }
+                nvis += (uint64_t)(l1 - l0) + (uint64_t)(qe - aoff[pac]);
+                triangle_terms(ey, a, b, l0, aoff[rev[p]], k, k4);
+            }
+            wave_sync();   // the run arrays are rewritten by the next run
+            eb += nb;
+        }
+        if (gcur >= 0) wave_flush_runs<5>(s, gcur, acc, ACC_STRIDE, ids);
+        flush_count(nvis, visits);
+        return;
+    }
     for (int64_t e = e_first; e < e_end; e += e_step) {
         if (batched) {
             const int g = gm.graph(elo[e]);   // wave-uniform
@@ -364,7 +447,7 @@ esc_status stage_k4_triangles(esc_ctx *c) {
         m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
         (const int32_t *)c->buf[B_REV], (const int32_t *)c->buf[B_ARC_EID], (const int32_t *)c->buf[B_EARC],
         (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], (const int64_t *)c->buf[B_AOFF],
-        (const uint32_t *)c->buf[B_AA], c->av, k4e, gmap_of(c),
+        (const uint32_t *)c->buf[B_AA], c->av, k4e, gmap_of(c), c->G && c->tab_n <= 4096 ? 1 : 0,
         (unsigned long long *)c->buf[B_ACC],
         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
     HIP_TRY(hipGetLastError());

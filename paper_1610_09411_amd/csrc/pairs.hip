@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         // cleared per source, so no touched list and no workgroup barrier
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
         uint32_t *wt = sl + (size_t)wid * pw_words;
+        int (*wrun)[64] = (int (*)[64])pref;   // per wave: inclusive entry counts of 64 arcs
         int wgc = -1;   // graph of the wave's sums
         for (;;) {
             if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
@@ -93,22 +94,38 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                               });
                 }
                 wave_sync();
-                // diamonds with tips i and j: for each arc (i,k), the entries l
-                // after k of its list, then the suffix of the list of (k,l) after i
+                // diamonds with tips i and j: the entries l after k of the
+                // lists of the arcs (i,k), 64 arcs at a time numbered in one
+                // run (a lane per entry), then the suffix of the list of (k,l)
+                // after i, walked by the wave
                 uint64_t acc17 = 0;
-                for (int32_t pk = oi; pk < ei; pk++) {
-                    const int32_t k = adj[pk];
-                    const int64_t e0 = aoff[pk], e1 = aoff[pk + 1];
-                    const int64_t r0 = aoff[rev[pk]];
-                    for (int64_t xb = e0; xb < e1; xb += 64) {
-                        const int64_t x = xb + lane;
+                for (int32_t pb = oi; pb < ei; pb += 64) {
+                    const int32_t pl = pb + lane;
+                    const int cnt = pl < ei ? (int)(aoff[pl + 1] - aoff[pl]) : 0;
+                    int incl = cnt;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int y = __shfl_up(incl, o);
+                        if (lane >= o) incl += y;
+                    }
+                    const int total = __shfl(incl, 63);
+                    wrun[wid][lane] = incl;
+                    wave_sync();
+                    int y = 0;
+                    for (int tb = 0; tb < total; tb += 64) {
+                        const int f = tb + lane;
                         int64_t a0 = 0, a1 = 0;
-                        if (x < e1 && apex_at(av, adj, aa, x) > k) {
-                            const int32_t qkl = (int32_t)aa[r0 + (x - e0)];   // arc (k,l) in row k
-                            int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
-                            a1 = hi2;
-                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
-                            a0 = lo2;
+                        if (f < total) {
+                            while (wrun[wid][y] <= f) y++;
+                            const int32_t pk = pb + y;
+                            const int64_t e0 = aoff[pk];
+                            const int64_t x = e0 + (f - (wrun[wid][y] - (int)(aoff[pk + 1] - e0)));
+                            if (apex_at(av, adj, aa, x) > adj[pk]) {
+                                const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - e0)];   // arc (k,l) in row k
+                                int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
+                                a1 = hi2;
+                                while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
+                                a0 = lo2;
+                            }
                         }
                         nvis += (uint64_t)(a1 - a0);
                         wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return apex_at(av, adj, aa, q); },
@@ -117,6 +134,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                                       acc17 += (uint64_t)((wt[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask) - 2;
                                   });
                     }
+                    wave_sync();   // wrun is rewritten by the next 64 arcs
                 }
                 sv[1] += acc17;
                 // sum of C(W,3) over the keys

@@ -18,6 +18,10 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+
+// Batches whose graphs all have at most this many vertices run the per-source
+// passes a source per wave (per-wave LDS tables over a graph's keys).
+constexpr int32_t PW_MAX_N = 4096;
 #include <vector>
 #include "device.h"
 #include "ctx.h"
@@ -148,17 +152,24 @@ void worker(esc_server *s, esc_ctx *c) {
             if (s->stopping) break;
             continue;
         }
-        // the launch: the head, plus following small requests of the same k
+        // the launch: the head, plus queued requests of the same k and size
+        // class (graphs of at most PW_MAX_N vertices batch apart from larger
+        // ones, so their launches take the per-wave passes); requests that
+        // do not match stay queued for the next free worker
         std::vector<Req *> grp{s->queue.front()};
+        std::vector<size_t> pos{0};
         size_t est = footprint(grp, s->nwg);
         if (grp[0]->n <= s->small_n) {
-            for (size_t i = 1; i < s->queue.size() && (int)grp.size() < s->max_group; i++) {
+            const bool tiny = grp[0]->n <= PW_MAX_N;
+            const size_t scan = s->queue.size() < (size_t)4 * s->max_group ? s->queue.size() : (size_t)4 * s->max_group;
+            for (size_t i = 1; i < scan && (int)grp.size() < s->max_group; i++) {
                 Req *r = s->queue[i];
-                if (r->k != grp[0]->k || r->n > s->small_n) break;
+                if (r->k != grp[0]->k || r->n > s->small_n || (r->n <= PW_MAX_N) != tiny) continue;
                 grp.push_back(r);
                 size_t e2 = footprint(grp, s->nwg);
                 if (e2 > s->budget) { grp.pop_back(); break; }
                 est = e2;
+                pos.push_back(i);
             }
         }
         if (grp.size() == 1 && est > s->budget) {
@@ -176,7 +187,7 @@ void worker(esc_server *s, esc_ctx *c) {
             s->cv.wait(lk);   // until a launch in flight releases its memory
             continue;
         }
-        for (size_t i = 0; i < grp.size(); i++) s->queue.pop_front();
+        for (size_t j = pos.size(); j-- > 0;) s->queue.erase(s->queue.begin() + (ptrdiff_t)pos[j]);
         s->reserved += est;
         s->running++;
         if (s->running > s->peak_running) s->peak_running = s->running;

@@ -266,29 +266,50 @@ __global__ void k_edges(int32_t n, const int32_t *off, const int32_t *adj, const
 #define SEG_SMALL 32
 #define SEG_WAVE 1024   // segments up to this length are sorted by one wave
 
-__global__ void k_seg_classify(const int64_t *seg_off, int64_t nseg, int32_t *q, int32_t *counts, int64_t qcap,
-                               int64_t lds_keys) {
-    // one atomic per wave and class: lanes of the same class take
-    // consecutive slots from their leader's reservation
+#define SEG_PER_THREAD 8   // segments each thread classifies per tile
+
+// Work lists of the segment classes.  A workgroup classifies a tile of
+// blockDim * SEG_PER_THREAD segments: slots inside the tile come from LDS
+// counters (one LDS atomic per wave and class), and the tile reserves its
+// range of each class list with one global atomic per class; a global
+// atomic per wave had serialised on the four counters.
+__global__ void __launch_bounds__(256) k_seg_classify(const int64_t *seg_off, int64_t nseg, int32_t *q,
+                                                      int32_t *counts, int64_t qcap, int64_t lds_keys) {
+    __shared__ int lcnt[4], lbase[4];
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nseg; base += stride) {
-        const int64_t s = base + threadIdx.x;
-        int cls = -1;
-        if (s < nseg) {
-            int64_t len = seg_off[s + 1] - seg_off[s];
-            if (len > 1) cls = len <= SEG_SMALL ? 0 : (len <= SEG_WAVE ? 1 : (len <= lds_keys ? 2 : 3));
+    const int64_t tile = (int64_t)blockDim.x * SEG_PER_THREAD;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < nseg; t0 += (int64_t)gridDim.x * tile) {
+        if (threadIdx.x < 4) lcnt[threadIdx.x] = 0;
+        __syncthreads();
+        int cls[SEG_PER_THREAD], slot[SEG_PER_THREAD];
+#pragma unroll
+        for (int u = 0; u < SEG_PER_THREAD; u++) {
+            const int64_t s = t0 + (int64_t)u * blockDim.x + threadIdx.x;
+            cls[u] = -1;
+            slot[u] = 0;
+            if (s < nseg) {
+                const int64_t len = seg_off[s + 1] - seg_off[s];
+                if (len > 1) cls[u] = len <= SEG_SMALL ? 0 : (len <= SEG_WAVE ? 1 : (len <= lds_keys ? 2 : 3));
+            }
+            for (int c = 0; c < 4; c++) {
+                const uint64_t m = __ballot(cls[u] == c);
+                if (!m) continue;
+                const int leader = __ffsll((long long)m) - 1;
+                int b = 0;
+                if (lane == leader) b = atomicAdd(&lcnt[c], __popcll(m));
+                b = __shfl(b, leader);
+                if (cls[u] == c) slot[u] = b + __popcll(m & lt);
+            }
         }
-        for (int c = 0; c < 4; c++) {
-            const uint64_t m = __ballot(cls == c);
-            if (!m) continue;
-            const int leader = __ffsll((long long)m) - 1;
-            int32_t basepos = 0;
-            if (lane == leader) basepos = atomicAdd(&counts[c], __popcll(m));
-            basepos = __shfl(basepos, leader);
-            if (cls == c) q[c * qcap + basepos + __popcll(m & lt)] = (int32_t)s;
-        }
+        __syncthreads();
+        if (threadIdx.x < 4) lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]) : 0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SEG_PER_THREAD; u++)
+            if (cls[u] >= 0)
+                q[cls[u] * qcap + lbase[cls[u]] + slot[u]] = (int32_t)(t0 + (int64_t)u * blockDim.x + threadIdx.x);
+        __syncthreads();   // lcnt and lbase are reset by the next tile
     }
 }
 
@@ -413,7 +434,9 @@ esc_status dev_segsort_u32(esc_ctx *c, uint32_t *keys, const int64_t *seg_off, i
     // largest power-of-two key count one workgroup's LDS holds
     int64_t lds_keys = 1;
     while (lds_keys * 2 * (int64_t)sizeof(uint32_t) <= c->max_lds) lds_keys *= 2;
-    k_seg_classify<<<blocks, 256, 0, st>>>(seg_off, nseg, q, counts, nseg, lds_keys);
+    const int64_t ctiles = (nseg + 256 * SEG_PER_THREAD - 1) / (256 * SEG_PER_THREAD);
+    k_seg_classify<<<(int)(ctiles < 65535 ? (ctiles > 0 ? ctiles : 1) : 65535), 256, 0, st>>>(seg_off, nseg, q, counts,
+                                                                                            nseg, lds_keys);
     HIP_TRY(hipGetLastError());
     k_seg_small<<<blocks, 256, 0, st>>>(keys, seg_off, q, counts);
     HIP_TRY(hipGetLastError());

@@ -603,9 +603,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
         __syncthreads();
         const int64_t t0 = (int64_t)s_i * chunk;
-        // s_i is read by every thread before it is taken again: a chunk whose
-        // sources are all skipped has no other barrier before the next take
-        __syncthreads();
+        __syncthreads();   // s_i is read by every thread before it is taken again
         if (t0 >= n) break;
         const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {

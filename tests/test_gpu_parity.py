@@ -177,9 +177,6 @@ def test_canonicalize_counts_the_described_graph(ctx):
     assert e.value.status == esc.ESC_EINVAL
 
 
-@pytest.mark.skip(reason="a GPU memory fault ended the box during this test once, in a build whose 5-cycle and "
-                         "K4 kernels carried occupancy attributes (since removed); the cause was not found, so the "
-                         "case stays off the GPU until it is")
 def test_tuned_and_forced_parameters_give_same_counts(ctx):
     """The autotuner picks launch parameters per degree-statistics key; any
     parameters give the same counts."""

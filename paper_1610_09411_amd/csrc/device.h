@@ -141,6 +141,17 @@ __device__ inline int block_exclusive_scan(int x, int *tmp, int *total) {
     return res;
 }
 
+// Spans of per-source work taken from a shared counter, sources in
+// decreasing rank order.  The first TASK_HEAD grabs take `chunk` sources
+// each (the high-rank sources, whose work varies most); every later grab
+// takes TASK_TAIL, so the long tail of low-degree sources costs few atomics
+// on the one counter.  Grab g covers [task_begin(g), task_begin(g + 1)).
+#define TASK_HEAD 16384
+#define TASK_TAIL 16
+__device__ inline int64_t task_begin(int64_t g, int chunk) {
+    return g < TASK_HEAD ? g * chunk : (int64_t)TASK_HEAD * chunk + (g - TASK_HEAD) * TASK_TAIL;
+}
+
 // Load-balanced expansion.  A batch of up to blockDim segments, thread t
 // describing segment t by (start, len); every element (segment s, position
 // start_s + r) is visited exactly once, spread evenly over the block.

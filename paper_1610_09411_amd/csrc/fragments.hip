@@ -574,12 +574,12 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     for (;;) {
         if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
         __syncthreads();
-        const int64_t t0 = (int64_t)s_h * chunk;
+        const int64_t t0 = task_begin(s_h, chunk), tn = task_begin((int64_t)s_h + 1, chunk);
         // s_h is read by every thread before it is taken again: a chunk whose
         // tops are all skipped has no other barrier before the next take
         __syncthreads();
         if (t0 >= n) break;
-        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        const int32_t t1 = (int32_t)(tn < n ? tn : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {
             const int32_t h = n - 1 - t;
             const int g = gm.graph(h);

@@ -153,12 +153,12 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
     for (;;) {
         if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
         __syncthreads();
-        const int64_t t0 = (int64_t)s_i * chunk;
+        const int64_t t0 = task_begin(s_i, chunk), tn = task_begin((int64_t)s_i + 1, chunk);
         // s_i is read by every thread before it is taken again: a chunk whose
         // sources are all skipped has no other barrier before the next take
         __syncthreads();
         if (t0 >= n) break;
-        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        const int32_t t1 = (int32_t)(tn < n ? tn : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t i = n - 1 - t;
         const int g = gm.graph(i);
@@ -421,9 +421,9 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     for (;;) {
         if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
         __syncthreads();
-        const int64_t t0 = (int64_t)s_h * chunk;
+        const int64_t t0 = task_begin(s_h, chunk), tn = task_begin((int64_t)s_h + 1, chunk);
         if (t0 >= n) break;
-        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        const int32_t t1 = (int32_t)(tn < n ? tn : n);
         __syncthreads();   // s_h is read by every thread before it is taken again
         for (int32_t t = (int32_t)t0; t < t1; t++) {
             const int32_t h = n - 1 - t;
@@ -602,10 +602,10 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     for (;;) {
         if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
         __syncthreads();
-        const int64_t t0 = (int64_t)s_i * chunk;
+        const int64_t t0 = task_begin(s_i, chunk), tn = task_begin((int64_t)s_i + 1, chunk);
         __syncthreads();   // s_i is read by every thread before it is taken again
         if (t0 >= n) break;
-        const int32_t t1 = (int32_t)(t0 + chunk < n ? t0 + chunk : n);
+        const int32_t t1 = (int32_t)(tn < n ? tn : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t i = n - 1 - t;
         const int g = gm.graph(i);

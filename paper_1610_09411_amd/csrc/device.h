@@ -155,7 +155,8 @@ __device__ inline int64_t task_begin(int64_t g, int chunk) {
 // Load-balanced expansion.  A batch of up to blockDim segments, thread t
 // describing segment t by (start, len); every element (segment s, position
 // start_s + r) is visited exactly once, spread evenly over the block.
-// `pref` and `beg` are LDS arrays of blockDim+1 entries, `tmp` as above.
+// `pref` and `beg` are LDS arrays of blockDim+1 entries, `tmp` as above
+// with two more entries (blockDim / 64 + 2 in all).
 template <class Item>
 __device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg, int *tmp, Item item) {
     int total;
@@ -163,10 +164,15 @@ __device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg
     pref[threadIdx.x] = ex;
     beg[threadIdx.x] = start;
     if (threadIdx.x == 0) pref[blockDim.x] = total;
+    // the last non-empty segment (the one whose inclusive prefix reaches
+    // total) bounds the search: every later segment starts at total > x.
+    // tmp[nw + 1] is free once the scan has returned.
+    if (len > 0 && ex + len == total) tmp[blockDim.x / ESC_WAVE + 1] = threadIdx.x;
     __syncthreads();
+    const int last = total > 0 ? tmp[blockDim.x / ESC_WAVE + 1] : 0;
     for (int x = threadIdx.x; x < total; x += blockDim.x) {
         // last segment whose prefix is <= x
-        int lo = 0, hi = blockDim.x - 1;
+        int lo = 0, hi = last;
         while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
             if (pref[mid] <= x) lo = mid; else hi = mid - 1;

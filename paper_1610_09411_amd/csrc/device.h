@@ -194,6 +194,34 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A lane's place in the concatenation of a wave's 64 segments (LDS arrays
+// sa = first position, se = exclusive and si = inclusive element prefix):
+// the segment y holding element e is the first with si[y] > e.  Its end and
+// the offset mapping e to a position (sa[y] - se[y]) stay in registers and
+// are reloaded only when e passes the end, so a lane that stays inside one
+// segment reads no LDS.  Elements are asked for in increasing order, all
+// below si[63].
+struct SegCursor {
+    int y;
+    int32_t end;
+    int64_t base;
+    __device__ inline void init(const int64_t *sa, const int32_t *se, const int32_t *si) {
+        y = 0;
+        end = si[0];
+        base = sa[0] - se[0];
+    }
+    __device__ inline int64_t pos(int32_t e, const int64_t *sa, const int32_t *se, const int32_t *si) {
+        if (end <= e) {
+            do {
+                y++;
+                end = si[y];
+            } while (end <= e);
+            base = sa[y] - se[y];
+        }
+        return base + e;
+    }
+};
+
 // Walk the concatenation of up to 64 segments held one per lane (lane y
 // holds segment y = [a0, a1)), 64 consecutive elements per step, so that one
 // step spans as many short segments as it needs; eight steps are issued
@@ -216,7 +244,8 @@ __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_
     se[lane] = incl - len;
     si[lane] = incl;
     wave_sync();
-    int y = 0;
+    SegCursor c;
+    c.init(sa, se, si);
     int32_t e = lane;
     constexpr int NU = 8;   // steps in flight
     for (; e + (NU - 1) * ESC_WAVE < total; e += NU * ESC_WAVE) {
@@ -224,9 +253,8 @@ __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_
         int yy[NU];
 #pragma unroll
         for (int u = 0; u < NU; u++) {
-            while (si[y] <= e + u * ESC_WAVE) y++;
-            yy[u] = y;
-            q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
+            q[u] = c.pos(e + u * ESC_WAVE, sa, se, si);
+            yy[u] = c.y;
         }
         decltype(load(q[0])) v[NU];
 #pragma unroll
@@ -235,9 +263,8 @@ __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_
         for (int u = 0; u < NU; u++) use(yy[u], q[u], v[u]);
     }
     for (; e < total; e += ESC_WAVE) {
-        while (si[y] <= e) y++;
-        const int64_t q = sa[y] + (e - se[y]);
-        use(y, q, load(q));
+        const int64_t q = c.pos(e, sa, se, si);
+        use(c.y, q, load(q));
     }
     wave_sync();   // the arrays are reused by the next call
 }
@@ -261,6 +288,8 @@ __device__ inline void wave_walk_act(int64_t a0, int64_t a1, int64_t *sa, int32_
     se[lane] = incl - len;
     si[lane] = incl;
     wave_sync();
+    // each element's segment is looked up in LDS (no SegCursor): fewer
+    // registers, and the wheel walks gain nothing from it
     int y = 0;
     int32_t e = lane;
     constexpr int NU = 8;   // steps in flight
@@ -313,16 +342,17 @@ __device__ inline uint32_t wave_count(int64_t a0, int64_t a1, int64_t *sa, int32
     si[lane] = incl;
     cnt[lane] = 0;
     wave_sync();
-    int y = 0, ycur = 0;
+    SegCursor c;
+    c.init(sa, se, si);
+    int ycur = 0;
     uint32_t run = 0;
     int32_t e = lane;
     for (; e + 3 * ESC_WAVE < total; e += 4 * ESC_WAVE) {
         int yy[4];
         int64_t q[4];
         for (int u = 0; u < 4; u++) {
-            while (si[y] <= e + u * ESC_WAVE) y++;
-            yy[u] = y;
-            q[u] = sa[y] + (e + u * ESC_WAVE - se[y]);
+            q[u] = c.pos(e + u * ESC_WAVE, sa, se, si);
+            yy[u] = c.y;
         }
         const auto v0 = load(q[0]), v1 = load(q[1]), v2 = load(q[2]), v3 = load(q[3]);
         const uint32_t b[4] = {(uint32_t)pred(v0), (uint32_t)pred(v1), (uint32_t)pred(v2), (uint32_t)pred(v3)};
@@ -336,13 +366,13 @@ __device__ inline uint32_t wave_count(int64_t a0, int64_t a1, int64_t *sa, int32
         }
     }
     for (; e < total; e += ESC_WAVE) {
-        while (si[y] <= e) y++;
-        if (y != ycur) {
+        const int64_t q = c.pos(e, sa, se, si);
+        if (c.y != ycur) {
             if (run) atomicAdd(&cnt[ycur], run);
             run = 0;
-            ycur = y;
+            ycur = c.y;
         }
-        run += (uint32_t)pred(load(sa[y] + (e - se[y])));
+        run += (uint32_t)pred(load(q));
     }
     if (run) atomicAdd(&cnt[ycur], run);
     wave_sync();

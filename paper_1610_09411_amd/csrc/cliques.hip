@@ -36,6 +36,7 @@ __device__ inline uint32_t count_common(const int32_t *av, const int32_t *adj, c
     return c;
 }
 
+template <bool IDS>
 __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *off, const int32_t *adj,
                                                       const int32_t *split, const int32_t *rev,
                                                       const int32_t *arc_eid, const int32_t *earc,
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
     // the terms of triangle (a,b,c) whose list entry is k in the list of edge
     // e = (a,b) (c after b), given K4 of the triangle
     auto triangle_terms = [&](int64_t e, int32_t a, int32_t b, int64_t l0, int64_t r0, int64_t k, uint32_t k4) {
-        const int32_t cc = apex_at(av, adj, aa, k);
+        const int32_t cc = apex_at<IDS>(av, adj, aa, k);
         const int32_t pac = (int32_t)aa[k];                  // arc (a,c) in row a
         const int32_t pbc = (int32_t)aa[r0 + (k - l0)];      // arc (b,c) in row b
         const int32_t eac = arc_eid[pac], ebc = arc_eid[pbc];
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
                 const int32_t b = adj[p];
                 int64_t hi = l1;   // first apex after b
                 lo = l0;
-                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
+                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
                 cnt = (int)(l1 - lo);
             }
             int incl = cnt;
@@ -161,7 +162,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
         if (l1 == l0) continue;
         const int32_t a = elo[e], b = adj[p];
         int64_t lo = l0, hi = l1;   // first apex after b
-        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
+        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
         if (lo == l1) continue;
         const int32_t oa = off[a];
         const int32_t da_i = off[a + 1] - oa;
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
             int32_t cc = 0, pac = 0, pbc = 0;
             int64_t q0 = 0, q1 = 0;
             if (ok) {
-                cc = apex_at(av, adj, aa, k);
+                cc = apex_at<IDS>(av, adj, aa, k);
                 pac = (int32_t)aa[k];                  // arc (a,c) in row a
                 pbc = (int32_t)aa[r0 + (k - l0)];      // arc (b,c) in row b
                 q0 = aoff[pac];
@@ -443,7 +444,8 @@ esc_status stage_k4_triangles(esc_ctx *c) {
     if (!k4e) return ESC_ENOMEM;
     HIP_TRY(hipMemsetAsync(k4e, 0, sizeof(uint64_t) * (size_t)(m + 1), st));
     if (m == 0 || c->narcs_apex == 0) return ESC_OK;
-    k_k4_triangles<<<grid_cap(c, m * 64, 256, 8), 256, 0, st>>>(
+    auto kern = c->av ? k_k4_triangles<true> : k_k4_triangles<false>;
+    kern<<<grid_cap(c, m * 64, 256, 8), 256, 0, st>>>(
         m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
         (const int32_t *)c->buf[B_REV], (const int32_t *)c->buf[B_ARC_EID], (const int32_t *)c->buf[B_EARC],
         (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], (const int64_t *)c->buf[B_AOFF],

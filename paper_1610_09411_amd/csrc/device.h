@@ -388,6 +388,13 @@ __device__ inline int32_t apex_at(const int32_t *av, const int32_t *adj, const u
     return av ? av[q] : adj[aa[q]];
 }
 
+// The same with the layout fixed at compile time (IDS: apex ids are stored),
+// for kernels instantiated per layout: no test of av per entry.
+template <bool IDS>
+__device__ inline int32_t apex_at(const int32_t *av, const int32_t *adj, const uint32_t *aa, int64_t q) {
+    return IDS ? av[q] : adj[aa[q]];
+}
+
 // Counts bounded by d pack 32 / 2^shift to a 32-bit word: 2-bit fields for
 // d < 4, 4-bit for d < 16, 8-bit for d < 256, 16-bit for d < 2^16.
 // Returns shift = log2(fields per word).

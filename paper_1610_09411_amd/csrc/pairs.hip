@@ -31,6 +31,7 @@
 // The tips of diamonds are mostly hubs as well, so the diamond gathers stay
 // in LDS too.
 
+template <bool IDS>
 __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off, const int32_t *adj,
                                                   const int32_t *rev, const int64_t *aoff, const uint32_t *aa,
                                                   const int32_t *av, uint32_t *tab_all, int32_t *touch_all,
@@ -119,16 +120,16 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                             const int32_t pk = pb + y;
                             const int64_t e0 = aoff[pk];
                             const int64_t x = e0 + (f - (wrun[wid][y] - (int)(aoff[pk + 1] - e0)));
-                            if (apex_at(av, adj, aa, x) > adj[pk]) {
+                            if (apex_at<IDS>(av, adj, aa, x) > adj[pk]) {
                                 const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - e0)];   // arc (k,l) in row k
                                 int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
                                 a1 = hi2;
-                                while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
+                                while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
                                 a0 = lo2;
                             }
                         }
                         nvis += (uint64_t)(a1 - a0);
-                        wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return apex_at(av, adj, aa, q); },
+                        wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return apex_at<IDS>(av, adj, aa, q); },
                                   [&](int32_t j) {
                                       const int32_t idx = j - i - 1;
                                       acc17 += (uint64_t)((wt[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask) - 2;
@@ -228,19 +229,19 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                         const int32_t pk = base + lo;
                         const int64_t e0 = aoff[pk];
                         const int64_t x = e0 + (f - pref[lo]);
-                        const int32_t l = apex_at(av, adj, aa, x);
+                        const int32_t l = apex_at<IDS>(av, adj, aa, x);
                         if (l > adj[pk]) {
                             const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - e0)];   // arc (k,l) in row k
                             int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
                             a1 = hi2;
-                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
+                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
                             a0 = lo2;
                         }
                     }
                     nvis += (uint64_t)(a1 - a0);
                     uint64_t acc17 = 0;
                     wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid],
-                              [&](int64_t q) { return apex_at(av, adj, aa, q); },
+                              [&](int64_t q) { return apex_at<IDS>(av, adj, aa, q); },
                               [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? SLAB_GET(j) : TAB_GET(j)) - 2; });
                     sv[1] += acc17;
                 }
@@ -304,6 +305,7 @@ __global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int64_t
     }
 }
 
+template <bool IDS>
 __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
@@ -357,7 +359,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
             if (l1 - l0 < 2) continue;   // a rim 4-cycle needs two triangles on (h,i)
             // entries l of list(h,i) below i
             int64_t lo = l0, hi = l1;
-            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
+            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
             const int nl = (int)(lo - l0);
             if (nl == 0) continue;
             if (threadIdx.x == 0) s_nt = 0;
@@ -373,7 +375,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                     const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
                     b0 = aoff[qhl];
                     int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                    while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
+                    while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
                     b1 = lo2;
                 }
                 nvis += (uint64_t)(b1 - b0);
@@ -437,7 +439,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                 const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
                 if (l1 - l0 < 2) continue;
                 int64_t lo = l0, hi = l1;
-                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
+                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
                 const int nl = (int)(lo - l0);
                 if (nl == 0) continue;
                 if (lane == 0) s_ntw[wid] = 0;
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                         const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
                         b0 = aoff[qhl];
                         int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
                         b1 = lo2;
                     }
                     nvis += (uint64_t)(b1 - b0);
@@ -765,7 +767,8 @@ esc_status stage_pairs(esc_ctx *c) {
     // LDS tables over a graph's keys (16-bit counts at most)
     const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
     const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
-    k_pairs_wd<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
+    auto kern = c->av ? k_pairs_wd<true> : k_pairs_wd<false>;
+    kern<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
                                           n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                           (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
                                           (const uint32_t *)c->buf[B_AA], c->av, tab, touch,
@@ -811,7 +814,8 @@ esc_status stage_wheels(esc_ctx *c) {
     int64_t nbig = 0;
     int32_t *town = nullptr;
     ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
-    k_wheels<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+    auto kern = c->av ? k_wheels<true> : k_wheels<false>;
+    kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
                                               c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],

@@ -490,7 +490,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
 // WALK: the final sum may run as wave walks; the kernel without them needs
 // half the registers, so more workgroups stay resident (batches of small
 // graphs, where few sources have FIVE_WAVE_KEYS keys)
-template <bool WALK>
+template <bool WALK, bool YSUM>
 __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *off, const int32_t *adj,
                                                      const int32_t *split, uint32_t *tabX_all, uint32_t *tabW_all,
                                                      int32_t *touchX_all, int32_t *touchW_all, int32_t tab_n,
@@ -656,6 +656,78 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         }
         __syncthreads();
         if (s_nx == 0) continue;   // s_nw is still zero; the next write of s_nx is behind a barrier
+        if (YSUM) {
+            // The same sum taken from the other side: sum_j Wnt(i,j) Y(i,j)
+            // with Y(i,j) = sum of X(i,b) over the keys b with j in N+(b).
+            // The few out-rows of the keys b build Y (atomics); the many
+            // Wnt wedges (c, j) only read it.  Y(i,j) < d(i) d(j) < 2^32
+            // (maximum degree below 2^16): one word per key, LDS keys
+            // [hy, ge), the rest in the workgroup's table, reset through
+            // the touched list tw.
+            const int32_t hy = ge - slab > gb ? ge - slab : gb;
+            for (int q = threadIdx.x; q < ge - hy; q += blockDim.x) sW[q] = 0;
+            __syncthreads();
+            auto yadd = [&](int32_t j, uint32_t xv) {
+                if (j >= hy) atomicAdd(&sW[j - hy], xv);
+                else if (atomicAdd(&Wt[j - gb], xv) == 0) tw[atomicAdd(&s_nw, 1)] = j;   // xv >= 1
+            };
+            const int nx = s_nx;
+            if (nx < FIVE_WAVE_KEYS) {
+                for (int base = 0; base < nx; base += blockDim.x) {
+                    const int xi = base + threadIdx.x;
+                    int start = 0, len = 0;
+                    if (xi < nx) { const int32_t b = tx[xi]; start = split[b]; len = off[b + 1] - split[b]; }
+                    nvis += (uint64_t)len;
+                    lbs_batch(start, len, pref, beg, tmp,
+                              [&](int s, int q) { yadd(adj[q], get(sX, Xt, tx[base + s])); });
+                }
+            } else {
+                const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+                int64_t *wsa = beg + wid * 64;
+                int32_t *wse = pref + wid * 64;
+                for (int xb = 0; xb < nx; xb += nwv * 64) {
+                    const int xi = xb + lane * nwv + wid;   // keys dealt to the waves in turn
+                    int64_t a0 = 0, a1 = 0;
+                    uint32_t xv = 0;
+                    if (xi < nx) {
+                        const int32_t b = tx[xi];
+                        a0 = split[b];
+                        a1 = off[b + 1];
+                        xv = get(sX, Xt, b);
+                    }
+                    nvis += (uint64_t)(a1 - a0);
+                    wxs[wid][lane] = xv;   // visible to the wave after the walk's own wave_sync
+                    wave_walk_seg(a0, a1, wsa, wse, wsi[wid], [&](int64_t q) { return adj[q]; },
+                                  [&](int y, int64_t, int32_t j) { yadd(j, wxs[wid][y]); });
+                }
+            }
+            __syncthreads();
+            // Wnt wedges: c in N(i); all of N(c) when c is before i, else N+(c)
+            uint64_t part = 0;
+            for (int32_t base = oi; base < ei; base += blockDim.x) {
+                int32_t p = base + threadIdx.x;
+                int start = 0, len = 0;
+                if (p < ei) {
+                    int32_t cv = adj[p];
+                    if (cv < i) { start = off[cv]; len = off[cv + 1] - off[cv]; }
+                    else { start = split[cv]; len = off[cv + 1] - split[cv]; }
+                }
+                lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
+                    const int32_t j = adj[q];
+                    nvis++;
+                    if (j == i) return;
+                    part += j >= hy ? sW[j - hy] : Wt[j - gb];
+                });
+            }
+            sc[0] += part;
+            __syncthreads();
+            for (int q = threadIdx.x; q < nx; q += blockDim.x) clr(sX, Xt, tx[q]);
+            const int ny = s_nw;
+            for (int q = threadIdx.x; q < ny; q += blockDim.x) Wt[tw[q] - gb] = 0;
+            __syncthreads();
+            if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }   // next reads are behind a barrier
+            continue;
+        }
         // Wnt(i,j): c in N(i); all of N(c) when c is before i, else only N+(c).
         // Its LDS keys are only read afterwards, never listed: the array is
         // cleared here and counted without return values; table keys are
@@ -843,7 +915,10 @@ esc_status stage_cycles(esc_ctx *c) {
     // per-wave LDS tables over a graph's keys (16-bit counts at most)
     const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
     const int32_t lds_words = 16 * pw_words > 2 * slab ? 16 * pw_words : (2 * slab > 0 ? 2 * slab : 1);
-    auto kern = c->G ? k_five_cycles<false> : k_five_cycles<true>;
+    // one graph with maximum degree below 2^16: the Y-table order (32-bit
+    // Y(i,j) < d(i) d(j))
+    auto kern = c->G ? k_five_cycles<false, false>
+                     : (c->maxdeg < 65536 ? k_five_cycles<true, true> : k_five_cycles<true, false>);
     kern<<<nwg, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,

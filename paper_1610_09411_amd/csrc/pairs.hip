@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                                                      int chunk, GMap gm, int *task, int32_t slab,
                                                      int32_t pw_words, unsigned long long *acc,
                                                      unsigned long long *visits) {
-    extern __shared__ uint32_t dyn[];   // [0, slab) X, [slab, 2 slab) Wnt
+    extern __shared__ uint32_t dyn[];   // [0, xslab) X, [xslab, 2 slab) Wnt or Y
     uint64_t nvis = 0;
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
@@ -510,7 +510,11 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     uint32_t *Wt = tabW_all + (size_t)blockIdx.x * tab_n;
     int32_t *tx = touchX_all + (size_t)blockIdx.x * tab_n;
     int32_t *tw = touchW_all + (size_t)blockIdx.x * tab_n;
-    uint32_t *sX = dyn, *sW = dyn + slab;
+    // LDS words of the X array: half of the two arrays, or in the Y order an
+    // eighth (X counts pack several per word, Y takes a word per key and
+    // its reads are the many)
+    const int32_t xslab = YSUM ? slab / 4 : slab;
+    uint32_t *sX = dyn, *sW = dyn + xslab;
     u128 sc[1] = {0};
     int gcur = -1;
     if (pw_words > 0) {
@@ -620,7 +624,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         const int shift = count_shift(ei - oi);
         const int cb = 32 >> shift;
         const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
-        const int32_t hi0 = ge - (slab << shift) > gb ? ge - (slab << shift) : gb;   // first key held in LDS
+        const int32_t hi0 = ge - (xslab << shift) > gb ? ge - (xslab << shift) : gb;   // first key held in LDS
         // count of key x in the LDS array s (latest keys) or the table t: add
         // one (returns the old count), read, clear; separate branches keep
         // LDS and global accesses apart
@@ -664,7 +668,8 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             // (maximum degree below 2^16): one word per key, LDS keys
             // [hy, ge), the rest in the workgroup's table, reset through
             // the touched list tw.
-            const int32_t hy = ge - slab > gb ? ge - slab : gb;
+            const int32_t ys = 2 * slab - xslab;   // LDS words of the Y array
+            const int32_t hy = ge - ys > gb ? ge - ys : gb;
             for (int q = threadIdx.x; q < ge - hy; q += blockDim.x) sW[q] = 0;
             __syncthreads();
             auto yadd = [&](int32_t j, uint32_t xv) {

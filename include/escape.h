@@ -218,12 +218,18 @@ typedef struct {
                                tenth of device memory) */
     int32_t k5_work_log2;   /* 5-cliques: a vertex with out-degree d is split
                                into units of min(256, 2^k5_work_log2 / d^2)
-                               out-neighbours, 16..30 (default 24) */
-    int32_t reserved;       /* 0 */
+                               out-neighbours, 16..30 (default 20) */
+    int32_t five_order;     /* 5-cycles of one graph (Thm 5cycle): 0 sums
+                               Wnt(i,j) Y(i,j) with a table of Y (the faster
+                               order) when the largest degree is below 2^16,
+                               else X(i,b) Wnt(i,j) with a table of Wnt; 1
+                               always the latter.  Batches always use the
+                               latter.  0 or 1 (default 0) */
 } esc_params;
 
 /* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}
- * x wg_per_cu in {1, 2, 3}, then k5_work_log2 in {22, 24, 26} for k = 5),
+ * x wg_per_cu in {1, 2, 3}, then k5_work_log2 in {22, 26} for k = 5; the
+ * other fields at their defaults),
  * keep the fastest (total device time of the call) in the context's table
  * under the graph's key and return it in *best, its time in *best_ms
  * (nullable).  Arguments as in esc_count_subgraphs. */

@@ -59,11 +59,12 @@ class _U128(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("task_chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("k5_work_log2", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("five_order", ctypes.c_int32)]
 
 
 def _params_dict(p):
-    return {"task_chunk": p.task_chunk, "wg_per_cu": p.wg_per_cu, "k5_work_log2": p.k5_work_log2}
+    return {"task_chunk": p.task_chunk, "wg_per_cu": p.wg_per_cu, "k5_work_log2": p.k5_work_log2,
+            "five_order": p.five_order}
 
 
 _lib = None
@@ -195,11 +196,13 @@ class Context:
 
     def set_params(self, params):
         """Force launch parameters (dict with task_chunk, wg_per_cu,
-        k5_work_log2) on later calls; None returns to the tuned/default ones."""
+        k5_work_log2 and optionally five_order, default 0) on later calls;
+        None returns to the tuned/default ones."""
         if params is None:
             _check(_load().esc_set_params(self.ptr, None), "esc_set_params")
             return
-        p = _Params(int(params["task_chunk"]), int(params["wg_per_cu"]), int(params["k5_work_log2"]), 0)
+        p = _Params(int(params["task_chunk"]), int(params["wg_per_cu"]), int(params["k5_work_log2"]),
+                    int(params.get("five_order", 0)))
         _check(_load().esc_set_params(self.ptr, ctypes.byref(p)), "esc_set_params")
 
     def last_params(self):

@@ -75,7 +75,7 @@ static esc_params default_params(const esc_ctx *c) {
     p.task_chunk = c->G ? 8 : 1;
     p.wg_per_cu = 3;
     p.k5_work_log2 = 20;
-    p.reserved = 0;
+    p.five_order = 0;
     return p;
 }
 
@@ -92,13 +92,15 @@ static void select_params(esc_ctx *c) {
     c->task_chunk = p.task_chunk;
     c->wg_per_cu = p.wg_per_cu < c->wg_cap ? p.wg_per_cu : c->wg_cap;
     c->k5_work_log2 = p.k5_work_log2;
+    c->five_order = p.five_order;
     c->params = p;
     c->params.wg_per_cu = c->wg_per_cu;
 }
 
 static bool params_valid(const esc_params *p) {
     return p->task_chunk >= 1 && p->task_chunk <= 64 && p->wg_per_cu >= 1 && p->wg_per_cu <= 3 &&
-           p->k5_work_log2 >= 16 && p->k5_work_log2 <= 30 && p->reserved == 0;
+           p->k5_work_log2 >= 16 && p->k5_work_log2 <= 30 &&
+           (p->five_order == 0 || p->five_order == 1);
 }
 
 static void store_tuned(esc_ctx *c, uint32_t key, const esc_params &p) {
@@ -153,6 +155,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
         hipMemcpy(c->d_inv5, h5, sizeof(h5), hipMemcpyHostToDevice) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     c->scratch_clean = true;
     c->k5_work_log2 = 20;
+    c->five_order = 0;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = (size_t)64 << 30;
     c->dev_mem = tot;

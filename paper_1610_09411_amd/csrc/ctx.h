@@ -133,6 +133,7 @@ struct esc_ctx {
     int wg_per_cu;             // workgroups per CU of the per-source kernels
     int wg_cap;                // largest wg_per_cu the tables' memory allows for this call
     int k5_work_log2;          // 5-clique work units (see k5_chunk)
+    int five_order;            // 5-cycles of one graph: 0 Y table when maxdeg < 2^16, 1 Wnt table
     size_t dev_mem;            // device memory in bytes
     // tuning: parameters in use, forced ones, the table
     esc_params params;

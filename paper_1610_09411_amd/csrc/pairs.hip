@@ -921,9 +921,10 @@ esc_status stage_cycles(esc_ctx *c) {
     const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
     const int32_t lds_words = 16 * pw_words > 2 * slab ? 16 * pw_words : (2 * slab > 0 ? 2 * slab : 1);
     // one graph with maximum degree below 2^16: the Y-table order (32-bit
-    // Y(i,j) < d(i) d(j))
+    // Y(i,j) < d(i) d(j)), unless the Wnt order is asked for
     auto kern = c->G ? k_five_cycles<false, false>
-                     : (c->maxdeg < 65536 ? k_five_cycles<true, true> : k_five_cycles<true, false>);
+                     : (c->maxdeg < 65536 && c->five_order == 0 ? k_five_cycles<true, true>
+                                                                 : k_five_cycles<true, false>);
     kern<<<nwg, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
                                        n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                        (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,

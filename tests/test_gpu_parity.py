@@ -187,13 +187,20 @@ def test_tuned_and_forced_parameters_give_same_counts(ctx):
     assert ms > 0 and 1 <= best["wg_per_cu"] <= 3 and best["task_chunk"] in (1, 4, 16)
     assert ctx.count(g, 5) == want
     assert ctx.last_params() == best             # the table entry is used for this graph
-    for p in ({"task_chunk": 64, "wg_per_cu": 1, "k5_work_log2": 16},
-              {"task_chunk": 3, "wg_per_cu": 3, "k5_work_log2": 30}):
+    assert best["five_order"] == 0
+    # five_order 1: the 5-cycle sum in the Wnt-table order (else taken only
+    # by graphs whose largest degree reaches 2^16, and by batches)
+    for p in ({"task_chunk": 64, "wg_per_cu": 1, "k5_work_log2": 16, "five_order": 1},
+              {"task_chunk": 3, "wg_per_cu": 3, "k5_work_log2": 30, "five_order": 0},
+              {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20, "five_order": 1}):
         ctx.set_params(p)
         assert ctx.count(g, 5) == want
         assert ctx.last_params() == p
     with pytest.raises(esc.EscapeError) as e:
         ctx.set_params({"task_chunk": 0, "wg_per_cu": 1, "k5_work_log2": 24})
+    assert e.value.status == esc.ESC_EINVAL
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.set_params({"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "five_order": 2})
     assert e.value.status == esc.ESC_EINVAL
     ctx.set_params(None)
     graphs = [synth.from_spec(s) for s in synth.batch_specs(40, 3)]
@@ -305,6 +312,12 @@ def test_chung_lu_1m_full_size(ctx):
     assert sum(got[:11]) == comb(g.n, 4)
     assert sum(got[11:]) == comb(g.n, 5)
     assert [int(x) for x in gold["counts"]] == got
+    # the 5-cycle sum in the Wnt-table order gives the same counts
+    ctx.set_params({"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20, "five_order": 1})
+    try:
+        assert ctx.count(g, 5) == got
+    finally:
+        ctx.set_params(None)
 
 
 def test_chung_lu_1m_sampled_fragments(ctx):

@@ -909,9 +909,9 @@ esc_status stage_cycles(esc_ctx *c) {
     int32_t *touch;
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
-    // the kernel with wave walks holds 103 VGPRs, so two 8-wave workgroups
-    // per CU are resident: launch two, each with the larger LDS slab; the
-    // one without (batches) keeps wg_per_cu of them
+    // the kernels with wave walks hold 94 (Y order) and 114 (Wnt order)
+    // VGPRs, so two 8-wave workgroups per CU are resident: launch two, each
+    // with the larger LDS slab; the one without (batches) keeps wg_per_cu
     const int per_cu = c->G ? c->wg_per_cu : slab_wgs_per_cu(c);
     int nwg = per_cu * c->num_cu;
     // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays

@@ -505,6 +505,7 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     __shared__ u128 red[8];
     __shared__ int32_t wsi[8][64];    // wave walks: segment ends (starts alias pref, firsts alias beg)
     __shared__ uint32_t wxs[8][64];   // X(i,b) of each lane's segment
+    __shared__ int32_t wkb[8][64];    // per-wave path: keys b staged for a walk of their out-rows
     const int ids[1] = {AC_CYC};
     uint32_t *Xt = tabX_all + (size_t)blockIdx.x * tab_n;
     uint32_t *Wt = tabW_all + (size_t)blockIdx.x * tab_n;
@@ -576,25 +577,44 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                               [&](int32_t j) { if (j != i) add(ww, j); });
                 }
                 wave_sync();
-                // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j): each lane takes words
-                // of the X table and walks the out-rows of their keys
+                // sum_b X(i,b) sum_{j in N+(b)} Wnt(i,j): the keys b with
+                // X(i,b) > 0 are gathered (ballot over 64 keys at a time) into
+                // the wave's staging array, and each full batch of them has
+                // its out-rows walked by the wave as one run
                 u128 part = 0;
-                for (int q = lane; q < nwd; q += 64) {
-                    const uint32_t x = wx[q];
-                    if (x == 0) continue;
-                    for (int f = 0; f < (1 << shift); f++) {
-                        const uint32_t xv = (x >> (f * cb)) & cmask;
-                        if (xv == 0) continue;
-                        const int32_t b = gb + (q << shift) + f;
-                        uint64_t sw = 0;
-                        for (int32_t r = split[b]; r < off[b + 1]; r++) {
-                            const int32_t idx = adj[r] - gb;
-                            sw += (ww[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask;
-                        }
-                        nvis += (uint64_t)(off[b + 1] - split[b]);
-                        part += (u128)xv * sw;
+                const int32_t nk = ge - gb;
+                const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+                int staged = 0;   // wave-uniform
+                auto walk_staged = [&]() {
+                    wave_sync();   // staged keys visible to the wave
+                    int64_t a0 = 0, a1 = 0;
+                    if (lane < staged) { const int32_t b = wkb[wid][lane]; a0 = split[b]; a1 = off[b + 1]; }
+                    nvis += (uint64_t)(a1 - a0);
+                    uint64_t sw = 0;   // X(i,b) Wnt(i,j) <= d(i)^2 per entry
+                    wave_walk_seg(a0, a1, wsa, wse, wsi[wid], [&](int64_t q) { return adj[q]; },
+                                  [&](int y, int64_t, int32_t j) {
+                                      const int32_t idx = j - gb;
+                                      const uint32_t w = (ww[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask;
+                                      sw += (uint64_t)wxs[wid][y] * w;
+                                  });
+                    part += sw;
+                    staged = 0;   // the walk ends with a wave_sync: the arrays are free
+                };
+                for (int32_t kb = 0; kb < nk; kb += 64) {
+                    const int32_t f = kb + lane;
+                    uint32_t xv = 0;
+                    if (f < nk) xv = (wx[f >> shift] >> ((f & ((1 << shift) - 1)) * cb)) & cmask;
+                    const uint64_t m = __ballot(xv != 0);
+                    if (m == 0) continue;
+                    if (staged + __popcll(m) > 64) walk_staged();
+                    if (xv) {
+                        const int slot = staged + __popcll(m & lt);
+                        wkb[wid][slot] = gb + f;
+                        wxs[wid][slot] = xv;
                     }
+                    staged += __popcll(m);
                 }
+                if (staged > 0) walk_staged();
                 sc[0] += part;
                 wave_sync();   // the tables are cleared by the wave's next source
             }
@@ -915,7 +935,7 @@ esc_status stage_cycles(esc_ctx *c) {
     const int per_cu = c->G ? c->wg_per_cu : slab_wgs_per_cu(c);
     int nwg = per_cu * c->num_cu;
     // two LDS arrays (X and Wnt) for the latest keys, leaving room for the static arrays
-    const int32_t slab = slab_words(c, per_cu, 2, 8192, 12288);
+    const int32_t slab = slab_words(c, per_cu, 2, 8192, 13312);
     // a batch whose graphs are small takes a source per wave, with two
     // per-wave LDS tables over a graph's keys (16-bit counts at most)
     const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;

@@ -295,6 +295,8 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 #define WHEEL_WAVES 8          // most waves per workgroup of the wheel pass (a launch may use fewer)
 #define WHEEL_RIMS 16          // rim vertices per task of a large hub
 #define WHEEL_SPLIT_DEG 1024   // hubs up to this degree are one task
+#define WHEEL_TINY 32          // batches: hubs up to this degree are taken whole by one wave
+#define WHEEL_TINY_WORDS (WHEEL_TINY * WHEEL_TINY / 2)   // its table: 16-bit counts of (rim, key)
 
 __device__ inline int32_t wheel_rims(int32_t d) { return d > WHEEL_SPLIT_DEG ? WHEEL_RIMS : d; }
 
@@ -311,7 +313,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
                                                 int32_t lds_cap, const int64_t *toff, const int32_t *town,
                                                 int64_t nbig, int *task_big, int chunk,
-                                                GMap gm, int *task, unsigned long long *acc,
+                                                GMap gm, int *task, int tiny, unsigned long long *acc,
                                                 unsigned long long *visits) {
     uint64_t nvis = 0;
     extern __shared__ uint32_t dyn[];
@@ -319,6 +321,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     __shared__ u128 red[WHEEL_WAVES];   // one sum per wave (block_flush_u128)
     __shared__ int64_t wsa[WHEEL_WAVES][64];
     __shared__ int32_t wse[WHEEL_WAVES][64], wsi[WHEEL_WAVES][64];
+    __shared__ int32_t wkb[WHEEL_WAVES][64];   // tiny hubs: key base (rim index * d(h)) of each segment
     const int ids[1] = {AC_N18};
     u128 s18[1] = {0};
     int gcur = -1;
@@ -420,6 +423,9 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     const int32_t rw = (wq + 1) / 2;   // words of a wave's table, and of its touched list
     uint32_t *wc = dyn + (size_t)wid * 2 * rw;
     uint16_t *wt = (uint16_t *)(wc + rw);
+    uint32_t *tt = dyn + (size_t)nw * 2 * rw + (size_t)wid * WHEEL_TINY_WORDS;   // tiny hubs
+    u128 ts[1] = {0};   // tiny hubs: the wave's sums, for graph tg
+    int tg = -1;
     for (;;) {
         if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
         __syncthreads();
@@ -431,6 +437,73 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
             const int32_t h = n - 1 - t;
             const int32_t oh = off[h], dh = off[h + 1] - oh;
             if (dh > wq || dh < 3) continue;   // large hubs are done; a wheel hub has 4 neighbours
+            if (dh <= tiny) {
+                // one wave takes the whole hub: counts keyed by (rim index a,
+                // key), d(h)^2 16-bit counts in the wave's own table, so the
+                // rim vertices need no reset between them and all their
+                // (i, l) segments are walked as runs of 64
+                if ((t - (int32_t)t0) % nw != wid) continue;
+                const int g = gm.graph(h);
+                if (g != tg) {
+                    if (tg >= 0) wave_flush_runs<1>(ts, tg, acc, ACC_STRIDE, ids);
+                    tg = g;
+                }
+                for (int q = lane; q < (dh * dh + 1) / 2; q += 64) tt[q] = 0;
+                // lane a < d(h): rim vertex i = adj[oh + a] and its entries l below i
+                int32_t ia = 0;
+                long long la = 0;
+                int na = 0;
+                if (lane < dh) {
+                    ia = adj[oh + lane];
+                    const int64_t l0 = aoff[oh + lane], l1 = aoff[oh + lane + 1];
+                    la = l0;
+                    if (l1 - l0 >= 2) {   // a rim 4-cycle needs two triangles on (h,i)
+                        int64_t lo = l0, hi = l1;
+                        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < ia) lo = mid + 1; else hi = mid; }
+                        na = (int)(lo - l0);
+                    }
+                }
+                int incl = na;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                const int np = __shfl(incl, 63);   // (rim vertex, entry) pairs of the hub
+                wave_sync();   // the table is cleared
+                uint64_t olds = 0;   // the counts before each increment
+                for (int xb = 0; xb < np; xb += 64) {
+                    const int x = xb + lane;
+                    // rim index a of pair x: the first lane with incl > x (every
+                    // lane takes part in the shuffles)
+                    int a = 0;
+                    for (int sb = 32; sb > 0; sb >>= 1)
+                        if (__shfl(incl, a + sb - 1) <= x) a += sb;
+                    a = a < 63 ? a : 63;
+                    const int32_t iA = __shfl(ia, a);
+                    const long long lA = __shfl(la, a);
+                    const int eA = __shfl(incl, a) - __shfl(na, a);   // pairs before rim index a
+                    int64_t b0 = 0, b1 = 0;
+                    if (x < np) {
+                        const int32_t qhl = (int32_t)aa[lA + (x - eA)];   // arc (h,l) in row h
+                        b0 = aoff[qhl];
+                        int64_t lo2 = b0, hi2 = aoff[qhl + 1];
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < iA) lo2 = mid + 1; else hi2 = mid; }
+                        b1 = lo2;
+                    }
+                    nvis += (uint64_t)(b1 - b0);
+                    wkb[wid][lane] = a * dh;   // visible to the wave after the walk's own wave_sync
+                    wave_walk_seg(b0, b1, wsa[wid], wse[wid], wsi[wid],
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                                  [&](int y, int64_t, int32_t j) {
+                                      const int32_t key = wkb[wid][y] + j;
+                                      const uint32_t old = atomicAdd(&tt[key >> 1], 1u << ((key & 1) << 4));
+                                      olds += (old >> ((key & 1) << 4)) & 0xFFFFu;
+                                  });
+                }
+                ts[0] += olds;
+                wave_sync();   // the table is cleared by the wave's next tiny hub
+                continue;
+            }
             block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
             for (int q = lane; q < (dh + 1) / 2; q += 64) wc[q] = 0;
             wave_sync();
@@ -475,6 +548,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
             }
         }
     }
+    if (tg >= 0) wave_flush_runs<1>(ts, tg, acc, ACC_STRIDE, ids);
     if (gcur >= 0) block_flush_u128<1>(s18, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
@@ -894,6 +968,11 @@ esc_status stage_wheels(esc_ctx *c) {
     // graphs, whose hubs have few rim vertices to share among the waves
     const int waves = c->G ? 4 : WHEEL_WAVES;
     size_t lds_waves = sizeof(uint32_t) * waves * 2 * (size_t)((lds_cap / waves + 1) / 2) + 16;   // one-wave tables
+    // a batch also takes its hubs of at most WHEEL_TINY neighbours whole, one
+    // per wave, with tables after the one-wave tables (workgroups per CU
+    // stay at their cap); one graph keeps its three workgroups per CU
+    const int tiny = c->G ? WHEEL_TINY : 0;
+    if (tiny) lds_waves += sizeof(uint32_t) * waves * (size_t)WHEEL_TINY_WORDS;
     if (lds_waves > lds) lds = lds_waves;
     // as many workgroups per CU as LDS holds: the walk is bound by
     // load latency, so resident waves matter; the global tables have room
@@ -915,7 +994,7 @@ esc_status stage_wheels(esc_ctx *c) {
     kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
-                                              c->task_chunk, gmap_of(c), task + 1, (unsigned long long *)c->buf[B_ACC],
+                                              c->task_chunk, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
                                               (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
     HIP_TRY(hipGetLastError());
     return ESC_OK;

@@ -423,7 +423,9 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     const int32_t rw = (wq + 1) / 2;   // words of a wave's table, and of its touched list
     uint32_t *wc = dyn + (size_t)wid * 2 * rw;
     uint16_t *wt = (uint16_t *)(wc + rw);
-    uint32_t *tt = dyn + (size_t)nw * 2 * rw + (size_t)wid * WHEEL_TINY_WORDS;   // tiny hubs
+    // tiny hubs: the wave's one-wave table when it is large enough (the wave
+    // uses either, never both at once), else a table after those tables
+    uint32_t *tt = 2 * rw >= WHEEL_TINY_WORDS ? wc : dyn + (size_t)nw * 2 * rw + (size_t)wid * WHEEL_TINY_WORDS;
     u128 ts[1] = {0};   // tiny hubs: the wave's sums, for graph tg
     int tg = -1;
     for (;;) {
@@ -968,11 +970,12 @@ esc_status stage_wheels(esc_ctx *c) {
     // graphs, whose hubs have few rim vertices to share among the waves
     const int waves = c->G ? 4 : WHEEL_WAVES;
     size_t lds_waves = sizeof(uint32_t) * waves * 2 * (size_t)((lds_cap / waves + 1) / 2) + 16;   // one-wave tables
-    // a batch also takes its hubs of at most WHEEL_TINY neighbours whole, one
-    // per wave, with tables after the one-wave tables (workgroups per CU
-    // stay at their cap); one graph keeps its three workgroups per CU
-    const int tiny = c->G ? WHEEL_TINY : 0;
-    if (tiny) lds_waves += sizeof(uint32_t) * waves * (size_t)WHEEL_TINY_WORDS;
+    // hubs of at most WHEEL_TINY neighbours are taken whole, one per wave,
+    // in the wave's one-wave table when it holds WHEEL_TINY_WORDS words,
+    // else in tables after those (a batch of small graphs: workgroups per
+    // CU stay at their cap)
+    const int tiny = WHEEL_TINY;
+    if (2 * ((lds_cap / waves + 1) / 2) < WHEEL_TINY_WORDS) lds_waves += sizeof(uint32_t) * waves * (size_t)WHEEL_TINY_WORDS;
     if (lds_waves > lds) lds = lds_waves;
     // as many workgroups per CU as LDS holds: the walk is bound by
     // load latency, so resident waves matter; the global tables have room

@@ -98,8 +98,29 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                 // diamonds with tips i and j: the entries l after k of the
                 // lists of the arcs (i,k), 64 arcs at a time numbered in one
                 // run (a lane per entry), then the suffix of the list of (k,l)
-                // after i, walked by the wave
+                // after i.  Non-empty suffixes are gathered by ballot into the
+                // wave's staging array (start << 24 | length: lists of a batch
+                // of small graphs hold fewer than 2^40 entries, a suffix
+                // fewer than 2^24) and walked by the wave 64 at a time.
                 uint64_t acc17 = 0;
+                uint64_t *stg = (uint64_t *)beg + wid * 64;   // beg is unused by this path
+                const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+                int staged = 0;   // wave-uniform
+                auto walk_staged = [&]() {
+                    wave_sync();   // staged suffixes visible to the wave
+                    int64_t a0 = 0, a1 = 0;
+                    if (lane < staged) {
+                        const uint64_t v = stg[lane];
+                        a0 = (int64_t)(v >> 24);
+                        a1 = a0 + (int64_t)(v & 0xFFFFFFu);
+                    }
+                    wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return apex_at<IDS>(av, adj, aa, q); },
+                              [&](int32_t j) {
+                                  const int32_t idx = j - i - 1;
+                                  acc17 += (uint64_t)((wt[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask) - 2;
+                              });
+                    staged = 0;   // the walk ends with a wave_sync: the array is free
+                };
                 for (int32_t pb = oi; pb < ei; pb += 64) {
                     const int32_t pl = pb + lane;
                     const int cnt = pl < ei ? (int)(aoff[pl + 1] - aoff[pl]) : 0;
@@ -129,14 +150,15 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                             }
                         }
                         nvis += (uint64_t)(a1 - a0);
-                        wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return apex_at<IDS>(av, adj, aa, q); },
-                                  [&](int32_t j) {
-                                      const int32_t idx = j - i - 1;
-                                      acc17 += (uint64_t)((wt[idx >> shift] >> ((idx & ((1 << shift) - 1)) * cb)) & cmask) - 2;
-                                  });
+                        const uint64_t m = __ballot(a1 > a0);
+                        if (m == 0) continue;
+                        if (staged + __popcll(m) > 64) walk_staged();
+                        if (a1 > a0) stg[staged + __popcll(m & lt)] = ((uint64_t)a0 << 24) | (uint64_t)(a1 - a0);
+                        staged += __popcll(m);
                     }
                     wave_sync();   // wrun is rewritten by the next 64 arcs
                 }
+                if (staged > 0) walk_staged();
                 sv[1] += acc17;
                 // sum of C(W,3) over the keys
                 for (int q = lane; q < nwd; q += 64) {
@@ -937,8 +959,9 @@ esc_status stage_pairs(esc_ctx *c) {
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
     const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 16384);
     // a batch whose graphs are small takes a source per wave, with per-wave
-    // LDS tables over a graph's keys (16-bit counts at most)
-    const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
+    // LDS tables over a graph's keys (16-bit counts at most); its diamond
+    // suffixes are staged as start << 24 | length (lists below 2^40 entries)
+    const int32_t pw_words = c->G && c->tab_n <= 4096 && c->narcs_apex < ((int64_t)1 << 40) ? (c->tab_n + 1) / 2 : 0;
     const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
     auto kern = c->av ? k_pairs_wd<true> : k_pairs_wd<false>;
     kern<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(

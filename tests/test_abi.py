@@ -28,6 +28,19 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_params_struct_matches_header():
+    """esc_params in the header and the binding's ctypes struct: same fields,
+    same order, all int32 (the struct crosses the ABI by pointer)."""
+    text = open(os.path.join(ROOT, "include", "escape.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*esc_params;", text).group(1)
+    fields = re.findall(r"(\w+)\s+(\w+);", body)
+    assert fields and all(t == "int32_t" for t, _ in fields), fields
+    assert [n for _, n in fields] == [n for n, _ in esc._Params._fields_]
+    assert all(t is ctypes.c_int32 for _, t in esc._Params._fields_)
+    assert ctypes.sizeof(esc._Params) == 4 * len(fields)
+
+
 def test_strerror_and_invalid_arguments():
     assert esc.esc_strerror(esc.ESC_OK) == "ok"
     assert "range" in esc.esc_strerror(esc.ESC_ERANGE)

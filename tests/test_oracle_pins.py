@@ -297,3 +297,67 @@ def test_three_vertex_special_graphs():
     # {0,1,2},{1,2,3} paths; {0,1,3},{0,2,3} one edge
     assert oracle.three_vertex_brute(path) == [0, 2, 2, 0]
     assert oracle.three_vertex(path) == [0, 2, 2, 0]
+
+
+# ------------------------------------------- one-by-one checkers (sampled tests)
+
+def _fragment_graphs():
+    out = [synth.erdos_renyi(18 + s, 0.2 + 0.05 * s, 700 + s) for s in range(5)]
+    out += [synth.chung_lu(30 + 5 * s, 2.0 + 0.15 * s, 6.0 + s, 20.0, 720 + s) for s in range(5)]
+    out.append(synth.erdos_renyi(16, 0.8, 731))                                              # dense
+    out.append(synth.from_edges(12, [(0, v) for v in range(1, 12)] + [(v, v % 11 + 1) for v in range(1, 12)]))  # wheel W11
+    out.append(synth.from_edges(11, [(u, v) for u in range(4) for v in range(u + 1, 11)]))    # split graph, 4-clique core
+    return out
+
+
+def _brute_edge(A, u, v):
+    """Triangles, 4-cliques and 4-cycles through edge uv by enumerating the
+    vertex sets that contain u and v."""
+    n = len(A)
+    rest = [x for x in range(n) if x != u and x != v]
+    t = sum(1 for x in rest if A[u, x] and A[v, x])
+    k4 = sum(1 for i, x in enumerate(rest) for y in rest[i + 1:]
+             if A[u, x] and A[v, x] and A[u, y] and A[v, y] and A[x, y])
+    # a 4-cycle u-v-x-y-u for each ordered pair (x, y) of distinct other vertices
+    c4 = sum(1 for x in rest for y in rest if x != y and A[v, x] and A[x, y] and A[y, u])
+    return t, k4, c4
+
+
+@pytest.mark.parametrize("g", _fragment_graphs(), ids=lambda g: g.name or "special")
+def test_edge_fragments_and_vertex_triangles_brute_force(g):
+    """The one-by-one checkers against subset enumeration and against the
+    oracle's per-item arrays (a separate code path, escape_oracle.c)."""
+    A = _dense(g)
+    _, it = oracle.sums(g, 4, per_item=True)
+    for u in range(g.n):
+        tv = sum(1 for x in range(g.n) for y in range(x + 1, g.n)
+                 if A[u, x] and A[u, y] and A[x, y])
+        assert oracle.vertex_triangles(g, u) == tv == int(it["t_v"][u])
+        for p in range(g.row_ptr[u], g.row_ptr[u + 1]):
+            v = int(g.col[p])
+            t, k4, c4 = _brute_edge(A, u, v)
+            got = oracle.edge_fragments(g, u, v)
+            assert (got["t"], got["k4"], got["c4"]) == (t, k4, c4), (u, v)
+            assert (int(it["t_e"][p]), int(it["k4_e"][p]), int(it["c4_e"][p])) == (t, k4, c4)
+
+
+def test_edge_fragments_closed_forms():
+    for n in (5, 8):
+        kn = synth.from_edges(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+        # K_n: every other vertex closes a triangle, every other pair a 4-clique,
+        # every ordered pair of other vertices a 4-cycle through the edge
+        assert oracle.edge_fragments(kn, 0, 1) == {"t": n - 2, "k4": comb(n - 2, 2), "c4": (n - 2) * (n - 3)}
+        assert oracle.vertex_triangles(kn, 0) == comb(n - 1, 2)
+    for a, b in ((2, 5), (3, 4)):
+        kab = synth.from_edges(a + b, [(u, a + v) for u in range(a) for v in range(b)])
+        assert oracle.edge_fragments(kab, 0, a) == {"t": 0, "k4": 0, "c4": (a - 1) * (b - 1)}
+        assert oracle.vertex_triangles(kab, 0) == 0
+    c4g = synth.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)])
+    assert oracle.edge_fragments(c4g, 0, 1) == {"t": 0, "k4": 0, "c4": 1}
+    wheel = synth.from_edges(7, [(0, v) for v in range(1, 7)] + [(v, v % 6 + 1) for v in range(1, 7)])
+    # spoke 0-1: triangles 0-1-2 and 0-1-6; rim vertex 1 lies on its two rim
+    # triangles only; no 4-clique in a wheel with a 6-rim
+    assert oracle.edge_fragments(wheel, 0, 1)["t"] == 2
+    assert oracle.edge_fragments(wheel, 0, 1)["k4"] == 0
+    assert oracle.vertex_triangles(wheel, 0) == 6
+    assert oracle.vertex_triangles(wheel, 1) == 2

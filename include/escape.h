@@ -225,11 +225,32 @@ typedef struct {
                                else X(i,b) Wnt(i,j) with a table of Wnt; 1
                                always the latter.  Batches always use the
                                latter.  0 or 1 (default 0) */
+    int32_t k5_light;       /* 5-cliques: vertices with at most this many
+                               out-neighbours (one-word rows) are counted a
+                               wave each, 3..64 (default 64) */
+    int32_t k5_wave_words;  /* 5-cliques: heavier vertices whose rows have at
+                               most this many 64-bit words take a wave per
+                               out-neighbour, the rest a workgroup per unit,
+                               1..8 (default 8) */
+    int32_t k5_dense_pct;   /* 5-cliques (Thm 5clique): a vertex with more than
+                               k5_light and at most 4096 out-neighbours whose
+                               out-neighbourhood has at least this percentage
+                               of all pairs as edges is counted through the
+                               complement of that neighbourhood; 0..101
+                               (101: never; default 50) */
+    int32_t wheel_split_deg;/* wheels (pattern 18): hubs with more neighbours
+                               are split into tasks of 16 rim vertices,
+                               32..2^30 (default 1024) */
+    int32_t four_range_deg; /* 4-cycles (Thm 4cycle): tops with more
+                               neighbours are split into key-range tasks,
+                               16..2^30 (default 256) */
 } esc_params;
 
 /* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}
- * x wg_per_cu in {1, 2, 3}, then k5_work_log2 in {22, 26} for k = 5; the
- * other fields at their defaults),
+ * x wg_per_cu in {1, 2, 3}; then, one field at a time from the best so far,
+ * four_range_deg in {128, 1024}, and for k = 5 k5_work_log2 in {22, 26},
+ * k5_dense_pct in {25, 101}, k5_light in {32}, k5_wave_words in {4} and
+ * wheel_split_deg in {256, 4096}; the other fields at their defaults),
  * keep the fastest (total device time of the call) in the context's table
  * under the graph's key and return it in *best, its time in *best_ms
  * (nullable).  Arguments as in esc_count_subgraphs. */

@@ -59,12 +59,18 @@ class _U128(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("task_chunk", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("k5_work_log2", ctypes.c_int32),
-                ("five_order", ctypes.c_int32)]
+                ("five_order", ctypes.c_int32), ("k5_light", ctypes.c_int32), ("k5_wave_words", ctypes.c_int32),
+                ("k5_dense_pct", ctypes.c_int32), ("wheel_split_deg", ctypes.c_int32),
+                ("four_range_deg", ctypes.c_int32)]
+
+
+# defaults of the fields a set_params dict may leave out
+PARAM_DEFAULTS = {"five_order": 0, "k5_light": 64, "k5_wave_words": 8, "k5_dense_pct": 50,
+                  "wheel_split_deg": 1024, "four_range_deg": 256}
 
 
 def _params_dict(p):
-    return {"task_chunk": p.task_chunk, "wg_per_cu": p.wg_per_cu, "k5_work_log2": p.k5_work_log2,
-            "five_order": p.five_order}
+    return {name: int(getattr(p, name)) for name, _ in _Params._fields_}
 
 
 _lib = None
@@ -196,13 +202,14 @@ class Context:
 
     def set_params(self, params):
         """Force launch parameters (dict with task_chunk, wg_per_cu,
-        k5_work_log2 and optionally five_order, default 0) on later calls;
-        None returns to the tuned/default ones."""
+        k5_work_log2 and optionally the fields of PARAM_DEFAULTS) on later
+        calls; None returns to the tuned/default ones."""
         if params is None:
             _check(_load().esc_set_params(self.ptr, None), "esc_set_params")
             return
-        p = _Params(int(params["task_chunk"]), int(params["wg_per_cu"]), int(params["k5_work_log2"]),
-                    int(params.get("five_order", 0)))
+        full = dict(PARAM_DEFAULTS)
+        full.update(params)
+        p = _Params(*[int(full[name]) for name, _ in _Params._fields_])
         _check(_load().esc_set_params(self.ptr, ctypes.byref(p)), "esc_set_params")
 
     def last_params(self):

@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <limits.h>
 #include <string.h>
+#include <initializer_list>
 #include "device.h"
 #include "ctx.h"
 
@@ -76,6 +77,11 @@ static esc_params default_params(const esc_ctx *c) {
     p.wg_per_cu = 3;
     p.k5_work_log2 = 20;
     p.five_order = 0;
+    p.k5_light = 64;
+    p.k5_wave_words = 8;
+    p.k5_dense_pct = 50;
+    p.wheel_split_deg = 1024;
+    p.four_range_deg = 256;
     return p;
 }
 
@@ -93,6 +99,11 @@ static void select_params(esc_ctx *c) {
     c->wg_per_cu = p.wg_per_cu < c->wg_cap ? p.wg_per_cu : c->wg_cap;
     c->k5_work_log2 = p.k5_work_log2;
     c->five_order = p.five_order;
+    c->k5_light = p.k5_light;
+    c->k5_wave_words = p.k5_wave_words;
+    c->k5_dense_pct = p.k5_dense_pct;
+    c->wheel_split_deg = p.wheel_split_deg;
+    c->four_range_deg = p.four_range_deg;
     c->params = p;
     c->params.wg_per_cu = c->wg_per_cu;
 }
@@ -100,7 +111,11 @@ static void select_params(esc_ctx *c) {
 static bool params_valid(const esc_params *p) {
     return p->task_chunk >= 1 && p->task_chunk <= 64 && p->wg_per_cu >= 1 && p->wg_per_cu <= 3 &&
            p->k5_work_log2 >= 16 && p->k5_work_log2 <= 30 &&
-           (p->five_order == 0 || p->five_order == 1);
+           (p->five_order == 0 || p->five_order == 1) &&
+           p->k5_light >= 3 && p->k5_light <= 64 && p->k5_wave_words >= 1 && p->k5_wave_words <= 8 &&
+           p->k5_dense_pct >= 0 && p->k5_dense_pct <= 101 &&
+           p->wheel_split_deg >= 32 && p->wheel_split_deg <= (1 << 30) &&
+           p->four_range_deg >= 16 && p->four_range_deg <= (1 << 30);
 }
 
 static void store_tuned(esc_ctx *c, uint32_t key, const esc_params &p) {
@@ -154,8 +169,16 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hipMemcpy(c->d_inv4, h4, sizeof(h4), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_inv5, h5, sizeof(h5), hipMemcpyHostToDevice) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     c->scratch_clean = true;
-    c->k5_work_log2 = 20;
-    c->five_order = 0;
+    {
+        const esc_params p = default_params(c);
+        c->k5_work_log2 = p.k5_work_log2;
+        c->five_order = p.five_order;
+        c->k5_light = p.k5_light;
+        c->k5_wave_words = p.k5_wave_words;
+        c->k5_dense_pct = p.k5_dense_pct;
+        c->wheel_split_deg = p.wheel_split_deg;
+        c->four_range_deg = p.four_range_deg;
+    }
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = (size_t)64 << 30;
     c->dev_mem = tot;
@@ -533,12 +556,23 @@ static esc_status tune_with(esc_ctx *c, int k, esc_params *best, float *best_ms,
             p.wg_per_cu = w;
             st = try_one(p);
         }
-    if (k == 5)
-        for (int lg = 22; lg <= 26 && st == ESC_OK; lg += 4) {
+    // thresholds, one field at a time from the best so far
+    auto sweep = [&](int32_t esc_params::*field, std::initializer_list<int32_t> vals) {
+        for (int32_t v : vals) {
+            if (st != ESC_OK) return;
             p = bp;
-            p.k5_work_log2 = lg;
+            p.*field = v;
             st = try_one(p);
         }
+    };
+    sweep(&esc_params::four_range_deg, {128, 1024});
+    if (k == 5) {
+        sweep(&esc_params::k5_work_log2, {22, 26});
+        sweep(&esc_params::k5_dense_pct, {25, 101});
+        sweep(&esc_params::k5_light, {32});
+        sweep(&esc_params::k5_wave_words, {4});
+        sweep(&esc_params::wheel_split_deg, {256, 4096});
+    }
     restore();
     if (st != ESC_OK) return st;
     store_tuned(c, key, bp);

@@ -11,11 +11,19 @@
 // the 5-cycle correction term of each triangle.
 //
 // 5-cliques: a 5-clique is found once, from its earliest vertex a, as a
-// 4-clique of the DAG restricted to N+(a).  For every out-arc (c,x) a bitmap
+// 4-clique of H_a = G[N+(a)].  Direct count: for every out-arc (c,x) a bitmap
 // over the positions of N+(c) marks N+(c) & N+(x) (read off the triangle list
 // of (c,x)); with these rows, for a and b<c<x in N+(a):
 //   S = row(a,b) & row(a,c)           (common out-neighbours of a, b, c)
 //   5-cliques += popcount(S & row(a,x)) for every x in S.
+// That visits every 4-clique of H_a, which is too much when H_a is nearly
+// complete (hub cores of heavy-tailed graphs).  Such a vertex is counted
+// through the complement Hc of H_a instead: a 4-set of H_a is a clique when
+// it spans no edge of Hc, so by the sign rule of the inverse of A (App. B)
+// applied to the empty pattern, K4(H_a) = sum over the 11 four-vertex
+// patterns j of (-1)^e(j) N_j(Hc), the non-induced counts of Hc given by
+// the 4-vertex formulas (Thm 4vertex-easy, Thm 4cycle, Thm 4clique) with
+// the disconnected patterns in closed form (App. A).
 #include "device.h"
 #include "ctx.h"
 
@@ -233,31 +241,67 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
 
 // ---------------------------------------------------------------- 5-cliques
 
-__global__ void k_ob_sizes(int32_t n, const int32_t *off, const int32_t *split, int64_t *len) {
-    for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        int64_t dp = off[c + 1] - split[c];
-        len[c] = dp * ((dp + 63) >> 6);
+// Vertices of the direct pass with at most `light` (<= 64) out-neighbours
+// (one-word rows) are counted a wave each, lane = b, after the units of the
+// others; heavier ones with rows of at most `wave_words` (<= K5_WAVE_WORDS)
+// words take a wave per b.
+#define K5_LIGHT 64
+#define K5_LIGHT_RUN 32    // consecutive light vertices per wave at a time
+#define K5_WAVE_WORDS 8    // most words of a row held in registers by the wave path
+#define K5_DENSE_HMAX 4096 // largest out-degree counted through the complement
+
+// Classification, one wave per vertex a with h = d+(a): e(H_a) = sum over b
+// in N+(a) of the apexes of list(a,b) after b (the entries whose arc index
+// in the row of a lies after b's).  a is dense when light < h <=
+// K5_DENSE_HMAX and e(H_a) >= dense_pct % of C(h,2); a dense vertex gets no
+// rows (len = 0) and is appended to the dense list.
+__global__ void k_k5_classify(int32_t n, const int32_t *off, const int32_t *split, const int64_t *aoff,
+                              const uint32_t *aa, int light, int dense_pct, int64_t *len, int32_t *dlist,
+                              int *ndense) {
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int32_t a = wave; a < n; a += nwaves) {
+        const int32_t sa = split[a], ea = off[a + 1];
+        const int64_t dp = ea - sa;
+        bool dense = false;
+        if (dp > light && dp <= K5_DENSE_HMAX && dense_pct <= 100) {
+            uint64_t e = 0;
+            for (int32_t p = sa + lane; p < ea; p += 64) {
+                int64_t lo = aoff[p], hi = aoff[p + 1];
+                const int64_t l1 = hi;
+                while (lo < hi) { const int64_t mid = (lo + hi) >> 1; if ((int32_t)aa[mid] <= p) lo = mid + 1; else hi = mid; }
+                e += (uint64_t)(l1 - lo);
+            }
+            e = wave_sum_u64(e);
+            dense = 200 * e >= (uint64_t)dense_pct * (uint64_t)(dp * (dp - 1));
+        }
+        if (lane == 0) {
+            len[a] = dense ? 0 : dp * ((dp + 63) >> 6);
+            if (dense) dlist[atomicAdd(ndense, 1)] = a;
+        }
     }
 }
 
-// one thread per out-arc (c,x): the row of (c,x) marks the apexes of its
-// triangle list that come after x, by position in N+(c)
+// one wave per vertex c, a lane per out-arc (c,x): the row of (c,x) marks
+// the apexes of its triangle list that come after x, by position in N+(c)
+// (entries with an arc index in the row of c after x's, a suffix of the
+// list).  Dense vertices have no rows.
 __global__ void k_ob_rows(int32_t n, const int32_t *off, const int32_t *split, const int64_t *aoff,
-                          const uint32_t *aa, const int32_t *av, const int32_t *adj, const int64_t *ob_off,
-                          unsigned long long *ob) {
+                          const uint32_t *aa, const int64_t *ob_off, unsigned long long *ob) {
     const int lane = threadIdx.x & 63;
     const int32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     for (int32_t c = wave; c < n; c += nwaves) {
+        if (ob_off[c + 1] == ob_off[c]) continue;
         const int32_t sc = split[c], ec = off[c + 1];
         const int32_t dp = ec - sc;
         const int wc = (dp + 63) >> 6;
         for (int32_t p = sc + lane; p < ec; p += 64) {
-            const int32_t x = adj[p];
             unsigned long long *row = ob + ob_off[c] + (int64_t)(p - sc) * wc;
             const int64_t k1 = aoff[p + 1];
-            int64_t k = aoff[p];
-            while (k < k1 && apex_at(av, adj, aa, k) <= x) k++;   // apexes after x only
+            int64_t k = aoff[p], hi = k1;
+            while (k < hi) { const int64_t mid = (k + hi) >> 1; if ((int32_t)aa[mid] <= p) k = mid + 1; else hi = mid; }
             for (; k < k1; k++) {
                 int32_t pos = (int32_t)aa[k] - sc;
                 row[pos >> 6] |= 1ull << (pos & 63);
@@ -280,23 +324,21 @@ __device__ inline int nth_set_bit(const unsigned long long *row, int words, int 
 }
 
 // Work of vertex a grows like d+(a)^3 / 64 word operations, so a is split
-// into units of ch out-neighbours b, ch = min(256, 2^lg / d+(a)^2) (lg = 24
+// into units of ch out-neighbours b, ch = min(256, 2^lg / d+(a)^2) (lg = 20
 // unless tuned): a hub spreads over many workgroups.
 __device__ inline int k5_chunk(int32_t dp, int lg) {
     const int64_t q = ((int64_t)1 << lg) / ((int64_t)dp * dp);
     return q >= 256 ? 256 : (q < 1 ? 1 : (int)q);
 }
 
-// Vertices with at most K5_LIGHT out-neighbours (one-word rows) are counted
-// a wave each, lane = b, after the units of the others.
-#define K5_LIGHT 64
-#define K5_LIGHT_RUN 32   // consecutive light vertices per wave at a time
-#define K5_WAVE_WORDS 8   // heavy vertices with rows of at most this many words: a wave per b
-
-__global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, int lg, int64_t *len) {
+// units of the direct pass: none for light vertices (their own loop) and
+// for dense ones (no rows)
+__global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, const int64_t *ob_off, int lg,
+                           int light, int64_t *len) {
     for (int32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
         const int32_t dp = off[a + 1] - split[a];
-        len[a] = dp <= K5_LIGHT ? 0 : (dp + k5_chunk(dp, lg) - 1) / k5_chunk(dp, lg);
+        const bool rows = ob_off[a + 1] > ob_off[a];
+        len[a] = dp <= light || !rows ? 0 : (dp + k5_chunk(dp, lg) - 1) / k5_chunk(dp, lg);
     }
 }
 
@@ -305,7 +347,7 @@ __global__ void k_k5_units(int32_t n, const int32_t *off, const int32_t *split, 
 __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const int32_t *split,
                                             const int64_t *ob_off, const unsigned long long *ob,
                                             const int64_t *uoff, const int32_t *uown, int64_t nunits, int lg,
-                                            int *task, GMap gm,
+                                            int light, int wave_words, int *task, GMap gm,
                                             unsigned long long *acc, unsigned long long *visits) {
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
@@ -334,8 +376,8 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
         const int32_t ib1 = ib0 + ch < dpa ? ib0 + ch : dpa;
         const int wa = (dpa + 63) >> 6;
         const unsigned long long *rows = ob + ob_off[a];
-        if (wa <= K5_WAVE_WORDS) {
-            // rows of at most K5_WAVE_WORDS words: one wave per b, the row of
+        if (wa <= wave_words) {
+            // rows of at most wave_words words: one wave per b, the row of
             // b in registers; lane l takes the c = 64 w + l of row(a,b), ANDs
             // the two rows once and counts, for each x of the result, the y
             // adjacent to all of b, c, x
@@ -406,7 +448,7 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
         const int32_t r1 = (int32_t)(r0 + K5_LIGHT_RUN < n ? r0 + K5_LIGHT_RUN : n);
         for (int32_t a = (int32_t)r0; a < r1; a++) {
             const int32_t dp = off[a + 1] - split[a];
-            if (dp < 4 || dp > K5_LIGHT) continue;
+            if (dp < 4 || dp > light) continue;
             const int g = gm.graph(a);
             if (g != wg) {
                 if (wg >= 0) wave_flush_u128(s, acc + (size_t)wg * ACC_STRIDE + 2 * AC_K5);
@@ -432,6 +474,180 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
         }
     }
     if (wg >= 0) wave_flush_u128(s, acc + (size_t)wg * ACC_STRIDE + 2 * AC_K5);
+    flush_count(nvis, visits);
+}
+
+// Dense vertices, one workgroup per vertex a (h = d+(a), taken from the
+// dense list): the 4-cliques of H_a through its complement Hc.
+//  1. Rows of Hc over the positions 0..h-1 of N+(a): N(v) & N+(a) is the
+//     suffix of list(a,v) whose arc indices in the row of a come after a's
+//     in-arcs; its complement (without v itself) is the row.  Rows are
+//     stored word-major (T[w * h + v]) so that lanes taking consecutive v
+//     read consecutive words; dc(v) = complement degree.
+//  2. Terms of the degrees alone (thread 0): C(h,4) - e C(h-2,2) + W (h-3)
+//     + C(e,2) - W - S with e, W, S the edges, wedges and 3-stars of Hc
+//     (App. A: one edge, a wedge or a matching, a 3-star with the rest of
+//     the 4-set free).
+//  3. One wave per vertex u, a lane per v > u, with c = common Hc
+//     neighbours after u: + C(c,2), each 4-cycle of Hc once, from its
+//     earliest vertex u and the opposite vertex v (Thm 4cycle).  For an Hc
+//     edge u-v with t common neighbours (Thm 4vertex-tri): - (dc(u)-1)
+//     (dc(v)-1) - C(t,2) (3-paths of the edge, diamonds on it); for each Hc
+//     triangle u<v<x: + dc(u)+dc(v)+dc(x) - h (its -(h-3) for triangle+point,
+//     +3 undoing the 3-path count's triangles, the tailed triangles at its
+//     three vertices); + the Hc 4-cliques u<v<x<y (Thm 4clique).
+// The signed terms add up modulo 2^128; their total, the 5-cliques, is a
+// count in range.
+template <bool IDS>
+__global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int32_t *split, const int64_t *aoff,
+                                                  const uint32_t *aa, const int32_t *dlist, const int *ndense,
+                                                  unsigned long long *scr_all, int64_t scr_words, int32_t hcap,
+                                                  int *task, GMap gm, unsigned long long *acc,
+                                                  unsigned long long *visits) {
+    __shared__ unsigned long long fu[4][K5_DENSE_HMAX / 64];
+    __shared__ int s_t;
+    __shared__ u128 red[3 * 4];
+    const int ids[1] = {AC_K5};
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    unsigned long long *T = scr_all + (size_t)blockIdx.x * scr_words;
+    int64_t *los = (int64_t *)(T + (size_t)hcap * (hcap / 64));
+    int32_t *dc = (int32_t *)(los + hcap);
+    const int nd = *ndense;
+    u128 k5[1] = {0};
+    int gcur = -1;
+    uint64_t nvis = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(task, 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();   // s_t is read by every thread before it is taken again
+        if (t >= nd) break;
+        const int32_t a = dlist[t];
+        block_switch_graph<1>(k5, gcur, gm.graph(a), red, acc, ACC_STRIDE, ids);
+        const int32_t sa = split[a];
+        const int h = off[a + 1] - sa;
+        const int wa = (h + 63) >> 6;
+        // 1. complement rows; first the start of each list's suffix in N+(a)
+        for (int v = threadIdx.x; v < h; v += blockDim.x) {
+            int64_t lo = aoff[sa + v], hi = aoff[sa + v + 1];
+            while (lo < hi) { const int64_t mid = (lo + hi) >> 1; if ((int32_t)aa[mid] < sa) lo = mid + 1; else hi = mid; }
+            los[v] = lo;
+        }
+        __syncthreads();
+        for (int v = wid; v < h; v += nwv) {
+            unsigned long long *row = fu[wid];
+            for (int w = lane; w < wa; w += 64) row[w] = 0;
+            wave_sync();
+            const int64_t l0 = los[v], l1 = aoff[sa + v + 1];
+            // four entries per lane in flight
+            for (int64_t q = l0 + lane; q < l1; q += 256) {
+                int32_t p4[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) p4[r] = q + 64 * r < l1 ? (int32_t)aa[q + 64 * r] - sa : -1;
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    if (p4[r] >= 0) atomicOr(&row[p4[r] >> 6], 1ull << (p4[r] & 63));
+            }
+            nvis += (uint64_t)(l1 - l0);
+            wave_sync();
+            int d = 0;
+            for (int w = lane; w < wa; w += 64) {
+                unsigned long long x = ~row[w];
+                const int top = h - 64 * w;   // positions of this word below h
+                if (top < 64) x &= (1ull << top) - 1ull;
+                if (w == (v >> 6)) x &= ~(1ull << (v & 63));
+                T[(size_t)w * h + v] = x;
+                d += __popcll(x);
+            }
+            d = (int)wave_sum_u64((uint64_t)d);
+            if (lane == 0) dc[v] = d;
+            wave_sync();   // the row buffer is reused by the wave's next row
+        }
+        __syncthreads();
+        // 2. degree terms
+        {
+            u128 e2 = 0, w2 = 0, s3 = 0;
+            for (int v = threadIdx.x; v < h; v += blockDim.x) {
+                const uint64_t d = (uint64_t)dc[v];
+                e2 += d;
+                w2 += c2(d);
+                s3 += c3(d);
+            }
+            e2 = wave_sum_u128(e2);
+            w2 = wave_sum_u128(w2);
+            s3 = wave_sum_u128(s3);
+            if (lane == 0) { red[wid] = e2; red[4 + wid] = w2; red[8 + wid] = s3; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                u128 E = 0, W = 0, S = 0;
+                for (int w = 0; w < nwv; w++) { E += red[w]; W += red[4 + w]; S += red[8 + w]; }
+                E >>= 1;
+                const u128 hh = (u128)h;
+                k5[0] += c4((uint64_t)h);
+                k5[0] -= E * (u128)c2((uint64_t)(h - 2));
+                k5[0] += W * (hh - 3);
+                k5[0] += (u128)c2((uint64_t)E);
+                k5[0] -= W;
+                k5[0] -= S;
+            }
+            __syncthreads();   // red is reused by the flushes
+        }
+        // 3. pairs u < v
+        for (int u = wid; u < h; u += nwv) {
+            for (int w = lane; w < wa; w += 64) fu[wid][w] = T[(size_t)w * h + u];
+            wave_sync();
+            const uint64_t du = (uint64_t)dc[u];
+            const int w0 = (u + 1) >> 6;
+            const unsigned long long m0 = ~0ull << ((u + 1) & 63);   // positions after u in word w0
+            for (int v = u + 1 + lane; v < h; v += 64) {
+                // w0 < wa: v <= h - 1 lies in the last word at the latest
+                const unsigned long long *tv = T + v;
+                uint32_t cnt = (uint32_t)__popcll(fu[wid][w0] & tv[(size_t)w0 * h] & m0);
+                int w = w0 + 1;
+                for (; w + 8 <= wa; w += 8) {   // eight loads in flight
+                    unsigned long long x[8];
+#pragma unroll
+                    for (int r = 0; r < 8; r++) x[r] = tv[(size_t)(w + r) * h];
+#pragma unroll
+                    for (int r = 0; r < 8; r++) cnt += (uint32_t)__popcll(fu[wid][w + r] & x[r]);
+                }
+                for (; w < wa; w++) cnt += (uint32_t)__popcll(fu[wid][w] & tv[(size_t)w * h]);
+                nvis += (uint64_t)(wa - w0);
+                k5[0] += c2(cnt);
+                if (!((fu[wid][v >> 6] >> (v & 63)) & 1ull)) continue;
+                // an edge of Hc
+                uint32_t tf = cnt;
+                for (int w = 0; w <= w0 && w < wa; w++) {
+                    unsigned long long x = fu[wid][w] & T[(size_t)w * h + v];
+                    if (w == w0) x &= ~m0;
+                    tf += (uint32_t)__popcll(x);
+                }
+                const uint64_t dv = (uint64_t)dc[v];
+                k5[0] -= (u128)((du - 1) * (dv - 1)) + (u128)c2(tf);
+                const int wv = v >> 6;
+                for (int w = wv; w < wa; w++) {
+                    unsigned long long sx = fu[wid][w] & T[(size_t)w * h + v];
+                    if (w == wv) sx &= (v & 63) == 63 ? 0ull : ~0ull << ((v & 63) + 1);
+                    while (sx) {
+                        const int x = w * 64 + __ffsll((long long)sx) - 1;
+                        sx &= sx - 1;
+                        k5[0] += (u128)(du + dv + (uint64_t)dc[x]);
+                        k5[0] -= (u128)h;
+                        const int wx = x >> 6;
+                        for (int w2 = wx; w2 < wa; w2++) {
+                            unsigned long long y = fu[wid][w2] & T[(size_t)w2 * h + v] & T[(size_t)w2 * h + x];
+                            if (w2 == wx) y &= (x & 63) == 63 ? 0ull : ~0ull << ((x & 63) + 1);
+                            k5[0] += (uint64_t)__popcll(y);
+                        }
+                        nvis += (uint64_t)(wa - wx);
+                    }
+                }
+            }
+            wave_sync();   // fu is reused by the wave's next u
+        }
+        __syncthreads();   // T, los and dc are rewritten for the next vertex
+    }
+    if (gcur >= 0) block_flush_u128<1>(k5, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
 }
 
@@ -461,37 +677,56 @@ esc_status stage_k5(esc_ctx *c) {
     const int32_t n = c->n;
     if (n == 0 || c->narcs_apex == 0) return ESC_OK;
     const int32_t *off = (const int32_t *)c->buf[B_OFF], *split = (const int32_t *)c->buf[B_SPLIT];
+    const int64_t *aoff = (const int64_t *)c->buf[B_AOFF];
+    const uint32_t *aa = (const uint32_t *)c->buf[B_AA];
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *ob_off = (int64_t *)ctx_buf(c, B_OB_OFF, sizeof(int64_t) * (size_t)(n + 2));
-    if (!len || !ob_off) return ESC_ENOMEM;
-    k_ob_sizes<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, len);
+    int32_t *dlist = (int32_t *)ctx_buf(c, B_K5_DENSE, sizeof(int32_t) * (size_t)(n + 1));
+    int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
+    if (!len || !ob_off || !dlist || !task) return ESC_ENOMEM;
+    // task[3]: units of the direct pass, task[5]: dense vertices listed,
+    // task[6]: dense vertices taken
+    HIP_TRY(hipMemsetAsync(task + 3, 0, 4 * sizeof(int), st));
+    k_k5_classify<<<grid_cap(c, (int64_t)n * 64, 256), 256, 0, st>>>(n, off, split, aoff, aa, c->k5_light,
+                                                                     c->k5_dense_pct, len, dlist, task + 5);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, ob_off, n));
     int64_t words = 0;
     HIP_TRY(hipMemcpyAsync(&words, ob_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     unsigned long long *ob = (unsigned long long *)ctx_buf(c, B_OB, sizeof(uint64_t) * (size_t)(words + 1));
-    int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
-    if (!ob || !task) return ESC_ENOMEM;
+    if (!ob) return ESC_ENOMEM;
     HIP_TRY(hipMemsetAsync(ob, 0, sizeof(uint64_t) * (size_t)(words + 1), st));
-    HIP_TRY(hipMemsetAsync(task + 3, 0, sizeof(int), st));
-    k_ob_rows<<<grid_cap(c, (int64_t)n * 64, 256), 256, 0, st>>>(
-        n, off, split, (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av,
-        (const int32_t *)c->buf[B_ADJ], ob_off, ob);
+    k_ob_rows<<<grid_cap(c, (int64_t)n * 64, 256), 256, 0, st>>>(n, off, split, aoff, aa, ob_off, ob);
     HIP_TRY(hipGetLastError());
-    // units of work (see k5_chunk): per-vertex counts, then offsets
+    // units of work of the direct pass (see k5_chunk): per-vertex counts, then offsets
     int64_t *uoff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
     if (!uoff) return ESC_ENOMEM;
-    k_k5_units<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, c->k5_work_log2, len);
+    k_k5_units<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, ob_off, c->k5_work_log2, c->k5_light, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, uoff, n));
     int64_t nunits = 0;
     int32_t *uown = nullptr;
     ESC_TRY(dev_task_owner(c, n, uoff, &nunits, &uown));
-    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, uown, nunits, c->k5_work_log2, task + 3,
-                                        gmap_of(c),
-                                        (unsigned long long *)c->buf[B_ACC],
-                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4);
+    unsigned long long *acc = (unsigned long long *)c->buf[B_ACC];
+    unsigned long long *vis = (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4;
+    k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, uown, nunits, c->k5_work_log2,
+                                        c->k5_light, c->k5_wave_words, task + 3, gmap_of(c), acc, vis);
     HIP_TRY(hipGetLastError());
+    if (c->maxdplus > c->k5_light && c->k5_dense_pct <= 100) {
+        // dense vertices: per-workgroup scratch for the complement rows of
+        // the largest out-neighbourhood, its list starts and degrees
+        int32_t hmax = c->maxdplus < K5_DENSE_HMAX ? c->maxdplus : K5_DENSE_HMAX;
+        const int32_t hcap = (hmax + 63) & ~63;
+        const int64_t per_wg = (int64_t)hcap * (hcap / 64) + hcap + (hcap + 1) / 2;
+        int nwg = 4 * c->num_cu;   // 113 VGPRs: four 4-wave workgroups per CU are resident
+        while (nwg > c->num_cu && (size_t)nwg * (size_t)per_wg * 8 > c->dev_mem / 16) nwg -= c->num_cu;
+        unsigned long long *scr = (unsigned long long *)ctx_buf(c, B_K5_DENSE_SCR, sizeof(uint64_t) * (size_t)per_wg * nwg);
+        if (!scr) return ESC_ENOMEM;
+        auto kern = c->av ? k_k5_dense<true> : k_k5_dense<false>;
+        kern<<<nwg, 256, 0, st>>>(off, split, aoff, aa, dlist, task + 5, scr, per_wg, hcap, task + 6, gmap_of(c), acc,
+                                  vis);
+        HIP_TRY(hipGetLastError());
+    }
     return ESC_OK;
 }

@@ -145,11 +145,23 @@ esc_status combine_tables(int32_t *host_inv4 /*121*/, int32_t *host_inv5 /*1156*
 
 // ------------------------------------------------------------ device side
 
+__device__ inline uint32_t gcd_u32(uint32_t a, uint32_t b) {
+    while (b) { const uint32_t t = a % b; a = b; b = t; }
+    return a;
+}
+
 __device__ inline u128 binom(u128 n, int k) {
-    // C(n,k) with exact intermediate divisions; 0 when n < k
+    // C(n,k), 0 when n < k.  Step i turns r = C(n,i) into C(n,i+1) =
+    // r (n-i) / (i+1) dividing first: with g = gcd(r, i+1), (i+1)/g divides
+    // n-i, so (r/g) ((n-i) / ((i+1)/g)) is exact and no intermediate exceeds
+    // the result (r (n-i) itself would pass 2^128 for C(n,5) from n near 9.6e7)
     if (n < (u128)k) return 0;
     u128 r = 1;
-    for (int i = 0; i < k; i++) r = r * (n - i) / (u128)(i + 1);
+    for (int i = 0; i < k; i++) {
+        const uint32_t d = (uint32_t)(i + 1);
+        const uint32_t g = gcd_u32(d, (uint32_t)(r % (u128)d));
+        r = (r / (u128)g) * ((n - (u128)i) / (u128)(d / g));
+    }
     return r;
 }
 

@@ -72,6 +72,8 @@ enum Buf {
     B_TASK_OWNER,               // vertex of each task of a split per-vertex pass
     B_TRIREC,                   // triangles found by the count pass: 3 arcs and 3 slots each
     B_TRICNT,                   // count of B_TRIREC entries, bound of oriented wedges
+    B_K5_DENSE,                 // vertices whose 5-cliques are counted through the complement
+    B_K5_DENSE_SCR,             // per-workgroup complement rows of those vertices
     B_COUNT
 };
 
@@ -133,6 +135,11 @@ struct esc_ctx {
     int wg_per_cu;             // workgroups per CU of the per-source kernels
     int wg_cap;                // largest wg_per_cu the tables' memory allows for this call
     int k5_work_log2;          // 5-clique work units (see k5_chunk)
+    int k5_light;              // 5-cliques: out-degrees up to this take the one-word-row loop
+    int k5_wave_words;         // 5-cliques: rows up to this many words take a wave per b
+    int k5_dense_pct;          // 5-cliques: density (percent) from which the complement count is used
+    int wheel_split_deg;       // wheels: hubs above this degree are split into rim tasks
+    int four_range_deg;        // 4-cycles: tops above this degree are split into key-range tasks
     int five_order;            // 5-cycles of one graph: 0 Y table when maxdeg < 2^16, 1 Wnt table
     size_t dev_mem;            // device memory in bytes
     // tuning: parameters in use, forced ones, the table

@@ -333,7 +333,7 @@ esc_status stage_triangles(esc_ctx *c) {
 //   (c-1) * c * (d(h) + d(o) - 4)  per key }
 // With per_edge set, pass 2 also adds c-1 to C4 of edges hk and ko.
 //
-// A top vertex with more than FOUR_RANGE_DEG neighbours is split into tasks by
+// A top vertex with more than range_deg neighbours is split into tasks by
 // key range: task r counts the keys o in [gb + r*R, gb + (r+1)*R) (R = the
 // LDS slab in keys at h's packing), its pass 1 and 2 reading from every row
 // N(k) only the run of keys in the range (rows are sorted, so two binary
@@ -342,14 +342,12 @@ esc_status stage_triangles(esc_ctx *c) {
 // Smaller tops go one per workgroup: keys in the latest `slab` ranks of h's
 // graph are counted in LDS, the rest in the workgroup's dense table (relative
 // to the graph's first rank).
-#define FOUR_RANGE_DEG 256
-
-__global__ void k_four_tasks(int32_t n, const int32_t *off, GMap gm, int32_t slab, int64_t *len) {
+__global__ void k_four_tasks(int32_t n, const int32_t *off, GMap gm, int32_t slab, int32_t range_deg, int64_t *len) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t d = off[v + 1] - off[v];
         const int64_t keys = v - gm.begin(gm.graph(v));   // keys before v in its graph
         const int64_t rk = (int64_t)slab << count_shift(d);
-        len[v] = d > FOUR_RANGE_DEG && slab > 0 ? (keys + rk - 1) / rk : 0;
+        len[v] = d > range_deg && slab > 0 ? (keys + rk - 1) / rk : 0;
     }
 }
 
@@ -360,7 +358,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                                                      const int64_t *toff, const int32_t *town, int64_t nbig,
                                                      int *task_big,
                                                      int chunk, GMap gm, int *task, int32_t slab,
-                                                     int32_t pw_words, unsigned long long *acc,
+                                                     int32_t range_deg, int32_t pw_words, unsigned long long *acc,
                                                      unsigned long long *c4e, unsigned long long *visits) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
@@ -502,7 +500,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 const int32_t h = n - 1 - (int32_t)t;
                 const int32_t oh = off[h], sh = split[h];
                 const int64_t dh = off[h + 1] - oh;
-                if (dh > FOUR_RANGE_DEG && slab > 0) continue;   // done by key range
+                if (dh > range_deg && slab > 0) continue;   // done by key range
                 if (sh - oh < 2) continue;                        // c(h,o) >= 2 needs two middles
                 const int g = gm.graph(h);
                 if (g != wgc) {
@@ -587,7 +585,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
             const int32_t gb = gm.begin(g), ge = gm.end(g);
             const int32_t oh = off[h], sh = split[h];
             const int64_t dh = off[h + 1] - oh;
-            if (dh > FOUR_RANGE_DEG && slab > 0) continue;   // done by key range
+            if (dh > range_deg && slab > 0) continue;   // done by key range
             // c(h,o) <= d(h): a low-degree top vertex packs 16, 8, 4 or 2
             // counts per word (count_shift), in LDS (that many times more
             // latest ranks) and in the table
@@ -673,7 +671,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
 esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
-    if (n == 0) return ESC_OK;
+    if (n == 0 || c->m == 0) return ESC_OK;   // no wedge: no 4-cycle, no tables to size
     int nwg = pair_wgs(c);
     size_t per = (size_t)c->tab_n * sizeof(uint32_t);
     uint32_t *tab = (uint32_t *)ctx_buf(c, B_WG_SCRATCH, per * 2 * nwg);
@@ -693,11 +691,12 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     // per-wave LDS tables over a graph's keys (16-bit counts at most)
     const int32_t pw_words = c->G && c->tab_n <= 4096 ? (c->tab_n + 1) / 2 : 0;
     const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
-    // key-range tasks of the tops with more than FOUR_RANGE_DEG neighbours
+    // key-range tasks of the tops with more than four_range_deg neighbours
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
     if (!len || !toff) return ESC_ENOMEM;
-    k_four_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], gmap_of(c), slab, len);
+    k_four_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], gmap_of(c), slab,
+                                                      c->four_range_deg, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     int64_t nbig = 0;
@@ -708,7 +707,7 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
                                        (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
                                        (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
                                        tab, touch, c->tab_n, toff, town, nbig, task + 4, c->task_chunk, gmap_of(c),
-                                       task, slab, pw_words,
+                                       task, slab, c->four_range_deg, pw_words,
                                        (unsigned long long *)c->buf[B_ACC], c4e,
                                        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
     HIP_TRY(hipGetLastError());

@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // 16-bit.
 //
 // Hubs with d(h) > wq = lds_cap / (waves per workgroup) come first, those above
-// WHEEL_SPLIT_DEG split into tasks of WHEEL_RIMS rim vertices, the others one
+// split_deg split into tasks of WHEEL_RIMS rim vertices, the others one
 // task each (task offsets per hub in toff, latest hubs first):
 // every workgroup of the chip works on the same few hubs at a time, so their
 // triangle lists, re-read for every rim vertex, stay in each XCD's L2.  The
@@ -316,16 +316,16 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // vertices with its own table and no workgroup barrier per rim vertex.
 #define WHEEL_WAVES 8          // most waves per workgroup of the wheel pass (a launch may use fewer)
 #define WHEEL_RIMS 16          // rim vertices per task of a large hub
-#define WHEEL_SPLIT_DEG 1024   // hubs up to this degree are one task
 #define WHEEL_TINY 32          // batches: hubs up to this degree are taken whole by one wave
 #define WHEEL_TINY_WORDS (WHEEL_TINY * WHEEL_TINY / 2)   // its table: 16-bit counts of (rim, key)
 
-__device__ inline int32_t wheel_rims(int32_t d) { return d > WHEEL_SPLIT_DEG ? WHEEL_RIMS : d; }
+// rim vertices per task of hub with d neighbours: all of them up to split_deg
+__device__ inline int32_t wheel_rims(int32_t d, int32_t split_deg) { return d > split_deg ? WHEEL_RIMS : d; }
 
-__global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int64_t *len) {
+__global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int32_t split_deg, int64_t *len) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t d = off[v + 1] - off[v];
-        len[v] = d > wq ? (d + wheel_rims(d) - 1) / wheel_rims(d) : 0;
+        len[v] = d > wq ? (d + wheel_rims(d, split_deg) - 1) / wheel_rims(d, split_deg) : 0;
     }
 }
 
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
                                                 uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
                                                 int32_t lds_cap, const int64_t *toff, const int32_t *town,
-                                                int64_t nbig, int *task_big, int chunk,
+                                                int64_t nbig, int *task_big, int chunk, int32_t split_deg,
                                                 GMap gm, int *task, int tiny, unsigned long long *acc,
                                                 unsigned long long *visits) {
     uint64_t nvis = 0;
@@ -373,8 +373,9 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
         block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
         const int32_t oh = off[h], dh = off[h + 1] - oh;
         const bool in_lds = dh <= lds_cap;
-        const int32_t r0 = rtask * wheel_rims(dh);
-        const int32_t r1 = r0 + wheel_rims(dh) < dh ? r0 + wheel_rims(dh) : dh;
+        const int32_t rims = wheel_rims(dh, split_deg);
+        const int32_t r0 = rtask * rims;
+        const int32_t r1 = r0 + rims < dh ? r0 + rims : dh;
         if (in_lds)
             for (int q = threadIdx.x; q < (dh + 1) / 2; q += blockDim.x) lcnt[q] = 0;
         __syncthreads();
@@ -950,7 +951,7 @@ static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int 
 esc_status stage_pairs(esc_ctx *c) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
-    if (n == 0) return ESC_OK;
+    if (n == 0 || c->m == 0) return ESC_OK;   // no wedge: nothing to add, no tables to size
     uint32_t *tab;
     int32_t *touch;
     int *task;
@@ -1010,7 +1011,8 @@ esc_status stage_wheels(esc_ctx *c) {
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
     if (!len || !toff) return ESC_ENOMEM;
-    k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], lds_cap / waves, len);
+    k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], lds_cap / waves,
+                                                       c->wheel_split_deg, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     int64_t nbig = 0;
@@ -1020,7 +1022,7 @@ esc_status stage_wheels(esc_ctx *c) {
     kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                               (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
                                               c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
-                                              c->task_chunk, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
+                                              c->task_chunk, c->wheel_split_deg, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
                                               (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
     HIP_TRY(hipGetLastError());
     return ESC_OK;
@@ -1029,7 +1031,7 @@ esc_status stage_wheels(esc_ctx *c) {
 esc_status stage_cycles(esc_ctx *c) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
-    if (n == 0) return ESC_OK;
+    if (n == 0 || c->m == 0) return ESC_OK;   // no 3-path: nothing to add, no tables to size
     uint32_t *tab;
     int32_t *touch;
     int *task;

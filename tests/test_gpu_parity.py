@@ -190,18 +190,30 @@ def test_tuned_and_forced_parameters_give_same_counts(ctx):
     assert best["five_order"] == 0
     # five_order 1: the 5-cycle sum in the Wnt-table order (else taken only
     # by graphs whose largest degree reaches 2^16, and by batches)
+    # the split thresholds at their extremes: every 4-cycle top above 16
+    # neighbours in key-range tasks, every wheel hub split into rim tasks,
+    # 5-clique vertices above 8 out-neighbours through the complement (or
+    # never), rows of one word in the per-b wave path or none of them
     for p in ({"task_chunk": 64, "wg_per_cu": 1, "k5_work_log2": 16, "five_order": 1},
               {"task_chunk": 3, "wg_per_cu": 3, "k5_work_log2": 30, "five_order": 0},
-              {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20, "five_order": 1}):
+              {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20, "five_order": 1},
+              {"task_chunk": 1, "wg_per_cu": 2, "k5_work_log2": 20, "k5_light": 8, "k5_wave_words": 1,
+               "k5_dense_pct": 0, "wheel_split_deg": 32, "four_range_deg": 16},
+              {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20, "k5_light": 3, "k5_wave_words": 8,
+               "k5_dense_pct": 101, "wheel_split_deg": 1 << 30, "four_range_deg": 1 << 30}):
         ctx.set_params(p)
-        assert ctx.count(g, 5) == want
-        assert ctx.last_params() == p
-    with pytest.raises(esc.EscapeError) as e:
-        ctx.set_params({"task_chunk": 0, "wg_per_cu": 1, "k5_work_log2": 24})
-    assert e.value.status == esc.ESC_EINVAL
-    with pytest.raises(esc.EscapeError) as e:
-        ctx.set_params({"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "five_order": 2})
-    assert e.value.status == esc.ESC_EINVAL
+        assert ctx.count(g, 5) == want, p
+        assert ctx.last_params() == dict(esc.PARAM_DEFAULTS, **p)
+    for bad in ({"task_chunk": 0, "wg_per_cu": 1, "k5_work_log2": 24},
+                {"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "five_order": 2},
+                {"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "k5_light": 65},
+                {"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "k5_wave_words": 9},
+                {"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "k5_dense_pct": 102},
+                {"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "wheel_split_deg": 31},
+                {"task_chunk": 1, "wg_per_cu": 1, "k5_work_log2": 24, "four_range_deg": 15}):
+        with pytest.raises(esc.EscapeError) as e:
+            ctx.set_params(bad)
+        assert e.value.status == esc.ESC_EINVAL, bad
     ctx.set_params(None)
     graphs = [synth.from_spec(s) for s in synth.batch_specs(40, 3)]
     bbest, _ = ctx.tune_batched(graphs, 5)
@@ -343,3 +355,51 @@ def test_chung_lu_1m_sampled_fragments(ctx):
             if deg[v] < 3000 and deg[u] < 3000:
                 assert fr["c4_e"][p] == exp["c4"], (v, u)
         assert fr["tri_v"][v] == oracle.vertex_triangles(g, v)
+
+
+def test_binomials_at_the_vertex_bound(ctx):
+    """Edgeless graph with n at the k = 5 bound (1e8): every 4- and 5-subset
+    is independent, so the empty-pattern slots must be C(n,4) and C(n,5)
+    exactly (a multiply-before-divide binomial passes 2^128 from n near
+    9.6e7).  One vertex more is refused."""
+    import paper_1610_09411_amd as esc
+    n = 100_000_000
+    g = synth.Graph(n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), "edgeless 1e8")
+    got = ctx.count(g, 5)
+    want = [0] * 45
+    want[6] = comb(n, 4)
+    want[32] = comb(n, 5)
+    assert got == want
+    g1 = synth.Graph(n + 1, np.zeros(n + 2, np.int32), np.zeros(0, np.int32), "edgeless 1e8+1")
+    with pytest.raises(esc.EscapeError) as e:
+        ctx.count(g1, 5)
+    assert e.value.status == esc.ESC_EOVERFLOW
+
+
+def _dense_core_graph(seed, core=130, per=250):
+    """A near-clique core (each core pair missing with probability 0.04) and
+    periphery vertices tied to random fractions of it and sparsely to each
+    other: out-neighbourhoods of every density, many above 64 vertices."""
+    rng = random.Random(seed)
+    edges = [(u, v) for u in range(core) for v in range(u + 1, core) if rng.random() > 0.04]
+    for x in range(core, core + per):
+        q = rng.random() * 0.6
+        edges += [(x, u) for u in range(core) if rng.random() < q]
+        edges += [(x, y) for y in range(core, x) if rng.random() < 0.02]
+    return synth.from_edges(core + per, edges, "dense core %d" % seed)
+
+
+def test_five_cliques_through_the_complement(ctx):
+    """Thm 5clique with dense out-neighbourhoods counted through their
+    complement (every vertex above 64 out-neighbours: pct 0; the default
+    density cut: 50; never: 101): the same 45 counts as the oracle."""
+    for g in (_dense_core_graph(1), synth.erdos_renyi(160, 0.6, 11), synth.erdos_renyi(200, 0.45, 12)):
+        print(g.name, g.n, g.m, flush=True)
+        want = oracle.count(g, 5, threads=8)
+        for pct in (0, 50, 101):
+            ctx.set_params({"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20, "k5_dense_pct": pct})
+            try:
+                got = ctx.count(g, 5)
+            finally:
+                ctx.set_params(None)
+            assert got == want, (g.name, pct)

@@ -361,3 +361,25 @@ def test_edge_fragments_closed_forms():
     assert oracle.edge_fragments(wheel, 0, 1)["k4"] == 0
     assert oracle.vertex_triangles(wheel, 0) == 6
     assert oracle.vertex_triangles(wheel, 1) == 2
+
+
+def _complement(g):
+    A = _dense(g)
+    return synth.from_edges(g.n, [(u, v) for u in range(g.n) for v in range(u + 1, g.n) if not A[u, v]])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_clique_count_through_the_complement(seed):
+    """The 4-cliques of a dense graph H are the 4-sets spanning no edge of its
+    complement Hc: with the sign rule of the inverse of A (App. B) on the
+    empty pattern's row, K4(H) = sum over the 11 four-vertex patterns j of
+    (-1)^e(j) N_j(Hc), N_j the non-induced counts of Hc (the 5-clique pass
+    counts dense out-neighbourhoods this way).  Checked against the
+    classification of every 4-subset of H."""
+    n = 14 + 3 * seed
+    h = synth.erdos_renyi(n, 0.55 + 0.07 * seed, 800 + seed)
+    hc = _complement(h)
+    N = oracle.noninduced_from_sums(oracle.sums(hc, 4), 4)
+    signed = sum((-1) ** pat.edge_count(4, j) * N[j] for j in range(11))
+    assert signed == _induced(h, 4)[5]
+    assert list(pat.a_inverse(4)[6]) == [(-1) ** pat.edge_count(4, j) for j in range(11)]

@@ -108,6 +108,26 @@ esc_status esc_count_subgraphs(esc_ctx *ctx, int32_t n, const int32_t *row_ptr,
                                const int32_t *col, int k, uint32_t flags,
                                esc_u128 *out, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): esc_count_subgraphs with every device
+ * buffer of the call taken from one fixed region of ESC_NOALLOC_SCRATCH_BYTES
+ * that the library holds per GPU (a static device array, present from the
+ * first use of the library on that GPU until the process ends).  The call
+ * makes no hipMalloc / hipFree; the context must come from esc_create
+ * (which looks the region up once per device).  Arguments, output and
+ * errors as in esc_count_subgraphs; a graph whose buffers do not fit the
+ * region (roughly: up to some 10^4 vertices and 10^5 edges, fewer for
+ * graphs with many triangles) returns ESC_ENOMEM, with nothing retained.
+ * The context's own buffers are left as they were.  All calls on one GPU
+ * share the region and leave their contents in it (each call clears what
+ * it needs zeroed): calls that overlap on one GPU race, so a caller
+ * serialises them (one host thread, or one stream waited on between
+ * calls).  Triangle lists are kept in the compact layout. */
+#define ESC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+esc_status esc_count_subgraphs_noalloc(esc_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                                       const int32_t *col, int k, uint32_t flags,
+                                       esc_u128 *out, void *stream);
+
 /* Same enumeration, also returning the per-vertex and per-edge fragment counts
  * of Thm 4vertex-tri, in the caller's vertex ids:
  *   tri_v, c4_v, k4_v   n uint64 each: triangles, 4-cycles and 4-cliques

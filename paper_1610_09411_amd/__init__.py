@@ -31,7 +31,8 @@ ESC_F_RANDOM_ORDER = 8
 ESC_F_COMPACT_LISTS = 16
 
 ABI_FUNCTIONS = [
-    "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_fragments", "esc_count_batched",
+    "esc_create", "esc_destroy", "esc_count_subgraphs", "esc_count_subgraphs_noalloc", "esc_count_fragments",
+    "esc_count_batched",
     "esc_server_start", "esc_submit", "esc_poll", "esc_wait", "esc_server_stats", "esc_server_stop",
     "esc_tune", "esc_tune_batched", "esc_set_params", "esc_last_params",
     "esc_last_work", "esc_last_profile", "esc_last_noninduced", "esc_last_three", "esc_inverse_matrix", "esc_strerror",
@@ -95,6 +96,8 @@ def _load():
         lib.esc_destroy.restype = None
         lib.esc_count_subgraphs.argtypes = [vp, i32, vp, vp, ctypes.c_int, u32, vp, vp]
         lib.esc_count_subgraphs.restype = ctypes.c_int
+        lib.esc_count_subgraphs_noalloc.argtypes = [vp, i32, vp, vp, ctypes.c_int, u32, vp, vp]
+        lib.esc_count_subgraphs_noalloc.restype = ctypes.c_int
         lib.esc_count_fragments.argtypes = [vp, i32, vp, vp, ctypes.c_int, u32, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.esc_count_fragments.restype = ctypes.c_int
         lib.esc_count_batched.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.c_int, u32, vp, vp, vp]
@@ -275,6 +278,17 @@ def esc_count_subgraphs(ctx, n, row_ptr, col, k=5, flags=0, stream=None):
     out = (_U128 * 45)()
     st = _load().esc_count_subgraphs(ctx, int(n), rp, ci, int(k), flags, out, _stream_ptr(stream))
     _check(st, "esc_count_subgraphs")
+    del keep
+    return _ints(out, 11 if k == 4 else 45)
+
+
+def esc_count_subgraphs_noalloc(ctx, n, row_ptr, col, k=5, flags=0, stream=None):
+    """esc_count_subgraphs with every device buffer taken from the library's
+    fixed per-GPU region (no device allocation by the call)."""
+    rp, ci, flags, keep = _csr_args(row_ptr, col, flags)
+    out = (_U128 * 45)()
+    st = _load().esc_count_subgraphs_noalloc(ctx, int(n), rp, ci, int(k), flags, out, _stream_ptr(stream))
+    _check(st, "esc_count_subgraphs_noalloc")
     del keep
     return _ints(out, 11 if k == 4 else 45)
 

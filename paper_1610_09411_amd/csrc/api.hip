@@ -4,12 +4,25 @@
 #include <limits.h>
 #include <string.h>
 #include <initializer_list>
+#include <mutex>
 #include "device.h"
 #include "ctx.h"
 
 void *ctx_buf(esc_ctx *c, Buf b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (c->buf[b] && c->cap[b] >= bytes) return c->buf[b];
+    if (c->arena) {
+        // no-allocation call: carve from the fixed region (a buffer that
+        // grows leaves its old block unused until the call ends)
+        const size_t want = (bytes + 255) & ~(size_t)255;
+        if (want > c->arena_size - c->arena_used) return nullptr;
+        void *p = c->arena + c->arena_used;
+        c->arena_used += want;
+        c->buf[b] = p;
+        c->cap[b] = want;
+        if (b == B_WG_SCRATCH && hipMemsetAsync(p, 0, want, c->stream) != hipSuccess) return nullptr;
+        return p;
+    }
     if (c->buf[b]) {
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->buf[b]);
@@ -39,11 +52,27 @@ size_t ctx_held(const esc_ctx *c, Buf b) { return c->buf[b] ? c->cap[b] : 0; }
 
 void ctx_release(esc_ctx *c, Buf b) {
     if (!c->buf[b]) return;
+    if (c->arena) {   // carved blocks are not freed
+        c->buf[b] = nullptr;
+        c->cap[b] = 0;
+        return;
+    }
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->buf[b]);
     c->held -= c->cap[b];
     c->buf[b] = nullptr;
     c->cap[b] = 0;
+}
+
+esc_status ctx_free_bytes(esc_ctx *c, size_t *out) {
+    if (c->arena) {
+        *out = c->arena_size - c->arena_used;
+        return ESC_OK;
+    }
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    *out = fr;
+    return ESC_OK;
 }
 
 // Per-source kernels run up to three workgroups per CU (more resident waves
@@ -140,6 +169,35 @@ extern "C" const char *esc_strerror(esc_status s) {
     return "unknown status";
 }
 
+// Device scratch of esc_count_subgraphs_noalloc: a file-scope array that
+// every GPU the library runs on holds until the process ends.  Host code
+// never passes the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): the address is looked up once per device
+// at context creation and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[ESC_NOALLOC_SCRATCH_BYTES];
+
+#define MAX_DEVICES 64
+static std::mutex scratch_mu;
+static void *scratch_ptr[MAX_DEVICES];
+static bool scratch_tried[MAX_DEVICES];
+
+// with hip_device current
+static void resolve_scratch(int hip_device) {
+    if (hip_device < 0 || hip_device >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_tried[hip_device]) return;
+    scratch_tried[hip_device] = true;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) scratch_ptr[hip_device] = p;
+    else (void)hipGetLastError();
+}
+
+static void *device_scratch(int hip_device) {
+    if (hip_device < 0 || hip_device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return scratch_ptr[hip_device];
+}
+
 extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budget_bytes) {
     if (!out) return ESC_EINVAL;
     *out = nullptr;
@@ -147,6 +205,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ESC_EDEVICE;
     if (hip_device < 0 || hip_device >= ndev) return ESC_EINVAL;
     HIP_TRY(hipSetDevice(hip_device));
+    resolve_scratch(hip_device);
     esc_ctx *c = (esc_ctx *)calloc(1, sizeof(esc_ctx));
     if (!c) return ESC_ENOMEM;
     c->device = hip_device;
@@ -504,6 +563,40 @@ static esc_status run_batched(esc_ctx *c, int32_t G, const int64_t *vtx_off, con
 extern "C" esc_status esc_count_subgraphs(esc_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col, int k,
                                           uint32_t flags, esc_u128 *out, void *stream) {
     return run(ctx, n, row_ptr, col, k, flags, out, nullptr, stream);
+}
+
+extern "C" esc_status esc_count_subgraphs_noalloc(esc_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                                                  const int32_t *col, int k, uint32_t flags, esc_u128 *out,
+                                                  void *stream) {
+    if (!ctx) return ESC_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    char *base = (char *)device_scratch(ctx->device);
+    if (!base) return ESC_EDEVICE;
+    // the context's own buffers are set aside (not freed) for the call
+    void *buf[B_COUNT];
+    size_t cap[B_COUNT];
+    memcpy(buf, ctx->buf, sizeof(buf));
+    memcpy(cap, ctx->cap, sizeof(cap));
+    const size_t held = ctx->held, budget = ctx->budget, dev_mem = ctx->dev_mem;
+    const bool clean = ctx->scratch_clean;
+    memset(ctx->buf, 0, sizeof(ctx->buf));
+    memset(ctx->cap, 0, sizeof(ctx->cap));
+    ctx->held = 0;
+    ctx->budget = 0;
+    ctx->dev_mem = ESC_NOALLOC_SCRATCH_BYTES;   // sizes the per-workgroup tables and scratch
+    ctx->arena = base;
+    ctx->arena_size = ESC_NOALLOC_SCRATCH_BYTES;
+    ctx->arena_used = 0;
+    esc_status st = run(ctx, n, row_ptr, col, k, flags, out, nullptr, stream);
+    if (st != ESC_OK) (void)hipStreamSynchronize(ctx->stream);   // nothing of the call is left in flight
+    ctx->arena = nullptr;
+    memcpy(ctx->buf, buf, sizeof(buf));
+    memcpy(ctx->cap, cap, sizeof(cap));
+    ctx->held = held;
+    ctx->budget = budget;
+    ctx->dev_mem = dev_mem;
+    ctx->scratch_clean = clean;
+    return st;
 }
 
 extern "C" esc_status esc_count_fragments(esc_ctx *ctx, int32_t n, const int32_t *row_ptr, const int32_t *col, int k,

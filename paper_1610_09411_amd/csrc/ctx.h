@@ -150,6 +150,11 @@ struct esc_ctx {
     int tune_used;
     uint32_t tune_keys[TUNE_SLOTS];
     esc_params tune_vals[TUNE_SLOTS];
+    // esc_count_subgraphs_noalloc: during such a call every buffer is carved
+    // from this fixed device region (bump pointer, never freed) instead of
+    // being allocated
+    char *arena;
+    size_t arena_size, arena_used;
 };
 
 // Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):
@@ -194,6 +199,9 @@ void *ctx_buf(esc_ctx *c, Buf b, size_t bytes);
 // Bytes held by a buffer; release one (it is allocated again on next use).
 size_t ctx_held(const esc_ctx *c, Buf b);
 void ctx_release(esc_ctx *c, Buf b);
+// Device bytes still free for the call's buffers: the device's free memory,
+// or what is left of the fixed region of a no-allocation call.
+esc_status ctx_free_bytes(esc_ctx *c, size_t *out);
 esc_status ctx_check(hipError_t e);
 
 // B_WORK layout: [0] W++, [1] W+-, [2 + s] visits of stage s (see esc_last_profile),

@@ -257,8 +257,8 @@ esc_status stage_triangles(esc_ctx *c) {
     // vertices in turn, so the regions fill about evenly)
     const int64_t rcap = (int64_t)(2 * wpp / TRI_REGIONS + 64);
     if (wpp > 0 && !(c->flags & ESC_F_COMPACT_LISTS)) {
-        size_t fr = 0, tot = 0;
-        HIP_TRY(hipMemGetInfo(&fr, &tot));
+        size_t fr = 0;
+        ESC_TRY(ctx_free_bytes(c, &fr));
         const size_t want = sizeof(TriRec) * (size_t)rcap * TRI_REGIONS;
         if (want <= (fr + ctx_held(c, B_TRIREC)) / 8) rec = (TriRec *)ctx_buf(c, B_TRIREC, want);
     }
@@ -279,14 +279,15 @@ esc_status stage_triangles(esc_ctx *c) {
     const size_t list_bytes = sizeof(uint32_t) * (size_t)(total + 1);
     size_t later = sizeof(uint64_t) * (size_t)(m + 1) + 16 * (size_t)c->tab_n * (size_t)pair_wgs(c) + ((size_t)4 << 30);
     if (c->k == 5) later += sizeof(uint64_t) * (size_t)m * (size_t)(c->maxdplus / 64 + 1);
-    size_t fr = 0, tot = 0;
-    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    size_t fr = 0;
+    ESC_TRY(ctx_free_bytes(c, &fr));
     size_t avail = fr + ctx_held(c, B_AA) + ctx_held(c, B_AV);   // the two list buffers may be reallocated
     if (c->budget) {
         const size_t room = c->budget > c->held ? c->budget - c->held + ctx_held(c, B_AA) + ctx_held(c, B_AV) : 0;
         if (room < avail) avail = room;
     }
-    const bool keep_av = avail >= 2 * list_bytes + later && !(c->flags & ESC_F_COMPACT_LISTS);
+    // a no-allocation call keeps the compact layout: its region is small
+    const bool keep_av = avail >= 2 * list_bytes + later && !(c->flags & ESC_F_COMPACT_LISTS) && !c->arena;
     if (!keep_av) ctx_release(c, B_AV);
     uint32_t *aa = (uint32_t *)ctx_buf(c, B_AA, list_bytes);
     int32_t *av = keep_av ? (int32_t *)ctx_buf(c, B_AV, list_bytes) : nullptr;

@@ -238,6 +238,14 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
         c->wheel_split_deg = p.wheel_split_deg;
         c->four_range_deg = p.four_range_deg;
     }
+    {
+        const char *ms = getenv("ESC_SLICE_MS");
+        long slice_ms = ms && ms[0] ? atol(ms) : (trace_on() ? 30000 : 0);
+        int khz = 0;
+        if (slice_ms > 0 &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0)
+            c->slice_ticks = (uint64_t)slice_ms * (uint64_t)khz;
+    }
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = (size_t)64 << 30;
     c->dev_mem = tot;
@@ -292,7 +300,7 @@ __global__ void k_fragments_out(int32_t n, const int32_t *rp, const int32_t *col
 // bracketed by events on the call's stream (see esc_last_profile).
 // ESC_TRACE=1 in the environment: after every stage, wait for it and print
 // its name and time to stderr (long runs report their progress).
-static bool trace_on() {
+bool trace_on() {
     static int on = -1;
     if (on < 0) {
         const char *e = getenv("ESC_TRACE");

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdio.h>
 #include "escape.h"
 
 // Indices of the exact 128-bit sums produced on the device.  Each stage adds
@@ -155,6 +156,9 @@ struct esc_ctx {
     // being allocated
     char *arena;
     size_t arena_size, arena_used;
+    // time slices of the per-source kernels (wall-clock ticks, 0 = none):
+    // ESC_SLICE_MS in the environment, or 30 s when ESC_TRACE is set
+    uint64_t slice_ticks;
 };
 
 // Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):
@@ -211,6 +215,34 @@ esc_status ctx_check(hipError_t e);
 
 #define ESC_TRY(x) do { esc_status _s = (x); if (_s != ESC_OK) return _s; } while (0)
 #define HIP_TRY(x) do { hipError_t _e = (x); if (_e != hipSuccess) return ESC_EDEVICE; } while (0)
+
+// ESC_TRACE=1 in the environment: stages and slices report to stderr
+bool trace_on();
+
+// A per-source kernel taking tasks from the shared counter `counter` (see
+// slice_grab): launch(ticks) enqueues one launch.  Without slices, one
+// launch with no limit.  With them, launches follow each other until a
+// workgroup has seen the counter run out (*done, zeroed here), each one
+// reporting its progress under ESC_TRACE, so that no launch runs much
+// longer than a slice.
+template <class Launch>
+esc_status run_sliced(esc_ctx *c, const char *name, int *done, const int *counter, Launch launch) {
+    if (c->slice_ticks == 0) return launch((uint64_t)0);
+    hipStream_t st = c->stream;
+    HIP_TRY(hipMemsetAsync(done, 0, sizeof(int), st));
+    for (int part = 1;; part++) {
+        ESC_TRY(launch(c->slice_ticks));
+        int h[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(&h[0], done, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&h[1], counter, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h[0]) return ESC_OK;
+        if (trace_on()) {
+            fprintf(stderr, "esc: %s slice %d ended, %d grabs taken\n", name, part, h[1]);
+            fflush(stderr);
+        }
+    }
+}
 
 // pipeline stages (each returns ESC_OK or an error)
 esc_status stage_orient(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col);

@@ -152,6 +152,22 @@ __device__ inline int64_t task_begin(int64_t g, int chunk) {
     return g < TASK_HEAD ? g * chunk : (int64_t)TASK_HEAD * chunk + (g - TASK_HEAD) * TASK_TAIL;
 }
 
+// Time slices of the per-source kernels.  A workgroup stops taking tasks
+// once the wall clock passes slice_end (ticks of wall_clock64; 0 = no
+// limit): the grab then returns GRAB_STOP, which maps past every task, so
+// the workgroup finishes the tasks it holds and leaves; a later launch goes
+// on from the shared counter.  A workgroup that sees the counter run out
+// (a real grab past the end) sets *done: every task has then been taken by
+// some workgroup of this launch, which completes it.
+#define GRAB_STOP (1 << 30)
+__device__ inline uint64_t slice_end_of(uint64_t slice_ticks) {
+    return slice_ticks ? wall_clock64() + slice_ticks : 0;
+}
+__device__ inline int slice_grab(int *task, uint64_t slice_end) {
+    if (slice_end && wall_clock64() > slice_end) return GRAB_STOP;
+    return atomicAdd(task, 1);
+}
+
 // Load-balanced expansion.  A batch of up to blockDim segments, thread t
 // describing segment t by (start, len); every element (segment s, position
 // start_s + r) is visited exactly once, spread evenly over the block.

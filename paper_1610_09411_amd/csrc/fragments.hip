@@ -360,9 +360,11 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                                                      int *task_big,
                                                      int chunk, GMap gm, int *task, int32_t slab,
                                                      int32_t range_deg, int32_t pw_words, unsigned long long *acc,
-                                                     unsigned long long *c4e, unsigned long long *visits) {
+                                                     unsigned long long *c4e, unsigned long long *visits,
+                                                     uint64_t slice_ticks, int *done) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
+    const uint64_t slice_end = slice_end_of(slice_ticks);
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_h, s_r, s_nt;
@@ -378,7 +380,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     // large tops: one key range per task, latest tops first
     for (;;) {
         if (threadIdx.x == 0) {
-            const int64_t u = nbig - 1 - atomicAdd(task_big, 1);
+            const int64_t u = nbig - 1 - slice_grab(task_big, slice_end);
             int32_t v = -1;
             if (u >= 0) {
                 v = town[u];
@@ -491,11 +493,15 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
         uint32_t *wt = sl + (size_t)wid * pw_words;
         int wgc = -1;   // graph of the wave's sums
         for (;;) {
-            if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
+            if (threadIdx.x == 0) s_h = slice_grab(task, slice_end);
             __syncthreads();
-            const int64_t t0 = (int64_t)s_h * chunk * nwv;
+            const int gi = s_h;
+            const int64_t t0 = (int64_t)gi * chunk * nwv;
             __syncthreads();   // s_h is read by every thread before it is taken again
-            if (t0 >= n) break;
+            if (t0 >= n) {
+                if (gi != GRAB_STOP && threadIdx.x == 0) *done = 1;
+                break;
+            }
             const int64_t t1 = t0 + (int64_t)chunk * nwv < n ? t0 + (int64_t)chunk * nwv : n;
             for (int64_t t = t0 + wid; t < t1; t += nwv) {
                 const int32_t h = n - 1 - (int32_t)t;
@@ -571,13 +577,17 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     // smaller tops: one per workgroup
     if (threadIdx.x == 0) s_nt = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
+        if (threadIdx.x == 0) s_h = slice_grab(task, slice_end);
         __syncthreads();
-        const int64_t t0 = task_begin(s_h, chunk), tn = task_begin((int64_t)s_h + 1, chunk);
+        const int gi = s_h;
+        const int64_t t0 = task_begin(gi, chunk), tn = task_begin((int64_t)gi + 1, chunk);
         // s_h is read by every thread before it is taken again: a chunk whose
         // tops are all skipped has no other barrier before the next take
         __syncthreads();
-        if (t0 >= n) break;
+        if (t0 >= n) {
+            if (gi != GRAB_STOP && threadIdx.x == 0) *done = 1;
+            break;
+        }
         const int32_t t1 = (int32_t)(tn < n ? tn : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {
             const int32_t h = n - 1 - t;
@@ -703,16 +713,16 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     int64_t nbig = 0;
     int32_t *town = nullptr;
     ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
-    k_four_cycles<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
-                                       n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
-                                       (const int32_t *)c->buf[B_SPLIT], (const int32_t *)c->buf[B_REV],
-                                       (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
-                                       tab, touch, c->tab_n, toff, town, nbig, task + 4, c->task_chunk, gmap_of(c),
-                                       task, slab, c->four_range_deg, pw_words,
-                                       (unsigned long long *)c->buf[B_ACC], c4e,
-                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2);
-    HIP_TRY(hipGetLastError());
-    return ESC_OK;
+    return run_sliced(c, "four_cycles", task + 8, task, [&](uint64_t ticks) -> esc_status {
+        k_four_cycles<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
+            n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
+            (const int32_t *)c->buf[B_REV], (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TARC],
+            tab, touch, c->tab_n, toff, town, nbig, task + 4, c->task_chunk, gmap_of(c), task, slab,
+            c->four_range_deg, pw_words, (unsigned long long *)c->buf[B_ACC], c4e,
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 2, ticks, task + 8);
+        HIP_TRY(hipGetLastError());
+        return ESC_OK;
+    });
 }
 
 // -------------------------------------------------------------- reductions

@@ -37,9 +37,10 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                                                   const int32_t *av, uint32_t *tab_all, int32_t *touch_all,
                                                   int32_t tab_n, int chunk, GMap gm, int *task, int32_t slab,
                                                   int32_t pw_words, unsigned long long *acc,
-                                                  unsigned long long *visits) {
+                                                  unsigned long long *visits, uint64_t slice_ticks, int *done) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
+    const uint64_t slice_end = slice_end_of(slice_ticks);
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_i, s_nt;
@@ -60,11 +61,15 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         int (*wrun)[64] = (int (*)[64])pref;   // per wave: inclusive entry counts of 64 arcs
         int wgc = -1;   // graph of the wave's sums
         for (;;) {
-            if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
+            if (threadIdx.x == 0) s_i = slice_grab(task, slice_end);
             __syncthreads();
-            const int64_t t0 = (int64_t)s_i * chunk * nwv;
+            const int gi = s_i;
+            const int64_t t0 = (int64_t)gi * chunk * nwv;
             __syncthreads();   // s_i is read by every thread before it is taken again
-            if (t0 >= n) break;
+            if (t0 >= n) {
+                if (gi != GRAB_STOP && threadIdx.x == 0) *done = 1;
+                break;
+            }
             const int64_t t1 = t0 + (int64_t)chunk * nwv < n ? t0 + (int64_t)chunk * nwv : n;
             for (int64_t t = t0 + wid; t < t1; t += nwv) {
                 const int32_t i = n - 1 - (int32_t)t;
@@ -174,13 +179,17 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
     }
     if (threadIdx.x == 0) s_nt = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
+        if (threadIdx.x == 0) s_i = slice_grab(task, slice_end);
         __syncthreads();
-        const int64_t t0 = task_begin(s_i, chunk), tn = task_begin((int64_t)s_i + 1, chunk);
+        const int gi = s_i;
+        const int64_t t0 = task_begin(gi, chunk), tn = task_begin((int64_t)gi + 1, chunk);
         // s_i is read by every thread before it is taken again: a chunk whose
         // sources are all skipped has no other barrier before the next take
         __syncthreads();
-        if (t0 >= n) break;
+        if (t0 >= n) {
+            if (gi != GRAB_STOP && threadIdx.x == 0) *done = 1;
+            break;
+        }
         const int32_t t1 = (int32_t)(tn < n ? tn : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t i = n - 1 - t;
@@ -336,8 +345,9 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                                                 int32_t lds_cap, const int64_t *toff, const int32_t *town,
                                                 int64_t nbig, int *task_big, int chunk, int32_t split_deg,
                                                 GMap gm, int *task, int tiny, unsigned long long *acc,
-                                                unsigned long long *visits) {
+                                                unsigned long long *visits, uint64_t slice_ticks, int *done) {
     uint64_t nvis = 0;
+    const uint64_t slice_end = slice_end_of(slice_ticks);
     extern __shared__ uint32_t dyn[];
     __shared__ int s_h, s_r, s_nt, s_ntw[WHEEL_WAVES];
     __shared__ u128 red[WHEEL_WAVES];   // one sum per wave (block_flush_u128)
@@ -357,7 +367,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     // large hubs: tasks of WHEEL_RIMS rim vertices
     for (;;) {
         if (threadIdx.x == 0) {
-            const int64_t u = nbig - 1 - atomicAdd(task_big, 1);
+            const int64_t u = nbig - 1 - slice_grab(task_big, slice_end);
             int32_t v = -1;
             if (u >= 0) {
                 v = town[u];
@@ -452,10 +462,14 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     u128 ts[1] = {0};   // tiny hubs: the wave's sums, for graph tg
     int tg = -1;
     for (;;) {
-        if (threadIdx.x == 0) s_h = atomicAdd(task, 1);
+        if (threadIdx.x == 0) s_h = slice_grab(task, slice_end);
         __syncthreads();
-        const int64_t t0 = task_begin(s_h, chunk), tn = task_begin((int64_t)s_h + 1, chunk);
-        if (t0 >= n) break;
+        const int gi = s_h;
+        const int64_t t0 = task_begin(gi, chunk), tn = task_begin((int64_t)gi + 1, chunk);
+        if (t0 >= n) {
+            if (gi != GRAB_STOP && threadIdx.x == 0) *done = 1;
+            break;
+        }
         const int32_t t1 = (int32_t)(tn < n ? tn : n);
         __syncthreads();   // s_h is read by every thread before it is taken again
         for (int32_t t = (int32_t)t0; t < t1; t++) {
@@ -595,9 +609,10 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                                                      int32_t *touchX_all, int32_t *touchW_all, int32_t tab_n,
                                                      int chunk, GMap gm, int *task, int32_t slab,
                                                      int32_t pw_words, unsigned long long *acc,
-                                                     unsigned long long *visits) {
+                                                     unsigned long long *visits, uint64_t slice_ticks, int *done) {
     extern __shared__ uint32_t dyn[];   // [0, xslab) X, [xslab, 2 slab) Wnt or Y
     uint64_t nvis = 0;
+    const uint64_t slice_end = slice_end_of(slice_ticks);
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
     __shared__ int s_i, s_nx, s_nw;
@@ -627,11 +642,15 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
         int32_t *wse = pref + wid * 64;
         int wgc = -1;   // graph of the wave's sums
         for (;;) {
-            if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
+            if (threadIdx.x == 0) s_i = slice_grab(task, slice_end);
             __syncthreads();
-            const int64_t t0 = (int64_t)s_i * chunk * nwv;
+            const int gi = s_i;
+            const int64_t t0 = (int64_t)gi * chunk * nwv;
             __syncthreads();   // s_i is read by every thread before it is taken again
-            if (t0 >= n) break;
+            if (t0 >= n) {
+                if (gi != GRAB_STOP && threadIdx.x == 0) *done = 1;
+                break;
+            }
             const int64_t t1 = t0 + (int64_t)chunk * nwv < n ? t0 + (int64_t)chunk * nwv : n;
             for (int64_t t = t0 + wid; t < t1; t += nwv) {
                 const int32_t i = n - 1 - (int32_t)t;
@@ -725,11 +744,15 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     for (int q = threadIdx.x; q < 2 * slab; q += blockDim.x) dyn[q] = 0;
     if (threadIdx.x == 0) { s_nx = 0; s_nw = 0; }
     for (;;) {
-        if (threadIdx.x == 0) s_i = atomicAdd(task, 1);
+        if (threadIdx.x == 0) s_i = slice_grab(task, slice_end);
         __syncthreads();
-        const int64_t t0 = task_begin(s_i, chunk), tn = task_begin((int64_t)s_i + 1, chunk);
+        const int gi = s_i;
+        const int64_t t0 = task_begin(gi, chunk), tn = task_begin((int64_t)gi + 1, chunk);
         __syncthreads();   // s_i is read by every thread before it is taken again
-        if (t0 >= n) break;
+        if (t0 >= n) {
+            if (gi != GRAB_STOP && threadIdx.x == 0) *done = 1;
+            break;
+        }
         const int32_t t1 = (int32_t)(tn < n ? tn : n);
         for (int32_t t = (int32_t)t0; t < t1; t++) {
         const int32_t i = n - 1 - t;
@@ -965,15 +988,15 @@ esc_status stage_pairs(esc_ctx *c) {
     const int32_t pw_words = c->G && c->tab_n <= 4096 && c->narcs_apex < ((int64_t)1 << 40) ? (c->tab_n + 1) / 2 : 0;
     const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
     auto kern = c->av ? k_pairs_wd<true> : k_pairs_wd<false>;
-    kern<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
-                                          n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
-                                          (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
-                                          (const uint32_t *)c->buf[B_AA], c->av, tab, touch,
-                                          c->tab_n, c->task_chunk, gmap_of(c), task, slab, pw_words,
-                                          (unsigned long long *)c->buf[B_ACC],
-                                          (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6);
-    HIP_TRY(hipGetLastError());
-    return ESC_OK;
+    return run_sliced(c, "pairs_13_17", task + 8, task, [&](uint64_t ticks) -> esc_status {
+        kern<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
+            n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_REV],
+            (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av, tab, touch, c->tab_n,
+            c->task_chunk, gmap_of(c), task, slab, pw_words, (unsigned long long *)c->buf[B_ACC],
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6, ticks, task + 8);
+        HIP_TRY(hipGetLastError());
+        return ESC_OK;
+    });
 }
 
 esc_status stage_wheels(esc_ctx *c) {
@@ -1019,13 +1042,15 @@ esc_status stage_wheels(esc_ctx *c) {
     int32_t *town = nullptr;
     ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
     auto kern = c->av ? k_wheels<true> : k_wheels<false>;
-    kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
-                                              (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA],
-                                              c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
-                                              c->task_chunk, c->wheel_split_deg, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
-                                              (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7);
-    HIP_TRY(hipGetLastError());
-    return ESC_OK;
+    return run_sliced(c, "wheels", task + 8, task + 1, [&](uint64_t ticks) -> esc_status {
+        kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(
+            n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int64_t *)c->buf[B_AOFF],
+            (const uint32_t *)c->buf[B_AA], c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
+            c->task_chunk, c->wheel_split_deg, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7, ticks, task + 8);
+        HIP_TRY(hipGetLastError());
+        return ESC_OK;
+    });
 }
 
 esc_status stage_cycles(esc_ctx *c) {
@@ -1052,12 +1077,13 @@ esc_status stage_cycles(esc_ctx *c) {
     auto kern = c->G ? k_five_cycles<false, false>
                      : (c->maxdeg < 65536 && c->five_order == 0 ? k_five_cycles<true, true>
                                                                  : k_five_cycles<true, false>);
-    kern<<<nwg, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
-                                       n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
-                                       (const int32_t *)c->buf[B_SPLIT], tab, tab + (size_t)c->tab_n * nwg, touch,
-                                       touch + (size_t)c->tab_n * nwg, c->tab_n, c->task_chunk, gmap_of(c),
-                                       task + 2, slab, pw_words, (unsigned long long *)c->buf[B_ACC],
-                                       (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 8);
-    HIP_TRY(hipGetLastError());
-    return ESC_OK;
+    return run_sliced(c, "five_cycles", task + 8, task + 2, [&](uint64_t ticks) -> esc_status {
+        kern<<<nwg, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
+            n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT], tab,
+            tab + (size_t)c->tab_n * nwg, touch, touch + (size_t)c->tab_n * nwg, c->tab_n, c->task_chunk,
+            gmap_of(c), task + 2, slab, pw_words, (unsigned long long *)c->buf[B_ACC],
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 8, ticks, task + 8);
+        HIP_TRY(hipGetLastError());
+        return ESC_OK;
+    });
 }

@@ -403,3 +403,26 @@ def test_five_cliques_through_the_complement(ctx):
             finally:
                 ctx.set_params(None)
             assert got == want, (g.name, pct)
+
+
+def test_time_sliced_launches_give_same_counts():
+    """Per-source kernels launched in 2 ms slices (ESC_SLICE_MS, read when
+    the context is created): each stage is relaunched from its task counter
+    until every task is taken; counts equal the oracle's."""
+    import paper_1610_09411_amd as esc
+    g = synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2)
+    want = oracle.count(g, 5, threads=8)
+    os.environ["ESC_SLICE_MS"] = "2"
+    try:
+        c = esc.Context(0)
+    finally:
+        del os.environ["ESC_SLICE_MS"]
+    try:
+        assert c.count(g, 5) == want
+        assert c.count(g, 4) == want[:11]
+        batch = [synth.from_spec(s) for s in synth.batch_specs(30, 5)]
+        rows, _ = c.count_batched(batch, 5)
+        for i in (0, 11, 29):
+            assert [int(x) for x in rows[i]] == oracle.count(batch[i], 5), i
+    finally:
+        c.close()

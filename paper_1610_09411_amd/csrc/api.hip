@@ -77,11 +77,13 @@ esc_status ctx_free_bytes(esc_ctx *c, size_t *out) {
 
 // Per-source kernels run up to three workgroups per CU (more resident waves
 // for their latency-bound gathers), fewer when their dense tables (two tables
-// and two touched lists of tab_n entries each) would pass a tenth of the
-// device: wg_cap.  The parameters proper are chosen after the degree order.
+// and two touched lists of tab_n entries each) would pass an eighth of the
+// device: wg_cap (two per CU for a 4M-vertex graph, 33 GB of tables beside
+// its 221 GB of triangle lists).  The parameters proper are chosen after the
+// degree order.
 static void set_pair_wgs(esc_ctx *c) {
     c->wg_cap = 3;
-    while (c->wg_cap > 1 && 16 * (size_t)c->tab_n * (size_t)(c->wg_cap * c->num_cu) > c->dev_mem / 10) c->wg_cap--;
+    while (c->wg_cap > 1 && 16 * (size_t)c->tab_n * (size_t)(c->wg_cap * c->num_cu) > c->dev_mem / 8) c->wg_cap--;
     c->wg_per_cu = c->wg_cap;
 }
 

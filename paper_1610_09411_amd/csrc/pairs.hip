@@ -310,19 +310,22 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 // the triangle list of arc (h,i) below i, j over the triangle list of arc
 // (h,l) below i; key = position of j in the row of h, and C(count,2) summed
 // over keys counts the rim 4-cycles with latest vertex i (summed as the
-// count before each increment).  The table lives in
-// LDS when d(h) fits, else in the workgroup's global scratch.  In LDS a count
-// is below d(h) <= lds_cap < 2^16, so two counts share a word (16 bits each;
-// one 32-bit atomic adds 1 << 16 for odd keys) and the touched keys are
-// 16-bit.
+// count before each increment).  Counts live in LDS: a count is below d(h),
+// so two share a word when d(h) < 2^16 (16 bits each; one 32-bit atomic
+// adds 1 << 16 for odd keys), else one count per word.
 //
-// Hubs with d(h) > wq = lds_cap / (waves per workgroup) come first, those above
-// split_deg split into tasks of WHEEL_RIMS rim vertices, the others one
-// task each (task offsets per hub in toff, latest hubs first):
-// every workgroup of the chip works on the same few hubs at a time, so their
-// triangle lists, re-read for every rim vertex, stay in each XCD's L2.  The
-// smaller hubs follow, one per workgroup, each wave taking its own rim
-// vertices with its own table and no workgroup barrier per rim vertex.
+// Hubs with d(h) > wq (the largest hub of the per-wave mode) come first as
+// tasks of (a block of rim vertices, a range of keys): blocks of WHEEL_RIMS
+// rim vertices above split_deg neighbours (else all of them), key ranges of
+// `wk` keys (wk / 2 for 32-bit counts), so every table fits the LDS of a
+// workgroup whatever d(h).  A task reads from each list of (h,l) only the run
+// of keys in its range below i (the lists are sorted by position in the row
+// of h: two binary searches find it).  Tasks are numbered per hub in toff,
+// latest hubs first: every workgroup of the chip works on the same few hubs
+// at a time, so their triangle lists, re-read for every rim vertex, stay in
+// each XCD's L2.  The smaller hubs follow, one per workgroup, each wave
+// taking its own rim vertices with its own table and no workgroup barrier
+// per rim vertex.
 #define WHEEL_WAVES 8          // most waves per workgroup of the wheel pass (a launch may use fewer)
 #define WHEEL_RIMS 16          // rim vertices per task of a large hub
 #define WHEEL_TINY 32          // batches: hubs up to this degree are taken whole by one wave
@@ -330,26 +333,30 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
 
 // rim vertices per task of hub with d neighbours: all of them up to split_deg
 __device__ inline int32_t wheel_rims(int32_t d, int32_t split_deg) { return d > split_deg ? WHEEL_RIMS : d; }
+// keys per range of a hub with d neighbours (16-bit counts below 2^16)
+__device__ inline int32_t wheel_keys(int32_t d, int32_t wk) { return d < 65536 ? wk : wk / 2; }
 
-__global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int32_t split_deg, int64_t *len) {
+__global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int32_t split_deg, int32_t wk,
+                              int64_t *len) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t d = off[v + 1] - off[v];
-        len[v] = d > wq ? (d + wheel_rims(d, split_deg) - 1) / wheel_rims(d, split_deg) : 0;
+        const int64_t nr = (d + wheel_rims(d, split_deg) - 1) / wheel_rims(d, split_deg);
+        const int64_t nk = (d + wheel_keys(d, wk) - 1) / wheel_keys(d, wk);
+        len[v] = d > wq ? nr * nk : 0;
     }
 }
 
 template <bool IDS>
 __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
-                                                uint32_t *gtab_all, int32_t *gtouch_all, int32_t tab_n,
-                                                int32_t lds_cap, const int64_t *toff, const int32_t *town,
+                                                int32_t wq, int32_t wk, const int64_t *toff, const int32_t *town,
                                                 int64_t nbig, int *task_big, int chunk, int32_t split_deg,
                                                 GMap gm, int *task, int tiny, unsigned long long *acc,
                                                 unsigned long long *visits, uint64_t slice_ticks, int *done) {
     uint64_t nvis = 0;
     const uint64_t slice_end = slice_end_of(slice_ticks);
     extern __shared__ uint32_t dyn[];
-    __shared__ int s_h, s_r, s_nt, s_ntw[WHEEL_WAVES];
+    __shared__ int s_h, s_r, s_ntw[WHEEL_WAVES];
     __shared__ u128 red[WHEEL_WAVES];   // one sum per wave (block_flush_u128)
     __shared__ int64_t wsa[WHEEL_WAVES][64];
     __shared__ int32_t wse[WHEEL_WAVES][64], wsi[WHEEL_WAVES][64];
@@ -358,11 +365,10 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     u128 s18[1] = {0};
     int gcur = -1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int32_t wq = lds_cap / nw;   // largest d(h) of the one-wave-per-rim-vertex mode
-    uint32_t *gcnt = gtab_all + (size_t)blockIdx.x * tab_n;
-    int32_t *gtch = gtouch_all + (size_t)blockIdx.x * tab_n;
-    uint32_t *lcnt = dyn;                                        // (lds_cap + 1) / 2 words
-    uint16_t *ltch = (uint16_t *)(dyn + (lds_cap + 1) / 2);      // lds_cap keys
+    uint32_t *lcnt = dyn;   // wk / 2 words: the key range of a large-hub task
+    // zero at the start; every rim vertex leaves the table zero again
+    for (int q = threadIdx.x; q < wk / 2; q += blockDim.x) lcnt[q] = 0;
+    __syncthreads();
 
     // large hubs: tasks of WHEEL_RIMS rim vertices
     for (;;) {
@@ -382,72 +388,63 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
         if (h < 0) break;
         block_switch_graph<1>(s18, gcur, gm.graph(h), red, acc, ACC_STRIDE, ids);
         const int32_t oh = off[h], dh = off[h + 1] - oh;
-        const bool in_lds = dh <= lds_cap;
-        const int32_t rims = wheel_rims(dh, split_deg);
-        const int32_t r0 = rtask * rims;
+        const int32_t rims = wheel_rims(dh, split_deg), kr = wheel_keys(dh, wk);
+        const int32_t nk = (dh + kr - 1) / kr;
+        const int32_t r0 = (rtask / nk) * rims;
         const int32_t r1 = r0 + rims < dh ? r0 + rims : dh;
-        if (in_lds)
-            for (int q = threadIdx.x; q < (dh + 1) / 2; q += blockDim.x) lcnt[q] = 0;
-        __syncthreads();
+        const int32_t k0 = (rtask % nk) * kr;   // keys [k0, k0 + kr) of this task
+        const bool wide = dh >= 65536;          // 32-bit counts
         for (int32_t pi = oh + r0; pi < oh + r1; pi++) {
-            const int32_t i = adj[pi];
+            const int32_t ip = pi - oh;         // position of i: its keys lie below it
+            if (ip <= k0) continue;
+            const int32_t k1 = ip < k0 + kr ? ip : k0 + kr;
             const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
             if (l1 - l0 < 2) continue;   // a rim 4-cycle needs two triangles on (h,i)
-            // entries l of list(h,i) below i
+            // entries l of list(h,i) below i (positions below ip)
             int64_t lo = l0, hi = l1;
-            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
+            while (lo < hi) { int64_t mid = (lo + hi) >> 1; if ((int32_t)aa[mid] - oh < ip) lo = mid + 1; else hi = mid; }
             const int nl = (int)(lo - l0);
             if (nl == 0) continue;
-            if (threadIdx.x == 0) s_nt = 0;
-            __syncthreads();
-            // each wave takes entries l; its lanes stride over the list of (h,l) below i
+            // each wave takes entries l; its lanes stride over the run of
+            // the list of (h,l) with keys in [k0, k1)
             for (int xb = 0; xb < nl; xb += nw * 64) {
-                // each lane finds one segment: the list of (h,l) below i;
-                // entries are dealt to the waves in turn, so a short list
-                // of l still keeps every wave busy
+                // each lane finds one segment; entries are dealt to the
+                // waves in turn, so a short list of l still keeps every
+                // wave busy
                 const int x = xb + lane * nw + wid;
                 int64_t b0 = 0, b1 = 0;
                 if (x < nl) {
                     const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
-                    b0 = aoff[qhl];
-                    int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                    while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
+                    int64_t e0 = aoff[qhl], e1 = aoff[qhl + 1];
+                    if (k0 > 0) {
+                        int64_t hi2 = e1;
+                        while (e0 < hi2) { int64_t mid = (e0 + hi2) >> 1; if ((int32_t)aa[mid] - oh < k0) e0 = mid + 1; else hi2 = mid; }
+                    }
+                    b0 = e0;
+                    int64_t lo2 = e0;
+                    while (lo2 < e1) { int64_t mid = (lo2 + e1) >> 1; if ((int32_t)aa[mid] - oh < k1) lo2 = mid + 1; else e1 = mid; }
                     b1 = lo2;
                 }
                 nvis += (uint64_t)(b1 - b0);
                 // sum over keys of C(count,2) = sum over increments of the
                 // count before it
                 uint64_t olds = 0;
-                if (in_lds)
+                if (!wide)
                     wave_walk_act(b0, b1, wsa[wid], wse[wid], wsi[wid],
-                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh - k0; },
                                   [&](int32_t key) { return atomicAdd(&lcnt[key >> 1], 1u << ((key & 1) << 4)); },
-                                  [&](int32_t key, uint32_t old) {
-                                      const uint32_t c = (old >> ((key & 1) << 4)) & 0xFFFFu;
-                                      olds += c;
-                                      if (c == 0) ltch[atomicAdd(&s_nt, 1)] = (uint16_t)key;
-                                  });
+                                  [&](int32_t key, uint32_t old) { olds += (old >> ((key & 1) << 4)) & 0xFFFFu; });
                 else
                     wave_walk_act(b0, b1, wsa[wid], wse[wid], wsi[wid],
-                                  [&](int64_t q) { return (int32_t)aa[q] - oh; },
-                                  [&](int32_t key) { return atomicAdd(&gcnt[key], 1u); },
-                                  [&](int32_t key, uint32_t old) {
-                                      olds += old;
-                                      if (old == 0) gtch[atomicAdd(&s_nt, 1)] = key;
-                                  });
+                                  [&](int64_t q) { return (int32_t)aa[q] - oh - k0; },
+                                  [&](int32_t key) { return atomicAdd(&lcnt[key], 1u); },
+                                  [&](int32_t, uint32_t old) { olds += old; });
                 s18[0] += olds;
             }
             __syncthreads();
-            // tables back to zero
-            const int nt = s_nt;
-            for (int q = threadIdx.x; q < nt; q += blockDim.x) {
-                if (in_lds) {
-                    const int32_t key = ltch[q];
-                    atomicAnd(&lcnt[key >> 1], ~(0xFFFFu << ((key & 1) << 4)));   // the other half may be reset concurrently
-                } else {
-                    gcnt[gtch[q]] = 0;
-                }
-            }
+            // the table back to zero: every key touched lies in [k0, k1)
+            const int32_t words = wide ? k1 - k0 : (k1 - k0 + 1) / 2;
+            for (int q = threadIdx.x; q < words; q += blockDim.x) lcnt[q] = 0;
             __syncthreads();
         }
     }
@@ -1003,39 +1000,34 @@ esc_status stage_wheels(esc_ctx *c) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
     if (n == 0 || c->narcs_apex == 0) return ESC_OK;
-    uint32_t *tab;
-    int32_t *touch;
-    int *task;
-    ESC_TRY(pair_scratch(c, &tab, &touch, &task));
-    // 16-bit counts and touched keys in LDS, two workgroups per CU, leaving
-    // room for the kernel's static arrays
-    int lds_cap = (c->max_lds / 2 - 8192) / 4;
-    if (lds_cap > 32768) lds_cap = 32768;
-    if (c->maxdeg + 1 < lds_cap) lds_cap = c->maxdeg + 1;
-    size_t lds = sizeof(uint32_t) * ((size_t)(lds_cap + 1) / 2) + sizeof(uint16_t) * (size_t)lds_cap + 16;
     // eight waves per workgroup for one graph; four for a batch of small
     // graphs, whose hubs have few rim vertices to share among the waves
     const int waves = c->G ? 4 : WHEEL_WAVES;
-    size_t lds_waves = sizeof(uint32_t) * waves * 2 * (size_t)((lds_cap / waves + 1) / 2) + 16;   // one-wave tables
+    // The kernel holds four waves per SIMD (its registers), so two 8-wave
+    // workgroups per CU: each gets half the CU's LDS less its static arrays
+    // (10 KB) for its tables.  Large-hub tasks: wk 16-bit counts (a range
+    // of keys); per-wave mode: a table and a touched list of (wq + 1) / 2
+    // words each per wave, wq the largest hub it takes.
+    const int32_t words = (int32_t)(((size_t)c->max_lds / 2 - 12288) / 4) & ~63;
+    const int32_t wk = 2 * words;
+    int32_t wq = words / waves;   // 2 * ((wq + 1) / 2) words per wave
+    if (wq > 4096) wq = 4096;
+    size_t lds = sizeof(uint32_t) * (size_t)words;
     // hubs of at most WHEEL_TINY neighbours are taken whole, one per wave,
     // in the wave's one-wave table when it holds WHEEL_TINY_WORDS words,
-    // else in tables after those (a batch of small graphs: workgroups per
-    // CU stay at their cap)
+    // else in tables after those (a batch of small graphs)
     const int tiny = WHEEL_TINY;
-    if (2 * ((lds_cap / waves + 1) / 2) < WHEEL_TINY_WORDS) lds_waves += sizeof(uint32_t) * waves * (size_t)WHEEL_TINY_WORDS;
-    if (lds_waves > lds) lds = lds_waves;
-    // as many workgroups per CU as LDS holds: the walk is bound by
-    // load latency, so resident waves matter; the global tables have room
-    // for 2 * wg_per_cu per CU
+    if (2 * ((wq + 1) / 2) < WHEEL_TINY_WORDS) lds += sizeof(uint32_t) * waves * (size_t)WHEEL_TINY_WORDS;
     int per_cu = (int)(c->max_lds / (lds + 10240));
-    if (per_cu > 2 * c->wg_per_cu) per_cu = 2 * c->wg_per_cu;
+    if (per_cu > 4) per_cu = 4;
     if (per_cu < 1) per_cu = 1;
-    // tasks of the hubs with more than lds_cap / waves neighbours
+    int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
+    // tasks of the hubs with more than wq neighbours
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
-    if (!len || !toff) return ESC_ENOMEM;
-    k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], lds_cap / waves,
-                                                       c->wheel_split_deg, len);
+    if (!len || !toff || !task) return ESC_ENOMEM;
+    k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], wq, c->wheel_split_deg, wk,
+                                                       len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     int64_t nbig = 0;
@@ -1045,7 +1037,7 @@ esc_status stage_wheels(esc_ctx *c) {
     return run_sliced(c, "wheels", task + 8, task + 1, [&](uint64_t ticks) -> esc_status {
         kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(
             n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int64_t *)c->buf[B_AOFF],
-            (const uint32_t *)c->buf[B_AA], c->av, tab, touch, c->tab_n, lds_cap, toff, town, nbig, task + 4,
+            (const uint32_t *)c->buf[B_AA], c->av, wq, wk, toff, town, nbig, task + 4,
             c->task_chunk, c->wheel_split_deg, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
             (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7, ticks, task + 8);
         HIP_TRY(hipGetLastError());

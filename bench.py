@@ -7,9 +7,16 @@ sums, the pattern 13/17 and wheel pair passes, 5-cycles and the final exact
 linear map; the 45 counts end on the host.  The CSR is resident in HBM when
 the timed region starts.
 
-Workload: Chung-Lu power-law graph, n = 1e6, exponent 2.1, mean degree 20,
-max expected degree 1e4 (seed 0, ~1e7 edges), standing in for the paper's
-web/social/technology graphs.  value = undirected edges / second.
+Headline workload: the largest single-GPU graph, Chung-Lu n = 4e6, exponent
+1.9, mean degree 40, max expected degree 5e4 (seed 0, 7.65e7 edges, a
+near-clique core of some 1.4e3 hubs), standing in for the paper's
+web/social/technology graphs; value = undirected edges / second.  One call
+takes minutes, so this leg times min(--steps, --headline-steps) calls with
+--headline-warmup warm-up calls before them (the line reports both the
+requested and the timed numbers); the library prints each stage as it ends
+(ESC_TRACE).  The 1M-vertex graph (exponent 2.1, mean degree 20, max expected
+degree 1e4) runs the full --steps / --warmup under the key "chung_lu_1m",
+beside the batched and serving workloads.
 
 Prints one JSON line (see the keys below).  --gpus above 1 is refused: this
 build runs on one GPU.
@@ -26,7 +33,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_VISIT = 4     # one int32 neighbour / triangle-list entry per visited element
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chung_lu_1m.json")
+TRAFFIC_FILES = {"chung_lu_4m": os.path.join(ROOT, "profiles", "traffic_chung_lu_4m.json"),
+                 "chung_lu_1m": os.path.join(ROOT, "profiles", "traffic_chung_lu_1m.json")}
 
 
 def kernel_sources_sha(source_file):
@@ -41,12 +49,12 @@ def kernel_sources_sha(source_file):
     return h.hexdigest()
 
 
-def measured_traffic(stage):
+def measured_traffic(workload, stage):
     """HBM bytes per launch of a stage's kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None when that kernel's sources have
-    changed since it was taken (or the summary does not cover the stage)."""
+    FETCH_SIZE/WRITE_SIZE summary of the workload, or None when that kernel's
+    sources have changed since it was taken (or no summary covers it)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[workload]) as f:
             t = json.load(f)
         e = t["stages"][stage]
         if e["sources_sha256"] != kernel_sources_sha(e["source_file"]):
@@ -60,12 +68,19 @@ def measured_traffic(stage):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--headline-steps", type=int, default=1,
+                    help="timed calls on the 4M-vertex graph at most (each takes minutes)")
+    ap.add_argument("--headline-warmup", type=int, default=0,
+                    help="warm-up calls on the 4M-vertex graph (0: buffer allocation is inside the timed call)")
+    ap.add_argument("--headline", choices=["chung_lu_4m", "chung_lu_1m"], default="chung_lu_4m")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="oracle timing sample: 1/N of sources and edges (0 = skip the CPU leg)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-one-thread", type=int, default=0,
+                    help="also time the oracle on one thread (about 150 s more: its setup stage alone takes 2 min)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--batched", type=int, default=1,
@@ -110,52 +125,39 @@ def main():
         ctx.close()
         return
 
-    g = synth.chung_lu_1m(args.seed)
-    n, m = g.n, g.m
+    # the headline context reports every stage as it ends (a call on the 4M
+    # graph takes minutes), one launch per stage so the per-launch roofline
+    # figures hold
+    os.environ["ESC_TRACE"] = "1"
+    os.environ["ESC_SLICE_MS"] = "0"
+    ctx_h = esc.Context(0)
+    del os.environ["ESC_TRACE"]
+    del os.environ["ESC_SLICE_MS"]
+    ctx = esc.Context(0)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    rp = torch.from_numpy(g.row_ptr).to(dev)
-    col = torch.from_numpy(g.col).to(dev)
-    ctx = esc.Context(0)
     stream = torch.cuda.current_stream(dev)
 
-    counts = None
-    for _ in range(args.warmup):
-        counts = esc.esc_count_subgraphs(ctx.ptr, n, rp, col, 5, stream=stream)
-    prof_sum = {k: [0.0, 0] for k in esc.STAGES}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        counts = esc.esc_count_subgraphs(ctx.ptr, n, rp, col, 5, stream=stream)
-        for k, (ms, vis) in esc.esc_last_profile(ctx.ptr).items():
-            prof_sum[k][0] += ms
-            prof_sum[k][1] += vis
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    value = m / (ms_per_step / 1000.0)
-    work = esc.esc_last_work(ctx.ptr)
+    big = args.headline == "chung_lu_4m"
+    g = synth.chung_lu_4m(args.seed) if big else synth.chung_lu_1m(args.seed)
+    print("headline graph n=%d m=%d generated" % (g.n, g.m), file=sys.stderr, flush=True)
+    h_steps = min(args.steps, args.headline_steps) if big else args.steps
+    h_warm = min(args.warmup, args.headline_warmup) if big else args.warmup
+    head = run_single(esc, ctx_h if big else ctx, torch, g, args.headline, h_steps, h_warm, stream)
+    head_g = g
+    ctx_h.close()
+    del g
 
-    # dominant kernel: the stage with the largest device time (each heavy stage
-    # is a single kernel launch, bracketed by HIP events on the call's stream)
-    prof = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in prof_sum.items()}
-    dom = max(prof, key=lambda k: prof[k][0])
-    dom_ms, dom_vis = prof[dom]
-    achieved = dom_vis * BYTES_PER_VISIT / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
-    tbytes = measured_traffic(dom)
-    traffic = tbytes / (dom_ms / 1000.0) / 1e9 if (tbytes is not None and dom_ms > 0) else None
+    small = None
+    if big:
+        g1 = synth.chung_lu_1m(args.seed)
+        small = run_single(esc, ctx, torch, g1, "chung_lu_1m", args.steps, args.warmup, stream)
+    else:
+        g1 = head_g
 
     cpu = None
     if rank == 0 and args.cpu_sample > 0:
-        import oracle
-        threads = args.cpu_threads or len(os.sched_getaffinity(0))
-        setup_s, sampled_s = oracle.timed_sample(g, 5, args.cpu_sample, threads)
-        est = setup_s + sampled_s * args.cpu_sample
-        cpu = {"value": m / est, "unit": "edges/s", "cores": threads, "kind": "oracle",
-               "sample": "same graph; degree order, triangle stage and triangle lists in full "
-                         "(%.1f s), every later per-source/per-edge loop on 1/%d of the ids "
-                         "(%.1f s, scaled x%d); estimated whole-job %.0f s"
-                         % (setup_s, args.cpu_sample, sampled_s, args.cpu_sample, est)}
+        cpu = cpu_baseline(g1, args.cpu_sample, args.cpu_threads, args.cpu_one_thread)
 
     batched = None
     if args.batched:
@@ -169,35 +171,126 @@ def main():
 
     line = {
         "metric": "edges/sec for all induced 4+5-vertex counts (bit-exact)",
-        "value": value,
+        "value": head["value"],
         "unit": "edges/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "steps": h_steps,
+        "warmup": h_warm,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "chung_lu n=1000000 gamma=2.1 mean_degree=20 max_expected_degree=10000 seed=%d"
-                               % args.seed, "n": n, "m": m, "k": 5, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": tbytes,
-                     "algorithmic_bytes_per_launch": dom_vis * BYTES_PER_VISIT},
+        "config": head["config"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "stages_ms": {k: round(v[0], 3) for k, v in prof.items()},
-        "stages_visits": {k: int(v[1]) for k, v in prof.items()},
-        "work": work,
-        "launch_params": ctx.last_params(),
-        "checksum": {"sum_5": str(sum(counts[11:])), "p8_5cycles": str(counts[11 + 7]),
-                     "p21_5cliques": str(counts[31])},
+        "stages_ms": head["stages_ms"],
+        "stages_visits": head["stages_visits"],
+        "work": head["work"],
+        "launch_params": head["launch_params"],
+        "checksum": head["checksum"],
+        "chung_lu_1m": small,
         "batched": batched,
         "serving": serving,
     }
     if rank == 0:
         print(json.dumps(line), flush=True)
     ctx.close()
+
+
+WORKLOADS = {
+    "chung_lu_4m": "chung_lu n=4000000 gamma=1.9 mean_degree=40 max_expected_degree=50000 seed=%d",
+    "chung_lu_1m": "chung_lu n=1000000 gamma=2.1 mean_degree=20 max_expected_degree=10000 seed=%d",
+}
+
+
+def run_single(esc, ctx, torch, g, name, steps, warmup, stream, seed=0):
+    """`warmup` untimed then `steps` timed k = 5 calls on graph g (CSR resident
+    on the device); per-stage device times and visits averaged over the timed
+    calls; the roofline of the stage with the largest device time (each heavy
+    stage is one kernel launch, bracketed by HIP events on the call's stream)."""
+    n, m = g.n, g.m
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    counts = None
+    for _ in range(warmup):
+        counts = esc.esc_count_subgraphs(ctx.ptr, n, rp, col, 5, stream=stream)
+    prof_sum = {k: [0.0, 0] for k in esc.STAGES}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        counts = esc.esc_count_subgraphs(ctx.ptr, n, rp, col, 5, stream=stream)
+        for k, (ms, vis) in esc.esc_last_profile(ctx.ptr).items():
+            prof_sum[k][0] += ms
+            prof_sum[k][1] += vis
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / steps
+    prof = {k: (v[0] / steps, v[1] / steps) for k, v in prof_sum.items()}
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_vis = prof[dom]
+    achieved = dom_vis * BYTES_PER_VISIT / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
+    tbytes = measured_traffic(name, dom)
+    traffic = tbytes / (dom_ms / 1000.0) / 1e9 if (tbytes is not None and dom_ms > 0) else None
+    del rp, col
+    return {"value": m / (ms_per_step / 1000.0), "ms_per_step": ms_per_step, "steps": steps, "warmup": warmup,
+            "config": {"workload": WORKLOADS[name] % seed, "n": n, "m": m, "k": 5, "parallelism": "single GPU"},
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": tbytes,
+                         "algorithmic_bytes_per_launch": dom_vis * BYTES_PER_VISIT},
+            "stages_ms": {k: round(v[0], 3) for k, v in prof.items()},
+            "stages_visits": {k: int(v[1]) for k, v in prof.items()},
+            "work": esc.esc_last_work(ctx.ptr),
+            "launch_params": ctx.last_params(),
+            "checksum": {"sum_4": str(sum(counts[:11])), "sum_5": str(sum(counts[11:])),
+                         "p8_5cycles": str(counts[11 + 7]), "p21_5cliques": str(counts[31])}}
+
+
+def cpu_baseline(g, sample, threads, one_thread):
+    """The oracle on the host cores, timed on a bounded sample of the 1M-vertex
+    graph's job (its per-edge triangle lists for the 4M-vertex graph, 12 B x
+    2.8e10 entries, do not fit host memory): degree order, triangle stage and
+    triangle lists in full, every later per-source / per-edge loop on 1/sample
+    of the ids (two sample offsets, their spread reported); with one_thread,
+    also on one thread at 4x the sampling."""
+    import platform
+    import oracle
+    threads = threads or len(os.sched_getaffinity(0))
+    runs = []
+    for off in (0, sample // 2):
+        setup_s, sampled_s = oracle.timed_sample(g, 5, sample, threads, off)
+        runs.append((setup_s, sampled_s))
+    est = [s + x * sample for s, x in runs]
+    mean = sum(est) / len(est)
+    one = None
+    if one_thread:
+        s1 = 4 * sample
+        setup1, sampled1 = oracle.timed_sample(g, 5, s1, 1, 0)
+        est1 = setup1 + sampled1 * s1
+        one = {"value": g.m / est1, "setup_s": setup1, "sampled_s": sampled1, "sample": s1, "estimated_s": est1}
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        cpu_model = platform.processor()
+    return {"value": g.m / mean, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model,
+            "workload": "chung_lu n=1000000 gamma=2.1 mean_degree=20 max_expected_degree=10000 (the oracle "
+                        "cannot hold the 4M-vertex graph's triangle lists in host memory)",
+            "sample": "degree order, triangle stage and triangle lists in full (%.1f s), every later "
+                      "per-source/per-edge loop on 1/%d of the ids at offsets 0 and %d (%.1f s, %.1f s, scaled "
+                      "x%d); estimated whole job %.0f s and %.0f s"
+                      % (runs[0][0], sample, sample // 2, runs[0][1], runs[1][1], sample, est[0], est[1]),
+            "spread": abs(est[0] - est[1]) / mean,
+            "one_thread": one}
 
 
 def bench_batched(esc, ctx, synth, torch, stream, steps, seed, plain_sample):

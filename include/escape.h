@@ -84,7 +84,13 @@ enum {
 
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
  * device memory the context may hold (0 = no cap).  On success *out owns all
- * device scratch memory; release it with esc_destroy. */
+ * device scratch memory; release it with esc_destroy.  Read from the
+ * environment here: ESC_TRACE=1 makes the context's calls report each stage
+ * (and slice) to stderr as it ends; ESC_SLICE_MS=t runs the per-source
+ * kernels (4-cycles, pair passes, 5-cycles) in launches of about t ms each,
+ * a workgroup taking no new task once its slice is over and the next launch
+ * going on from the shared task counter (default: 30000 under ESC_TRACE,
+ * else one launch; 0: one launch).  Counts do not depend on either. */
 esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budget_bytes);
 
 /* Release every resource held by the context.  NULL is ignored. */
@@ -179,9 +185,13 @@ esc_status esc_count_batched(esc_ctx *ctx, int32_t G, const int64_t *vtx_off,
  * run.  The server owns max_inflight contexts (one stream and one set of
  * device buffers each) and a worker thread per context.  A free worker takes
  * the oldest queued request and, if it has at most 2^20 vertices, the
- * following queued requests of the same k up to 256 in all, and runs them as
- * one batched launch (esc_count_batched's pipeline); larger requests run
- * alone.  A launch starts only when its estimated device footprint (CSR and
+ * following queued requests of the same k and size class up to 256 in all,
+ * and runs them as one batched launch (esc_count_batched's pipeline); larger
+ * requests run alone.  A group also stops growing once its predicted work
+ * reaches 2^32 list visits (the wedges plus the directed 3-path bound, the
+ * terms of Thm fivevertex known before counting, computed at submission), so
+ * one launch does not hold many large requests.  A launch starts only when
+ * its estimated device footprint (CSR and
  * arc arrays, triangle lists bounded by the wedge count, per-workgroup tables)
  * fits in the admission budget beside the launches in flight, so launches
  * overlap on the device as workers and memory free up.  Results are exact and
@@ -290,12 +300,21 @@ esc_status esc_set_params(esc_ctx *ctx, const esc_params *params);
 esc_status esc_last_params(const esc_ctx *ctx, esc_params *out);
 
 /* Work counters of the last successful call on this context (Thm fourvertex
- * and Thm fivevertex state the running time in these terms):
+ * and Thm fivevertex state the running time in these terms; Fig. predict
+ * fits the 5-vertex time as a linear function of W, D, DP and DBP):
  *   [0] W++  out-wedges of the DAG      [1] W+-  in-out wedges
  *   [2] W    wedges                     [3] T    triangles
  *   [4] D    diamonds                   [5] max out-degree
  *   [6] n    vertices                   [7] m    edges
- * `out` is a host array of 8 uint64. */
+ *   [8] DP   directed 3-paths i <- a -> b -> j of the DAG (four distinct
+ *            vertices; the paths of the 5-cycle count, Thm 5cycle)
+ *   [9] DBP  directed bipyramids: pairs of common out-neighbours of the
+ *            triangles a < b < c (the 5-clique enumeration of Thm 5clique
+ *            read from the triangle of the three earliest vertices); 0 for
+ *            k = 4 calls, whose 5-clique pass does not run
+ * Totals over the graphs of a batched call.  `out` is a host array of
+ * ESC_WORK_COUNTERS uint64. */
+#define ESC_WORK_COUNTERS 10
 esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out);
 
 /* Non-induced counts of the last successful call (the number of subgraphs,

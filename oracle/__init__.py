@@ -36,6 +36,7 @@ SUM_NAMES = [
     "n", "m", "W", "T", "TT", "D", "C4", "K4", "sum_C(d,3)", "sum_e(d-1)(d-1)",
     "N1", "N2", "N3", "N4", "N5", "N6", "N7", "N8", "N9", "N10",
     "N11", "N12", "N13", "N14", "N15", "N16", "N17", "N18", "N19", "N20", "N21",
+    "DP", "DBP",
 ]
 
 
@@ -59,6 +60,8 @@ def _load():
                                    vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_num_sums.restype = ctypes.c_int
+        lib.oracle_set_sample_offset.argtypes = [ctypes.c_int]
+        lib.oracle_set_sample_offset.restype = None
         lib.brute_count.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int, vp, ctypes.c_int,
                                     ctypes.c_int, vp]
         lib.brute_count.restype = ctypes.c_int
@@ -148,18 +151,21 @@ def count(graph, k=5, order_rank=None, threads=0):
     return C4 + C5
 
 
-def timed_sample(graph, k=5, sample=64, threads=0):
+def timed_sample(graph, k=5, sample=64, threads=0, offset=0):
     """Time the oracle on a sample of its own work: the degree order, triangle
     stage and triangle lists run in full; every later loop visits only sources
-    and edges whose id is a multiple of `sample` (ids are a seeded shuffle, so
-    this is a uniform sample).  Returns (setup_seconds, sampled_seconds); the
-    counts of such a run are not meaningful and are not returned."""
+    and edges whose id plus `offset` is a multiple of `sample` (ids are a
+    seeded shuffle, so this is a uniform sample).  Returns (setup_seconds,
+    sampled_seconds); the counts of such a run are not meaningful and are not
+    returned."""
     lib = _load()
+    lib.oracle_set_sample_offset(int(offset) % max(1, int(sample)))
     rp, ci = _csr(graph)
     out = np.zeros(2 * len(SUM_NAMES), dtype=np.uint64)
     secs = np.zeros(2, dtype=np.float64)
     rc = lib.oracle_run(graph.n, _ptr(rp), _ptr(ci), k, None, threads, _ptr(out), *([None] * 6),
                         int(sample), _ptr(secs))
+    lib.oracle_set_sample_offset(0)
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return float(secs[0]), float(secs[1])

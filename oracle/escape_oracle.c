@@ -37,11 +37,15 @@ typedef unsigned __int128 u128;
 typedef uint64_t u64;
 
 /* Timing sample for the CPU baseline: with g_sample = s > 1 the loops after
- * the triangle stage visit only sources (and edges) whose id is a multiple of
- * s; the sums are then meaningless and only the elapsed time is used.  With
- * s = 1 (every test) nothing is skipped. */
+ * the triangle stage visit only sources (and edges) whose id plus g_offset
+ * is a multiple of s; the sums are then meaningless and only the elapsed time
+ * is used.  With s = 1 (every test) nothing is skipped. */
 static int g_sample = 1;
-#define SAMPLED(x) (g_sample > 1 && ((int64_t)(x) % g_sample) != 0)
+static int g_offset = 0;
+#define SAMPLED(x) (g_sample > 1 && (((int64_t)(x) + g_offset) % g_sample) != 0)
+
+/* offset of the next sampled run (timing only) */
+void oracle_set_sample_offset(int offset) { g_offset = offset > 0 ? offset : 0; }
 
 /* ------------------------------------------------------------------ graph */
 
@@ -338,6 +342,7 @@ enum {
     S_3STAR, S_EDGEPAIR,                       /* sum C(d,3); sum_e (d(u)-1)(d(v)-1) */
     S_N1, S_N2, S_N3, S_N4, S_N5, S_N6, S_N7, S_N8, S_N9, S_N10,
     S_N11, S_N12, S_N13, S_N14, S_N15, S_N16, S_N17, S_N18, S_N19, S_N20, S_N21,
+    S_DP, S_DBP,          /* work counts of Thm fivevertex: directed 3-paths, directed bipyramids */
     S_COUNT
 };
 
@@ -566,8 +571,8 @@ static int five_vertex(graph *g, u128 *S) {
      * orientations whose 3-path splits as 1+4, so ordered pairs are used; and
      * the tailed triangle correction has three directed shapes, not one.) */
     {
-        u128 acc = 0;
-        #pragma omp parallel reduction(+:acc)
+        u128 acc = 0, npaths = 0;
+        #pragma omp parallel reduction(+:acc, npaths)
         {
             u64 *P = (u64 *)calloc((size_t)n + 1, sizeof(u64));
             u64 *Wn = (u64 *)calloc((size_t)n + 1, sizeof(u64));
@@ -585,6 +590,7 @@ static int five_vertex(graph *g, u128 *S) {
                         for (int64_t r = g->rp[b]; r < g->rp[b + 1]; r++) {
                             int32_t j = g->ci[r];
                             if (j == i || !prec(g, b, j)) continue;
+                            npaths++;   /* one directed 3-path i <- a -> b -> j */
                             if (P[j]++ == 0) touched[nt++] = j;
                         }
                     }
@@ -619,6 +625,7 @@ static int five_vertex(graph *g, u128 *S) {
             }
         free(dp);
         S[S_N8] = sub(acc, Z);
+        S[S_DP] = npaths;
     }
 
     /* ---- 5-cliques (Thm 5clique).  For a triangle t, the other triangles on
@@ -629,8 +636,8 @@ static int five_vertex(graph *g, u128 *S) {
      * contains a directed cycle, impossible in a DAG; the configuration used is
      * the one that makes the count exact.) */
     {
-        u128 K5 = 0;
-        #pragma omp parallel reduction(+:K5)
+        u128 K5 = 0, pairs = 0;
+        #pragma omp parallel reduction(+:K5, pairs)
         {
             int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (n + 1));
             #pragma omp for schedule(dynamic, 1024)
@@ -646,6 +653,7 @@ static int five_vertex(graph *g, u128 *S) {
                         int32_t l = g->apex[s];
                         if (prec(g, c, l) && adjacent(g, a, l)) L[nl++] = l;
                     }
+                    pairs += (u128)nl * (nl > 0 ? nl - 1 : 0) / 2;   /* directed bipyramids tried */
                     for (int64_t x = 0; x < nl; x++)
                         for (int64_t y = x + 1; y < nl; y++)
                             if (adjacent(g, L[x], L[y])) K5++;
@@ -654,6 +662,7 @@ static int five_vertex(graph *g, u128 *S) {
             free(L);
         }
         S[S_N21] = K5;
+        S[S_DBP] = pairs;
     }
     return 0;
 }

@@ -405,9 +405,9 @@ class Server:
 
 
 def esc_last_work(ctx):
-    out = (ctypes.c_uint64 * 8)()
+    out = (ctypes.c_uint64 * 10)()
     _check(_load().esc_last_work(ctx, out), "esc_last_work")
-    keys = ["W++", "W+-", "W", "T", "D", "max_dplus", "n", "m"]
+    keys = ["W++", "W+-", "W", "T", "D", "max_dplus", "n", "m", "DP", "DBP"]
     return dict(zip(keys, [int(x) for x in out]))
 
 

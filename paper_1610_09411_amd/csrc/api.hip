@@ -93,13 +93,15 @@ static int floor_log2(int64_t x) {
     return b;
 }
 
-// key of the tuning table: batched or not, log2 of the (largest) graph's
-// vertex count, of the mean degree and of the largest degree
-static uint32_t degree_key(const esc_ctx *c) {
+// key of the tuning table, from the work terms known after the degree order
+// (Thm fivevertex puts the running time in W, D, DP and DBP; D and DBP come
+// only from the counting stages): batched or not, log2 of the (largest)
+// graph's vertex count, of the wedges W and of the directed 3-path bound
+// sum over arcs a -> b of (d+(a) - 1) d+(b) (totals over a batch)
+static uint32_t work_key(const esc_ctx *c) {
     const int64_t nn = c->G ? c->tab_n : c->n;
-    const int64_t mean = c->n > 0 ? 2 * c->m / c->n : 0;
-    return (c->G ? 1u << 24 : 0u) | (uint32_t)floor_log2(nn + 1) << 16 | (uint32_t)floor_log2(mean + 1) << 8 |
-           (uint32_t)floor_log2((int64_t)c->maxdeg + 1);
+    return (c->G ? 1u << 24 : 0u) | (uint32_t)floor_log2(nn + 1) << 16 |
+           (uint32_t)floor_log2((int64_t)(c->key_w >> 1) + 1) << 8 | (uint32_t)floor_log2((int64_t)(c->key_dp >> 1) + 1);
 }
 
 static esc_params default_params(const esc_ctx *c) {
@@ -119,7 +121,7 @@ static esc_params default_params(const esc_ctx *c) {
 // after the degree order (the key needs the largest degree)
 static void select_params(esc_ctx *c) {
     esc_params p = default_params(c);
-    c->tune_key = degree_key(c);
+    c->tune_key = work_key(c);
     if (c->forced) {
         p = c->force;
     } else {
@@ -242,7 +244,8 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     }
     {
         const char *ms = getenv("ESC_SLICE_MS");
-        long slice_ms = ms && ms[0] ? atol(ms) : (trace_on() ? 30000 : 0);
+        c->trace = trace_env();
+        long slice_ms = ms && ms[0] ? atol(ms) : (c->trace ? 30000 : 0);
         int khz = 0;
         if (slice_ms > 0 &&
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0)
@@ -302,19 +305,15 @@ __global__ void k_fragments_out(int32_t n, const int32_t *rp, const int32_t *col
 // bracketed by events on the call's stream (see esc_last_profile).
 // ESC_TRACE=1 in the environment: after every stage, wait for it and print
 // its name and time to stderr (long runs report their progress).
-bool trace_on() {
-    static int on = -1;
-    if (on < 0) {
-        const char *e = getenv("ESC_TRACE");
-        on = (e && e[0] && e[0] != '0') ? 1 : 0;
-    }
-    return on == 1;
+bool trace_env() {
+    const char *e = getenv("ESC_TRACE");
+    return e && e[0] && e[0] != '0';
 }
 
 static esc_status trace_stage(esc_ctx *c, int ev) {
     static const char *names[NSTAGES] = {"orient", "triangles", "four_cycles", "k4_triangles", "five_cliques",
                                          "reduce", "pairs_13_17", "wheels", "five_cycles", "combine"};
-    if (!trace_on() || ev < 1 || ev > NSTAGES) return ESC_OK;
+    if (!c->trace || ev < 1 || ev > NSTAGES) return ESC_OK;
     HIP_TRY(hipEventSynchronize(c->ev[ev]));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, c->ev[ev - 1], c->ev[ev]);
@@ -365,6 +364,8 @@ esc_status call_finish(esc_ctx *c, uint64_t w, uint64_t t3, uint64_t d) {
     HIP_TRY(hipMemcpyAsync(hw, c->buf[B_WORK], sizeof(hw), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (c->G) { w = hw[12]; t3 = hw[13]; d = hw[14]; }
+    c->work[8] = hw[WORK_DP] - t3 / 3;   // directed 3-paths: the j closing a triangle are not paths
+    c->work[9] = hw[WORK_DBP];
     c->work[0] = hw[0];
     c->work[1] = hw[1];
     c->work[2] = w;
@@ -723,7 +724,7 @@ extern "C" esc_status esc_last_params(const esc_ctx *ctx, esc_params *out) {
 
 extern "C" esc_status esc_last_work(const esc_ctx *ctx, uint64_t *out) {
     if (!ctx || !out) return ESC_EINVAL;
-    memcpy(out, ctx->work, sizeof(uint64_t) * 8);
+    memcpy(out, ctx->work, sizeof(uint64_t) * ESC_WORK_COUNTERS);
     return ESC_OK;
 }
 

@@ -348,7 +348,8 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
                                             const int64_t *ob_off, const unsigned long long *ob,
                                             const int64_t *uoff, const int32_t *uown, int64_t nunits, int lg,
                                             int light, int wave_words, int *task, GMap gm,
-                                            unsigned long long *acc, unsigned long long *visits) {
+                                            unsigned long long *acc, unsigned long long *visits,
+                                            unsigned long long *dbp_out) {
     __shared__ int pref[257], tmp[8];
     __shared__ int64_t beg[257];
     __shared__ int64_t s_u;
@@ -358,6 +359,9 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
     u128 k5[1] = {0};
     int gcur = -1;
     uint64_t nvis = 0;
+    // directed bipyramids (work counter of Thm 5clique): C(|S|,2) for each
+    // triangle a < b < c, S its common out-neighbours
+    uint64_t dbp = 0;
     for (;;) {
         if (threadIdx.x == 0) {
             const int64_t t = atomicAdd(task, 1);
@@ -395,6 +399,10 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
                     unsigned long long sc[K5_WAVE_WORDS];
 #pragma unroll
                     for (int w2 = 0; w2 < K5_WAVE_WORDS; w2++) sc[w2] = w2 < wa ? (bw[w2] & rc[w2]) : 0ull;
+                    uint32_t ns = 0;
+#pragma unroll
+                    for (int w2 = 0; w2 < K5_WAVE_WORDS; w2++) ns += (uint32_t)__popcll(sc[w2]);
+                    dbp += c2(ns);
 #pragma unroll
                     for (int w2 = 0; w2 < K5_WAVE_WORDS; w2++) {
                         unsigned long long xs = sc[w2];
@@ -422,8 +430,10 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
                 const unsigned long long *rb = rows + (int64_t)(ib + s) * wa;
                 const int j = nth_set_bit(rb, wa, (int)r);
                 const unsigned long long *rc = rows + (int64_t)j * wa;
+                uint32_t ns = 0;
                 for (int w = 0; w < wa; w++) {
                     unsigned long long sw = rb[w] & rc[w];
+                    ns += (uint32_t)__popcll(sw);
                     while (sw) {
                         const int x = w * 64 + __ffsll((long long)sw) - 1;
                         sw &= sw - 1;
@@ -432,6 +442,7 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
                         nvis += wa;
                     }
                 }
+                dbp += c2(ns);
             });
         }
     }
@@ -462,6 +473,7 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
                     const int ci = __ffsll((long long)cs) - 1;
                     cs &= cs - 1;
                     const unsigned long long sw = rb & rows[ci];
+                    dbp += c2((uint64_t)__popcll(sw));
                     unsigned long long xs = sw;
                     while (xs) {
                         const int x = __ffsll((long long)xs) - 1;
@@ -475,6 +487,7 @@ __global__ void __launch_bounds__(256) k_k5(int32_t n, const int32_t *off, const
     }
     if (wg >= 0) wave_flush_u128(s, acc + (size_t)wg * ACC_STRIDE + 2 * AC_K5);
     flush_count(nvis, visits);
+    flush_count(dbp, dbp_out);
 }
 
 // Dense vertices, one workgroup per vertex a (h = d+(a), taken from the
@@ -503,8 +516,9 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                                                   const uint32_t *aa, const int32_t *dlist, const int *ndense,
                                                   unsigned long long *scr_all, int64_t scr_words, int32_t hcap,
                                                   int *task, GMap gm, unsigned long long *acc,
-                                                  unsigned long long *visits) {
+                                                  unsigned long long *visits, unsigned long long *dbp_out) {
     __shared__ unsigned long long fu[4][K5_DENSE_HMAX / 64];
+    __shared__ int fsum[4][K5_DENSE_HMAX / 64 + 1];   // popcounts of fu[w..] per wave
     __shared__ int s_t;
     __shared__ u128 red[3 * 4];
     const int ids[1] = {AC_K5};
@@ -512,10 +526,11 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
     unsigned long long *T = scr_all + (size_t)blockIdx.x * scr_words;
     int64_t *los = (int64_t *)(T + (size_t)hcap * (hcap / 64));
     int32_t *dc = (int32_t *)(los + hcap);
+    int32_t *dch = dc + hcap;   // complement neighbours after the vertex
     const int nd = *ndense;
     u128 k5[1] = {0};
     int gcur = -1;
-    uint64_t nvis = 0;
+    uint64_t nvis = 0, dbp = 0;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(task, 1);
         __syncthreads();
@@ -550,7 +565,7 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
             }
             nvis += (uint64_t)(l1 - l0);
             wave_sync();
-            int d = 0;
+            int d = 0, dh = 0;
             for (int w = lane; w < wa; w += 64) {
                 unsigned long long x = ~row[w];
                 const int top = h - 64 * w;   // positions of this word below h
@@ -558,9 +573,12 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                 if (w == (v >> 6)) x &= ~(1ull << (v & 63));
                 T[(size_t)w * h + v] = x;
                 d += __popcll(x);
+                if (w > (v >> 6)) dh += __popcll(x);
+                else if (w == (v >> 6) && (v & 63) != 63) dh += __popcll(x & (~0ull << ((v & 63) + 1)));
             }
             d = (int)wave_sum_u64((uint64_t)d);
-            if (lane == 0) dc[v] = d;
+            dh = (int)wave_sum_u64((uint64_t)dh);
+            if (lane == 0) { dc[v] = d; dch[v] = dh; }
             wave_sync();   // the row buffer is reused by the wave's next row
         }
         __syncthreads();
@@ -596,6 +614,12 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
         for (int u = wid; u < h; u += nwv) {
             for (int w = lane; w < wa; w += 64) fu[wid][w] = T[(size_t)w * h + u];
             wave_sync();
+            if (lane == 0) {
+                int acc_p = 0;
+                fsum[wid][wa] = 0;
+                for (int w = wa - 1; w >= 0; w--) { acc_p += __popcll(fu[wid][w]); fsum[wid][w] = acc_p; }
+            }
+            wave_sync();
             const uint64_t du = (uint64_t)dc[u];
             const int w0 = (u + 1) >> 6;
             const unsigned long long m0 = ~0ull << ((u + 1) & 63);   // positions after u in word w0
@@ -614,7 +638,19 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                 for (; w < wa; w++) cnt += (uint32_t)__popcll(fu[wid][w] & tv[(size_t)w * h]);
                 nvis += (uint64_t)(wa - w0);
                 k5[0] += c2(cnt);
-                if (!((fu[wid][v >> 6] >> (v & 63)) & 1ull)) continue;
+                if (!((fu[wid][v >> 6] >> (v & 63)) & 1ull)) {
+                    // an edge u-v of H_a: its common neighbours in H_a after v
+                    // (the positions after v less the Hc neighbours of u or v
+                    // there) close C(s,2) directed bipyramids
+                    const int wv = v >> 6;
+                    const unsigned long long mg = (v & 63) == 63 ? 0ull : ~0ull << ((v & 63) + 1);
+                    uint32_t chi = (uint32_t)__popcll(fu[wid][wv] & tv[(size_t)wv * h] & mg);
+                    for (int w = wv + 1; w < wa; w++) chi += (uint32_t)__popcll(fu[wid][w] & tv[(size_t)w * h]);
+                    const int duh = __popcll(fu[wid][wv] & mg) + fsum[wid][wv + 1];
+                    const int sh = (h - 1 - v) - duh - dch[v] + (int)chi;
+                    dbp += c2((uint64_t)sh);
+                    continue;
+                }
                 // an edge of Hc
                 uint32_t tf = cnt;
                 for (int w = 0; w <= w0 && w < wa; w++) {
@@ -649,6 +685,7 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
     }
     if (gcur >= 0) block_flush_u128<1>(k5, red, acc + (size_t)gcur * ACC_STRIDE, ids);
     flush_count(nvis, visits);
+    flush_count(dbp, dbp_out);
 }
 
 // ------------------------------------------------------------------- stages
@@ -710,22 +747,23 @@ esc_status stage_k5(esc_ctx *c) {
     ESC_TRY(dev_task_owner(c, n, uoff, &nunits, &uown));
     unsigned long long *acc = (unsigned long long *)c->buf[B_ACC];
     unsigned long long *vis = (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 4;
+    unsigned long long *dbp = (unsigned long long *)c->buf[B_WORK] + WORK_DBP;
     k_k5<<<c->num_cu * 4, 256, 0, st>>>(n, off, split, ob_off, ob, uoff, uown, nunits, c->k5_work_log2,
-                                        c->k5_light, c->k5_wave_words, task + 3, gmap_of(c), acc, vis);
+                                        c->k5_light, c->k5_wave_words, task + 3, gmap_of(c), acc, vis, dbp);
     HIP_TRY(hipGetLastError());
     if (c->maxdplus > c->k5_light && c->k5_dense_pct <= 100) {
         // dense vertices: per-workgroup scratch for the complement rows of
         // the largest out-neighbourhood, its list starts and degrees
         int32_t hmax = c->maxdplus < K5_DENSE_HMAX ? c->maxdplus : K5_DENSE_HMAX;
         const int32_t hcap = (hmax + 63) & ~63;
-        const int64_t per_wg = (int64_t)hcap * (hcap / 64) + hcap + (hcap + 1) / 2;
+        const int64_t per_wg = (int64_t)hcap * (hcap / 64) + hcap + hcap;   // rows, list starts, two degree arrays
         int nwg = 4 * c->num_cu;   // 113 VGPRs: four 4-wave workgroups per CU are resident
         while (nwg > c->num_cu && (size_t)nwg * (size_t)per_wg * 8 > c->dev_mem / 16) nwg -= c->num_cu;
         unsigned long long *scr = (unsigned long long *)ctx_buf(c, B_K5_DENSE_SCR, sizeof(uint64_t) * (size_t)per_wg * nwg);
         if (!scr) return ESC_ENOMEM;
         auto kern = c->av ? k_k5_dense<true> : k_k5_dense<false>;
         kern<<<nwg, 256, 0, st>>>(off, split, aoff, aa, dlist, task + 5, scr, per_wg, hcap, task + 6, gmap_of(c), acc,
-                                  vis);
+                                  vis, dbp);
         HIP_TRY(hipGetLastError());
     }
     return ESC_OK;

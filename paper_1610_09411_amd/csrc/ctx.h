@@ -110,7 +110,7 @@ struct esc_ctx {
     size_t held;
     int num_cu;
     int max_lds;               // bytes of LDS one workgroup may allocate
-    uint64_t work[8];
+    uint64_t work[ESC_WORK_COUNTERS];
     float stage_ms[NSTAGES];
     uint64_t visits[NSTAGES];
     esc_u128 noninduced[45];
@@ -123,6 +123,7 @@ struct esc_ctx {
     int64_t narcs_apex;        // total per-arc triangle list entries (6T)
     int32_t maxdeg;
     int32_t maxdplus;
+    uint64_t key_w, key_dp;    // W and the directed 3-path bound of the call, after the degree order
     int k;
     uint32_t flags;
     bool scratch_clean;        // per-workgroup tables are all zero
@@ -159,6 +160,7 @@ struct esc_ctx {
     // time slices of the per-source kernels (wall-clock ticks, 0 = none):
     // ESC_SLICE_MS in the environment, or 30 s when ESC_TRACE is set
     uint64_t slice_ticks;
+    bool trace;                // report stages and slices to stderr (ESC_TRACE at creation)
 };
 
 // Workgroups of the per-source kernels (4-cycles, pair passes, 5-cycles):
@@ -209,15 +211,21 @@ esc_status ctx_free_bytes(esc_ctx *c, size_t *out);
 esc_status ctx_check(hipError_t e);
 
 // B_WORK layout: [0] W++, [1] W+-, [2 + s] visits of stage s (see esc_last_profile),
-// [12] W, [13] 3T, [14] D summed over the graphs of a batched call
+// [12] W, [13] 3T, [14] D summed over the graphs of a batched call,
+// [16] sum over arcs a->b of (d+(a)-1) d+(b) (the directed 3-paths and T),
+// [17] directed bipyramids, [18] W (both from the degree order)
 #define WORK_VISITS 2
-#define WORK_WORDS 16
+#define WORK_DP 16
+#define WORK_DBP 17
+#define WORK_W 18
+#define WORK_WORDS 32
 
 #define ESC_TRY(x) do { esc_status _s = (x); if (_s != ESC_OK) return _s; } while (0)
 #define HIP_TRY(x) do { hipError_t _e = (x); if (_e != hipSuccess) return ESC_EDEVICE; } while (0)
 
-// ESC_TRACE=1 in the environment: stages and slices report to stderr
-bool trace_on();
+// ESC_TRACE=1 in the environment when a context is created: its calls report
+// every stage and slice to stderr
+bool trace_env();
 
 // A per-source kernel taking tasks from the shared counter `counter` (see
 // slice_grab): launch(ticks) enqueues one launch.  Without slices, one
@@ -237,7 +245,7 @@ esc_status run_sliced(esc_ctx *c, const char *name, int *done, const int *counte
         HIP_TRY(hipMemcpyAsync(&h[1], counter, sizeof(int), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (h[0]) return ESC_OK;
-        if (trace_on()) {
+        if (c->trace) {
             fprintf(stderr, "esc: %s slice %d ended, %d grabs taken\n", name, part, h[1]);
             fflush(stderr);
         }

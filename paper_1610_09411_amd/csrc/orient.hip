@@ -241,6 +241,28 @@ __global__ void k_split(int32_t n, const int32_t *off, const int32_t *adj, int32
     }
 }
 
+// Work terms known once the degree order is (Thm fivevertex): wedges W, and
+// the directed 3-paths i <- a -> b -> j counted with the j that close a
+// triangle, sum over arcs a -> b of (d+(a) - 1) d+(b), taken at b over its
+// in-neighbours a.  One thread per vertex b.
+__global__ void k_work_terms(int32_t n, const int32_t *off, const int32_t *adj, const int32_t *split,
+                             unsigned long long *w_out, unsigned long long *dp_out) {
+    uint64_t w = 0, dp = 0;
+    for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += gridDim.x * blockDim.x) {
+        const uint64_t d = (uint64_t)(off[b + 1] - off[b]), dpb = (uint64_t)(off[b + 1] - split[b]);
+        w += c2(d);
+        if (dpb == 0) continue;
+        uint64_t s = 0;
+        for (int32_t p = off[b]; p < split[b]; p++) {
+            const int32_t a = adj[p];
+            s += (uint64_t)(off[a + 1] - split[a] - 1);
+        }
+        dp += s * dpb;
+    }
+    flush_count(w, w_out);
+    flush_count(dp, dp_out);
+}
+
 // edge id = index of the out-arc in the concatenation of all out-lists
 __global__ void k_edges(int32_t n, const int32_t *off, const int32_t *adj, const int32_t *split,
                         const int64_t *eoff, int32_t *arc_eid, int32_t *rev, int32_t *earc, int32_t *elo) {
@@ -475,6 +497,7 @@ static int grid_for(esc_ctx *c, int64_t items, int threads) {
 esc_status stage_orient(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
+    c->key_w = c->key_dp = 0;
     int32_t *deg = (int32_t *)ctx_buf(c, B_DEG, sizeof(int32_t) * (size_t)(n + 1));
     int *err = (int *)ctx_buf(c, B_ERR, sizeof(int) * 4);
     if (!deg || !err) return ESC_ENOMEM;
@@ -567,7 +590,14 @@ esc_status stage_orient(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col) {
     ESC_TRY(dev_scan<int64_t>(c, len, off64, n));   // off64 := out-arc offsets (edge ids)
     k_edges<<<grid_for(c, n, 256), 256, 0, st>>>(n, off, adj, split, off64, arc_eid, rev, earc, elo);
     HIP_TRY(hipGetLastError());
+    unsigned long long *work = (unsigned long long *)c->buf[B_WORK];
+    k_work_terms<<<grid_for(c, n, 256), 256, 0, st>>>(n, off, adj, split, work + WORK_W, work + WORK_DP);
+    HIP_TRY(hipGetLastError());
+    uint64_t terms[3] = {0, 0, 0};   // [WORK_DP], [WORK_DBP], [WORK_W]
+    HIP_TRY(hipMemcpyAsync(terms, work + WORK_DP, sizeof(terms), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     c->maxdplus = h_err[0];
+    c->key_dp = terms[0];
+    c->key_w = terms[2];
     return ESC_OK;
 }

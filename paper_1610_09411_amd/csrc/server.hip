@@ -38,6 +38,7 @@ struct Req {
     int k;
     std::vector<int32_t> rp, col;
     uint64_t wedges;           // sum_v C(d(v),2), for the footprint estimate
+    uint64_t cost;             // predicted device work (see work_cost)
     double t_submit = 0, t_done = 0;
     esc_status status = ESC_OK;
     bool done = false;
@@ -53,6 +54,7 @@ struct esc_server {
     int32_t small_n;           // requests up to this size may share a launch
     int max_group;             // requests per batched launch
     int nwg;                   // workgroups of the per-source kernels (table footprint)
+    uint64_t cost_cap;         // predicted work of one grouped launch at most (a request alone may pass it)
     size_t max_queue = 1 << 20;   // requests waiting at most; esc_submit returns ESC_EBUSY beyond
     std::mutex mu;
     std::condition_variable cv;        // queue, memory or stop changed
@@ -86,6 +88,37 @@ size_t footprint(const std::vector<Req *> &grp, int nwg) {
     }
     bytes += 24 * (size_t)nmax * (size_t)nwg + ((size_t)64 << 20);
     return bytes;
+}
+
+// Predicted device work of a request, in visited list entries: the wedges W
+// (pair passes) plus the directed 3-paths i <- a -> b -> j of the degree
+// order with the j closing a triangle, sum over arcs a -> b of
+// (d+(a) - 1) d+(b) (5-cycle pass), the two work terms of Thm fivevertex
+// that are known before counting (Fig. predict fits the running time
+// linearly in W, D, DP and DBP).  Ids outside [0, n) are skipped: the device
+// rejects such input.
+uint64_t work_cost(int32_t n, const int32_t *rp, const int32_t *col, uint64_t w) {
+    std::vector<int32_t> dplus((size_t)n + 1, 0);
+    auto later = [&](int32_t a, int32_t b) {   // b after a in the degree order
+        const int32_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
+        return db > da || (db == da && b > a);
+    };
+    for (int32_t v = 0; v < n; v++)
+        for (int32_t p = rp[v]; p < rp[v + 1]; p++) {
+            const int32_t u = col[p];
+            if (u >= 0 && u < n && later(v, u)) dplus[v]++;
+        }
+    uint64_t dp = 0;
+    for (int32_t b = 0; b < n; b++) {
+        if (dplus[b] == 0) continue;
+        uint64_t s = 0;
+        for (int32_t p = rp[b]; p < rp[b + 1]; p++) {
+            const int32_t a = col[p];
+            if (a >= 0 && a < n && later(a, b) && dplus[a] > 0) s += (uint64_t)(dplus[a] - 1);
+        }
+        dp += s * (uint64_t)dplus[b];
+    }
+    return w + dp;
 }
 
 // Host-side shape checks at submission; the device checks the rest (every
@@ -159,12 +192,15 @@ void worker(esc_server *s, esc_ctx *c) {
         std::vector<Req *> grp{s->queue.front()};
         std::vector<size_t> pos{0};
         size_t est = footprint(grp, s->nwg);
+        uint64_t gcost = grp[0]->cost;
         if (grp[0]->n <= s->small_n) {
             const bool tiny = grp[0]->n <= PW_MAX_N;
             const size_t scan = s->queue.size() < (size_t)4 * s->max_group ? s->queue.size() : (size_t)4 * s->max_group;
             for (size_t i = 1; i < scan && (int)grp.size() < s->max_group; i++) {
                 Req *r = s->queue[i];
                 if (r->k != grp[0]->k || r->n > s->small_n || (r->n <= PW_MAX_N) != tiny) continue;
+                if (gcost + r->cost > s->cost_cap) break;   // the launch holds enough work
+                gcost += r->cost;
                 grp.push_back(r);
                 size_t e2 = footprint(grp, s->nwg);
                 if (e2 > s->budget) { grp.pop_back(); break; }
@@ -229,6 +265,7 @@ extern "C" esc_status esc_server_start(esc_ctx *ctx, int max_inflight, esc_serve
     s->nwg = pair_wgs(ctx);
     s->small_n = 1 << 20;
     s->max_group = 256;
+    s->cost_cap = (uint64_t)1 << 32;   // some 10 ms of device work on MI355X
     size_t budget = ctx->budget;
     if (budget == 0) {
         size_t fr = 0, tot = 0;
@@ -270,6 +307,7 @@ extern "C" esc_status esc_submit(esc_server *s, int32_t n, const int32_t *row_pt
         w += d * (d - (d > 0)) / 2;
     }
     r->wedges = w;
+    r->cost = work_cost(n, row_ptr, col, w);
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) {

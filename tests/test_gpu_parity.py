@@ -426,3 +426,65 @@ def test_time_sliced_launches_give_same_counts():
             assert [int(x) for x in rows[i]] == oracle.count(batch[i], 5), i
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("a", [2, 3])
+def test_degrees_above_2_16(ctx, a):
+    """K_{a,70000}: hubs of degree 70000 >= 2^16, so the per-source tables
+    keep 32-bit counts, the wheel pass its 32-bit key ranges and the 5-cycle
+    pass the Wnt order; induced counts in closed form (4-subsets with x
+    vertices on the small side: an independent set, a 3-star, a 4-cycle;
+    5-subsets: an independent set, a 4-star, K_{2,3})."""
+    b = 70000
+    g = synth.from_edges(a + b, [(u, a + v) for u in range(a) for v in range(b)], "K_%d,%d" % (a, b))
+    want = [0] * 45
+    want[0] = a * comb(b, 3) + b * comb(a, 3)
+    want[3] = comb(a, 2) * comb(b, 2)
+    want[6] = comb(a, 4) + comb(b, 4)
+    want[11] = a * comb(b, 4) + b * comb(a, 4)
+    want[11 + 12] = comb(a, 2) * comb(b, 3) + comb(a, 3) * comb(b, 2)
+    want[32] = comb(a, 5) + comb(b, 5)
+    assert ctx.count(g, 5) == want
+    assert ctx.count(g, 4) == want[:11]
+    # and a hub of degree >= 2^16 that also has triangles and wheels: the
+    # hub joined to a path and a clique
+    h = synth.from_edges(b + 1, [(0, v) for v in range(1, b + 1)] + [(v, v + 1) for v in range(1, b)] +
+                         [(u, v) for u in range(1, 40) for v in range(u + 1, 40)], "hub 70000")
+    assert ctx.count(h, 5) == oracle.count(h, 5, threads=8)
+
+
+def _degree_order_work(g):
+    d = g.degrees()
+    order = np.lexsort((np.arange(g.n), d))            # by degree, ties by id
+    rank = np.empty(g.n, np.int64)
+    rank[order] = np.arange(g.n)
+    dp = np.zeros(g.n, np.int64)
+    for u in range(g.n):
+        nb = g.col[g.row_ptr[u]:g.row_ptr[u + 1]]
+        dp[u] = int((rank[nb] > rank[u]).sum())
+    dm = d - dp
+    return {"W++": int((dp * (dp - 1) // 2).sum()), "W+-": int((dp * dm).sum()),
+            "W": int((d * (d - 1) // 2).sum()), "max_dplus": int(dp.max()) if g.n else 0}
+
+
+def test_noninduced_and_work_counters(ctx):
+    """esc_last_noninduced against the oracle's non-induced counts (App. B:
+    N = A C), and esc_last_work against the definitions of its counters
+    (out-wedges and in-out wedges of the degree-ordered DAG, wedges, the
+    largest out-degree) and the oracle's triangle and diamond totals."""
+    for g in _cases_small()[::3] + [synth.chung_lu(3000, 2.1, 12.0, 400.0, 1), synth.er_small(4),
+                                    synth.erdos_renyi(160, 0.6, 11), _dense_core_graph(2, core=90, per=120)]:
+        S = oracle.sums(g, 5)
+        want_non = oracle.noninduced_from_sums(S, 4) + oracle.noninduced_from_sums(S, 5)
+        for k in (4, 5):
+            ctx.count(g, k)
+            assert ctx.last_noninduced(k) == want_non[:11 if k == 4 else 45], (g.name, k)
+            w = ctx.last_work()
+            dw = _degree_order_work(g)
+            for key in ("W++", "W+-", "W", "max_dplus"):
+                assert w[key] == dw[key], (g.name, k, key)
+            assert (w["T"], w["D"], w["n"], w["m"]) == (S["T"], S["D"], g.n, g.m), (g.name, k)
+            # directed 3-paths and directed bipyramids (the oracle enumerates
+            # them; the 5-clique pass, and so DBP, runs for k = 5 only)
+            assert w["DP"] == S["DP"], (g.name, k)
+            assert w["DBP"] == (S["DBP"] if k == 5 else 0), (g.name, k)

@@ -383,3 +383,42 @@ def test_clique_count_through_the_complement(seed):
     signed = sum((-1) ** pat.edge_count(4, j) * N[j] for j in range(11))
     assert signed == _induced(h, 4)[5]
     assert list(pat.a_inverse(4)[6]) == [(-1) ** pat.edge_count(4, j) for j in range(11)]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_work_counts_directed_paths_and_bipyramids(seed):
+    """The work counts of Thm fivevertex that Fig. predict fits the running
+    time with, by their definitions in the degree-ordered DAG (arcs from the
+    earlier to the later vertex): DP = ordered 4-tuples (i, a, b, j) of
+    distinct vertices with arcs a->i, a->b, b->j (the directed 3-path);
+    DBP = 5-subsets whose three earliest vertices form a triangle and whose
+    two latest vertices are each adjacent to all three (the bipyramid from the
+    triangle of its three earliest vertices)."""
+    from itertools import combinations
+    g = synth.erdos_renyi(14 + seed, 0.45 + 0.08 * seed, 940 + seed)
+    A = _dense(g).astype(bool)
+    n = g.n
+    d = A.sum(1)
+    order = sorted(range(n), key=lambda v: (d[v], v))
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    arc = A & (rank[:, None] < rank[None, :])
+    dp = 0
+    for a in range(n):
+        for i in range(n):
+            if not arc[a, i]:
+                continue
+            for b in range(n):
+                if b == i or not arc[a, b]:
+                    continue
+                dp += int(sum(1 for j in range(n) if j != i and arc[b, j]))
+    dbp = 0
+    for sub in combinations(order, 5):
+        x, y, z, p, q = sub   # in rank order
+        if A[x, y] and A[x, z] and A[y, z] and all(A[w, t] for w in (p, q) for t in (x, y, z)):
+            dbp += 1
+    S = oracle.sums(g, 5)
+    assert S["DP"] == dp and S["DBP"] == dbp, (dp, dbp, S["DP"], S["DBP"])
+    # closed form of DP: sum over arcs a->b of (d+(a) - 1) d+(b), less T
+    dplus = arc.sum(1)
+    assert dp == int(sum((dplus[a] - 1) * dplus[b] for a in range(n) for b in range(n) if arc[a, b])) - S["T"]

@@ -75,8 +75,10 @@ def main():
     ap.add_argument("--headline-warmup", type=int, default=0,
                     help="warm-up calls on the 4M-vertex graph (0: buffer allocation is inside the timed call)")
     ap.add_argument("--headline", choices=["chung_lu_4m", "chung_lu_1m"], default="chung_lu_4m")
+    ap.add_argument("--small", type=int, default=1,
+                    help="also time the 1M-vertex graph when the headline is the 4M one (0 = skip)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=256,
+    ap.add_argument("--cpu-sample", type=int, default=128,
                     help="oracle timing sample: 1/N of sources and edges (0 = skip the CPU leg)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--cpu-one-thread", type=int, default=0,
@@ -149,9 +151,10 @@ def main():
     del g
 
     small = None
-    if big:
+    if big and (args.small or args.cpu_sample > 0):
         g1 = synth.chung_lu_1m(args.seed)
-        small = run_single(esc, ctx, torch, g1, "chung_lu_1m", args.steps, args.warmup, stream)
+        if args.small:
+            small = run_single(esc, ctx, torch, g1, "chung_lu_1m", args.steps, args.warmup, stream)
     else:
         g1 = head_g
 

@@ -188,7 +188,7 @@ esc_status esc_count_batched(esc_ctx *ctx, int32_t G, const int64_t *vtx_off,
  * following queued requests of the same k and size class up to 256 in all,
  * and runs them as one batched launch (esc_count_batched's pipeline); larger
  * requests run alone.  A group also stops growing once its predicted work
- * reaches 2^32 list visits (the wedges plus the directed 3-path bound, the
+ * reaches 2^38 list visits (the wedges plus the directed 3-path bound, the
  * terms of Thm fivevertex known before counting, computed at submission), so
  * one launch does not hold many large requests.  A launch starts only when
  * its estimated device footprint (CSR and

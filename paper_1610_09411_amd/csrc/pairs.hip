@@ -349,7 +349,8 @@ __global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int32_t
 template <bool IDS>
 __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const int32_t *off, const int32_t *adj,
                                                 const int64_t *aoff, const uint32_t *aa, const int32_t *av,
-                                                int32_t wq, int32_t wk, const int64_t *toff, const int32_t *town,
+                                                int32_t wq, int32_t wk, int32_t tab_words, const int64_t *toff,
+                                                const int32_t *town,
                                                 int64_t nbig, int *task_big, int chunk, int32_t split_deg,
                                                 GMap gm, int *task, int tiny, unsigned long long *acc,
                                                 unsigned long long *visits, uint64_t slice_ticks, int *done) {
@@ -365,9 +366,9 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
     u128 s18[1] = {0};
     int gcur = -1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint32_t *lcnt = dyn;   // wk / 2 words: the key range of a large-hub task
+    uint32_t *lcnt = dyn;   // the key range of a large-hub task
     // zero at the start; every rim vertex leaves the table zero again
-    for (int q = threadIdx.x; q < wk / 2; q += blockDim.x) lcnt[q] = 0;
+    for (int q = threadIdx.x; q < tab_words; q += blockDim.x) lcnt[q] = 0;
     __syncthreads();
 
     // large hubs: tasks of WHEEL_RIMS rim vertices
@@ -1008,11 +1009,17 @@ esc_status stage_wheels(esc_ctx *c) {
     // (10 KB) for its tables.  Large-hub tasks: wk 16-bit counts (a range
     // of keys); per-wave mode: a table and a touched list of (wq + 1) / 2
     // words each per wave, wq the largest hub it takes.
-    const int32_t words = (int32_t)(((size_t)c->max_lds / 2 - 12288) / 4) & ~63;
-    const int32_t wk = 2 * words;
-    int32_t wq = words / waves;   // 2 * ((wq + 1) / 2) words per wave
-    if (wq > 4096) wq = 4096;
-    size_t lds = sizeof(uint32_t) * (size_t)words;
+    const int32_t budget = (int32_t)(((size_t)c->max_lds / 2 - 12288) / 4) & ~63;   // words
+    const int32_t wk = 2 * budget;    // keys per range of a large-hub task
+    // per-wave mode up to a hub of wq neighbours: an eighth (a quarter for
+    // batches) of the keys the largest hub has, so graphs with small hubs
+    // keep small tables and more workgroups per CU
+    int32_t cap = c->maxdeg + 1 < wk ? c->maxdeg + 1 : wk;
+    int32_t wq = cap / waves;
+    if (wq > budget / waves) wq = budget / waves;
+    const int32_t tab_words = (cap + 1) / 2;   // a large-hub task's table
+    const int32_t wave_words_all = waves * 2 * ((wq + 1) / 2);
+    size_t lds = sizeof(uint32_t) * (size_t)(tab_words > wave_words_all ? tab_words : wave_words_all);
     // hubs of at most WHEEL_TINY neighbours are taken whole, one per wave,
     // in the wave's one-wave table when it holds WHEEL_TINY_WORDS words,
     // else in tables after those (a batch of small graphs)
@@ -1037,7 +1044,7 @@ esc_status stage_wheels(esc_ctx *c) {
     return run_sliced(c, "wheels", task + 8, task + 1, [&](uint64_t ticks) -> esc_status {
         kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(
             n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int64_t *)c->buf[B_AOFF],
-            (const uint32_t *)c->buf[B_AA], c->av, wq, wk, toff, town, nbig, task + 4,
+            (const uint32_t *)c->buf[B_AA], c->av, wq, wk, tab_words, toff, town, nbig, task + 4,
             c->task_chunk, c->wheel_split_deg, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
             (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7, ticks, task + 8);
         HIP_TRY(hipGetLastError());

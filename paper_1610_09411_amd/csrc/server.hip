@@ -265,7 +265,7 @@ extern "C" esc_status esc_server_start(esc_ctx *ctx, int max_inflight, esc_serve
     s->nwg = pair_wgs(ctx);
     s->small_n = 1 << 20;
     s->max_group = 256;
-    s->cost_cap = (uint64_t)1 << 32;   // some 10 ms of device work on MI355X
+    s->cost_cap = (uint64_t)1 << 38;   // some 0.5 s of device work on MI355X
     size_t budget = ctx->budget;
     if (budget == 0) {
         size_t fr = 0, tot = 0;

@@ -274,6 +274,17 @@ typedef struct {
     int32_t four_range_deg; /* 4-cycles (Thm 4cycle): tops with more
                                neighbours are split into key-range tasks,
                                16..2^30 (default 256) */
+    int32_t pairs_hub_ranks;/* pattern 17 (Thm 5cutwed) of one graph: the
+                               latest this many ranks are hubs, and the
+                               diamonds with two hub tips over a dense edge
+                               are summed as a matrix product of the hub /
+                               dense-edge incidence; 0 (off) or a multiple
+                               of 256 up to 65536 (default 16384; off for
+                               batches and for graphs with fewer than twice
+                               as many vertices) */
+    int32_t pairs_hub_q;    /* pattern 17: an edge is dense when at least
+                               this many hubs close a triangle with it,
+                               1..2^30 (default 256) */
 } esc_params;
 
 /* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}

@@ -115,6 +115,8 @@ static esc_params default_params(const esc_ctx *c) {
     p.k5_dense_pct = 50;
     p.wheel_split_deg = 1024;
     p.four_range_deg = 256;
+    p.pairs_hub_ranks = 16384;
+    p.pairs_hub_q = 256;
     return p;
 }
 
@@ -137,6 +139,8 @@ static void select_params(esc_ctx *c) {
     c->k5_dense_pct = p.k5_dense_pct;
     c->wheel_split_deg = p.wheel_split_deg;
     c->four_range_deg = p.four_range_deg;
+    c->pairs_hub_r = p.pairs_hub_ranks;
+    c->pairs_hub_q = p.pairs_hub_q;
     c->params = p;
     c->params.wg_per_cu = c->wg_per_cu;
 }
@@ -148,7 +152,9 @@ static bool params_valid(const esc_params *p) {
            p->k5_light >= 3 && p->k5_light <= 64 && p->k5_wave_words >= 1 && p->k5_wave_words <= 8 &&
            p->k5_dense_pct >= 0 && p->k5_dense_pct <= 101 &&
            p->wheel_split_deg >= 32 && p->wheel_split_deg <= (1 << 30) &&
-           p->four_range_deg >= 16 && p->four_range_deg <= (1 << 30);
+           p->four_range_deg >= 16 && p->four_range_deg <= (1 << 30) &&
+           p->pairs_hub_ranks >= 0 && p->pairs_hub_ranks <= 65536 && p->pairs_hub_ranks % 256 == 0 &&
+           p->pairs_hub_q >= 1 && p->pairs_hub_q <= (1 << 30);
 }
 
 static void store_tuned(esc_ctx *c, uint32_t key, const esc_params &p) {
@@ -241,6 +247,8 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
         c->k5_dense_pct = p.k5_dense_pct;
         c->wheel_split_deg = p.wheel_split_deg;
         c->four_range_deg = p.four_range_deg;
+        c->pairs_hub_r = p.pairs_hub_ranks;
+        c->pairs_hub_q = p.pairs_hub_q;
     }
     {
         const char *ms = getenv("ESC_SLICE_MS");

@@ -75,6 +75,11 @@ enum Buf {
     B_TRICNT,                   // count of B_TRIREC entries, bound of oriented wedges
     B_K5_DENSE,                 // vertices whose 5-cliques are counted through the complement
     B_K5_DENSE_SCR,             // per-workgroup complement rows of those vertices
+    B_HUB_DID,                  // pattern 17 hub pairs: number of each dense arc (or -1)
+    B_HUB_CNT, B_HUB_BASE,      // dense arcs per row and their exclusive prefix
+    B_HUB_KR,                   // first and last row of each chunk of dense edges
+    B_HUB_W,                    // W(i,j) of the hub pairs, R x R
+    B_HUB_Y,                    // one chunk of the hub / dense-edge incidence bytes
     B_COUNT
 };
 
@@ -142,6 +147,8 @@ struct esc_ctx {
     int k5_dense_pct;          // 5-cliques: density (percent) from which the complement count is used
     int wheel_split_deg;       // wheels: hubs above this degree are split into rim tasks
     int four_range_deg;        // 4-cycles: tops above this degree are split into key-range tasks
+    int pairs_hub_r;           // pattern 17: hub ranks of the hub-pair product (0: off)
+    int pairs_hub_q;           // pattern 17: hub apexes that make an edge dense
     int five_order;            // 5-cycles of one graph: 0 Y table when maxdeg < 2^16, 1 Wnt table
     size_t dev_mem;            // device memory in bytes
     // tuning: parameters in use, forced ones, the table

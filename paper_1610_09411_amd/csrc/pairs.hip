@@ -37,7 +37,9 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                                                   const int32_t *av, uint32_t *tab_all, int32_t *touch_all,
                                                   int32_t tab_n, int chunk, GMap gm, int *task, int32_t slab,
                                                   int32_t pw_words, unsigned long long *acc,
-                                                  unsigned long long *visits, uint64_t slice_ticks, int *done) {
+                                                  unsigned long long *visits, uint64_t slice_ticks, int *done,
+                                                  int32_t hub0, int32_t hub_r, const int32_t *did,
+                                                  uint32_t *wtop) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
     const uint64_t slice_end = slice_end_of(slice_ticks);
@@ -231,6 +233,13 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             });
         }
         __syncthreads();
+        // a hub source keeps its row W(i, j) over the later hubs for the
+        // hub-pair product (the slab holds every key from hub0 on)
+        if (i >= hub0) {
+            uint32_t *row = wtop + (size_t)(i - hub0) * hub_r;
+            for (int32_t j = i + 1 + threadIdx.x; j < ge; j += blockDim.x)
+                row[j - hub0] = j >= hi0 ? SLAB_GET(j) : TAB_GET(j);
+        }
         // diamonds with tips i and j (j after i): triangles (i,k,l), k<l, then
         // apexes j of edge (k,l) after i.  The entries l of the triangle
         // lists of the arcs (i,k), up to blockDim arcs at a time, are
@@ -261,8 +270,14 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                         const int64_t e0 = aoff[pk];
                         const int64_t x = e0 + (f - pref[lo]);
                         const int32_t l = apex_at<IDS>(av, adj, aa, x);
-                        if (l > adj[pk]) {
-                            const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - e0)];   // arc (k,l) in row k
+                        const int32_t qkl = l > adj[pk] ? (int32_t)aa[aoff[rev[pk]] + (x - e0)] : 0;   // arc (k,l) in row k
+                        // a hub source leaves the edges with many hub apexes
+                        // to the hub-pair product (every j after it is a hub);
+                        // such an edge has a number at its arc in the row of
+                        // its earlier end
+                        bool skip = l <= adj[pk];
+                        if (!skip && i >= hub0) skip = did[qkl] >= 0;
+                        if (!skip) {
                             int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
                             a1 = hi2;
                             while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
@@ -957,6 +972,263 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
     flush_count(nvis, visits);
 }
 
+
+// -------------------------------------------------- pattern 17, hub pairs
+//
+// Nearly all diamond work of a heavy-tailed graph has both tips among the
+// latest ranks (the hubs): an edge (k,l) inside the common neighbourhood of
+// many hubs is met once per pair of them.  Let the hubs be the latest R ranks
+// and call an edge dense when at least Q hubs are apexes of its triangles.
+// For hub tips i < j, the dense edges inside N(i) & N(j) number
+//     Dd(i,j) = sum_e Y(i,e) Y(j,e),   Y(v,e) = 1 when v is an apex of e,
+// a dense contraction over the dense edges.  The pattern-17 sum splits as
+// the diamond walk over the edges that are not dense (hub sources skip the
+// dense ones) plus sum_{hub i < j} (W(i,j) - 2) Dd(i,j), W from the rows
+// the hub sources keep.  Y is built in chunks of HUB_EC dense edges (one
+// byte per entry, 0 or 1) and contracted on the int8 matrix cores: the 0/1
+// bytes multiply exactly and a chunk's counts fit the 32-bit accumulators.
+
+#define HUB_EC 65536   // dense edges per chunk of Y (bytes of a Y row)
+#define HUB_T 256      // tile of the hub-pair product (hub rows and columns)
+#define HUB_K 128      // bytes of a row staged per step
+
+// Dense arcs of each row k: the arcs k -> l (l after k) whose triangle lists
+// hold at least q apexes from hub0 on (the lists are sorted by apex).  A
+// wave per row; cnt[k] = number of dense arcs.
+template <bool IDS>
+__global__ void __launch_bounds__(256) k_hub_count(int32_t n, const int32_t *off, const int32_t *split,
+                                                   const int32_t *adj, const int64_t *aoff, const uint32_t *aa,
+                                                   const int32_t *av, int32_t hub0, int32_t qmin, int64_t *cnt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t k = w0; k < n; k += nwv) {
+        uint32_t c = 0;
+        for (int32_t q = split[k] + lane; q < off[k + 1]; q += 64) {
+            int64_t lo = aoff[q], hi = aoff[q + 1];
+            const int64_t end = hi;
+            while (lo < hi) { const int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < hub0) lo = mid + 1; else hi = mid; }
+            c += end - lo >= qmin;
+        }
+        c = (uint32_t)wave_sum_u64(c);
+        if (lane == 0) cnt[k] = c;
+    }
+}
+
+// Number the dense arcs in arc order from base[k] (did = -1 for the other
+// arcs after the split); chunk c of HUB_EC numbers spans rows
+// kr[2c] .. kr[2c+1].
+template <bool IDS>
+__global__ void __launch_bounds__(256) k_hub_number(int32_t n, const int32_t *off, const int32_t *split,
+                                                    const int32_t *adj, const int64_t *aoff, const uint32_t *aa,
+                                                    const int32_t *av, int32_t hub0, int32_t qmin,
+                                                    const int64_t *base, int32_t *did, int32_t *kr) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t total = base[n];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t k = w0; k < n; k += nwv) {
+        int64_t next = base[k];
+        for (int32_t qb = split[k]; qb < off[k + 1]; qb += 64) {
+            const int32_t q = qb + lane;
+            bool dense = false;
+            if (q < off[k + 1]) {
+                int64_t lo = aoff[q], hi = aoff[q + 1];
+                const int64_t end = hi;
+                while (lo < hi) { const int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < hub0) lo = mid + 1; else hi = mid; }
+                dense = end - lo >= qmin;
+            }
+            const uint64_t m = __ballot(dense);
+            if (q < off[k + 1]) {
+                const int64_t d = next + __popcll(m & below);
+                did[q] = dense ? (int32_t)d : -1;
+                if (dense) {
+                    if (d % HUB_EC == 0) kr[2 * (d / HUB_EC)] = (int32_t)k;
+                    if (d % HUB_EC == HUB_EC - 1 || d == total - 1) kr[2 * (d / HUB_EC) + 1] = (int32_t)k;
+                }
+            }
+            next += __popcll(m);
+        }
+    }
+}
+
+// Rows of Y for one chunk: a workgroup per hub i sets, in an LDS row of kb
+// bytes, the byte of every dense edge (k,l) of the chunk with i as apex --
+// the entries l after k of the lists of the arcs (i,k), k in the chunk's
+// rows -- then stores the row.
+template <bool IDS>
+__global__ void __launch_bounds__(256) k_hub_rows(const int32_t *off, const int32_t *adj, const int32_t *rev,
+                                                  const int64_t *aoff, const uint32_t *aa, const int32_t *av,
+                                                  int32_t hub0, const int32_t *did, int64_t base, int32_t kb,
+                                                  const int32_t *kr, int32_t chunk, uint8_t *y) {
+    extern __shared__ uint32_t rowb[];
+    __shared__ int pref[257], tmp[8];
+    __shared__ int64_t beg[257];
+    const int32_t i = hub0 + (int32_t)blockIdx.x;
+    for (int q = threadIdx.x; q < kb / 4; q += blockDim.x) rowb[q] = 0;
+    const int32_t kf = kr[2 * chunk], kl = kr[2 * chunk + 1];
+    int32_t p0 = off[i], p1 = off[i + 1];
+    {
+        int32_t lo = p0, hi = p1;
+        while (lo < hi) { const int32_t mid = (lo + hi) >> 1; if (adj[mid] < kf) lo = mid + 1; else hi = mid; }
+        p0 = lo;
+        hi = p1;
+        while (lo < hi) { const int32_t mid = (lo + hi) >> 1; if (adj[mid] <= kl) lo = mid + 1; else hi = mid; }
+        p1 = lo;
+    }
+    __syncthreads();
+    for (int32_t bp = p0; bp < p1; bp += blockDim.x) {
+        const int32_t p = bp + threadIdx.x;
+        int64_t start = 0;
+        int len = 0;
+        if (p < p1) { start = aoff[p]; len = (int)(aoff[p + 1] - start); }
+        lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t x) {
+            const int32_t pk = bp + s;
+            if (apex_at<IDS>(av, adj, aa, x) > adj[pk]) {
+                const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - beg[s])];   // arc (k,l) in row k
+                const int64_t e = (int64_t)did[qkl] - base;
+                if (did[qkl] >= 0 && e >= 0 && e < kb) atomicOr(&rowb[e >> 2], 1u << ((e & 3) * 8));
+            }
+        });
+    }
+    __syncthreads();
+    uint4 *dst = (uint4 *)(y + (size_t)blockIdx.x * kb);
+    const uint4 *src = (const uint4 *)rowb;
+    for (int q = threadIdx.x; q < kb / 16; q += blockDim.x) dst[q] = src[q];
+}
+
+typedef int hub_v4i __attribute__((ext_vector_type(4)));
+
+// Tiles of the hub-pair product are grouped in patches of HUB_PR x HUB_PC
+// tiles (a patch of tile rows and columns with at least one tile on or above
+// the diagonal); patch p goes to XCD p mod 8 (workgroup b runs on XCD b mod
+// 8), its tiles to consecutive workgroups of that XCD, so the 32 CUs of an
+// XCD hold one patch at a time and read each of its HUB_PR row blocks and
+// HUB_PC column blocks once into their shared L2.
+#define HUB_PR 4
+#define HUB_PC 8
+
+// number of patches with a tile on or above the diagonal, and patch p's
+// first tile row and column
+__host__ __device__ inline int hub_patch_rows(int nb) { return (nb + HUB_PR - 1) / HUB_PR; }
+__host__ __device__ inline int hub_patch_cols(int nb) { return (nb + HUB_PC - 1) / HUB_PC; }
+__host__ __device__ inline int hub_npatches(int nb) {
+    int t = 0;
+    for (int a = 0; a < hub_patch_rows(nb); a++) {
+        const int c0 = (a * HUB_PR) / HUB_PC;   // first patch column reaching tile column a * HUB_PR
+        t += hub_patch_cols(nb) - c0;
+    }
+    return t;
+}
+
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// One step of operand bytes into an LDS buffer by direct global -> LDS
+// loads: the step's HUB_K bytes of the tile's 2 x HUB_T rows, as 64 loads
+// of 8 rows (1 KB, 16 bytes a lane, the lanes' bytes land one after the
+// other from the wave's LDS address), 8 per wave.  Row r keeps its 16-byte
+// chunk c at chunk position c ^ (r & 7) of its 128 LDS bytes, so the 8 rows
+// a fragment read touches at one chunk fall in distinct banks.
+__device__ inline void hub_stage(lds_u8 *buf, const uint8_t *ya, const uint8_t *yb, int32_t kb, int32_t k0, int wid,
+                                 int lane) {
+#pragma unroll
+    for (int u8 = 0; u8 < 8; u8++) {
+        const int u = wid * 8 + u8;                      // load number, 0..63
+        const int op = u >> 5, r0 = (u & 31) * 8;        // operand (A, B), first row
+        const int row = r0 + (lane >> 3), cpos = lane & 7;
+        const int cc = cpos ^ (row & 7);                 // the chunk that lands at cpos
+        const uint8_t *g = (op ? yb : ya) + (size_t)row * kb + k0 + cc * 16;
+        __builtin_amdgcn_global_load_lds((const void *)g, (lds_u8 *)(buf + op * HUB_T * HUB_K + r0 * HUB_K), 16, 0, 0);
+    }
+}
+
+// fragment of 16 rows from `row0` of one operand in an LDS buffer: lane
+// takes row row0 + (lane & 15), bytes kk + (lane >> 4) * 16 of the step
+__device__ inline hub_v4i hub_frag(const lds_u8 *opb, int row0, int kk, int lane) {
+    const int row = row0 + (lane & 15), c = (kk >> 4) + (lane >> 4);
+    return *(const __attribute__((address_space(3))) hub_v4i *)(opb + row * HUB_K + ((c ^ (row & 7)) << 4));
+}
+
+// sum over hub pairs i < j of one tile of (W(i,j) - 2) sum_e Y(i,e) Y(j,e),
+// over the kb bytes of the chunk's rows.  Eight waves in a 2 x 4 grid, each
+// a 128 x 64 part of the HUB_T x HUB_T tile: 8 x 4 products 16 x 16 x 64
+// (int8) per 64 bytes.  Operands pass through two LDS buffers: the loads of
+// the next step's bytes are in flight while the current step computes.
+__global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_r, int32_t kb, const uint32_t *wtop,
+                                                  int32_t nb, unsigned long long *acc) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
+    lds_u8 *lds = (lds_u8 *)hub_lds;
+    __shared__ u128 red[8];
+    // patch and tile of this workgroup
+    const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
+    const int patch = (local / (HUB_PR * HUB_PC)) * 8 + xcd, within = local % (HUB_PR * HUB_PC);
+    int pa_ = -1, pc_ = 0;
+    {
+        int t = patch;
+        for (int a = 0; a < hub_patch_rows(nb); a++) {
+            const int c0 = (a * HUB_PR) / HUB_PC, cnt = hub_patch_cols(nb) - c0;
+            if (t < cnt) { pa_ = a; pc_ = c0 + t; break; }
+            t -= cnt;
+        }
+    }
+    const int ti = pa_ * HUB_PR + within / HUB_PC, tj = pc_ * HUB_PC + within % HUB_PC;
+    if (pa_ < 0 || ti >= nb || tj >= nb || ti > tj) return;   // the whole workgroup leaves
+    const uint8_t *ya = y + (size_t)ti * HUB_T * kb, *yb = y + (size_t)tj * HUB_T * kb;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = (wid >> 2) * 128, wc = (wid & 3) * 64;
+    hub_v4i cacc[8][4];
+#pragma unroll
+    for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) cacc[a][b] = hub_v4i{0, 0, 0, 0};
+    const int bufsz = 2 * HUB_T * HUB_K;
+    hub_stage(lds, ya, yb, kb, 0, wid, lane);
+    __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0): this wave's loads have landed
+    __syncthreads();
+    int cur = 0;
+    for (int32_t k0 = 0; k0 < kb; k0 += HUB_K) {
+        if (k0 + HUB_K < kb) hub_stage(lds + (cur ^ 1) * bufsz, ya, yb, kb, k0 + HUB_K, wid, lane);
+        const lds_u8 *la = lds + cur * bufsz, *lb = la + HUB_T * HUB_K;
+#pragma unroll
+        for (int kk = 0; kk < HUB_K; kk += 64) {
+            hub_v4i fa[8], fb[4];
+#pragma unroll
+            for (int a = 0; a < 8; a++) fa[a] = hub_frag(la, wr + a * 16, kk, lane);
+#pragma unroll
+            for (int b = 0; b < 4; b++) fb[b] = hub_frag(lb, wc + b * 16, kk, lane);
+#pragma unroll
+            for (int a = 0; a < 8; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    cacc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], cacc[a][b], 0, 0, 0);
+        }
+        // the next buffer has landed (every wave's part) and the current one
+        // is read by every wave before it is loaded again
+        __builtin_amdgcn_s_waitcnt(0xF70);
+        __syncthreads();
+        cur ^= 1;
+    }
+    // result (r, c) of a 16 x 16 product: lane c + 16 * (r / 4), element r % 4
+    uint64_t s = 0;
+#pragma unroll
+    for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int32_t i = ti * HUB_T + wr + a * 16 + 4 * (lane >> 4) + r;
+                const int32_t j = tj * HUB_T + wc + b * 16 + (lane & 15);
+                if (i < j) {
+                    const uint32_t w = wtop[(size_t)i * hub_r + j];
+                    // a row left at 0 belongs to a source of degree <= 2, whose
+                    // pairs with a common edge have W = 2
+                    if (w > 2) s += (uint64_t)(w - 2) * (uint32_t)cacc[a][b][r];
+                }
+            }
+    u128 v[1] = {(u128)s};
+    const int ids[1] = {AC_N17};
+    block_flush_u128<1>(v, red, acc, ids);
+}
+
 // ------------------------------------------------------------------- stages
 
 static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int **task) {
@@ -969,6 +1241,84 @@ static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int 
     return ESC_OK;
 }
 
+// The hub-pair split of pattern 17 (above) for one graph: numbers the dense
+// edges and clears the kept W rows.  *hub0 = the first hub rank, or n when
+// the split is off (a batch, too few vertices, no memory); *ndense = the
+// number of dense edges.
+static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
+    const int32_t n = c->n, R = c->pairs_hub_r;
+    hipStream_t st = c->stream;
+    *hub0 = n;
+    *ndense = 0;
+    if (c->G || R <= 0 || (int64_t)n < 2 * (int64_t)R || c->narcs_apex == 0) return ESC_OK;
+    // the product's operand tiles and a chunk's Y row must fit a workgroup's LDS
+    if ((size_t)c->max_lds < 4 * (size_t)HUB_T * HUB_K + 1024 || (size_t)c->max_lds < (size_t)HUB_EC + 4096)
+        return ESC_OK;
+    const size_t need = sizeof(int32_t) * (size_t)c->m2 + 2 * sizeof(int64_t) * (size_t)(n + 1) +
+                        sizeof(uint32_t) * (size_t)R * R + (size_t)R * HUB_EC +
+                        sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2);
+    size_t free_b = 0;
+    ESC_TRY(ctx_free_bytes(c, &free_b));
+    if (need > free_b / 2) return ESC_OK;
+    int32_t *did = (int32_t *)ctx_buf(c, B_HUB_DID, sizeof(int32_t) * (size_t)c->m2);
+    int64_t *cnt = (int64_t *)ctx_buf(c, B_HUB_CNT, sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *base = (int64_t *)ctx_buf(c, B_HUB_BASE, sizeof(int64_t) * (size_t)(n + 1));
+    int32_t *kr = (int32_t *)ctx_buf(c, B_HUB_KR, sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2));
+    uint32_t *wtop = (uint32_t *)ctx_buf(c, B_HUB_W, sizeof(uint32_t) * (size_t)R * R);
+    if (!did || !cnt || !base || !kr || !wtop) return ESC_ENOMEM;
+    const int32_t h0 = n - R;
+    const int grid = grid_cap(c, (int64_t)n * 64, 256);
+    const int32_t *off = (const int32_t *)c->buf[B_OFF], *split = (const int32_t *)c->buf[B_SPLIT];
+    const int32_t *adj = (const int32_t *)c->buf[B_ADJ];
+    const int64_t *aoff = (const int64_t *)c->buf[B_AOFF];
+    const uint32_t *aa = (const uint32_t *)c->buf[B_AA];
+    HIP_TRY(hipMemsetAsync(cnt + n, 0, sizeof(int64_t), st));
+    if (c->av) k_hub_count<true><<<grid, 256, 0, st>>>(n, off, split, adj, aoff, aa, c->av, h0, c->pairs_hub_q, cnt);
+    else k_hub_count<false><<<grid, 256, 0, st>>>(n, off, split, adj, aoff, aa, c->av, h0, c->pairs_hub_q, cnt);
+    HIP_TRY(hipGetLastError());
+    ESC_TRY(dev_exclusive_scan_i64(c, cnt, base, n + 1));
+    if (c->av) k_hub_number<true><<<grid, 256, 0, st>>>(n, off, split, adj, aoff, aa, c->av, h0, c->pairs_hub_q, base, did, kr);
+    else k_hub_number<false><<<grid, 256, 0, st>>>(n, off, split, adj, aoff, aa, c->av, h0, c->pairs_hub_q, base, did, kr);
+    HIP_TRY(hipGetLastError());
+    int64_t nd = 0;
+    HIP_TRY(hipMemcpyAsync(&nd, base + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemsetAsync(wtop, 0, sizeof(uint32_t) * (size_t)R * R, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *hub0 = h0;
+    *ndense = nd;
+    return ESC_OK;
+}
+
+// sum_{hub i < j} (W(i,j) - 2) Dd(i,j) into pattern 17, chunk by chunk of
+// the dense edges
+static esc_status hub_product(esc_ctx *c, int32_t hub0, int64_t ndense) {
+    const int32_t R = c->pairs_hub_r;
+    hipStream_t st = c->stream;
+    if (ndense == 0) return ESC_OK;
+    uint8_t *y = (uint8_t *)ctx_buf(c, B_HUB_Y, (size_t)R * HUB_EC);
+    if (!y) return ESC_ENOMEM;
+    const int32_t nb = R / HUB_T;
+    const int nwg = 8 * HUB_PR * HUB_PC * ((hub_npatches(nb) + 7) / 8);
+    const size_t lds = 4 * (size_t)HUB_T * HUB_K;   // two buffers of both operands
+    const int64_t nchunks = (ndense + HUB_EC - 1) / HUB_EC;
+    auto rows = c->av ? k_hub_rows<true> : k_hub_rows<false>;
+    for (int64_t ch = 0; ch < nchunks; ch++) {
+        const int64_t base = ch * HUB_EC;
+        const int64_t left = ndense - base < HUB_EC ? ndense - base : HUB_EC;
+        const int32_t kb = (int32_t)((left + HUB_K - 1) / HUB_K * HUB_K);
+        rows<<<R, 256, (size_t)kb, st>>>((const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
+                                         (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
+                                         (const uint32_t *)c->buf[B_AA], c->av, hub0,
+                                         (const int32_t *)c->buf[B_HUB_DID], base, kb,
+                                         (const int32_t *)c->buf[B_HUB_KR], (int32_t)ch, y);
+        HIP_TRY(hipGetLastError());
+        k_hub_gemm<<<nwg, 512, lds, st>>>(y, R, kb, (const uint32_t *)c->buf[B_HUB_W], nb,
+                                          (unsigned long long *)c->buf[B_ACC]);
+        HIP_TRY(hipGetLastError());
+    }
+    return ESC_OK;
+}
+
 esc_status stage_pairs(esc_ctx *c) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
@@ -977,6 +1327,9 @@ esc_status stage_pairs(esc_ctx *c) {
     int32_t *touch;
     int *task;
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
+    int32_t hub0 = n;
+    int64_t ndense = 0;
+    ESC_TRY(hub_prepare(c, &hub0, &ndense));
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
     const int32_t slab = slab_words(c, slab_wgs_per_cu(c), 1, 16384, 16384);
@@ -986,15 +1339,19 @@ esc_status stage_pairs(esc_ctx *c) {
     const int32_t pw_words = c->G && c->tab_n <= 4096 && c->narcs_apex < ((int64_t)1 << 40) ? (c->tab_n + 1) / 2 : 0;
     const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
     auto kern = c->av ? k_pairs_wd<true> : k_pairs_wd<false>;
-    return run_sliced(c, "pairs_13_17", task + 8, task, [&](uint64_t ticks) -> esc_status {
+    const int32_t *did = hub0 < n ? (const int32_t *)c->buf[B_HUB_DID] : nullptr;
+    uint32_t *wtop = hub0 < n ? (uint32_t *)c->buf[B_HUB_W] : nullptr;
+    ESC_TRY(run_sliced(c, "pairs_13_17", task + 8, task, [&](uint64_t ticks) -> esc_status {
         kern<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
             n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_REV],
             (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av, tab, touch, c->tab_n,
             c->task_chunk, gmap_of(c), task, slab, pw_words, (unsigned long long *)c->buf[B_ACC],
-            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6, ticks, task + 8);
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6, ticks, task + 8, hub0, c->pairs_hub_r, did, wtop);
         HIP_TRY(hipGetLastError());
         return ESC_OK;
-    });
+    }));
+    if (hub0 < n) ESC_TRY(hub_product(c, hub0, ndense));
+    return ESC_OK;
 }
 
 esc_status stage_wheels(esc_ctx *c) {

@@ -405,6 +405,39 @@ def test_five_cliques_through_the_complement(ctx):
             assert got == want, (g.name, pct)
 
 
+def test_hub_pair_product(ctx):
+    """Pattern 17 with the diamonds of two hub tips over a dense edge summed
+    as the int8 product of the hub / dense-edge incidence (Thm 5cutwed):
+    hubs of one 256-rank tile up to 39 tiles, every edge with a hub apex
+    dense (several chunks of dense edges) or only the heaviest, the lists
+    with and without apex ids.  Same counts as the oracle."""
+    import paper_1610_09411_amd as esc
+    base = {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20}
+    g = synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2)
+    want = oracle.count(g, 5, threads=8)
+    try:
+        for r, q, flags in ((256, 1, 0), (512, 1, 0), (1024, 4, esc.ESC_F_COMPACT_LISTS), (8192, 1, 0),
+                            (8192, 64, 0), (9984, 2, esc.ESC_F_COMPACT_LISTS), (0, 1, 0)):
+            ctx.set_params(dict(base, pairs_hub_ranks=r, pairs_hub_q=q))
+            print("hubs", r, "q", q, "flags", flags, flush=True)
+            assert ctx.count(g, 5, flags=flags) == want, (r, q, flags)
+            assert ctx.count(g, 4, flags=flags) == want[:11], (r, q, flags)
+        # a near-clique core: edges with hundreds of hub apexes
+        gc = _dense_core_graph(2, core=300, per=400)
+        wc = oracle.count(gc, 5, threads=8)
+        for r, q in ((256, 1), (256, 100), (256, 1 << 30)):
+            ctx.set_params(dict(base, pairs_hub_ranks=r, pairs_hub_q=q))
+            print("dense core hubs", r, "q", q, flush=True)
+            assert ctx.count(gc, 5) == wc, (r, q)
+        for bad in ({"pairs_hub_ranks": 100}, {"pairs_hub_ranks": 384}, {"pairs_hub_ranks": 65536 + 256}, {"pairs_hub_ranks": -128},
+                    {"pairs_hub_q": 0}):
+            with pytest.raises(esc.EscapeError) as e:
+                ctx.set_params(dict(base, **bad))
+            assert e.value.status == esc.ESC_EINVAL, bad
+    finally:
+        ctx.set_params(None)
+
+
 def test_time_sliced_launches_give_same_counts():
     """Per-source kernels launched in 2 ms slices (ESC_SLICE_MS, read when
     the context is created): each stage is relaunched from its task counter

@@ -278,10 +278,12 @@ typedef struct {
                                latest this many ranks are hubs, and the
                                diamonds with two hub tips over a dense edge
                                are summed as a matrix product of the hub /
-                               dense-edge incidence; 0 (off) or a multiple
-                               of 256 up to 65536 (default 16384; off for
-                               batches and for graphs with fewer than twice
-                               as many vertices) */
+                               dense-edge incidence; 0 (off), a multiple of
+                               256 up to 65536, or -1: n / 256 rounded down
+                               to a multiple of 256, at most 16384 (the
+                               default).  Off for batches, for graphs with
+                               fewer than twice as many vertices and when
+                               its buffers would not fit the free memory */
     int32_t pairs_hub_q;    /* pattern 17: an edge is dense when at least
                                this many hubs close a triangle with it,
                                1..2^30 (default 256) */
@@ -290,8 +292,9 @@ typedef struct {
 /* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}
  * x wg_per_cu in {1, 2, 3}; then, one field at a time from the best so far,
  * four_range_deg in {128, 1024}, and for k = 5 k5_work_log2 in {22, 26},
- * k5_dense_pct in {25, 101}, k5_light in {32}, k5_wave_words in {4} and
- * wheel_split_deg in {256, 4096}; the other fields at their defaults),
+ * k5_dense_pct in {25, 101}, k5_light in {32}, k5_wave_words in {4},
+ * wheel_split_deg in {256, 4096} and pairs_hub_ranks in {0, 4096, 16384};
+ * the other fields at their defaults),
  * keep the fastest (total device time of the call) in the context's table
  * under the graph's key and return it in *best, its time in *best_ms
  * (nullable).  Arguments as in esc_count_subgraphs. */

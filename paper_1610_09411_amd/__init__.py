@@ -68,7 +68,7 @@ class _Params(ctypes.Structure):
 
 # defaults of the fields a set_params dict may leave out
 PARAM_DEFAULTS = {"five_order": 0, "k5_light": 64, "k5_wave_words": 8, "k5_dense_pct": 50,
-                  "wheel_split_deg": 1024, "four_range_deg": 256, "pairs_hub_ranks": 16384,
+                  "wheel_split_deg": 1024, "four_range_deg": 256, "pairs_hub_ranks": -1,
                   "pairs_hub_q": 256}
 
 

@@ -115,7 +115,7 @@ static esc_params default_params(const esc_ctx *c) {
     p.k5_dense_pct = 50;
     p.wheel_split_deg = 1024;
     p.four_range_deg = 256;
-    p.pairs_hub_ranks = 16384;
+    p.pairs_hub_ranks = -1;
     p.pairs_hub_q = 256;
     return p;
 }
@@ -153,7 +153,8 @@ static bool params_valid(const esc_params *p) {
            p->k5_dense_pct >= 0 && p->k5_dense_pct <= 101 &&
            p->wheel_split_deg >= 32 && p->wheel_split_deg <= (1 << 30) &&
            p->four_range_deg >= 16 && p->four_range_deg <= (1 << 30) &&
-           p->pairs_hub_ranks >= 0 && p->pairs_hub_ranks <= 65536 && p->pairs_hub_ranks % 256 == 0 &&
+           (p->pairs_hub_ranks == -1 ||
+            (p->pairs_hub_ranks >= 0 && p->pairs_hub_ranks <= 65536 && p->pairs_hub_ranks % 256 == 0)) &&
            p->pairs_hub_q >= 1 && p->pairs_hub_q <= (1 << 30);
 }
 
@@ -684,6 +685,7 @@ static esc_status tune_with(esc_ctx *c, int k, esc_params *best, float *best_ms,
         sweep(&esc_params::k5_light, {32});
         sweep(&esc_params::k5_wave_words, {4});
         sweep(&esc_params::wheel_split_deg, {256, 4096});
+        sweep(&esc_params::pairs_hub_ranks, {0, 4096, 16384});
     }
     restore();
     if (st != ESC_OK) return st;

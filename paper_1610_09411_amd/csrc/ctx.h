@@ -147,7 +147,8 @@ struct esc_ctx {
     int k5_dense_pct;          // 5-cliques: density (percent) from which the complement count is used
     int wheel_split_deg;       // wheels: hubs above this degree are split into rim tasks
     int four_range_deg;        // 4-cycles: tops above this degree are split into key-range tasks
-    int pairs_hub_r;           // pattern 17: hub ranks of the hub-pair product (0: off)
+    int pairs_hub_r;           // pattern 17: hub ranks of the hub-pair product (0: off, -1: by n)
+    int pairs_hub_used;        // hub ranks the last pair pass used (0: no product)
     int pairs_hub_q;           // pattern 17: hub apexes that make an edge dense
     int five_order;            // 5-cycles of one graph: 0 Y table when maxdeg < 2^16, 1 Wnt table
     size_t dev_mem;            // device memory in bytes

@@ -386,14 +386,76 @@ __global__ void __launch_bounds__(256) k_seg_wave(uint32_t *keys, const int64_t 
     }
 }
 
+// long segments: one workgroup per segment.  Keys that are distinct and
+// span fewer than 32 x (the LDS words) values -- a triangle list holds
+// distinct positions inside one row -- are sorted through a bitmap over
+// [min, max]: set a bit per key, then every thread emits the set bits of
+// its run of words at its place in the prefix count (O(len + span / 32),
+// a few barriers).  Other segments (repeated keys: the popcount falls
+// short of the length; a wider span) take the bitonic network in LDS.
 __global__ void __launch_bounds__(256) k_seg_lds(uint32_t *keys, const int64_t *seg_off, const int32_t *q,
-                                                 const int32_t *counts, int64_t qcap) {
+                                                 const int32_t *counts, int64_t qcap, int32_t lds_words) {
     extern __shared__ uint32_t sk[];
+    __shared__ uint32_t rmin[4], rmax[4];
+    __shared__ int tmp[8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int32_t cnt = counts[2];
     for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         int64_t s = q[2 * qcap + i];
         int64_t a = seg_off[s];
         int len = (int)(seg_off[s + 1] - a);
+        // span of the keys
+        uint32_t lo = 0xFFFFFFFFu, hi = 0;
+        for (int j = threadIdx.x; j < len; j += blockDim.x) {
+            const uint32_t k = keys[a + j];
+            lo = k < lo ? k : lo;
+            hi = k > hi ? k : hi;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t l2 = __shfl_xor(lo, o), h2 = __shfl_xor(hi, o);
+            lo = l2 < lo ? l2 : lo;
+            hi = h2 > hi ? h2 : hi;
+        }
+        if (lane == 0) { rmin[wid] = lo; rmax[wid] = hi; }
+        __syncthreads();
+        lo = rmin[0];
+        hi = rmax[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) {
+            lo = rmin[w] < lo ? rmin[w] : lo;
+            hi = rmax[w] > hi ? rmax[w] : hi;
+        }
+        const uint64_t span = (uint64_t)hi - lo + 1;
+        bool sorted = false;
+        if (span <= 32ull * (uint64_t)lds_words) {
+            const int nw = (int)((span + 31) >> 5);
+            for (int w = threadIdx.x; w < nw; w += blockDim.x) sk[w] = 0;
+            __syncthreads();
+            for (int j = threadIdx.x; j < len; j += blockDim.x) {
+                const uint32_t d = keys[a + j] - lo;
+                atomicOr(&sk[d >> 5], 1u << (d & 31));
+            }
+            __syncthreads();
+            // thread t owns words [t * per, (t + 1) * per)
+            const int per = (nw + (int)blockDim.x - 1) / (int)blockDim.x;
+            const int w0 = threadIdx.x * per, w1 = w0 + per < nw ? w0 + per : nw;
+            int mine = 0;
+            for (int w = w0; w < w1; w++) mine += __popc(sk[w]);
+            int total;
+            int pos = block_exclusive_scan(mine, tmp, &total);
+            if (total == len) {   // distinct keys: the bitmap holds them all
+                for (int w = w0; w < w1; w++) {
+                    uint32_t x = sk[w];
+                    while (x) {
+                        const int b = __ffs(x) - 1;
+                        x &= x - 1;
+                        keys[a + pos++] = lo + (uint32_t)(w * 32 + b);
+                    }
+                }
+                sorted = true;
+            }
+            __syncthreads();   // the bitmap is rewritten by the next segment or the network below
+        }
+        if (sorted) continue;
         int N = 1;
         while (N < len) N <<= 1;
         for (int j = threadIdx.x; j < N; j += blockDim.x) sk[j] = j < len ? keys[a + j] : 0xFFFFFFFFu;
@@ -470,7 +532,7 @@ esc_status dev_segsort_u32(esc_ctx *c, uint32_t *keys, const int64_t *seg_off, i
         int lds_n = 1;
         while (lds_n < maxlen && lds_n < lds_keys) lds_n <<= 1;
         int g = c->num_cu * 4;
-        k_seg_lds<<<g, 256, sizeof(uint32_t) * lds_n, st>>>(keys, seg_off, q, counts, nseg);
+        k_seg_lds<<<g, 256, sizeof(uint32_t) * lds_n, st>>>(keys, seg_off, q, counts, nseg, lds_n);
         HIP_TRY(hipGetLastError());
     }
     if (maxlen > lds_keys) {

@@ -1246,26 +1246,43 @@ static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int 
 // the split is off (a batch, too few vertices, no memory); *ndense = the
 // number of dense edges.
 static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
-    const int32_t n = c->n, R = c->pairs_hub_r;
+    const int32_t n = c->n;
     hipStream_t st = c->stream;
+    // -1: about one rank in 256, in whole tiles, at most 16384
+    int32_t R = c->pairs_hub_r;
+    if (R < 0) {
+        R = (int32_t)(((int64_t)n / 256) / HUB_T * HUB_T);
+        if (R > 16384) R = 16384;
+    }
     *hub0 = n;
     *ndense = 0;
     if (c->G || R <= 0 || (int64_t)n < 2 * (int64_t)R || c->narcs_apex == 0) return ESC_OK;
     // the product's operand tiles and a chunk's Y row must fit a workgroup's LDS
     if ((size_t)c->max_lds < 4 * (size_t)HUB_T * HUB_K + 1024 || (size_t)c->max_lds < (size_t)HUB_EC + 4096)
         return ESC_OK;
-    const size_t need = sizeof(int32_t) * (size_t)c->m2 + 2 * sizeof(int64_t) * (size_t)(n + 1) +
-                        sizeof(uint32_t) * (size_t)R * R + (size_t)R * HUB_EC +
-                        sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2);
+    // memory: what the buffers need beyond what they already hold, with 1 GiB
+    // left over for the later stages
+    const Buf bufs[6] = {B_HUB_DID, B_HUB_CNT, B_HUB_BASE, B_HUB_KR, B_HUB_W, B_HUB_Y};
+    const size_t sizes[6] = {sizeof(int32_t) * (size_t)c->m2, sizeof(int64_t) * (size_t)(n + 1),
+                             sizeof(int64_t) * (size_t)(n + 1), sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2),
+                             sizeof(uint32_t) * (size_t)R * R, (size_t)R * HUB_EC};
+    size_t more = 0;
+    for (int b = 0; b < 6; b++) {
+        const size_t want = sizes[b] + sizes[b] / 8 + ((size_t)2 << 20);   // ctx_buf's rounding
+        if (ctx_held(c, bufs[b]) < sizes[b]) more += want - ctx_held(c, bufs[b]);
+    }
     size_t free_b = 0;
     ESC_TRY(ctx_free_bytes(c, &free_b));
-    if (need > free_b / 2) return ESC_OK;
+    if (more + ((size_t)1 << 30) > free_b) return ESC_OK;
+    if (c->budget && c->held + more > c->budget) return ESC_OK;
     int32_t *did = (int32_t *)ctx_buf(c, B_HUB_DID, sizeof(int32_t) * (size_t)c->m2);
     int64_t *cnt = (int64_t *)ctx_buf(c, B_HUB_CNT, sizeof(int64_t) * (size_t)(n + 1));
     int64_t *base = (int64_t *)ctx_buf(c, B_HUB_BASE, sizeof(int64_t) * (size_t)(n + 1));
     int32_t *kr = (int32_t *)ctx_buf(c, B_HUB_KR, sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2));
     uint32_t *wtop = (uint32_t *)ctx_buf(c, B_HUB_W, sizeof(uint32_t) * (size_t)R * R);
-    if (!did || !cnt || !base || !kr || !wtop) return ESC_ENOMEM;
+    uint8_t *y = (uint8_t *)ctx_buf(c, B_HUB_Y, (size_t)R * HUB_EC);
+    if (!did || !cnt || !base || !kr || !wtop || !y) return ESC_OK;   // no room after all: off
+    c->pairs_hub_used = R;
     const int32_t h0 = n - R;
     const int grid = grid_cap(c, (int64_t)n * 64, 256);
     const int32_t *off = (const int32_t *)c->buf[B_OFF], *split = (const int32_t *)c->buf[B_SPLIT];
@@ -1292,11 +1309,10 @@ static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
 // sum_{hub i < j} (W(i,j) - 2) Dd(i,j) into pattern 17, chunk by chunk of
 // the dense edges
 static esc_status hub_product(esc_ctx *c, int32_t hub0, int64_t ndense) {
-    const int32_t R = c->pairs_hub_r;
+    const int32_t R = c->pairs_hub_used;
     hipStream_t st = c->stream;
     if (ndense == 0) return ESC_OK;
-    uint8_t *y = (uint8_t *)ctx_buf(c, B_HUB_Y, (size_t)R * HUB_EC);
-    if (!y) return ESC_ENOMEM;
+    uint8_t *y = (uint8_t *)c->buf[B_HUB_Y];
     const int32_t nb = R / HUB_T;
     const int nwg = 8 * HUB_PR * HUB_PC * ((hub_npatches(nb) + 7) / 8);
     const size_t lds = 4 * (size_t)HUB_T * HUB_K;   // two buffers of both operands
@@ -1329,6 +1345,7 @@ esc_status stage_pairs(esc_ctx *c) {
     ESC_TRY(pair_scratch(c, &tab, &touch, &task));
     int32_t hub0 = n;
     int64_t ndense = 0;
+    c->pairs_hub_used = 0;
     ESC_TRY(hub_prepare(c, &hub0, &ndense));
     HIP_TRY(hipMemsetAsync(task, 0, sizeof(int) * 16, st));
     // LDS slab for the latest keys of a graph, leaving room for the static arrays
@@ -1346,7 +1363,7 @@ esc_status stage_pairs(esc_ctx *c) {
             n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_REV],
             (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av, tab, touch, c->tab_n,
             c->task_chunk, gmap_of(c), task, slab, pw_words, (unsigned long long *)c->buf[B_ACC],
-            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6, ticks, task + 8, hub0, c->pairs_hub_r, did, wtop);
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6, ticks, task + 8, hub0, c->pairs_hub_used, did, wtop);
         HIP_TRY(hipGetLastError());
         return ESC_OK;
     }));

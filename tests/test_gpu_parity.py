@@ -168,6 +168,13 @@ def test_canonicalize_counts_the_described_graph(ctx):
         got = ctx.count(messy, 5, flags=esc.ESC_F_CANONICALIZE)
         assert got == oracle.count(g, 5, threads=8), g.name
         assert ctx.last_work()["m"] == g.m
+    # rows above 1024 entries with repeated neighbours: the long-segment sort
+    # meets repeated keys and takes its sorting network
+    g = synth.chung_lu(8000, 2.0, 12.0, 4000.0, 4)
+    messy = _messy_csr(g, 8)
+    assert int(np.diff(messy.row_ptr).max()) > 1024
+    assert ctx.count(messy, 4, flags=esc.ESC_F_CANONICALIZE) == oracle.count(g, 4, threads=8)
+    assert ctx.count(messy, 5, flags=esc.ESC_F_CANONICALIZE) == ctx.count(g, 5)
     bad = synth.Graph(3, np.array([0, 1, 2, 3], np.int32), np.array([1, 2, 5], np.int32))
     with pytest.raises(esc.EscapeError) as e:
         ctx.count(bad, 5, flags=esc.ESC_F_CANONICALIZE)

@@ -287,13 +287,27 @@ typedef struct {
     int32_t pairs_hub_q;    /* pattern 17: an edge is dense when at least
                                this many hubs close a triangle with it,
                                1..2^30 (default 256) */
+    int32_t wheel_dense_deg;/* wheels (pattern 18) of one graph: a hub with
+                               at least this many neighbours (at most 65536,
+                               among the latest 65536 ranks) whose walk
+                               would visit about S2/4 list entries (S2 = sum
+                               of t^2 over its edges) counts its rim
+                               4-cycles as (1/2) sum over rim pairs of
+                               C(c,2), c = (A A)(i,j) with A the adjacency
+                               of its neighbourhood, on the int8 matrix
+                               cores, when d^3/2 (d rounded up to 256) is
+                               below wheel_dense_ratio * S2/4; 0 (never) or
+                               4..2^30 (default 1024) */
+    int32_t wheel_dense_ratio; /* multiply-adds one walk visit is worth,
+                               1..2^20 (default 1024) */
 } esc_params;
 
 /* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}
  * x wg_per_cu in {1, 2, 3}; then, one field at a time from the best so far,
  * four_range_deg in {128, 1024}, and for k = 5 k5_work_log2 in {22, 26},
  * k5_dense_pct in {25, 101}, k5_light in {32}, k5_wave_words in {4},
- * wheel_split_deg in {256, 4096} and pairs_hub_ranks in {0, 4096, 16384};
+ * wheel_split_deg in {256, 4096}, pairs_hub_ranks in {0, 4096, 16384} and
+ * wheel_dense_deg in {0, 4096};
  * the other fields at their defaults),
  * keep the fastest (total device time of the call) in the context's table
  * under the graph's key and return it in *best, its time in *best_ms

@@ -6,6 +6,7 @@
 #include <initializer_list>
 #include <mutex>
 #include "device.h"
+#include <new>
 #include "ctx.h"
 
 void *ctx_buf(esc_ctx *c, Buf b, size_t bytes) {
@@ -117,6 +118,8 @@ static esc_params default_params(const esc_ctx *c) {
     p.four_range_deg = 256;
     p.pairs_hub_ranks = -1;
     p.pairs_hub_q = 256;
+    p.wheel_dense_deg = 1024;
+    p.wheel_dense_ratio = 1024;
     return p;
 }
 
@@ -141,6 +144,8 @@ static void select_params(esc_ctx *c) {
     c->four_range_deg = p.four_range_deg;
     c->pairs_hub_r = p.pairs_hub_ranks;
     c->pairs_hub_q = p.pairs_hub_q;
+    c->wheel_dense_deg = p.wheel_dense_deg;
+    c->wheel_dense_ratio = p.wheel_dense_ratio;
     c->params = p;
     c->params.wg_per_cu = c->wg_per_cu;
 }
@@ -155,7 +160,9 @@ static bool params_valid(const esc_params *p) {
            p->four_range_deg >= 16 && p->four_range_deg <= (1 << 30) &&
            (p->pairs_hub_ranks == -1 ||
             (p->pairs_hub_ranks >= 0 && p->pairs_hub_ranks <= 65536 && p->pairs_hub_ranks % 256 == 0)) &&
-           p->pairs_hub_q >= 1 && p->pairs_hub_q <= (1 << 30);
+           p->pairs_hub_q >= 1 && p->pairs_hub_q <= (1 << 30) &&
+           (p->wheel_dense_deg == 0 || (p->wheel_dense_deg >= 4 && p->wheel_dense_deg <= (1 << 30))) &&
+           p->wheel_dense_ratio >= 1 && p->wheel_dense_ratio <= (1 << 20);
 }
 
 static void store_tuned(esc_ctx *c, uint32_t key, const esc_params &p) {
@@ -217,7 +224,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hip_device < 0 || hip_device >= ndev) return ESC_EINVAL;
     HIP_TRY(hipSetDevice(hip_device));
     resolve_scratch(hip_device);
-    esc_ctx *c = (esc_ctx *)calloc(1, sizeof(esc_ctx));
+    esc_ctx *c = new (std::nothrow) esc_ctx();   // value-initialised: every plain field zero
     if (!c) return ESC_ENOMEM;
     c->device = hip_device;
     c->budget = hbm_budget_bytes;
@@ -228,7 +235,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) != hipSuccess || lds <= 0)
         lds = 65536;
     c->max_lds = lds;
-    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) { free(c); return ESC_EDEVICE; }
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) { delete c; return ESC_EDEVICE; }
     c->stream = c->own_stream;
     for (int i = 0; i <= NSTAGES; i++)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
@@ -250,6 +257,8 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
         c->four_range_deg = p.four_range_deg;
         c->pairs_hub_r = p.pairs_hub_ranks;
         c->pairs_hub_q = p.pairs_hub_q;
+        c->wheel_dense_deg = p.wheel_dense_deg;
+        c->wheel_dense_ratio = p.wheel_dense_ratio;
     }
     {
         const char *ms = getenv("ESC_SLICE_MS");
@@ -279,7 +288,7 @@ extern "C" void esc_destroy(esc_ctx *c) {
     for (int i = 0; i <= NSTAGES; i++)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
-    free(c);
+    delete c;
 }
 
 // per input vertex / arc: fragment counts in the caller's ids
@@ -686,6 +695,7 @@ static esc_status tune_with(esc_ctx *c, int k, esc_params *best, float *best_ms,
         sweep(&esc_params::k5_wave_words, {4});
         sweep(&esc_params::wheel_split_deg, {256, 4096});
         sweep(&esc_params::pairs_hub_ranks, {0, 4096, 16384});
+        sweep(&esc_params::wheel_dense_deg, {0, 4096});
     }
     restore();
     if (st != ESC_OK) return st;

@@ -231,7 +231,8 @@ __device__ void combine_one(const unsigned long long *acc, const int32_t *inv4, 
     N5[14] = S[AC_N15];
     N5[15] = S[AC_N16] - 12 * K4;
     N5[16] = S[AC_N17];
-    N5[17] = S[AC_N18];
+    // dense hubs: every rim 4-cycle was counted at both its diagonals
+    N5[17] = S[AC_N18] + (S[AC_WD2] >> 1);
     N5[18] = S[AC_N19];
     N5[19] = S[AC_N20];
     N5[20] = S[AC_K5];

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <stdio.h>
+#include <vector>
 #include "escape.h"
 
 // Indices of the exact 128-bit sums produced on the device.  Each stage adds
@@ -42,6 +43,7 @@ enum AccSlot {
     AC_K5,     // 5-cliques
     AC_SW,     // sum_b [C(d_b,2) d_b + (d_b-1) sum_{a in N(b)} d_a]
     AC_TD,     // sum_v t(v) d(v)
+    AC_WD2,    // wheels of the dense hubs, twice over: sum over rim pairs of C(c,2)
     AC_COUNT
 };
 
@@ -80,6 +82,8 @@ enum Buf {
     B_HUB_KR,                   // first and last row of each chunk of dense edges
     B_HUB_W,                    // W(i,j) of the hub pairs, R x R
     B_HUB_Y,                    // one chunk of the hub / dense-edge incidence bytes
+    B_WD_S2, B_WD_FLAG,         // wheels of dense hubs: sum of t^2 per candidate, chosen flags
+    B_WD_Y, B_WD_META,          // their adjacency matrices (a batch of hubs) and batch tables
     B_COUNT
 };
 
@@ -149,6 +153,11 @@ struct esc_ctx {
     int four_range_deg;        // 4-cycles: tops above this degree are split into key-range tasks
     int pairs_hub_r;           // pattern 17: hub ranks of the hub-pair product (0: off, -1: by n)
     int pairs_hub_used;        // hub ranks the last pair pass used (0: no product)
+    int wheel_dense_deg;       // wheels: hubs from this degree may take the product (0: never)
+    int wheel_dense_ratio;     // wheels: multiply-adds one walk visit is worth
+    std::vector<int32_t> wd_degs;   // row offsets of the latest ranks (for the chosen hubs)
+    int32_t wd_base;           // rank of wd_degs[0]
+    size_t wd_cap;             // bytes of the matrix buffer the chosen hubs go through
     int pairs_hub_q;           // pattern 17: hub apexes that make an edge dense
     int five_order;            // 5-cycles of one graph: 0 Y table when maxdeg < 2^16, 1 Wnt table
     size_t dev_mem;            // device memory in bytes

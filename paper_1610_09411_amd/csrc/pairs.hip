@@ -18,6 +18,7 @@
 //
 // Every per-source table is a dense per-workgroup array over the ranks of
 // the source's graph, reset through a list of touched keys.
+#include <vector>
 #include "device.h"
 #include "ctx.h"
 
@@ -351,13 +352,18 @@ __device__ inline int32_t wheel_rims(int32_t d, int32_t split_deg) { return d > 
 // keys per range of a hub with d neighbours (16-bit counts below 2^16)
 __device__ inline int32_t wheel_keys(int32_t d, int32_t wk) { return d < 65536 ? wk : wk / 2; }
 
+// hubs from rank wd_lo on with wflag set are counted by the product (below)
+__device__ inline bool wheel_dense(int32_t h, int32_t wd_lo, const uint8_t *wflag) {
+    return h >= wd_lo && wflag[h - wd_lo];
+}
+
 __global__ void k_wheel_tasks(int32_t n, const int32_t *off, int32_t wq, int32_t split_deg, int32_t wk,
-                              int64_t *len) {
+                              int32_t wd_lo, const uint8_t *wflag, int64_t *len) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t d = off[v + 1] - off[v];
         const int64_t nr = (d + wheel_rims(d, split_deg) - 1) / wheel_rims(d, split_deg);
         const int64_t nk = (d + wheel_keys(d, wk) - 1) / wheel_keys(d, wk);
-        len[v] = d > wq ? nr * nk : 0;
+        len[v] = d > wq && !wheel_dense(v, wd_lo, wflag) ? nr * nk : 0;
     }
 }
 
@@ -368,7 +374,8 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                                                 const int32_t *town,
                                                 int64_t nbig, int *task_big, int chunk, int32_t split_deg,
                                                 GMap gm, int *task, int tiny, unsigned long long *acc,
-                                                unsigned long long *visits, uint64_t slice_ticks, int *done) {
+                                                unsigned long long *visits, uint64_t slice_ticks, int *done,
+                                                int32_t wd_lo, const uint8_t *wflag) {
     uint64_t nvis = 0;
     const uint64_t slice_end = slice_end_of(slice_ticks);
     extern __shared__ uint32_t dyn[];
@@ -488,7 +495,8 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
         for (int32_t t = (int32_t)t0; t < t1; t++) {
             const int32_t h = n - 1 - t;
             const int32_t oh = off[h], dh = off[h + 1] - oh;
-            if (dh > wq || dh < 3) continue;   // large hubs are done; a wheel hub has 4 neighbours
+            // large hubs are done; a wheel hub has 4 neighbours
+            if (dh > wq || dh < 3 || wheel_dense(h, wd_lo, wflag)) continue;
             if (dh <= tiny) {
                 // one wave takes the whole hub: counts keyed by (rim index a,
                 // key), d(h)^2 16-bit counts in the wave's own table, so the
@@ -1148,34 +1156,30 @@ __device__ inline hub_v4i hub_frag(const lds_u8 *opb, int row0, int kk, int lane
     return *(const __attribute__((address_space(3))) hub_v4i *)(opb + row * HUB_K + ((c ^ (row & 7)) << 4));
 }
 
-// sum over hub pairs i < j of one tile of (W(i,j) - 2) sum_e Y(i,e) Y(j,e),
-// over the kb bytes of the chunk's rows.  Eight waves in a 2 x 4 grid, each
-// a 128 x 64 part of the HUB_T x HUB_T tile: 8 x 4 products 16 x 16 x 64
-// (int8) per 64 bytes.  Operands pass through two LDS buffers: the loads of
-// the next step's bytes are in flight while the current step computes.
-__global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_r, int32_t kb, const uint32_t *wtop,
-                                                  int32_t nb, unsigned long long *acc) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
-    lds_u8 *lds = (lds_u8 *)hub_lds;
-    __shared__ u128 red[8];
-    // patch and tile of this workgroup
-    const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
-    const int patch = (local / (HUB_PR * HUB_PC)) * 8 + xcd, within = local % (HUB_PR * HUB_PC);
+// Patch number -> tile (ti <= tj) of an nb x nb tile grid; false when the
+// patch or its tile lies outside the upper triangle.
+__device__ inline bool hub_patch_tile(int nb, int patch, int within, int *ti, int *tj) {
     int pa_ = -1, pc_ = 0;
-    {
-        int t = patch;
-        for (int a = 0; a < hub_patch_rows(nb); a++) {
-            const int c0 = (a * HUB_PR) / HUB_PC, cnt = hub_patch_cols(nb) - c0;
-            if (t < cnt) { pa_ = a; pc_ = c0 + t; break; }
-            t -= cnt;
-        }
+    int t = patch;
+    for (int a = 0; a < hub_patch_rows(nb); a++) {
+        const int c0 = (a * HUB_PR) / HUB_PC, cnt = hub_patch_cols(nb) - c0;
+        if (t < cnt) { pa_ = a; pc_ = c0 + t; break; }
+        t -= cnt;
     }
-    const int ti = pa_ * HUB_PR + within / HUB_PC, tj = pc_ * HUB_PC + within % HUB_PC;
-    if (pa_ < 0 || ti >= nb || tj >= nb || ti > tj) return;   // the whole workgroup leaves
+    *ti = pa_ * HUB_PR + within / HUB_PC;
+    *tj = pc_ * HUB_PC + within % HUB_PC;
+    return pa_ >= 0 && *ti < nb && *tj < nb && *ti <= *tj;
+}
+
+// One HUB_T x HUB_T tile (ti, tj) of Y Y^T over the kb bytes of the rows of
+// y (row stride kb): eight waves in a 2 x 4 grid, each a 128 x 64 part,
+// 8 x 4 products 16 x 16 x 64 (int8) per 64 bytes.  Operands pass through
+// two LDS buffers: the loads of the next step's bytes are in flight while
+// the current step computes.  Every thread of the workgroup calls it.
+__device__ inline void hub_tile(lds_u8 *lds, const uint8_t *y, int32_t kb, int ti, int tj, hub_v4i (&cacc)[8][4]) {
     const uint8_t *ya = y + (size_t)ti * HUB_T * kb, *yb = y + (size_t)tj * HUB_T * kb;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wr = (wid >> 2) * 128, wc = (wid & 3) * 64;
-    hub_v4i cacc[8][4];
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
@@ -1207,7 +1211,27 @@ __global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_
         __syncthreads();
         cur ^= 1;
     }
-    // result (r, c) of a 16 x 16 product: lane c + 16 * (r / 4), element r % 4
+}
+
+// Row i (within the tile, 0..HUB_T) and column j of accumulator element r of
+// product (a, b) of this lane: result (r, c) of a 16 x 16 product sits in
+// lane c + 16 * (r / 4), element r % 4.
+__device__ inline int hub_acc_row(int wid, int lane, int a, int r) { return (wid >> 2) * 128 + a * 16 + 4 * (lane >> 4) + r; }
+__device__ inline int hub_acc_col(int wid, int lane, int b) { return (wid & 3) * 64 + b * 16 + (lane & 15); }
+
+// sum over hub pairs i < j of one tile of (W(i,j) - 2) sum_e Y(i,e) Y(j,e),
+// over the kb bytes of the chunk's rows (tiles by patch, see above)
+__global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_r, int32_t kb, const uint32_t *wtop,
+                                                  int32_t nb, unsigned long long *acc) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
+    __shared__ u128 red[8];
+    const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
+    int ti, tj;
+    if (!hub_patch_tile(nb, (local / (HUB_PR * HUB_PC)) * 8 + xcd, local % (HUB_PR * HUB_PC), &ti, &tj))
+        return;   // the whole workgroup leaves
+    hub_v4i cacc[8][4];
+    hub_tile((lds_u8 *)hub_lds, y, kb, ti, tj, cacc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint64_t s = 0;
 #pragma unroll
     for (int a = 0; a < 8; a++)
@@ -1215,8 +1239,8 @@ __global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_
         for (int b = 0; b < 4; b++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int32_t i = ti * HUB_T + wr + a * 16 + 4 * (lane >> 4) + r;
-                const int32_t j = tj * HUB_T + wc + b * 16 + (lane & 15);
+                const int32_t i = ti * HUB_T + hub_acc_row(wid, lane, a, r);
+                const int32_t j = tj * HUB_T + hub_acc_col(wid, lane, b);
                 if (i < j) {
                     const uint32_t w = wtop[(size_t)i * hub_r + j];
                     // a row left at 0 belongs to a source of degree <= 2, whose
@@ -1227,6 +1251,100 @@ __global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_
     u128 v[1] = {(u128)s};
     const int ids[1] = {AC_N17};
     block_flush_u128<1>(v, red, acc, ids);
+}
+
+// ------------------------------------------------ pattern 18, dense hubs
+//
+// The rim 4-cycles of a hub h are the 4-cycles of G[N(h)]: with A_h its
+// 0/1 adjacency (rows and columns the positions in the row of h) and
+// c(i,j) = (A_h A_h)(i,j) the common neighbours of rim vertices i, j inside
+// N(h), each 4-cycle has two diagonals, so the hub's count is
+// (1/2) sum_{i<j} C(c(i,j), 2).  A hub whose walk would visit many list
+// entries (about S2/4, S2 = sum over its arcs of t^2) for its d^3/2
+// multiply-adds takes this product on the int8 matrix cores; the sum is
+// gathered twice over in AC_WD2 and halved when the counts are combined.
+// A batch of such hubs: matrix of hub q at byte mo[q] (dpad[q] x dpad[q],
+// dpad = d rounded up to HUB_T, zero beyond d), rows numbered from rp[q],
+// patches of its tile grid from pp[q].
+
+// row i of hub q's matrix: the list of arc (h, i-th neighbour) holds the
+// positions of the common neighbours in the row of h
+__global__ void __launch_bounds__(256) k_wheel_rows(const int32_t *off, const int64_t *aoff, const uint32_t *aa,
+                                                    int32_t nh, const int32_t *hub, const int32_t *dpad,
+                                                    const int64_t *rp, const int64_t *mo, uint8_t *y) {
+    extern __shared__ uint32_t rowb[];
+    int lo = 0, hi = nh - 1;   // last hub whose first row is <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const int32_t h = hub[lo], dp = dpad[lo];
+    const int64_t i = (int64_t)blockIdx.x - rp[lo];
+    const int32_t oh = off[h], d = off[h + 1] - oh;
+    for (int q = threadIdx.x; q < dp / 4; q += blockDim.x) rowb[q] = 0;
+    __syncthreads();
+    if (i < d) {
+        const int64_t x0 = aoff[oh + i], x1 = aoff[oh + i + 1];
+        for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+            const int32_t col = (int32_t)aa[x] - oh;
+            atomicOr(&rowb[col >> 2], 1u << ((col & 3) * 8));
+        }
+    }
+    __syncthreads();
+    uint4 *dst = (uint4 *)(y + mo[lo] + i * (int64_t)dp);
+    const uint4 *src = (const uint4 *)rowb;
+    for (int q = threadIdx.x; q < dp / 16; q += blockDim.x) dst[q] = src[q];
+}
+
+// sum over the hubs of a batch and their rim pairs i < j of C(c(i,j), 2)
+__global__ void __launch_bounds__(512) k_wheel_gemm(const uint8_t *y, int32_t nh, const int32_t *dpad,
+                                                    const int64_t *mo, const int32_t *pp,
+                                                    unsigned long long *acc) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
+    __shared__ u128 red[8];
+    const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
+    const int P = (local / (HUB_PR * HUB_PC)) * 8 + xcd;
+    if (P >= pp[nh]) return;   // the whole workgroup leaves
+    int lo = 0, hi = nh - 1;   // hub of patch P
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pp[mid] <= P) lo = mid; else hi = mid - 1;
+    }
+    const int32_t dp = dpad[lo];
+    int ti, tj;
+    if (!hub_patch_tile(dp / HUB_T, P - pp[lo], local % (HUB_PR * HUB_PC), &ti, &tj)) return;
+    hub_v4i cacc[8][4];
+    hub_tile((lds_u8 *)hub_lds, y + mo[lo], dp, ti, tj, cacc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t s = 0;
+#pragma unroll
+    for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int32_t i = ti * HUB_T + hub_acc_row(wid, lane, a, r);
+                const int32_t j = tj * HUB_T + hub_acc_col(wid, lane, b);
+                const uint64_t cij = (uint32_t)cacc[a][b][r];
+                if (i < j) s += cij * (cij - (cij > 0)) / 2;
+            }
+    u128 v[1] = {(u128)s};
+    const int ids[1] = {AC_WD2};
+    block_flush_u128<1>(v, red, acc, ids);
+}
+
+// S2 = sum over the arcs of hub h of t^2, for the candidates from rank lo on
+// (a wave per hub)
+__global__ void __launch_bounds__(256) k_wheel_s2(int32_t lo, int32_t n, const int32_t *off, const uint32_t *tarc,
+                                                  unsigned long long *s2) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t h = lo + w0; h < n; h += nwv) {
+        uint64_t x = 0;
+        for (int32_t p = off[h] + lane; p < off[h + 1]; p += 64) x += (uint64_t)tarc[p] * tarc[p];
+        x = wave_sum_u64(x);
+        if (lane == 0) s2[h - lo] = x;
+    }
 }
 
 // ------------------------------------------------------------------- stages
@@ -1371,6 +1489,135 @@ esc_status stage_pairs(esc_ctx *c) {
     return ESC_OK;
 }
 
+#define WD_CAND 65536      // hubs (latest ranks) considered for the dense wheel product
+#define WD_MAX_DEG 65536   // and at most this degree (its matrix row in LDS, 4 GiB matrix)
+
+// Hubs of one graph whose wheels go to the product: degree at least
+// wheel_dense_deg (and at most WD_MAX_DEG), among the latest WD_CAND ranks,
+// with dpad^3 / 2 < wheel_dense_ratio * S2 / 4.  *wd_lo = first candidate
+// rank, B_WD_FLAG[h - wd_lo] = 1 for the chosen hubs (listed in *dense).
+static esc_status wheel_dense_select(esc_ctx *c, int32_t *wd_lo, std::vector<int32_t> *dense) {
+    const int32_t n = c->n;
+    hipStream_t st = c->stream;
+    *wd_lo = n;
+    if (c->G || c->wheel_dense_deg <= 0 || c->maxdeg < c->wheel_dense_deg) return ESC_OK;
+    if ((size_t)c->max_lds < 4 * (size_t)HUB_T * HUB_K + 1024) return ESC_OK;
+    const int32_t K = n < WD_CAND ? n : WD_CAND;
+    std::vector<int32_t> hoff((size_t)K + 1);
+    HIP_TRY(hipMemcpyAsync(hoff.data(), (const int32_t *)c->buf[B_OFF] + (n - K), sizeof(int32_t) * ((size_t)K + 1),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int32_t first = K;   // first of the latest K ranks with degree >= wheel_dense_deg (degrees ascend)
+    while (first > 0 && hoff[first] - hoff[first - 1] >= c->wheel_dense_deg) first--;
+    if (first == K) return ESC_OK;
+    const int32_t lo = n - K + first, nc = n - lo;
+    unsigned long long *s2 = (unsigned long long *)ctx_buf(c, B_WD_S2, sizeof(uint64_t) * (size_t)nc);
+    uint8_t *flag = (uint8_t *)ctx_buf(c, B_WD_FLAG, (size_t)nc);
+    if (!s2 || !flag) return ESC_ENOMEM;
+    k_wheel_s2<<<grid_cap(c, (int64_t)nc * 64, 256), 256, 0, st>>>(lo, n, (const int32_t *)c->buf[B_OFF],
+                                                                   (const uint32_t *)c->buf[B_TARC], s2);
+    HIP_TRY(hipGetLastError());
+    std::vector<uint64_t> hs2((size_t)nc);
+    HIP_TRY(hipMemcpyAsync(hs2.data(), s2, sizeof(uint64_t) * (size_t)nc, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // matrix buffer: every chosen matrix, at most 8 GiB (the hubs then go in
+    // batches), at least the largest one; a matrix larger than the memory
+    // the buffer can have leaves its hub to the walk
+    size_t free_b = 0;
+    ESC_TRY(ctx_free_bytes(c, &free_b));
+    const size_t room = ctx_held(c, B_WD_Y) + (free_b > ((size_t)2 << 30) ? (free_b - ((size_t)2 << 30)) / 2 : 0);
+    std::vector<uint8_t> hf((size_t)nc, 0);
+    size_t total = 0, biggest = 0;
+    for (int32_t q = 0; q < nc; q++) {
+        const int32_t h = lo + q;
+        const int64_t d = hoff[h - (n - K) + 1] - hoff[h - (n - K)];
+        if (d > WD_MAX_DEG) continue;
+        const int64_t dpi = (d + HUB_T - 1) / HUB_T * HUB_T;
+        const double dp = (double)dpi;
+        if ((size_t)(dpi * dpi) > room) continue;
+        if (dp * dp * dp / 2 < (double)c->wheel_dense_ratio * (double)hs2[q] / 4) {
+            hf[q] = 1;
+            dense->push_back(h);
+            total += (size_t)(dpi * dpi);
+            biggest = (size_t)(dpi * dpi) > biggest ? (size_t)(dpi * dpi) : biggest;
+        }
+    }
+    if (dense->empty()) return ESC_OK;
+    size_t cap = total < ((size_t)8 << 30) ? total : ((size_t)8 << 30);
+    if (cap < biggest) cap = biggest;
+    if (cap > room) cap = room;   // >= biggest: every chosen matrix fits the room
+    c->wd_cap = cap;
+    HIP_TRY(hipMemcpyAsync(flag, hf.data(), (size_t)nc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // hf is a host temporary
+    c->wd_degs.assign(hoff.begin(), hoff.end());
+    c->wd_base = n - K;
+    *wd_lo = lo;
+    return ESC_OK;
+}
+
+// The chosen hubs in batches whose matrices fit the buffer: rows, then the
+// tile products of every hub of the batch in one launch.
+static esc_status wheel_dense_product(esc_ctx *c, const std::vector<int32_t> &dense) {
+    if (dense.empty()) return ESC_OK;
+    hipStream_t st = c->stream;
+    const int32_t n = c->n, K = n < WD_CAND ? n : WD_CAND;
+    auto deg = [&](int32_t h) { return (int64_t)(c->wd_degs[h - c->wd_base + 1] - c->wd_degs[h - c->wd_base]); };
+    auto pad = [&](int32_t h) { return (deg(h) + HUB_T - 1) / HUB_T * HUB_T; };
+    (void)K;
+    const size_t cap = c->wd_cap;   // holds the largest chosen matrix (wheel_dense_select)
+    uint8_t *y = (uint8_t *)ctx_buf(c, B_WD_Y, cap);
+    // per batch: hub, dpad, first row, matrix offset, first patch (int64 each)
+    const size_t nd = dense.size();
+    int64_t *meta = (int64_t *)ctx_buf(c, B_WD_META, sizeof(int64_t) * 5 * (nd + 1));
+    if (!y || !meta) return ESC_ENOMEM;
+    std::vector<int32_t> hub(nd + 1), dp(nd + 1), pp(nd + 1);
+    std::vector<int64_t> rp(nd + 1), mo(nd + 1);
+    const size_t lds = 4 * (size_t)HUB_T * HUB_K;
+    size_t q0 = 0;
+    while (q0 < nd) {
+        // one batch: hubs q0 .. q1-1
+        size_t q1 = q0;
+        int64_t bytes = 0, rows = 0;
+        int32_t patches = 0, maxdp = 0;
+        while (q1 < nd) {
+            const int64_t p = pad(dense[q1]);
+            if (q1 > q0 && bytes + p * p > (int64_t)cap) break;
+            hub[q1 - q0] = dense[q1];
+            dp[q1 - q0] = (int32_t)p;
+            rp[q1 - q0] = rows;
+            mo[q1 - q0] = bytes;
+            pp[q1 - q0] = patches;
+            rows += p;
+            bytes += p * p;
+            patches += hub_npatches((int)(p / HUB_T));
+            maxdp = (int32_t)p > maxdp ? (int32_t)p : maxdp;
+            q1++;
+        }
+        const int32_t nh = (int32_t)(q1 - q0);
+        rp[nh] = rows;
+        mo[nh] = bytes;
+        pp[nh] = patches;
+        int32_t *d_hub = (int32_t *)meta, *d_dp = d_hub + (nd + 1), *d_pp = d_dp + (nd + 1);
+        int64_t *d_rp = (int64_t *)(d_pp + (nd + 1) + ((nd + 1) & 1)), *d_mo = d_rp + (nd + 1);
+        HIP_TRY(hipMemcpyAsync(d_hub, hub.data(), sizeof(int32_t) * (nh + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_dp, dp.data(), sizeof(int32_t) * (nh + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_pp, pp.data(), sizeof(int32_t) * (nh + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_rp, rp.data(), sizeof(int64_t) * (nh + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_mo, mo.data(), sizeof(int64_t) * (nh + 1), hipMemcpyHostToDevice, st));
+        k_wheel_rows<<<(unsigned)rows, 256, (size_t)maxdp, st>>>((const int32_t *)c->buf[B_OFF],
+                                                                (const int64_t *)c->buf[B_AOFF],
+                                                                (const uint32_t *)c->buf[B_AA], nh, d_hub, d_dp, d_rp,
+                                                                d_mo, y);
+        HIP_TRY(hipGetLastError());
+        const int nwg = 8 * HUB_PR * HUB_PC * ((patches + 7) / 8);
+        k_wheel_gemm<<<nwg, 512, lds, st>>>(y, nh, d_dp, d_mo, d_pp, (unsigned long long *)c->buf[B_ACC]);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));   // the host arrays are rewritten by the next batch
+        q0 = q1;
+    }
+    return ESC_OK;
+}
+
 esc_status stage_wheels(esc_ctx *c) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
@@ -1403,27 +1650,33 @@ esc_status stage_wheels(esc_ctx *c) {
     if (per_cu > 4) per_cu = 4;
     if (per_cu < 1) per_cu = 1;
     int *task = (int *)ctx_buf(c, B_TASK, sizeof(int) * 16);
+    // hubs counted by the product instead of the walk
+    int32_t wd_lo = n;
+    std::vector<int32_t> dense;
+    ESC_TRY(wheel_dense_select(c, &wd_lo, &dense));
+    const uint8_t *wflag = wd_lo < n ? (const uint8_t *)c->buf[B_WD_FLAG] : nullptr;
     // tasks of the hubs with more than wq neighbours
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
     if (!len || !toff || !task) return ESC_ENOMEM;
     k_wheel_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], wq, c->wheel_split_deg, wk,
-                                                       len);
+                                                       wd_lo, wflag, len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     int64_t nbig = 0;
     int32_t *town = nullptr;
     ESC_TRY(dev_task_owner(c, n, toff, &nbig, &town));
     auto kern = c->av ? k_wheels<true> : k_wheels<false>;
-    return run_sliced(c, "wheels", task + 8, task + 1, [&](uint64_t ticks) -> esc_status {
+    ESC_TRY(run_sliced(c, "wheels", task + 8, task + 1, [&](uint64_t ticks) -> esc_status {
         kern<<<c->num_cu * per_cu, 64 * waves, lds, st>>>(
             n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int64_t *)c->buf[B_AOFF],
             (const uint32_t *)c->buf[B_AA], c->av, wq, wk, tab_words, toff, town, nbig, task + 4,
             c->task_chunk, c->wheel_split_deg, gmap_of(c), task + 1, tiny, (unsigned long long *)c->buf[B_ACC],
-            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7, ticks, task + 8);
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 7, ticks, task + 8, wd_lo, wflag);
         HIP_TRY(hipGetLastError());
         return ESC_OK;
-    });
+    }));
+    return wheel_dense_product(c, dense);
 }
 
 esc_status stage_cycles(esc_ctx *c) {

@@ -445,6 +445,35 @@ def test_hub_pair_product(ctx):
         ctx.set_params(None)
 
 
+def test_dense_hub_wheels(ctx):
+    """Pattern 18 with the rim 4-cycles of chosen hubs counted as
+    (1/2) sum over rim pairs of C(c,2), c = (A A)(i,j) over the adjacency of
+    the hub's neighbourhood on the int8 matrix cores: every hub from 4, 64 or
+    512 neighbours (matrices of one to six 256-tiles a side, several per
+    launch), the default choice, never; lists with and without apex ids.
+    Same counts as the oracle."""
+    import paper_1610_09411_amd as esc
+    base = {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20}
+    g = synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2)
+    want = oracle.count(g, 5, threads=8)
+    gc = _dense_core_graph(3)
+    wc = oracle.count(gc, 5, threads=8)
+    try:
+        for deg, ratio, flags in ((4, 1 << 20, 0), (64, 1 << 20, esc.ESC_F_COMPACT_LISTS), (512, 1 << 20, 0),
+                                  (1024, 256, 0), (0, 1, 0)):
+            ctx.set_params(dict(base, wheel_dense_deg=deg, wheel_dense_ratio=ratio))
+            print("dense wheels from", deg, "ratio", ratio, "flags", flags, flush=True)
+            assert ctx.count(g, 5, flags=flags) == want, (deg, ratio, flags)
+            assert ctx.count(gc, 5, flags=flags) == wc, (deg, ratio, flags)
+        for bad in ({"wheel_dense_deg": 3}, {"wheel_dense_deg": -1}, {"wheel_dense_ratio": 0},
+                    {"wheel_dense_ratio": (1 << 20) + 1}):
+            with pytest.raises(esc.EscapeError) as e:
+                ctx.set_params(dict(base, **bad))
+            assert e.value.status == esc.ESC_EINVAL, bad
+    finally:
+        ctx.set_params(None)
+
+
 def test_time_sliced_launches_give_same_counts():
     """Per-source kernels launched in 2 ms slices (ESC_SLICE_MS, read when
     the context is created): each stage is relaunched from its task counter

@@ -300,11 +300,20 @@ typedef struct {
                                4..2^30 (default 1024) */
     int32_t wheel_dense_ratio; /* multiply-adds one walk visit is worth,
                                1..2^20 (default 1024) */
+    int32_t k4_dense_dplus; /* 4-cliques per triangle (Thm 4clique) of one
+                               graph: a vertex a with at least this many
+                               out-neighbours (and at most 65536 neighbours)
+                               gets K4 of all its triangles (a,b,c), a
+                               earliest, from C = B B^T on the int8 matrix
+                               cores, B the 0/1 matrix of out-neighbours b
+                               by neighbours w of a, B(b,w) = [b ~ w];
+                               0 (never) or 16..2^30 (default 256) */
 } esc_params;
 
 /* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}
  * x wg_per_cu in {1, 2, 3}; then, one field at a time from the best so far,
- * four_range_deg in {128, 1024}, and for k = 5 k5_work_log2 in {22, 26},
+ * four_range_deg in {128, 1024}, k4_dense_dplus in {0, 1024}, and for
+ * k = 5 k5_work_log2 in {22, 26},
  * k5_dense_pct in {25, 101}, k5_light in {32}, k5_wave_words in {4},
  * wheel_split_deg in {256, 4096}, pairs_hub_ranks in {0, 4096, 16384} and
  * wheel_dense_deg in {0, 4096};

@@ -64,13 +64,14 @@ class _Params(ctypes.Structure):
                 ("k5_dense_pct", ctypes.c_int32), ("wheel_split_deg", ctypes.c_int32),
                 ("four_range_deg", ctypes.c_int32), ("pairs_hub_ranks", ctypes.c_int32),
                 ("pairs_hub_q", ctypes.c_int32), ("wheel_dense_deg", ctypes.c_int32),
-                ("wheel_dense_ratio", ctypes.c_int32)]
+                ("wheel_dense_ratio", ctypes.c_int32), ("k4_dense_dplus", ctypes.c_int32)]
 
 
 # defaults of the fields a set_params dict may leave out
 PARAM_DEFAULTS = {"five_order": 0, "k5_light": 64, "k5_wave_words": 8, "k5_dense_pct": 50,
                   "wheel_split_deg": 1024, "four_range_deg": 256, "pairs_hub_ranks": -1,
-                  "pairs_hub_q": 256, "wheel_dense_deg": 1024, "wheel_dense_ratio": 1024}
+                  "pairs_hub_q": 256, "wheel_dense_deg": 1024, "wheel_dense_ratio": 1024,
+                  "k4_dense_dplus": 256}
 
 
 def _params_dict(p):

@@ -76,6 +76,15 @@ esc_status ctx_free_bytes(esc_ctx *c, size_t *out) {
     return ESC_OK;
 }
 
+esc_status ctx_release_if_short(esc_ctx *c, std::initializer_list<Buf> bufs) {
+    if (c->arena) return ESC_OK;   // carved blocks are not freed
+    size_t fr = 0;
+    ESC_TRY(ctx_free_bytes(c, &fr));
+    if (fr >= ((size_t)64 << 30)) return ESC_OK;
+    for (Buf b : bufs) ctx_release(c, b);
+    return ESC_OK;
+}
+
 // Per-source kernels run up to three workgroups per CU (more resident waves
 // for their latency-bound gathers), fewer when their dense tables (two tables
 // and two touched lists of tab_n entries each) would pass an eighth of the
@@ -120,6 +129,7 @@ static esc_params default_params(const esc_ctx *c) {
     p.pairs_hub_q = 256;
     p.wheel_dense_deg = 1024;
     p.wheel_dense_ratio = 1024;
+    p.k4_dense_dplus = 256;
     return p;
 }
 
@@ -146,6 +156,7 @@ static void select_params(esc_ctx *c) {
     c->pairs_hub_q = p.pairs_hub_q;
     c->wheel_dense_deg = p.wheel_dense_deg;
     c->wheel_dense_ratio = p.wheel_dense_ratio;
+    c->k4_dense_dplus = p.k4_dense_dplus;
     c->params = p;
     c->params.wg_per_cu = c->wg_per_cu;
 }
@@ -162,7 +173,8 @@ static bool params_valid(const esc_params *p) {
             (p->pairs_hub_ranks >= 0 && p->pairs_hub_ranks <= 65536 && p->pairs_hub_ranks % 256 == 0)) &&
            p->pairs_hub_q >= 1 && p->pairs_hub_q <= (1 << 30) &&
            (p->wheel_dense_deg == 0 || (p->wheel_dense_deg >= 4 && p->wheel_dense_deg <= (1 << 30))) &&
-           p->wheel_dense_ratio >= 1 && p->wheel_dense_ratio <= (1 << 20);
+           p->wheel_dense_ratio >= 1 && p->wheel_dense_ratio <= (1 << 20) &&
+           (p->k4_dense_dplus == 0 || (p->k4_dense_dplus >= 16 && p->k4_dense_dplus <= (1 << 30)));
 }
 
 static void store_tuned(esc_ctx *c, uint32_t key, const esc_params &p) {
@@ -259,6 +271,7 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
         c->pairs_hub_q = p.pairs_hub_q;
         c->wheel_dense_deg = p.wheel_dense_deg;
         c->wheel_dense_ratio = p.wheel_dense_ratio;
+        c->k4_dense_dplus = p.k4_dense_dplus;
     }
     {
         const char *ms = getenv("ESC_SLICE_MS");
@@ -688,6 +701,7 @@ static esc_status tune_with(esc_ctx *c, int k, esc_params *best, float *best_ms,
         }
     };
     sweep(&esc_params::four_range_deg, {128, 1024});
+    sweep(&esc_params::k4_dense_dplus, {0, 1024});
     if (k == 5) {
         sweep(&esc_params::k5_work_log2, {22, 26});
         sweep(&esc_params::k5_dense_pct, {25, 101});

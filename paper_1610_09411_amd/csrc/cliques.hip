@@ -24,8 +24,10 @@
 // patterns j of (-1)^e(j) N_j(Hc), the non-induced counts of Hc given by
 // the 4-vertex formulas (Thm 4vertex-easy, Thm 4cycle, Thm 4clique) with
 // the disconnected patterns in closed form (App. A).
+#include <vector>
 #include "device.h"
 #include "ctx.h"
+#include "tiles.h"
 
 #define BM_WORDS 512   // LDS bitmap per wave: rows of up to 16384 vertices
 
@@ -51,7 +53,8 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
                                                       const int32_t *elo, const uint32_t *te, const int64_t *aoff,
                                                       const uint32_t *aa, const int32_t *av,
                                                       unsigned long long *k4e, GMap gm, int small,
-                                                      unsigned long long *acc, unsigned long long *visits) {
+                                                      unsigned long long *acc, unsigned long long *visits,
+                                                      const uint8_t *kdense) {
     __shared__ uint32_t bm_all[4][BM_WORDS];
     __shared__ u128 red[5 * 4];
     __shared__ int64_t wsa[4][64];
@@ -169,6 +172,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
         const int64_t l0 = aoff[p], l1 = aoff[p + 1];
         if (l1 == l0) continue;
         const int32_t a = elo[e], b = adj[p];
+        if (kdense && kdense[a]) continue;   // its triangles take the product (below)
         int64_t lo = l0, hi = l1;   // first apex after b
         while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
         if (lo == l1) continue;
@@ -237,6 +241,167 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
     if (batched) wave_flush_runs<5>(s, gcur, acc, ACC_STRIDE, ids);
     else block_flush_u128<5>(s, red, acc, ids);
     flush_count(nvis, visits);
+}
+
+// ------------------------------------------------- 4-cliques, dense rows
+//
+// For a vertex a, K4 of every triangle (a,b,c) with a earliest is
+// |N(a) & N(b) & N(c)| = (B_a B_a^T)(b,c), B_a the 0/1 matrix with a row per
+// out-neighbour b (its position in N+(a)) and a column per neighbour w of a
+// (its position in N(a)): B_a(b,w) = [b ~ w], read off the triangle list of
+// arc (a,b).  When N+(a) is large and dense (the core of a heavy-tailed
+// graph) the walk of Thm 4clique visits t(a,c) entries per triangle while
+// the product costs d+(a)^2 d(a) / 2 multiply-adds in all; such vertices
+// take the product on the int8 matrix cores and their triangles read K4 from
+// it.  A batch of them: vertex va[q], B_a at bo[q] (dpp[q] x dk[q] bytes:
+// d+ rounded up to HUB_T rows, d rounded up to HUB_K columns), C_a at co[q]
+// (dpp[q] x dpp[q] int32, the tiles on and above the diagonal), rows
+// numbered from rp[q], out-arcs from ap[q], product patches from pp[q].
+
+// row i of B_a (one workgroup per row)
+__global__ void __launch_bounds__(256) k_k4_rows(const int32_t *off, const int32_t *split, const int64_t *aoff,
+                                                 const uint32_t *aa, int32_t nq, const int32_t *va,
+                                                 const int32_t *dpp, const int32_t *dk, const int64_t *rp,
+                                                 const int64_t *bo, uint8_t *yb) {
+    extern __shared__ uint32_t rowb[];
+    int lo = 0, hi = nq - 1;   // last vertex whose first row is <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const int32_t a = va[lo], kb = dk[lo];
+    const int64_t i = (int64_t)blockIdx.x - rp[lo];
+    const int32_t oa = off[a], sa = split[a], dplus = off[a + 1] - sa;
+    for (int q = threadIdx.x; q < kb / 4; q += blockDim.x) rowb[q] = 0;
+    __syncthreads();
+    if (i < dplus) {
+        const int64_t x0 = aoff[sa + i], x1 = aoff[sa + i + 1];
+        for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+            const int32_t col = (int32_t)aa[x] - oa;   // position of w in N(a)
+            atomicOr(&rowb[col >> 2], 1u << ((col & 3) * 8));
+        }
+    }
+    __syncthreads();
+    uint4 *dst = (uint4 *)(yb + bo[lo] + i * (int64_t)kb);
+    const uint4 *src = (const uint4 *)rowb;
+    for (int q = threadIdx.x; q < kb / 16; q += blockDim.x) dst[q] = src[q];
+}
+
+// C_a = B_a B_a^T on the tiles on and above the diagonal
+__global__ void __launch_bounds__(512) k_k4_gemm(const uint8_t *yb, int32_t nq, const int32_t *dpp,
+                                                 const int32_t *dk, const int64_t *bo, const int64_t *co,
+                                                 const int32_t *pp, int32_t *cm) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
+    const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
+    const int P = (local / (HUB_PR * HUB_PC)) * 8 + xcd;
+    if (P >= pp[nq]) return;   // the whole workgroup leaves
+    int lo = 0, hi = nq - 1;   // vertex of patch P
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pp[mid] <= P) lo = mid; else hi = mid - 1;
+    }
+    const int32_t rows = dpp[lo];
+    int ti, tj;
+    if (!hub_patch_tile(rows / HUB_T, P - pp[lo], local % (HUB_PR * HUB_PC), &ti, &tj)) return;
+    hub_v4i cacc[8][4];
+    hub_tile((lds_u8 *)hub_lds, yb + bo[lo], dk[lo], ti, tj, cacc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t *out = cm + co[lo];
+#pragma unroll
+    for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t i = (int64_t)ti * HUB_T + hub_acc_row(wid, lane, a, r);
+                const int64_t j = (int64_t)tj * HUB_T + hub_acc_col(wid, lane, b);
+                out[i * rows + j] = cacc[a][b][r];
+            }
+}
+
+// The triangles (a,b,c), c after b, of the batch's vertices with K4 read
+// from C_a, and every per-triangle term of the walk kernel: one wave per
+// out-arc (a,b), a lane per triangle.
+template <bool IDS>
+__global__ void __launch_bounds__(256) k_k4_lookup(const int32_t *off, const int32_t *adj, const int32_t *split,
+                                                   const int32_t *rev, const int32_t *arc_eid, const uint32_t *te,
+                                                   const int64_t *aoff, const uint32_t *aa, const int32_t *av,
+                                                   int32_t nq, const int32_t *va, const int32_t *dpp,
+                                                   const int64_t *ap, const int64_t *co, const int32_t *cm,
+                                                   unsigned long long *k4e, unsigned long long *acc,
+                                                   unsigned long long *visits) {
+    __shared__ u128 red[5 * 4];
+    const int ids[5] = {AC_K4X4, AC_N20, AC_N10, AC_N16, AC_Z};
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    u128 s[5] = {0, 0, 0, 0, 0};
+    uint64_t nvis = 0;
+    for (int64_t w = w0; w < ap[nq]; w += nwv) {
+        int lo = 0, hi = nq - 1;   // vertex of out-arc w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ap[mid] <= w) lo = mid; else hi = mid - 1;
+        }
+        const int32_t a = va[lo], rows = dpp[lo];
+        const int64_t i = w - ap[lo];
+        const int32_t sa = split[a], p = sa + (int32_t)i, b = adj[p];
+        const int64_t l0 = aoff[p], l1 = aoff[p + 1];
+        int64_t kl = l0, kh = l1;   // first apex after b
+        while (kl < kh) { const int64_t mid = (kl + kh) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= b) kl = mid + 1; else kh = mid; }
+        if (kl == l1) continue;
+        nvis += (uint64_t)(l1 - kl);
+        const int32_t e = arc_eid[p];
+        const int64_t r0 = aoff[rev[p]];
+        const uint64_t da = off[a + 1] - off[a], db = off[b + 1] - off[b];
+        const uint64_t dpa = off[a + 1] - sa, dpb = off[b + 1] - split[b];
+        const uint64_t tab = te[e];
+        const int32_t *crow = cm + co[lo] + i * rows;
+        uint64_t k4sum = 0;
+        for (int64_t k = kl + lane; k < l1; k += 64) {
+            const int32_t cc = apex_at<IDS>(av, adj, aa, k);
+            const int32_t pac = (int32_t)aa[k];                  // arc (a,c) in row a
+            const int32_t pbc = (int32_t)aa[r0 + (k - l0)];      // arc (b,c) in row b
+            const uint32_t k4 = (uint32_t)crow[pac - sa];
+            const int32_t eac = arc_eid[pac], ebc = arc_eid[pbc];
+            const uint64_t tac = te[eac], tbc = te[ebc];
+            const uint64_t dc = off[cc + 1] - off[cc], dpc = off[cc + 1] - split[cc];
+            if (k4) {
+                atomicAdd(&k4e[eac], (unsigned long long)k4);
+                atomicAdd(&k4e[ebc], (unsigned long long)k4);
+            }
+            k4sum += k4;
+            s[0] += k4;
+            s[1] += c2(k4);
+            s[2] += (u128)(tbc - 1) * (da - 2) + (u128)(tac - 1) * (db - 2) + (u128)(tab - 1) * (dc - 2);
+            s[3] += (u128)(tab - 1) * (tac - 1) + (u128)(tab - 1) * (tbc - 1) + (u128)(tac - 1) * (tbc - 1);
+            s[4] += dpa + dpb + dpc - 3;
+        }
+        // the edge (a,b) takes the K4 of all its triangles after b at once
+        const uint64_t ksum = wave_sum_u64(k4sum);
+        if (lane == 0 && ksum) atomicAdd(&k4e[e], (unsigned long long)ksum);
+    }
+    block_flush_u128<5>(s, red, acc, ids);
+    flush_count(nvis, visits);
+}
+
+// candidates: out-degree at least dmin, degree at most K4_MAX_DEG (a row of
+// B_a in LDS); listed as (vertex, d+, d)
+#define K4_MAX_DEG 65536
+__global__ void k_k4_pick(int32_t n, const int32_t *off, const int32_t *split, int32_t dmin, int32_t *list,
+                          int *cnt) {
+    for (int32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+        const int32_t dp = off[a + 1] - split[a], d = off[a + 1] - off[a];
+        if (dp >= dmin && d <= K4_MAX_DEG) {
+            const int q = atomicAdd(cnt, 1);
+            list[3 * q] = a;
+            list[3 * q + 1] = dp;
+            list[3 * q + 2] = d;
+        }
+    }
+}
+
+__global__ void k_k4_flags(int32_t nq, const int32_t *list, uint8_t *flag) {
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) flag[list[q]] = 1;
 }
 
 // ---------------------------------------------------------------- 5-cliques
@@ -690,6 +855,142 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
 
 // ------------------------------------------------------------------- stages
 
+// Vertices whose triangles take the product: out-degree at least
+// k4_dense_dplus, their B_a and C_a within the memory the buffer can have.
+// Sets B_K4_FLAG and lists them (vertex, d+, d) in *dense.
+static esc_status k4_dense_select(esc_ctx *c, std::vector<int32_t> *dense) {
+    const int32_t n = c->n;
+    hipStream_t st = c->stream;
+    if (c->G || c->k4_dense_dplus <= 0 || c->maxdplus < c->k4_dense_dplus) return ESC_OK;
+    if ((size_t)c->max_lds < 4 * (size_t)HUB_T * HUB_K + 1024) return ESC_OK;
+    int32_t *list = (int32_t *)ctx_buf(c, B_K4_LIST, sizeof(int32_t) * 3 * (size_t)(n + 1));
+    int *cnt = (int *)ctx_buf(c, B_K4_CNT, sizeof(int) * 4);
+    uint8_t *flag = (uint8_t *)ctx_buf(c, B_K4_FLAG, (size_t)n + 1);
+    if (!list || !cnt || !flag) return ESC_ENOMEM;
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * 4, st));
+    HIP_TRY(hipMemsetAsync(flag, 0, (size_t)n + 1, st));
+    k_k4_pick<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_SPLIT],
+                                                   c->k4_dense_dplus, list, cnt);
+    HIP_TRY(hipGetLastError());
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h == 0) return ESC_OK;
+    std::vector<int32_t> all(3 * (size_t)h);
+    HIP_TRY(hipMemcpyAsync(all.data(), list, sizeof(int32_t) * 3 * (size_t)h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    size_t free_b = 0;
+    ESC_TRY(ctx_free_bytes(c, &free_b));
+    const size_t room = ctx_held(c, B_K4_Y) +
+                        (free_b > ((size_t)2 << 30) ? (free_b - ((size_t)2 << 30)) / 2 : 0);
+    size_t total = 0, biggest = 0;
+    std::vector<int32_t> ids;
+    for (int q = 0; q < h; q++) {
+        const size_t dpp = ((size_t)all[3 * q + 1] + HUB_T - 1) / HUB_T * HUB_T;
+        const size_t dk = ((size_t)all[3 * q + 2] + HUB_K - 1) / HUB_K * HUB_K;
+        const size_t bytes = dpp * dk + 4 * dpp * dpp;
+        if (bytes > room) continue;
+        dense->insert(dense->end(), {all[3 * q], all[3 * q + 1], all[3 * q + 2]});
+        ids.push_back(all[3 * q]);
+        total += bytes;
+        biggest = bytes > biggest ? bytes : biggest;
+    }
+    if (ids.empty()) return ESC_OK;
+    size_t cap = total < ((size_t)8 << 30) ? total : ((size_t)8 << 30);
+    if (cap < biggest) cap = biggest;
+    if (cap > room) cap = room;
+    c->k4_cap = cap;
+    HIP_TRY(hipMemcpyAsync(list, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, st));
+    k_k4_flags<<<grid_cap(c, (int64_t)ids.size(), 256), 256, 0, st>>>((int32_t)ids.size(), list, flag);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));   // ids is a host temporary
+    return ESC_OK;
+}
+
+// The chosen vertices in batches through the B and C buffers: rows of B_a,
+// the products C_a, then their triangles.
+static esc_status k4_dense_product(esc_ctx *c, const std::vector<int32_t> &dense) {
+    const size_t nd = dense.size() / 3;
+    if (nd == 0) return ESC_OK;
+    hipStream_t st = c->stream;
+    // the B and C parts of a batch share the cap: B bytes first, C after
+    const size_t cap = c->k4_cap;
+    uint8_t *yb = (uint8_t *)ctx_buf(c, B_K4_Y, cap + 256);   // C starts 16-byte aligned after B
+    int64_t *meta = (int64_t *)ctx_buf(c, B_K4_META, sizeof(int64_t) * 8 * (nd + 1));
+    if (!yb || !meta) return ESC_ENOMEM;
+    std::vector<int32_t> va(nd + 1), dpp(nd + 1), dk(nd + 1), pp(nd + 1);
+    std::vector<int64_t> rp(nd + 1), ap(nd + 1), bo(nd + 1), co(nd + 1);
+    const size_t lds = 4 * (size_t)HUB_T * HUB_K;
+    int32_t *d_va = (int32_t *)meta, *d_dpp = d_va + (nd + 1), *d_dk = d_dpp + (nd + 1), *d_pp = d_dk + (nd + 1);
+    int64_t *d_rp = meta + 2 * (nd + 1), *d_ap = d_rp + (nd + 1), *d_bo = d_ap + (nd + 1), *d_co = d_bo + (nd + 1);
+    size_t q0 = 0;
+    while (q0 < nd) {
+        size_t q1 = q0;
+        size_t bbytes = 0, cbytes = 0;
+        int64_t rows = 0, arcs = 0;
+        int32_t patches = 0, maxk = 0;
+        while (q1 < nd) {
+            const int32_t dplus = dense[3 * q1 + 1];
+            const int64_t r = ((int64_t)dplus + HUB_T - 1) / HUB_T * HUB_T;
+            const int64_t k = ((int64_t)dense[3 * q1 + 2] + HUB_K - 1) / HUB_K * HUB_K;
+            if (q1 > q0 && bbytes + cbytes + (size_t)(r * k + 4 * r * r) > cap) break;
+            const size_t j = q1 - q0;
+            va[j] = dense[3 * q1];
+            dpp[j] = (int32_t)r;
+            dk[j] = (int32_t)k;
+            rp[j] = rows;
+            ap[j] = arcs;
+            bo[j] = (int64_t)bbytes;
+            co[j] = (int64_t)(cbytes / 4);
+            pp[j] = patches;
+            rows += r;
+            arcs += dplus;
+            bbytes += (size_t)(r * k);
+            cbytes += (size_t)(4 * r * r);
+            patches += hub_npatches((int)(r / HUB_T));
+            maxk = (int32_t)k > maxk ? (int32_t)k : maxk;
+            q1++;
+        }
+        const int32_t nq = (int32_t)(q1 - q0);
+        rp[nq] = rows;
+        ap[nq] = arcs;
+        bo[nq] = (int64_t)bbytes;
+        co[nq] = (int64_t)(cbytes / 4);
+        pp[nq] = patches;
+        // C after the B part, 16-byte aligned
+        const size_t cstart = (bbytes + 15) & ~(size_t)15;
+        int32_t *cm = (int32_t *)(yb + cstart);
+        HIP_TRY(hipMemcpyAsync(d_va, va.data(), sizeof(int32_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_dpp, dpp.data(), sizeof(int32_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_dk, dk.data(), sizeof(int32_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_pp, pp.data(), sizeof(int32_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_rp, rp.data(), sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_ap, ap.data(), sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_bo, bo.data(), sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_co, co.data(), sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, st));
+        k_k4_rows<<<(unsigned)rows, 256, (size_t)maxk, st>>>((const int32_t *)c->buf[B_OFF],
+                                                            (const int32_t *)c->buf[B_SPLIT],
+                                                            (const int64_t *)c->buf[B_AOFF],
+                                                            (const uint32_t *)c->buf[B_AA], nq, d_va, d_dpp, d_dk,
+                                                            d_rp, d_bo, yb);
+        HIP_TRY(hipGetLastError());
+        const int nwg = 8 * HUB_PR * HUB_PC * ((patches + 7) / 8);
+        k_k4_gemm<<<nwg, 512, lds, st>>>(yb, nq, d_dpp, d_dk, d_bo, d_co, d_pp, cm);
+        HIP_TRY(hipGetLastError());
+        auto look = c->av ? k_k4_lookup<true> : k_k4_lookup<false>;
+        look<<<grid_cap(c, arcs * 64, 256, 8), 256, 0, st>>>(
+            (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
+            (const int32_t *)c->buf[B_REV], (const int32_t *)c->buf[B_ARC_EID], (const uint32_t *)c->buf[B_TE],
+            (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av, nq, d_va, d_dpp, d_ap, d_co,
+            cm, (unsigned long long *)c->buf[B_K4E], (unsigned long long *)c->buf[B_ACC],
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));   // the host arrays are rewritten by the next batch
+        q0 = q1;
+    }
+    return ESC_OK;
+}
+
 esc_status stage_k4_triangles(esc_ctx *c) {
     hipStream_t st = c->stream;
     const int64_t m = c->m;
@@ -697,6 +998,9 @@ esc_status stage_k4_triangles(esc_ctx *c) {
     if (!k4e) return ESC_ENOMEM;
     HIP_TRY(hipMemsetAsync(k4e, 0, sizeof(uint64_t) * (size_t)(m + 1), st));
     if (m == 0 || c->narcs_apex == 0) return ESC_OK;
+    std::vector<int32_t> dense;
+    ESC_TRY(k4_dense_select(c, &dense));
+    const uint8_t *kflag = dense.empty() ? nullptr : (const uint8_t *)c->buf[B_K4_FLAG];
     auto kern = c->av ? k_k4_triangles<true> : k_k4_triangles<false>;
     kern<<<grid_cap(c, m * 64, 256, 8), 256, 0, st>>>(
         m, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_SPLIT],
@@ -704,9 +1008,10 @@ esc_status stage_k4_triangles(esc_ctx *c) {
         (const int32_t *)c->buf[B_ELO], (const uint32_t *)c->buf[B_TE], (const int64_t *)c->buf[B_AOFF],
         (const uint32_t *)c->buf[B_AA], c->av, k4e, gmap_of(c), c->G && c->tab_n <= 4096 ? 1 : 0,
         (unsigned long long *)c->buf[B_ACC],
-        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3);
+        (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3, kflag);
     HIP_TRY(hipGetLastError());
-    return ESC_OK;
+    ESC_TRY(k4_dense_product(c, dense));
+    return ctx_release_if_short(c, {B_K4_Y});
 }
 
 esc_status stage_k5(esc_ctx *c) {

@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdio.h>
 #include <vector>
+#include <initializer_list>
 #include "escape.h"
 
 // Indices of the exact 128-bit sums produced on the device.  Each stage adds
@@ -84,6 +85,8 @@ enum Buf {
     B_HUB_Y,                    // one chunk of the hub / dense-edge incidence bytes
     B_WD_S2, B_WD_FLAG,         // wheels of dense hubs: sum of t^2 per candidate, chosen flags
     B_WD_Y, B_WD_META,          // their adjacency matrices (a batch of hubs) and batch tables
+    B_K4_LIST, B_K4_CNT, B_K4_FLAG,   // 4-cliques of dense rows: candidates, count, chosen flags
+    B_K4_Y, B_K4_META,          // their B_a and C_a matrices (a batch) and batch tables
     B_COUNT
 };
 
@@ -158,6 +161,8 @@ struct esc_ctx {
     std::vector<int32_t> wd_degs;   // row offsets of the latest ranks (for the chosen hubs)
     int32_t wd_base;           // rank of wd_degs[0]
     size_t wd_cap;             // bytes of the matrix buffer the chosen hubs go through
+    int k4_dense_dplus;        // 4-cliques: vertices from this out-degree take the product (0: never)
+    size_t k4_cap;             // bytes of the B_a / C_a buffer of the chosen vertices
     int pairs_hub_q;           // pattern 17: hub apexes that make an edge dense
     int five_order;            // 5-cycles of one graph: 0 Y table when maxdeg < 2^16, 1 Wnt table
     size_t dev_mem;            // device memory in bytes
@@ -225,6 +230,10 @@ void ctx_release(esc_ctx *c, Buf b);
 // Device bytes still free for the call's buffers: the device's free memory,
 // or what is left of the fixed region of a no-allocation call.
 esc_status ctx_free_bytes(esc_ctx *c, size_t *out);
+// Release the buffers listed when the device has less than 64 GiB free
+// (a graph whose triangle lists fill the device): a stage's large scratch
+// then goes back before the next stage sizes its own.
+esc_status ctx_release_if_short(esc_ctx *c, std::initializer_list<Buf> bufs);
 esc_status ctx_check(hipError_t e);
 
 // B_WORK layout: [0] W++, [1] W+-, [2 + s] visits of stage s (see esc_last_profile),

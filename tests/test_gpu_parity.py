@@ -474,6 +474,37 @@ def test_dense_hub_wheels(ctx):
         ctx.set_params(None)
 
 
+def test_dense_row_four_cliques(ctx):
+    """Thm 4clique with K4 of the triangles (a,b,c), a earliest, read from
+    C = B B^T on the int8 matrix cores for vertices a with many
+    out-neighbours (B: out-neighbours by neighbours of a): from 16, 64, 256
+    out-neighbours or never, lists with and without apex ids.  Same 45
+    counts and the same per-edge and per-vertex K4 as the oracle."""
+    import paper_1610_09411_amd as esc
+    base = {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20}
+    g = synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2)
+    want = oracle.count(g, 5, threads=8)
+    gf = synth.chung_lu(4000, 1.9, 20.0, 900.0, 6)
+    S, it = oracle.sums(gf, 4, per_item=True)
+    gc = _dense_core_graph(4)
+    wc = oracle.count(gc, 5, threads=8)
+    try:
+        for dmin, flags in ((16, 0), (64, esc.ESC_F_COMPACT_LISTS), (256, 0), (0, 0)):
+            ctx.set_params(dict(base, k4_dense_dplus=dmin))
+            print("dense K4 rows from", dmin, "flags", flags, flush=True)
+            assert ctx.count(g, 5, flags=flags) == want, (dmin, flags)
+            assert ctx.count(gc, 5, flags=flags) == wc, (dmin, flags)
+            counts, fr = ctx.fragments(gf, 4, flags=flags)
+            assert np.array_equal(fr["k4_e"], it["k4_e"]), (dmin, flags)
+            assert np.array_equal(fr["k4_v"], it["k4_v"]), (dmin, flags)
+        for bad in ({"k4_dense_dplus": 15}, {"k4_dense_dplus": -1}):
+            with pytest.raises(esc.EscapeError) as e:
+                ctx.set_params(dict(base, **bad))
+            assert e.value.status == esc.ESC_EINVAL, bad
+    finally:
+        ctx.set_params(None)
+
+
 def test_time_sliced_launches_give_same_counts():
     """Per-source kernels launched in 2 ms slices (ESC_SLICE_MS, read when
     the context is created): each stage is relaunched from its task counter

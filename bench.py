@@ -32,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak (5.0 POP/s; one multiply-add = 2 ops)
 BYTES_PER_VISIT = 4     # one int32 neighbour / triangle-list entry per visited element
 TRAFFIC_FILES = {"chung_lu_4m": os.path.join(ROOT, "profiles", "traffic_chung_lu_4m.json"),
                  "chung_lu_1m": os.path.join(ROOT, "profiles", "traffic_chung_lu_1m.json")}
@@ -154,7 +155,9 @@ def main():
     if big and (args.small or args.cpu_sample > 0):
         g1 = synth.chung_lu_1m(args.seed)
         if args.small:
-            small = run_single(esc, ctx, torch, g1, "chung_lu_1m", args.steps, args.warmup, stream)
+            # at least one warm-up call: the first call on a context sizes
+            # its buffers (seconds for the per-workgroup tables)
+            small = run_single(esc, ctx, torch, g1, "chung_lu_1m", args.steps, max(args.warmup, 1), stream)
     else:
         g1 = head_g
 
@@ -191,7 +194,9 @@ def main():
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "stages_ms": head["stages_ms"],
+        "walks_ms": head["walks_ms"],
         "stages_visits": head["stages_visits"],
+        "products": head["products"],
         "work": head["work"],
         "launch_params": head["launch_params"],
         "checksum": head["checksum"],
@@ -213,8 +218,10 @@ WORKLOADS = {
 def run_single(esc, ctx, torch, g, name, steps, warmup, stream, seed=0):
     """`warmup` untimed then `steps` timed k = 5 calls on graph g (CSR resident
     on the device); per-stage device times and visits averaged over the timed
-    calls; the roofline of the stage with the largest device time (each heavy
-    stage is one kernel launch, bracketed by HIP events on the call's stream)."""
+    calls, each stage split into its walk and its matrix-core product
+    (esc_last_products; HIP events on the call's stream); the roofline of
+    the longest of those kernels: a walk against the HBM peak (4 bytes per
+    visited element), a product against the int8 matrix-core peak."""
     n, m = g.n, g.m
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
@@ -223,6 +230,7 @@ def run_single(esc, ctx, torch, g, name, steps, warmup, stream, seed=0):
     for _ in range(warmup):
         counts = esc.esc_count_subgraphs(ctx.ptr, n, rp, col, 5, stream=stream)
     prof_sum = {k: [0.0, 0] for k in esc.STAGES}
+    prod_sum = {k: [0.0, 0.0, 0] for k in esc.STAGES}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -230,23 +238,46 @@ def run_single(esc, ctx, torch, g, name, steps, warmup, stream, seed=0):
         for k, (ms, vis) in esc.esc_last_profile(ctx.ptr).items():
             prof_sum[k][0] += ms
             prof_sum[k][1] += vis
+        for k, (wms, pms, macs) in esc.esc_last_products(ctx.ptr).items():
+            prod_sum[k][0] += wms
+            prod_sum[k][1] += pms
+            prod_sum[k][2] += macs
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1000.0 / steps
     prof = {k: (v[0] / steps, v[1] / steps) for k, v in prof_sum.items()}
-    dom = max(prof, key=lambda k: prof[k][0])
-    dom_ms, dom_vis = prof[dom]
-    achieved = dom_vis * BYTES_PER_VISIT / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
-    tbytes = measured_traffic(name, dom)
-    traffic = tbytes / (dom_ms / 1000.0) / 1e9 if (tbytes is not None and dom_ms > 0) else None
+    prods = {k: (v[0] / steps, v[1] / steps, v[2] / steps) for k, v in prod_sum.items()}
+    # the dominant kernel: a stage's walk (the whole stage where it has no
+    # matrix-core product; HBM-bound list reads) or a stage's product (int8
+    # matrix cores), whichever takes longest
+    walk_dom = max(prods, key=lambda k: prods[k][0])
+    prod_dom = max(prods, key=lambda k: prods[k][1])
+    products = {k: {"ms": round(v[1], 3), "multiply_adds": int(v[2]),
+                    "achieved_tops": 2 * v[2] / (v[1] / 1000.0) / 1e12 if v[1] > 0 else 0.0,
+                    "frac": 2 * v[2] / (v[1] / 1000.0) / 1e12 / INT8_PEAK_TOPS if v[1] > 0 else 0.0}
+                for k, v in prods.items() if v[2] > 0}
+    if prods[prod_dom][1] > prods[walk_dom][0] and prods[prod_dom][2] > 0:
+        pk = products[prod_dom]
+        roofline = {"bound": "mfma", "kernel": prod_dom + " product", "achieved": pk["achieved_tops"],
+                    "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "frac": pk["frac"], "traffic": None,
+                    "traffic_bytes_per_launch": None, "algorithmic_ops": 2 * prods[prod_dom][2]}
+    else:
+        dom = walk_dom
+        dom_ms, dom_vis = prods[dom][0], prof[dom][1]
+        achieved = dom_vis * BYTES_PER_VISIT / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
+        tbytes = measured_traffic(name, dom)
+        traffic = tbytes / (dom_ms / 1000.0) / 1e9 if (tbytes is not None and dom_ms > 0) else None
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": tbytes,
+                    "algorithmic_bytes_per_launch": dom_vis * BYTES_PER_VISIT}
     del rp, col
     return {"value": m / (ms_per_step / 1000.0), "ms_per_step": ms_per_step, "steps": steps, "warmup": warmup,
             "config": {"workload": WORKLOADS[name] % seed, "n": n, "m": m, "k": 5, "parallelism": "single GPU"},
-            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": tbytes,
-                         "algorithmic_bytes_per_launch": dom_vis * BYTES_PER_VISIT},
+            "roofline": roofline,
             "stages_ms": {k: round(v[0], 3) for k, v in prof.items()},
+            "walks_ms": {k: round(v[0], 3) for k, v in prods.items()},
             "stages_visits": {k: int(v[1]) for k, v in prof.items()},
+            "products": products,
             "work": esc.esc_last_work(ctx.ptr),
             "launch_params": ctx.last_params(),
             "checksum": {"sum_4": str(sum(counts[:11])), "sum_5": str(sum(counts[11:])),

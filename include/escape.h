@@ -379,6 +379,17 @@ esc_status esc_last_three(const esc_ctx *ctx, esc_u128 *out);
  * read, bitmap words for 5-cliques; 0 where not counted). */
 esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64_t *visits_out);
 
+/* Split of the last successful call's stages into their walk and their
+ * int8 matrix-core product (the 4-cliques of dense out-neighbourhoods in
+ * stage 3, Thm 4clique; the pattern-17 pairs of hubs in stage 6, Thm
+ * 5cutwed; the wheels of dense hubs in stage 7), stages as in
+ * esc_last_profile, each of the three arrays 10 entries, nullable:
+ * `walk_ms` device milliseconds from the stage's start to the end of its
+ * walk (the whole stage where it has no product), `product_ms` the rest of
+ * the stage (rows and products), `product_macs` multiply-adds the products
+ * issued (tiles of 256 x 256 over their padded depth). */
+esc_status esc_last_products(const esc_ctx *ctx, float *walk_ms, float *product_ms, uint64_t *product_macs);
+
 /* The signed inverse of the matrix that maps induced to non-induced counts
  * (Appendix B, figures A and A^-1), as the library builds and applies it:
  * 11 x 11 for k = 4, 34 x 34 for k = 5, rows and columns in the output order

@@ -35,7 +35,7 @@ ABI_FUNCTIONS = [
     "esc_count_batched",
     "esc_server_start", "esc_submit", "esc_poll", "esc_wait", "esc_server_stats", "esc_server_stop",
     "esc_tune", "esc_tune_batched", "esc_set_params", "esc_last_params",
-    "esc_last_work", "esc_last_profile", "esc_last_noninduced", "esc_last_three", "esc_inverse_matrix", "esc_strerror",
+    "esc_last_work", "esc_last_profile", "esc_last_products", "esc_last_noninduced", "esc_last_three", "esc_inverse_matrix", "esc_strerror",
 ]
 
 PATTERN_NAMES = [
@@ -130,6 +130,8 @@ def _load():
         lib.esc_last_work.restype = ctypes.c_int
         lib.esc_last_profile.argtypes = [vp, vp, vp]
         lib.esc_last_profile.restype = ctypes.c_int
+        lib.esc_last_products.argtypes = [vp, vp, vp, vp]
+        lib.esc_last_products.restype = ctypes.c_int
         lib.esc_last_noninduced.argtypes = [vp, vp]
         lib.esc_last_noninduced.restype = ctypes.c_int
         lib.esc_last_three.argtypes = [vp, vp]
@@ -229,6 +231,9 @@ class Context:
 
     def last_profile(self):
         return esc_last_profile(self.ptr)
+
+    def last_products(self):
+        return esc_last_products(self.ptr)
 
     def last_noninduced(self, k=5):
         return esc_last_noninduced(self.ptr, k)
@@ -439,6 +444,15 @@ def esc_last_profile(ctx):
     vis = (ctypes.c_uint64 * len(STAGES))()
     _check(_load().esc_last_profile(ctx, ms, vis), "esc_last_profile")
     return {k: (float(ms[i]), int(vis[i])) for i, k in enumerate(STAGES)}
+
+
+def esc_last_products(ctx):
+    """{stage: (walk ms, product ms, product multiply-adds)} of the last call."""
+    w = (ctypes.c_float * len(STAGES))()
+    p = (ctypes.c_float * len(STAGES))()
+    mac = (ctypes.c_uint64 * len(STAGES))()
+    _check(_load().esc_last_products(ctx, w, p, mac), "esc_last_products")
+    return {k: (float(w[i]), float(p[i]), int(mac[i])) for i, k in enumerate(STAGES)}
 
 
 def esc_inverse_matrix(k):

@@ -78,6 +78,9 @@ esc_status ctx_free_bytes(esc_ctx *c, size_t *out) {
 
 esc_status ctx_release_if_short(esc_ctx *c, std::initializer_list<Buf> bufs) {
     if (c->arena) return ESC_OK;   // carved blocks are not freed
+    bool any = false;
+    for (Buf b : bufs) any = any || c->buf[b] != nullptr;
+    if (!any) return ESC_OK;   // nothing to give back: no memory query
     size_t fr = 0;
     ESC_TRY(ctx_free_bytes(c, &fr));
     if (fr >= ((size_t)64 << 30)) return ESC_OK;
@@ -251,6 +254,8 @@ extern "C" esc_status esc_create(esc_ctx **out, int hip_device, size_t hbm_budge
     c->stream = c->own_stream;
     for (int i = 0; i <= NSTAGES; i++)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
+    for (int i = 0; i < NSTAGES; i++)
+        if (hipEventCreate(&c->ev_walk[i]) != hipSuccess) { esc_destroy(c); return ESC_EDEVICE; }
     int32_t h4[121], h5[1156];
     combine_tables(h4, h5);
     if (hipMalloc((void **)&c->d_inv4, sizeof(h4)) != hipSuccess ||
@@ -300,6 +305,8 @@ extern "C" void esc_destroy(esc_ctx *c) {
     if (c->d_inv5) (void)hipFree(c->d_inv5);
     for (int i = 0; i <= NSTAGES; i++)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    for (int i = 0; i < NSTAGES; i++)
+        if (c->ev_walk[i]) (void)hipEventDestroy(c->ev_walk[i]);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
@@ -365,6 +372,10 @@ static esc_status pipeline(esc_ctx *c, const int32_t *d_rp, const int32_t *d_col
         HIP_TRY(hipMemsetAsync(c->buf[B_WG_SCRATCH], 0, c->cap[B_WG_SCRATCH], st));
     }
     c->scratch_clean = false;   // until the pipeline completes
+    for (int i = 0; i < NSTAGES; i++) {
+        c->walk_rec[i] = false;
+        c->prod_macs[i] = 0;
+    }
     int ev = 0;
 #define STAGE(call)                                  \
     do {                                             \
@@ -410,6 +421,10 @@ esc_status call_finish(esc_ctx *c, uint64_t w, uint64_t t3, uint64_t d) {
         (void)hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
         c->stage_ms[i] = ms;
         c->visits[i] = hw[WORK_VISITS + i];
+        float wm = ms;
+        if (c->walk_rec[i]) (void)hipEventElapsedTime(&wm, c->ev[i], c->ev_walk[i]);
+        c->walk_ms[i] = wm;
+        c->prod_ms[i] = ms - wm;
     }
     c->scratch_clean = true;
     return ESC_OK;
@@ -778,6 +793,15 @@ extern "C" esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64
     if (!ctx) return ESC_EINVAL;
     if (ms_out) memcpy(ms_out, ctx->stage_ms, sizeof(float) * NSTAGES);
     if (visits_out) memcpy(visits_out, ctx->visits, sizeof(uint64_t) * NSTAGES);
+    return ESC_OK;
+}
+
+extern "C" esc_status esc_last_products(const esc_ctx *ctx, float *walk_ms, float *product_ms,
+                                        uint64_t *product_macs) {
+    if (!ctx) return ESC_EINVAL;
+    if (walk_ms) memcpy(walk_ms, ctx->walk_ms, sizeof(float) * NSTAGES);
+    if (product_ms) memcpy(product_ms, ctx->prod_ms, sizeof(float) * NSTAGES);
+    if (product_macs) memcpy(product_macs, ctx->prod_macs, sizeof(uint64_t) * NSTAGES);
     return ESC_OK;
 }
 

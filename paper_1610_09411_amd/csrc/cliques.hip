@@ -949,6 +949,7 @@ static esc_status k4_dense_product(esc_ctx *c, const std::vector<int32_t> &dense
             cbytes += (size_t)(4 * r * r);
             patches += hub_npatches((int)(r / HUB_T));
             maxk = (int32_t)k > maxk ? (int32_t)k : maxk;
+            c->prod_macs[STAGE_K4] += (uint64_t)((r / HUB_T) * (r / HUB_T + 1) / 2) * HUB_T * HUB_T * (uint64_t)k;
             q1++;
         }
         const int32_t nq = (int32_t)(q1 - q0);
@@ -1010,6 +1011,7 @@ esc_status stage_k4_triangles(esc_ctx *c) {
         (unsigned long long *)c->buf[B_ACC],
         (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 3, kflag);
     HIP_TRY(hipGetLastError());
+    ESC_TRY(mark_walk_end(c, STAGE_K4));
     ESC_TRY(k4_dense_product(c, dense));
     return ctx_release_if_short(c, {B_K4_Y});
 }

@@ -91,6 +91,10 @@ enum Buf {
 };
 
 #define NSTAGES 10
+// stage numbers (esc_last_profile order) of the stages with products
+#define STAGE_K4 3
+#define STAGE_PAIRS 6
+#define STAGE_WHEELS 7
 
 // Per-graph sums: graph g's slots start at acc + g * ACC_STRIDE.
 #define ACC_STRIDE (2 * AC_COUNT)
@@ -124,6 +128,13 @@ struct esc_ctx {
     int max_lds;               // bytes of LDS one workgroup may allocate
     uint64_t work[ESC_WORK_COUNTERS];
     float stage_ms[NSTAGES];
+    // stages with a matrix-core product after their walk: an event at the
+    // walk's end (walk_rec), the walk's and the product's times and the
+    // product's multiply-adds (see esc_last_products)
+    hipEvent_t ev_walk[NSTAGES];
+    bool walk_rec[NSTAGES];
+    float walk_ms[NSTAGES], prod_ms[NSTAGES];
+    uint64_t prod_macs[NSTAGES];
     uint64_t visits[NSTAGES];
     esc_u128 noninduced[45];
     esc_u128 three[4];         // induced 3-vertex counts of the last single-graph call
@@ -276,6 +287,13 @@ esc_status run_sliced(esc_ctx *c, const char *name, int *done, const int *counte
             fflush(stderr);
         }
     }
+}
+
+// the walk of stage s has been enqueued: its products follow
+inline esc_status mark_walk_end(esc_ctx *c, int s) {
+    if (hipEventRecord(c->ev_walk[s], c->stream) != hipSuccess) return ESC_EDEVICE;
+    c->walk_rec[s] = true;
+    return ESC_OK;
 }
 
 // pipeline stages (each returns ESC_OK or an error)

@@ -1333,6 +1333,7 @@ static esc_status hub_product(esc_ctx *c, int32_t hub0, int64_t ndense) {
         k_hub_gemm<<<nwg, 512, lds, st>>>(y, R, kb, (const uint32_t *)c->buf[B_HUB_W], nb,
                                           (unsigned long long *)c->buf[B_ACC]);
         HIP_TRY(hipGetLastError());
+        c->prod_macs[STAGE_PAIRS] += (uint64_t)(nb * (nb + 1) / 2) * HUB_T * HUB_T * (uint64_t)kb;
     }
     return ESC_OK;
 }
@@ -1369,6 +1370,7 @@ esc_status stage_pairs(esc_ctx *c) {
         HIP_TRY(hipGetLastError());
         return ESC_OK;
     }));
+    ESC_TRY(mark_walk_end(c, STAGE_PAIRS));
     if (hub0 < n) ESC_TRY(hub_product(c, hub0, ndense));
     return ctx_release_if_short(c, {B_HUB_Y, B_HUB_W, B_HUB_DID});
 }
@@ -1475,6 +1477,7 @@ static esc_status wheel_dense_product(esc_ctx *c, const std::vector<int32_t> &de
             bytes += p * p;
             patches += hub_npatches((int)(p / HUB_T));
             maxdp = (int32_t)p > maxdp ? (int32_t)p : maxdp;
+            c->prod_macs[STAGE_WHEELS] += (uint64_t)((p / HUB_T) * (p / HUB_T + 1) / 2) * HUB_T * HUB_T * (uint64_t)p;
             q1++;
         }
         const int32_t nh = (int32_t)(q1 - q0);
@@ -1560,6 +1563,7 @@ esc_status stage_wheels(esc_ctx *c) {
         HIP_TRY(hipGetLastError());
         return ESC_OK;
     }));
+    ESC_TRY(mark_walk_end(c, STAGE_WHEELS));
     ESC_TRY(wheel_dense_product(c, dense));
     return ctx_release_if_short(c, {B_WD_Y});
 }

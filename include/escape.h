@@ -279,8 +279,8 @@ typedef struct {
                                diamonds with two hub tips over a dense edge
                                are summed as a matrix product of the hub /
                                dense-edge incidence; 0 (off), a multiple of
-                               256 up to 65536, or -1: n / 256 rounded down
-                               to a multiple of 256, at most 16384 (the
+                               256 up to 65536, or -1: n / 160 rounded down
+                               to a multiple of 256, at most 24576 (the
                                default).  Off for batches, for graphs with
                                fewer than twice as many vertices and when
                                its buffers would not fit the free memory */

@@ -1250,11 +1250,11 @@ static esc_status pair_scratch(esc_ctx *c, uint32_t **tab, int32_t **touch, int 
 static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
     const int32_t n = c->n;
     hipStream_t st = c->stream;
-    // -1: about one rank in 256, in whole tiles, at most 16384
+    // -1: about one rank in 160, in whole tiles, at most 24576
     int32_t R = c->pairs_hub_r;
     if (R < 0) {
-        R = (int32_t)(((int64_t)n / 256) / HUB_T * HUB_T);
-        if (R > 16384) R = 16384;
+        R = (int32_t)(((int64_t)n / 160) / HUB_T * HUB_T);
+        if (R > 24576) R = 24576;
     }
     *hub0 = n;
     *ndense = 0;

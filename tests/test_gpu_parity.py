@@ -505,6 +505,31 @@ def test_dense_row_four_cliques(ctx):
         ctx.set_params(None)
 
 
+def test_stage_split_into_walk_and_product(ctx):
+    """esc_last_products: with every product forced on, the three stages that
+    have one report a walk no longer than the stage, a product taking the
+    rest and the multiply-adds of their 256 x 256 tiles; the other stages and
+    a call with the products off report no product."""
+    base = {"task_chunk": 1, "wg_per_cu": 3, "k5_work_log2": 20}
+    g = synth.chung_lu(20000, 2.1, 20.0, 1500.0, 2)
+    try:
+        ctx.set_params(dict(base, pairs_hub_ranks=512, pairs_hub_q=1, wheel_dense_deg=64,
+                            wheel_dense_ratio=1 << 20, k4_dense_dplus=16))
+        ctx.count(g, 5)
+        prof, prods = ctx.last_profile(), ctx.last_products()
+        for st in ("k4_triangles", "pairs_13_17", "wheels"):
+            walk, prod, macs = prods[st]
+            assert macs > 0 and macs % (256 * 256 * 128) == 0, (st, macs)
+            assert 0 <= walk <= prof[st][0] + 1e-3 and abs(walk + prod - prof[st][0]) < 1e-2, (st, prods[st])
+        for st in ("orient", "triangles", "four_cycles", "five_cliques", "reduce", "five_cycles", "combine"):
+            assert prods[st][2] == 0 and abs(prods[st][0] - prof[st][0]) < 1e-3, st
+        ctx.set_params(dict(base, pairs_hub_ranks=0, wheel_dense_deg=0, k4_dense_dplus=0))
+        ctx.count(g, 5)
+        assert all(v[2] == 0 for v in ctx.last_products().values())
+    finally:
+        ctx.set_params(None)
+
+
 def test_time_sliced_launches_give_same_counts():
     """Per-source kernels launched in 2 ms slices (ESC_SLICE_MS, read when
     the context is created): each stage is relaunched from its task counter

@@ -32,7 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-INT8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak (5.0 POP/s; one multiply-add = 2 ops)
+FP4_PEAK_TOPS = 10100.0  # dense 4-bit-float matrix-core peak (10.1 POP/s; one multiply-add = 2 ops)
 BYTES_PER_VISIT = 4     # one int32 neighbour / triangle-list entry per visited element
 TRAFFIC_FILES = {"chung_lu_4m": os.path.join(ROOT, "profiles", "traffic_chung_lu_4m.json"),
                  "chung_lu_1m": os.path.join(ROOT, "profiles", "traffic_chung_lu_1m.json")}
@@ -221,7 +221,8 @@ def run_single(esc, ctx, torch, g, name, steps, warmup, stream, seed=0):
     calls, each stage split into its walk and its matrix-core product
     (esc_last_products; HIP events on the call's stream); the roofline of
     the longest of those kernels: a walk against the HBM peak (4 bytes per
-    visited element), a product against the int8 matrix-core peak."""
+    visited element), a product against the matrix-core peak of its operand
+    type (4-bit floats)."""
     n, m = g.n, g.m
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
@@ -248,18 +249,18 @@ def run_single(esc, ctx, torch, g, name, steps, warmup, stream, seed=0):
     prof = {k: (v[0] / steps, v[1] / steps) for k, v in prof_sum.items()}
     prods = {k: (v[0] / steps, v[1] / steps, v[2] / steps) for k, v in prod_sum.items()}
     # the dominant kernel: a stage's walk (the whole stage where it has no
-    # matrix-core product; HBM-bound list reads) or a stage's product (int8
+    # matrix-core product; HBM-bound list reads) or a stage's product (fp4
     # matrix cores), whichever takes longest
     walk_dom = max(prods, key=lambda k: prods[k][0])
     prod_dom = max(prods, key=lambda k: prods[k][1])
     products = {k: {"ms": round(v[1], 3), "multiply_adds": int(v[2]),
                     "achieved_tops": 2 * v[2] / (v[1] / 1000.0) / 1e12 if v[1] > 0 else 0.0,
-                    "frac": 2 * v[2] / (v[1] / 1000.0) / 1e12 / INT8_PEAK_TOPS if v[1] > 0 else 0.0}
+                    "frac": 2 * v[2] / (v[1] / 1000.0) / 1e12 / FP4_PEAK_TOPS if v[1] > 0 else 0.0}
                 for k, v in prods.items() if v[2] > 0}
     if prods[prod_dom][1] > prods[walk_dom][0] and prods[prod_dom][2] > 0:
         pk = products[prod_dom]
         roofline = {"bound": "mfma", "kernel": prod_dom + " product", "achieved": pk["achieved_tops"],
-                    "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "frac": pk["frac"], "traffic": None,
+                    "peak": FP4_PEAK_TOPS, "unit": "TOP/s", "frac": pk["frac"], "traffic": None,
                     "traffic_bytes_per_launch": None, "algorithmic_ops": 2 * prods[prod_dom][2]}
     else:
         dom = walk_dom

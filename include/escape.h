@@ -294,8 +294,8 @@ typedef struct {
                                of t^2 over its edges) counts its rim
                                4-cycles as (1/2) sum over rim pairs of
                                C(c,2), c = (A A)(i,j) with A the adjacency
-                               of its neighbourhood, on the int8 matrix
-                               cores, when d^3/2 (d rounded up to 256) is
+                               of its neighbourhood, on the matrix cores
+                               (4-bit float 0/1 entries, exact), when d^3/2 (d rounded up to 256) is
                                below wheel_dense_ratio * S2/4; 0 (never) or
                                4..2^30 (default 1024) */
     int32_t wheel_dense_ratio; /* multiply-adds one walk visit is worth,
@@ -304,7 +304,7 @@ typedef struct {
                                graph: a vertex a with at least this many
                                out-neighbours (and at most 65536 neighbours)
                                gets K4 of all its triangles (a,b,c), a
-                               earliest, from C = B B^T on the int8 matrix
+                               earliest, from C = B B^T on the matrix
                                cores, B the 0/1 matrix of out-neighbours b
                                by neighbours w of a, B(b,w) = [b ~ w];
                                0 (never) or 16..2^30 (default 256) */
@@ -380,7 +380,7 @@ esc_status esc_last_three(const esc_ctx *ctx, esc_u128 *out);
 esc_status esc_last_profile(const esc_ctx *ctx, float *ms_out, uint64_t *visits_out);
 
 /* Split of the last successful call's stages into their walk and their
- * int8 matrix-core product (the 4-cliques of dense out-neighbourhoods in
+ * matrix-core product (the 4-cliques of dense out-neighbourhoods in
  * stage 3, Thm 4clique; the pattern-17 pairs of hubs in stage 6, Thm
  * 5cutwed; the wheels of dense hubs in stage 7), stages as in
  * esc_last_profile, each of the three arrays 10 entries, nullable:

@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
 // arc (a,b).  When N+(a) is large and dense (the core of a heavy-tailed
 // graph) the walk of Thm 4clique visits t(a,c) entries per triangle while
 // the product costs d+(a)^2 d(a) / 2 multiply-adds in all; such vertices
-// take the product on the int8 matrix cores and their triangles read K4 from
+// take the product on the matrix cores (tiles.h) and their triangles read K4 from
 // it.  A batch of them: vertex va[q], B_a at bo[q] (dpp[q] x dk[q] bytes:
 // d+ rounded up to HUB_T rows, d rounded up to HUB_K columns), C_a at co[q]
 // (dpp[q] x dpp[q] int32, the tiles on and above the diagonal), rows
@@ -277,8 +277,7 @@ __global__ void __launch_bounds__(256) k_k4_rows(const int32_t *off, const int32
     if (i < dplus) {
         const int64_t x0 = aoff[sa + i], x1 = aoff[sa + i + 1];
         for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
-            const int32_t col = (int32_t)aa[x] - oa;   // position of w in N(a)
-            atomicOr(&rowb[col >> 2], 1u << ((col & 3) * 8));
+            fp4_set_one(rowb, (int32_t)aa[x] - oa);   // column: the position of w in N(a)
         }
     }
     __syncthreads();
@@ -288,7 +287,7 @@ __global__ void __launch_bounds__(256) k_k4_rows(const int32_t *off, const int32
 }
 
 // C_a = B_a B_a^T on the tiles on and above the diagonal
-__global__ void __launch_bounds__(512) k_k4_gemm(const uint8_t *yb, int32_t nq, const int32_t *dpp,
+__global__ void __launch_bounds__(64 * HUB_WAVES) k_k4_gemm(const uint8_t *yb, int32_t nq, const int32_t *dpp,
                                                  const int32_t *dk, const int64_t *bo, const int64_t *co,
                                                  const int32_t *pp, int32_t *cm) {
     extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
@@ -303,19 +302,19 @@ __global__ void __launch_bounds__(512) k_k4_gemm(const uint8_t *yb, int32_t nq, 
     const int32_t rows = dpp[lo];
     int ti, tj;
     if (!hub_patch_tile(rows / HUB_T, P - pp[lo], local % (HUB_PR * HUB_PC), &ti, &tj)) return;
-    hub_v4i cacc[8][4];
+    hub_v4f cacc[8][HUB_BC];
     hub_tile((lds_u8 *)hub_lds, yb + bo[lo], dk[lo], ti, tj, cacc);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int32_t *out = cm + co[lo];
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++)
+        for (int b = 0; b < HUB_BC; b++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int64_t i = (int64_t)ti * HUB_T + hub_acc_row(wid, lane, a, r);
                 const int64_t j = (int64_t)tj * HUB_T + hub_acc_col(wid, lane, b);
-                out[i * rows + j] = cacc[a][b][r];
+                out[i * rows + j] = (int32_t)cacc[a][b][r];   // exact integer count
             }
 }
 
@@ -887,7 +886,7 @@ static esc_status k4_dense_select(esc_ctx *c, std::vector<int32_t> *dense) {
     std::vector<int32_t> ids;
     for (int q = 0; q < h; q++) {
         const size_t dpp = ((size_t)all[3 * q + 1] + HUB_T - 1) / HUB_T * HUB_T;
-        const size_t dk = ((size_t)all[3 * q + 2] + HUB_K - 1) / HUB_K * HUB_K;
+        const size_t dk = (((size_t)all[3 * q + 2] + 1) / 2 + HUB_K - 1) / HUB_K * HUB_K;   // bytes
         const size_t bytes = dpp * dk + 4 * dpp * dpp;
         if (bytes > room) continue;
         dense->insert(dense->end(), {all[3 * q], all[3 * q + 1], all[3 * q + 2]});
@@ -932,7 +931,7 @@ static esc_status k4_dense_product(esc_ctx *c, const std::vector<int32_t> &dense
         while (q1 < nd) {
             const int32_t dplus = dense[3 * q1 + 1];
             const int64_t r = ((int64_t)dplus + HUB_T - 1) / HUB_T * HUB_T;
-            const int64_t k = ((int64_t)dense[3 * q1 + 2] + HUB_K - 1) / HUB_K * HUB_K;
+            const int64_t k = (((int64_t)dense[3 * q1 + 2] + 1) / 2 + HUB_K - 1) / HUB_K * HUB_K;   // bytes
             if (q1 > q0 && bbytes + cbytes + (size_t)(r * k + 4 * r * r) > cap) break;
             const size_t j = q1 - q0;
             va[j] = dense[3 * q1];
@@ -949,7 +948,7 @@ static esc_status k4_dense_product(esc_ctx *c, const std::vector<int32_t> &dense
             cbytes += (size_t)(4 * r * r);
             patches += hub_npatches((int)(r / HUB_T));
             maxk = (int32_t)k > maxk ? (int32_t)k : maxk;
-            c->prod_macs[STAGE_K4] += (uint64_t)((r / HUB_T) * (r / HUB_T + 1) / 2) * HUB_T * HUB_T * (uint64_t)k;
+            c->prod_macs[STAGE_K4] += (uint64_t)((r / HUB_T) * (r / HUB_T + 1) / 2) * HUB_T * HUB_T * 2 * (uint64_t)k;
             q1++;
         }
         const int32_t nq = (int32_t)(q1 - q0);
@@ -976,7 +975,7 @@ static esc_status k4_dense_product(esc_ctx *c, const std::vector<int32_t> &dense
                                                             d_rp, d_bo, yb);
         HIP_TRY(hipGetLastError());
         const int nwg = 8 * HUB_PR * HUB_PC * ((patches + 7) / 8);
-        k_k4_gemm<<<nwg, 512, lds, st>>>(yb, nq, d_dpp, d_dk, d_bo, d_co, d_pp, cm);
+        k_k4_gemm<<<nwg, 64 * HUB_WAVES, lds, st>>>(yb, nq, d_dpp, d_dk, d_bo, d_co, d_pp, cm);
         HIP_TRY(hipGetLastError());
         auto look = c->av ? k_k4_lookup<true> : k_k4_lookup<false>;
         look<<<grid_cap(c, arcs * 64, 256, 8), 256, 0, st>>>(

@@ -993,11 +993,11 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
 // a dense contraction over the dense edges.  The pattern-17 sum splits as
 // the diamond walk over the edges that are not dense (hub sources skip the
 // dense ones) plus sum_{hub i < j} (W(i,j) - 2) Dd(i,j), W from the rows
-// the hub sources keep.  Y is built in chunks of HUB_EC dense edges (one
-// byte per entry, 0 or 1) and contracted on the int8 matrix cores: the 0/1
-// bytes multiply exactly and a chunk's counts fit the 32-bit accumulators.
+// the hub sources keep.  Y is built in chunks of HUB_EC dense edges (4-bit
+// entries, 0 or 1.0) and contracted on the matrix cores (tiles.h): the 0/1
+// entries multiply exactly and a chunk's counts stay below 2^24.
 
-#define HUB_EC 65536   // dense edges per chunk of Y (bytes of a Y row)
+#define HUB_EC 131072  // dense edges per chunk of Y (two to a byte of a Y row)
 
 // Dense arcs of each row k: the arcs k -> l (l after k) whose triangle lists
 // hold at least q apexes from hub0 on (the lists are sorted by apex).  A
@@ -1059,7 +1059,7 @@ __global__ void __launch_bounds__(256) k_hub_number(int32_t n, const int32_t *of
 }
 
 // Rows of Y for one chunk: a workgroup per hub i sets, in an LDS row of kb
-// bytes, the byte of every dense edge (k,l) of the chunk with i as apex --
+// bytes, the entry of every dense edge (k,l) of the chunk with i as apex --
 // the entries l after k of the lists of the arcs (i,k), k in the chunk's
 // rows -- then stores the row.
 template <bool IDS>
@@ -1093,7 +1093,7 @@ __global__ void __launch_bounds__(256) k_hub_rows(const int32_t *off, const int3
             if (apex_at<IDS>(av, adj, aa, x) > adj[pk]) {
                 const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - beg[s])];   // arc (k,l) in row k
                 const int64_t e = (int64_t)did[qkl] - base;
-                if (did[qkl] >= 0 && e >= 0 && e < kb) atomicOr(&rowb[e >> 2], 1u << ((e & 3) * 8));
+                if (did[qkl] >= 0 && e >= 0 && e < 2 * (int64_t)kb) fp4_set_one(rowb, e);
             }
         });
     }
@@ -1105,22 +1105,22 @@ __global__ void __launch_bounds__(256) k_hub_rows(const int32_t *off, const int3
 
 // sum over hub pairs i < j of one tile of (W(i,j) - 2) sum_e Y(i,e) Y(j,e),
 // over the kb bytes of the chunk's rows (tiles by patch, see above)
-__global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_r, int32_t kb, const uint32_t *wtop,
+__global__ void __launch_bounds__(64 * HUB_WAVES) k_hub_gemm(const uint8_t *y, int32_t hub_r, int32_t kb, const uint32_t *wtop,
                                                   int32_t nb, unsigned long long *acc) {
     extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
-    __shared__ u128 red[8];
+    __shared__ u128 red[HUB_WAVES];
     const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
     int ti, tj;
     if (!hub_patch_tile(nb, (local / (HUB_PR * HUB_PC)) * 8 + xcd, local % (HUB_PR * HUB_PC), &ti, &tj))
         return;   // the whole workgroup leaves
-    hub_v4i cacc[8][4];
+    hub_v4f cacc[8][HUB_BC];
     hub_tile((lds_u8 *)hub_lds, y, kb, ti, tj, cacc);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint64_t s = 0;
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++)
+        for (int b = 0; b < HUB_BC; b++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int32_t i = ti * HUB_T + hub_acc_row(wid, lane, a, r);
@@ -1129,7 +1129,7 @@ __global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_
                     const uint32_t w = wtop[(size_t)i * hub_r + j];
                     // a row left at 0 belongs to a source of degree <= 2, whose
                     // pairs with a common edge have W = 2
-                    if (w > 2) s += (uint64_t)(w - 2) * (uint32_t)cacc[a][b][r];
+                    if (w > 2) s += (uint64_t)(w - 2) * (uint32_t)cacc[a][b][r];   // exact integer count
                 }
             }
     u128 v[1] = {(u128)s};
@@ -1145,7 +1145,7 @@ __global__ void __launch_bounds__(512) k_hub_gemm(const uint8_t *y, int32_t hub_
 // N(h), each 4-cycle has two diagonals, so the hub's count is
 // (1/2) sum_{i<j} C(c(i,j), 2).  A hub whose walk would visit many list
 // entries (about S2/4, S2 = sum over its arcs of t^2) for its d^3/2
-// multiply-adds takes this product on the int8 matrix cores; the sum is
+// multiply-adds takes this product on the matrix cores (tiles.h); the sum is
 // gathered twice over in AC_WD2 and halved when the counts are combined.
 // A batch of such hubs: matrix of hub q at byte mo[q] (dpad[q] x dpad[q],
 // dpad = d rounded up to HUB_T, zero beyond d), rows numbered from rp[q],
@@ -1162,30 +1162,27 @@ __global__ void __launch_bounds__(256) k_wheel_rows(const int32_t *off, const in
         const int mid = (lo + hi + 1) >> 1;
         if (rp[mid] <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
     }
-    const int32_t h = hub[lo], dp = dpad[lo];
+    const int32_t h = hub[lo], dp = dpad[lo], rb = dp / 2;   // row bytes: two entries each
     const int64_t i = (int64_t)blockIdx.x - rp[lo];
     const int32_t oh = off[h], d = off[h + 1] - oh;
-    for (int q = threadIdx.x; q < dp / 4; q += blockDim.x) rowb[q] = 0;
+    for (int q = threadIdx.x; q < rb / 4; q += blockDim.x) rowb[q] = 0;
     __syncthreads();
     if (i < d) {
         const int64_t x0 = aoff[oh + i], x1 = aoff[oh + i + 1];
-        for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
-            const int32_t col = (int32_t)aa[x] - oh;
-            atomicOr(&rowb[col >> 2], 1u << ((col & 3) * 8));
-        }
+        for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) fp4_set_one(rowb, (int32_t)aa[x] - oh);
     }
     __syncthreads();
-    uint4 *dst = (uint4 *)(y + mo[lo] + i * (int64_t)dp);
+    uint4 *dst = (uint4 *)(y + mo[lo] + i * (int64_t)rb);
     const uint4 *src = (const uint4 *)rowb;
-    for (int q = threadIdx.x; q < dp / 16; q += blockDim.x) dst[q] = src[q];
+    for (int q = threadIdx.x; q < rb / 16; q += blockDim.x) dst[q] = src[q];
 }
 
 // sum over the hubs of a batch and their rim pairs i < j of C(c(i,j), 2)
-__global__ void __launch_bounds__(512) k_wheel_gemm(const uint8_t *y, int32_t nh, const int32_t *dpad,
+__global__ void __launch_bounds__(64 * HUB_WAVES) k_wheel_gemm(const uint8_t *y, int32_t nh, const int32_t *dpad,
                                                     const int64_t *mo, const int32_t *pp,
                                                     unsigned long long *acc) {
     extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
-    __shared__ u128 red[8];
+    __shared__ u128 red[HUB_WAVES];
     const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
     const int P = (local / (HUB_PR * HUB_PC)) * 8 + xcd;
     if (P >= pp[nh]) return;   // the whole workgroup leaves
@@ -1197,19 +1194,19 @@ __global__ void __launch_bounds__(512) k_wheel_gemm(const uint8_t *y, int32_t nh
     const int32_t dp = dpad[lo];
     int ti, tj;
     if (!hub_patch_tile(dp / HUB_T, P - pp[lo], local % (HUB_PR * HUB_PC), &ti, &tj)) return;
-    hub_v4i cacc[8][4];
-    hub_tile((lds_u8 *)hub_lds, y + mo[lo], dp, ti, tj, cacc);
+    hub_v4f cacc[8][HUB_BC];
+    hub_tile((lds_u8 *)hub_lds, y + mo[lo], dp / 2, ti, tj, cacc);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint64_t s = 0;
 #pragma unroll
     for (int a = 0; a < 8; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++)
+        for (int b = 0; b < HUB_BC; b++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int32_t i = ti * HUB_T + hub_acc_row(wid, lane, a, r);
                 const int32_t j = tj * HUB_T + hub_acc_col(wid, lane, b);
-                const uint64_t cij = (uint32_t)cacc[a][b][r];
+                const uint64_t cij = (uint32_t)cacc[a][b][r];   // exact: an integer below 2^17
                 if (i < j) s += cij * (cij - (cij > 0)) / 2;
             }
     u128 v[1] = {(u128)s};
@@ -1260,14 +1257,14 @@ static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
     *ndense = 0;
     if (c->G || R <= 0 || (int64_t)n < 2 * (int64_t)R || c->narcs_apex == 0) return ESC_OK;
     // the product's operand tiles and a chunk's Y row must fit a workgroup's LDS
-    if ((size_t)c->max_lds < 4 * (size_t)HUB_T * HUB_K + 1024 || (size_t)c->max_lds < (size_t)HUB_EC + 4096)
+    if ((size_t)c->max_lds < 4 * (size_t)HUB_T * HUB_K + 1024 || (size_t)c->max_lds < (size_t)HUB_EC / 2 + 4096)
         return ESC_OK;
     // memory: what the buffers need beyond what they already hold, with 1 GiB
     // left over for the later stages
     const Buf bufs[6] = {B_HUB_DID, B_HUB_CNT, B_HUB_BASE, B_HUB_KR, B_HUB_W, B_HUB_Y};
     const size_t sizes[6] = {sizeof(int32_t) * (size_t)c->m2, sizeof(int64_t) * (size_t)(n + 1),
                              sizeof(int64_t) * (size_t)(n + 1), sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2),
-                             sizeof(uint32_t) * (size_t)R * R, (size_t)R * HUB_EC};
+                             sizeof(uint32_t) * (size_t)R * R, (size_t)R * HUB_EC / 2};
     size_t more = 0;
     for (int b = 0; b < 6; b++) {
         const size_t want = sizes[b] + sizes[b] / 8 + ((size_t)2 << 20);   // ctx_buf's rounding
@@ -1282,7 +1279,7 @@ static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
     int64_t *base = (int64_t *)ctx_buf(c, B_HUB_BASE, sizeof(int64_t) * (size_t)(n + 1));
     int32_t *kr = (int32_t *)ctx_buf(c, B_HUB_KR, sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2));
     uint32_t *wtop = (uint32_t *)ctx_buf(c, B_HUB_W, sizeof(uint32_t) * (size_t)R * R);
-    uint8_t *y = (uint8_t *)ctx_buf(c, B_HUB_Y, (size_t)R * HUB_EC);
+    uint8_t *y = (uint8_t *)ctx_buf(c, B_HUB_Y, (size_t)R * HUB_EC / 2);
     if (!did || !cnt || !base || !kr || !wtop || !y) return ESC_OK;   // no room after all: off
     c->pairs_hub_used = R;
     const int32_t h0 = n - R;
@@ -1323,17 +1320,17 @@ static esc_status hub_product(esc_ctx *c, int32_t hub0, int64_t ndense) {
     for (int64_t ch = 0; ch < nchunks; ch++) {
         const int64_t base = ch * HUB_EC;
         const int64_t left = ndense - base < HUB_EC ? ndense - base : HUB_EC;
-        const int32_t kb = (int32_t)((left + HUB_K - 1) / HUB_K * HUB_K);
+        const int32_t kb = (int32_t)(((left + 1) / 2 + HUB_K - 1) / HUB_K * HUB_K);   // bytes: two entries each
         rows<<<R, 256, (size_t)kb, st>>>((const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ],
                                          (const int32_t *)c->buf[B_REV], (const int64_t *)c->buf[B_AOFF],
                                          (const uint32_t *)c->buf[B_AA], c->av, hub0,
                                          (const int32_t *)c->buf[B_HUB_DID], base, kb,
                                          (const int32_t *)c->buf[B_HUB_KR], (int32_t)ch, y);
         HIP_TRY(hipGetLastError());
-        k_hub_gemm<<<nwg, 512, lds, st>>>(y, R, kb, (const uint32_t *)c->buf[B_HUB_W], nb,
+        k_hub_gemm<<<nwg, 64 * HUB_WAVES, lds, st>>>(y, R, kb, (const uint32_t *)c->buf[B_HUB_W], nb,
                                           (unsigned long long *)c->buf[B_ACC]);
         HIP_TRY(hipGetLastError());
-        c->prod_macs[STAGE_PAIRS] += (uint64_t)(nb * (nb + 1) / 2) * HUB_T * HUB_T * (uint64_t)kb;
+        c->prod_macs[STAGE_PAIRS] += (uint64_t)(nb * (nb + 1) / 2) * HUB_T * HUB_T * 2 * (uint64_t)kb;
     }
     return ESC_OK;
 }
@@ -1420,12 +1417,13 @@ static esc_status wheel_dense_select(esc_ctx *c, int32_t *wd_lo, std::vector<int
         if (d > WD_MAX_DEG) continue;
         const int64_t dpi = (d + HUB_T - 1) / HUB_T * HUB_T;
         const double dp = (double)dpi;
-        if ((size_t)(dpi * dpi) > room) continue;
+        const size_t mbytes = (size_t)(dpi * dpi / 2);   // two entries a byte
+        if (mbytes > room) continue;
         if (dp * dp * dp / 2 < (double)c->wheel_dense_ratio * (double)hs2[q] / 4) {
             hf[q] = 1;
             dense->push_back(h);
-            total += (size_t)(dpi * dpi);
-            biggest = (size_t)(dpi * dpi) > biggest ? (size_t)(dpi * dpi) : biggest;
+            total += mbytes;
+            biggest = mbytes > biggest ? mbytes : biggest;
         }
     }
     if (dense->empty()) return ESC_OK;
@@ -1467,14 +1465,14 @@ static esc_status wheel_dense_product(esc_ctx *c, const std::vector<int32_t> &de
         int32_t patches = 0, maxdp = 0;
         while (q1 < nd) {
             const int64_t p = pad(dense[q1]);
-            if (q1 > q0 && bytes + p * p > (int64_t)cap) break;
+            if (q1 > q0 && bytes + p * p / 2 > (int64_t)cap) break;
             hub[q1 - q0] = dense[q1];
             dp[q1 - q0] = (int32_t)p;
             rp[q1 - q0] = rows;
             mo[q1 - q0] = bytes;
             pp[q1 - q0] = patches;
             rows += p;
-            bytes += p * p;
+            bytes += p * p / 2;
             patches += hub_npatches((int)(p / HUB_T));
             maxdp = (int32_t)p > maxdp ? (int32_t)p : maxdp;
             c->prod_macs[STAGE_WHEELS] += (uint64_t)((p / HUB_T) * (p / HUB_T + 1) / 2) * HUB_T * HUB_T * (uint64_t)p;
@@ -1491,13 +1489,13 @@ static esc_status wheel_dense_product(esc_ctx *c, const std::vector<int32_t> &de
         HIP_TRY(hipMemcpyAsync(d_pp, pp.data(), sizeof(int32_t) * (nh + 1), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(d_rp, rp.data(), sizeof(int64_t) * (nh + 1), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(d_mo, mo.data(), sizeof(int64_t) * (nh + 1), hipMemcpyHostToDevice, st));
-        k_wheel_rows<<<(unsigned)rows, 256, (size_t)maxdp, st>>>((const int32_t *)c->buf[B_OFF],
+        k_wheel_rows<<<(unsigned)rows, 256, (size_t)maxdp / 2, st>>>((const int32_t *)c->buf[B_OFF],
                                                                 (const int64_t *)c->buf[B_AOFF],
                                                                 (const uint32_t *)c->buf[B_AA], nh, d_hub, d_dp, d_rp,
                                                                 d_mo, y);
         HIP_TRY(hipGetLastError());
         const int nwg = 8 * HUB_PR * HUB_PC * ((patches + 7) / 8);
-        k_wheel_gemm<<<nwg, 512, lds, st>>>(y, nh, d_dp, d_mo, d_pp, (unsigned long long *)c->buf[B_ACC]);
+        k_wheel_gemm<<<nwg, 64 * HUB_WAVES, lds, st>>>(y, nh, d_dp, d_mo, d_pp, (unsigned long long *)c->buf[B_ACC]);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(st));   // the host arrays are rewritten by the next batch
         q0 = q1;

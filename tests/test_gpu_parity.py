@@ -414,7 +414,7 @@ def test_five_cliques_through_the_complement(ctx):
 
 def test_hub_pair_product(ctx):
     """Pattern 17 with the diamonds of two hub tips over a dense edge summed
-    as the int8 product of the hub / dense-edge incidence (Thm 5cutwed):
+    as the matrix-core product of the hub / dense-edge incidence (Thm 5cutwed):
     hubs of one 256-rank tile up to 39 tiles, every edge with a hub apex
     dense (several chunks of dense edges) or only the heaviest, the lists
     with and without apex ids.  Same counts as the oracle."""
@@ -448,7 +448,7 @@ def test_hub_pair_product(ctx):
 def test_dense_hub_wheels(ctx):
     """Pattern 18 with the rim 4-cycles of chosen hubs counted as
     (1/2) sum over rim pairs of C(c,2), c = (A A)(i,j) over the adjacency of
-    the hub's neighbourhood on the int8 matrix cores: every hub from 4, 64 or
+    the hub's neighbourhood on the matrix cores: every hub from 4, 64 or
     512 neighbours (matrices of one to six 256-tiles a side, several per
     launch), the default choice, never; lists with and without apex ids.
     Same counts as the oracle."""
@@ -476,7 +476,7 @@ def test_dense_hub_wheels(ctx):
 
 def test_dense_row_four_cliques(ctx):
     """Thm 4clique with K4 of the triangles (a,b,c), a earliest, read from
-    C = B B^T on the int8 matrix cores for vertices a with many
+    C = B B^T on the matrix cores for vertices a with many
     out-neighbours (B: out-neighbours by neighbours of a): from 16, 64, 256
     out-neighbours or never, lists with and without apex ids.  Same 45
     counts and the same per-edge and per-vertex K4 as the oracle."""

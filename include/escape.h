@@ -307,7 +307,7 @@ typedef struct {
                                earliest, from C = B B^T on the matrix
                                cores, B the 0/1 matrix of out-neighbours b
                                by neighbours w of a, B(b,w) = [b ~ w];
-                               0 (never) or 16..2^30 (default 256) */
+                               0 (never) or 16..2^30 (default 128) */
 } esc_params;
 
 /* Time every candidate parameter set on this graph (task_chunk in {1, 4, 16}

@@ -71,7 +71,7 @@ class _Params(ctypes.Structure):
 PARAM_DEFAULTS = {"five_order": 0, "k5_light": 64, "k5_wave_words": 8, "k5_dense_pct": 50,
                   "wheel_split_deg": 1024, "four_range_deg": 256, "pairs_hub_ranks": -1,
                   "pairs_hub_q": 256, "wheel_dense_deg": 1024, "wheel_dense_ratio": 1024,
-                  "k4_dense_dplus": 256}
+                  "k4_dense_dplus": 128}
 
 
 def _params_dict(p):

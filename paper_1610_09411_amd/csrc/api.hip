@@ -132,7 +132,7 @@ static esc_params default_params(const esc_ctx *c) {
     p.pairs_hub_q = 256;
     p.wheel_dense_deg = 1024;
     p.wheel_dense_ratio = 1024;
-    p.k4_dense_dplus = 256;
+    p.k4_dense_dplus = 128;
     return p;
 }
 

@@ -871,19 +871,28 @@ static esc_status k4_dense_select(esc_ctx *c, std::vector<int32_t> *dense) {
     k_k4_pick<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_SPLIT],
                                                    c->k4_dense_dplus, list, cnt);
     HIP_TRY(hipGetLastError());
+    // the count with the first K4_READ candidates in one read-back (more: a second)
+    const int32_t K4_READ = 16384;
+    const size_t first = (size_t)(n + 1 < K4_READ ? n + 1 : K4_READ);
+    std::vector<int32_t> all(3 * first);
     int h = 0;
     HIP_TRY(hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(all.data(), list, sizeof(int32_t) * 3 * first, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (h == 0) return ESC_OK;
-    std::vector<int32_t> all(3 * (size_t)h);
-    HIP_TRY(hipMemcpyAsync(all.data(), list, sizeof(int32_t) * 3 * (size_t)h, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    if ((size_t)h > first) {
+        all.resize(3 * (size_t)h);
+        HIP_TRY(hipMemcpyAsync(all.data() + 3 * first, list + 3 * first, sizeof(int32_t) * 3 * ((size_t)h - first),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
     size_t free_b = 0;
     ESC_TRY(ctx_free_bytes(c, &free_b));
     const size_t room = ctx_held(c, B_K4_Y) +
                         (free_b > ((size_t)2 << 30) ? (free_b - ((size_t)2 << 30)) / 2 : 0);
     size_t total = 0, biggest = 0;
-    std::vector<int32_t> ids;
+    std::vector<int32_t> &ids = c->k4_ids;   // kept until the next call: the copy below reads it
+    ids.clear();
     for (int q = 0; q < h; q++) {
         const size_t dpp = ((size_t)all[3 * q + 1] + HUB_T - 1) / HUB_T * HUB_T;
         const size_t dk = (((size_t)all[3 * q + 2] + 1) / 2 + HUB_K - 1) / HUB_K * HUB_K;   // bytes
@@ -902,7 +911,6 @@ static esc_status k4_dense_select(esc_ctx *c, std::vector<int32_t> *dense) {
     HIP_TRY(hipMemcpyAsync(list, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, st));
     k_k4_flags<<<grid_cap(c, (int64_t)ids.size(), 256), 256, 0, st>>>((int32_t)ids.size(), list, flag);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));   // ids is a host temporary
     return ESC_OK;
 }
 

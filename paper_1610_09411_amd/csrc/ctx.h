@@ -170,10 +170,12 @@ struct esc_ctx {
     int wheel_dense_deg;       // wheels: hubs from this degree may take the product (0: never)
     int wheel_dense_ratio;     // wheels: multiply-adds one walk visit is worth
     std::vector<int32_t> wd_degs;   // row offsets of the latest ranks (for the chosen hubs)
+    std::vector<uint8_t> wd_flags;  // their chosen flags (the source of an asynchronous copy)
     int32_t wd_base;           // rank of wd_degs[0]
     size_t wd_cap;             // bytes of the matrix buffer the chosen hubs go through
     int k4_dense_dplus;        // 4-cliques: vertices from this out-degree take the product (0: never)
     size_t k4_cap;             // bytes of the B_a / C_a buffer of the chosen vertices
+    std::vector<int32_t> k4_ids;    // the chosen vertices (the source of an asynchronous copy)
     int pairs_hub_q;           // pattern 17: hub apexes that make an edge dense
     int five_order;            // 5-cycles of one graph: 0 Y table when maxdeg < 2^16, 1 Wnt table
     size_t dev_mem;            // device memory in bytes

@@ -1385,35 +1385,37 @@ static esc_status wheel_dense_select(esc_ctx *c, int32_t *wd_lo, std::vector<int
     *wd_lo = n;
     if (c->G || c->wheel_dense_deg <= 0 || c->maxdeg < c->wheel_dense_deg) return ESC_OK;
     if ((size_t)c->max_lds < 4 * (size_t)HUB_T * HUB_K + 1024) return ESC_OK;
+    // S2 of the latest K ranks and their row offsets, read back together
     const int32_t K = n < WD_CAND ? n : WD_CAND;
-    std::vector<int32_t> hoff((size_t)K + 1);
+    unsigned long long *s2 = (unsigned long long *)ctx_buf(c, B_WD_S2, sizeof(uint64_t) * (size_t)K);
+    uint8_t *flag = (uint8_t *)ctx_buf(c, B_WD_FLAG, (size_t)K);
+    if (!s2 || !flag) return ESC_ENOMEM;
+    k_wheel_s2<<<grid_cap(c, (int64_t)K * 64, 256), 256, 0, st>>>(n - K, n, (const int32_t *)c->buf[B_OFF],
+                                                                  (const uint32_t *)c->buf[B_TARC], s2);
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> &hoff = c->wd_degs;
+    hoff.resize((size_t)K + 1);
+    std::vector<uint64_t> hs2((size_t)K);
     HIP_TRY(hipMemcpyAsync(hoff.data(), (const int32_t *)c->buf[B_OFF] + (n - K), sizeof(int32_t) * ((size_t)K + 1),
                            hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hs2.data(), s2, sizeof(uint64_t) * (size_t)K, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    c->wd_base = n - K;
     int32_t first = K;   // first of the latest K ranks with degree >= wheel_dense_deg (degrees ascend)
     while (first > 0 && hoff[first] - hoff[first - 1] >= c->wheel_dense_deg) first--;
     if (first == K) return ESC_OK;
-    const int32_t lo = n - K + first, nc = n - lo;
-    unsigned long long *s2 = (unsigned long long *)ctx_buf(c, B_WD_S2, sizeof(uint64_t) * (size_t)nc);
-    uint8_t *flag = (uint8_t *)ctx_buf(c, B_WD_FLAG, (size_t)nc);
-    if (!s2 || !flag) return ESC_ENOMEM;
-    k_wheel_s2<<<grid_cap(c, (int64_t)nc * 64, 256), 256, 0, st>>>(lo, n, (const int32_t *)c->buf[B_OFF],
-                                                                   (const uint32_t *)c->buf[B_TARC], s2);
-    HIP_TRY(hipGetLastError());
-    std::vector<uint64_t> hs2((size_t)nc);
-    HIP_TRY(hipMemcpyAsync(hs2.data(), s2, sizeof(uint64_t) * (size_t)nc, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
     // matrix buffer: every chosen matrix, at most 8 GiB (the hubs then go in
     // batches), at least the largest one; a matrix larger than the memory
     // the buffer can have leaves its hub to the walk
     size_t free_b = 0;
     ESC_TRY(ctx_free_bytes(c, &free_b));
     const size_t room = ctx_held(c, B_WD_Y) + (free_b > ((size_t)2 << 30) ? (free_b - ((size_t)2 << 30)) / 2 : 0);
-    std::vector<uint8_t> hf((size_t)nc, 0);
+    std::vector<uint8_t> &hf = c->wd_flags;   // kept until the next call: the copy below reads it
+    hf.assign((size_t)K, 0);
     size_t total = 0, biggest = 0;
-    for (int32_t q = 0; q < nc; q++) {
-        const int32_t h = lo + q;
-        const int64_t d = hoff[h - (n - K) + 1] - hoff[h - (n - K)];
+    for (int32_t q = first; q < K; q++) {
+        const int32_t h = n - K + q;
+        const int64_t d = hoff[q + 1] - hoff[q];
         if (d > WD_MAX_DEG) continue;
         const int64_t dpi = (d + HUB_T - 1) / HUB_T * HUB_T;
         const double dp = (double)dpi;
@@ -1431,11 +1433,8 @@ static esc_status wheel_dense_select(esc_ctx *c, int32_t *wd_lo, std::vector<int
     if (cap < biggest) cap = biggest;
     if (cap > room) cap = room;   // >= biggest: every chosen matrix fits the room
     c->wd_cap = cap;
-    HIP_TRY(hipMemcpyAsync(flag, hf.data(), (size_t)nc, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));   // hf is a host temporary
-    c->wd_degs.assign(hoff.begin(), hoff.end());
-    c->wd_base = n - K;
-    *wd_lo = lo;
+    HIP_TRY(hipMemcpyAsync(flag, hf.data(), (size_t)K, hipMemcpyHostToDevice, st));
+    *wd_lo = n - K;
     return ESC_OK;
 }
 

@@ -38,7 +38,10 @@ struct Req {
     int k;
     std::vector<int32_t> rp, col;
     uint64_t wedges;           // sum_v C(d(v),2), for the footprint estimate
-    uint64_t cost;             // predicted device work (see work_cost)
+    uint64_t cost = 0;         // predicted device work (see work_cost), once priced
+    bool priced = false;       // cost is set
+    bool pricing = false;      // the pricing thread holds it (not deleted meanwhile)
+    bool taken = false;        // its result was collected while it was being priced
     double t_submit = 0, t_done = 0;
     esc_status status = ESC_OK;
     bool done = false;
@@ -65,6 +68,8 @@ struct esc_server {
     bool stopping = false;
     std::vector<esc_ctx *> ctxs;
     std::vector<std::thread> workers;
+    std::deque<Req *> unpriced;   // submitted, cost not yet computed (pricing thread)
+    std::thread pricer;
     // statistics
     uint64_t completed = 0, launches = 0, batched_requests = 0;
     int running = 0, peak_running = 0;
@@ -199,6 +204,7 @@ void worker(esc_server *s, esc_ctx *c) {
             for (size_t i = 1; i < scan && (int)grp.size() < s->max_group; i++) {
                 Req *r = s->queue[i];
                 if (r->k != grp[0]->k || r->n > s->small_n || (r->n <= PW_MAX_N) != tiny) continue;
+                if (!r->priced) continue;   // joins a later launch once priced
                 if (gcost + r->cost > s->cost_cap) break;   // the launch holds enough work
                 gcost += r->cost;
                 grp.push_back(r);
@@ -250,8 +256,40 @@ esc_status take_result(esc_server *s, Req *r, esc_u128 *out, double *seconds) {
     if (st == ESC_OK && out) memcpy(out, r->out, sizeof(esc_u128) * (r->k == 4 ? 11 : 45));
     if (seconds) *seconds = r->t_done - r->t_submit;
     s->reqs.erase(r->ticket);
-    delete r;
+    if (r->pricing) r->taken = true;   // the pricing thread deletes it when done
+    else delete r;
     return st;
+}
+
+// Prices submitted requests off the submitting thread: work_cost is O(m)
+// host work, which a burst of submissions would otherwise pay in line.
+// The head of the queue runs without a price (a request alone may exceed
+// the cap); a request joins another's launch only once priced.
+void pricer(esc_server *s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv.wait(lk, [&] { return s->stopping || !s->unpriced.empty(); });
+        if (s->unpriced.empty()) {
+            if (s->stopping) break;
+            continue;
+        }
+        std::vector<Req *> batch;
+        while (!s->unpriced.empty() && batch.size() < 64) {
+            Req *r = s->unpriced.front();
+            s->unpriced.pop_front();
+            r->pricing = true;
+            batch.push_back(r);
+        }
+        lk.unlock();
+        for (Req *r : batch) r->cost = work_cost(r->n, r->rp.data(), r->col.data(), r->wedges);
+        lk.lock();
+        for (Req *r : batch) {
+            r->priced = true;
+            r->pricing = false;
+            if (r->taken) delete r;
+        }
+        s->cv.notify_all();   // priced requests may now join launches
+    }
 }
 
 }  // namespace
@@ -287,6 +325,7 @@ extern "C" esc_status esc_server_start(esc_ctx *ctx, int max_inflight, esc_serve
         s->ctxs.push_back(c);
     }
     for (esc_ctx *c : s->ctxs) s->workers.emplace_back(worker, s, c);
+    s->pricer = std::thread(pricer, s);
     *out = s;
     return ESC_OK;
 }
@@ -307,7 +346,6 @@ extern "C" esc_status esc_submit(esc_server *s, int32_t n, const int32_t *row_pt
         w += d * (d - (d > 0)) / 2;
     }
     r->wedges = w;
-    r->cost = work_cost(n, row_ptr, col, w);
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) {
@@ -321,6 +359,7 @@ extern "C" esc_status esc_submit(esc_server *s, int32_t n, const int32_t *row_pt
     r->ticket = s->next_ticket++;
     s->reqs[r->ticket] = r;
     s->queue.push_back(r);
+    s->unpriced.push_back(r);
     *ticket = r->ticket;
     s->cv.notify_all();
     return ESC_OK;
@@ -371,6 +410,7 @@ extern "C" esc_status esc_server_stop(esc_server *s) {
         s->cv.notify_all();
     }
     for (std::thread &t : s->workers) t.join();
+    if (s->pricer.joinable()) s->pricer.join();
     for (esc_ctx *c : s->ctxs) esc_destroy(c);
     for (auto &kv : s->reqs) delete kv.second;
     delete s;

@@ -167,6 +167,7 @@ struct esc_ctx {
     int four_range_deg;        // 4-cycles: tops above this degree are split into key-range tasks
     int pairs_hub_r;           // pattern 17: hub ranks of the hub-pair product (0: off, -1: by n)
     int pairs_hub_used;        // hub ranks the last pair pass used (0: no product)
+    bool hub_w16;              // its W table holds 16-bit entries (every degree below 2^16)
     int wheel_dense_deg;       // wheels: hubs from this degree may take the product (0: never)
     int wheel_dense_ratio;     // wheels: multiply-adds one walk visit is worth
     std::vector<int32_t> wd_degs;   // row offsets of the latest ranks (for the chosen hubs)

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                                                   int32_t pw_words, unsigned long long *acc,
                                                   unsigned long long *visits, uint64_t slice_ticks, int *done,
                                                   int32_t hub0, int32_t hub_r, const int32_t *did,
-                                                  uint32_t *wtop) {
+                                                  void *wtop, int w16) {
     extern __shared__ uint32_t sl[];
     uint64_t nvis = 0;
     const uint64_t slice_end = slice_end_of(slice_ticks);
@@ -238,9 +238,12 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
         // a hub source keeps its row W(i, j) over the later hubs for the
         // hub-pair product (the slab holds every key from hub0 on)
         if (i >= hub0) {
-            uint32_t *row = wtop + (size_t)(i - hub0) * hub_r;
-            for (int32_t j = i + 1 + threadIdx.x; j < ge; j += blockDim.x)
-                row[j - hub0] = j >= hi0 ? SLAB_GET(j) : TAB_GET(j);
+            const size_t r0 = (size_t)(i - hub0) * hub_r;
+            for (int32_t j = i + 1 + threadIdx.x; j < ge; j += blockDim.x) {
+                const uint32_t w = j >= hi0 ? SLAB_GET(j) : TAB_GET(j);
+                if (w16) ((uint16_t *)wtop)[r0 + (j - hub0)] = (uint16_t)w;   // W <= d(i) < 2^16
+                else ((uint32_t *)wtop)[r0 + (j - hub0)] = w;
+            }
         }
         // diamonds with tips i and j (j after i): triangles (i,k,l), k<l, then
         // apexes j of edge (k,l) after i.  The entries l of the triangle
@@ -1105,8 +1108,8 @@ __global__ void __launch_bounds__(256) k_hub_rows(const int32_t *off, const int3
 
 // sum over hub pairs i < j of one tile of (W(i,j) - 2) sum_e Y(i,e) Y(j,e),
 // over the kb bytes of the chunk's rows (tiles by patch, see above)
-__global__ void __launch_bounds__(64 * HUB_WAVES) k_hub_gemm(const uint8_t *y, int32_t hub_r, int32_t kb, const uint32_t *wtop,
-                                                  int32_t nb, unsigned long long *acc) {
+__global__ void __launch_bounds__(64 * HUB_WAVES) k_hub_gemm(const uint8_t *y, int32_t hub_r, int32_t kb, const void *wtop,
+                                                  int w16, int32_t nb, unsigned long long *acc) {
     extern __shared__ __attribute__((aligned(16))) uint8_t hub_lds[];
     __shared__ u128 red[HUB_WAVES];
     const int local = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
@@ -1126,7 +1129,8 @@ __global__ void __launch_bounds__(64 * HUB_WAVES) k_hub_gemm(const uint8_t *y, i
                 const int32_t i = ti * HUB_T + hub_acc_row(wid, lane, a, r);
                 const int32_t j = tj * HUB_T + hub_acc_col(wid, lane, b);
                 if (i < j) {
-                    const uint32_t w = wtop[(size_t)i * hub_r + j];
+                    const size_t wi = (size_t)i * hub_r + j;
+                    const uint32_t w = w16 ? ((const uint16_t *)wtop)[wi] : ((const uint32_t *)wtop)[wi];
                     // a row left at 0 belongs to a source of degree <= 2, whose
                     // pairs with a common edge have W = 2
                     if (w > 2) s += (uint64_t)(w - 2) * (uint32_t)cacc[a][b][r];   // exact integer count
@@ -1264,7 +1268,7 @@ static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
     const Buf bufs[6] = {B_HUB_DID, B_HUB_CNT, B_HUB_BASE, B_HUB_KR, B_HUB_W, B_HUB_Y};
     const size_t sizes[6] = {sizeof(int32_t) * (size_t)c->m2, sizeof(int64_t) * (size_t)(n + 1),
                              sizeof(int64_t) * (size_t)(n + 1), sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2),
-                             sizeof(uint32_t) * (size_t)R * R, (size_t)R * HUB_EC / 2};
+                             (c->maxdeg < 65536 ? 2 : 4) * (size_t)R * R, (size_t)R * HUB_EC / 2};
     size_t more = 0;
     for (int b = 0; b < 6; b++) {
         const size_t want = sizes[b] + sizes[b] / 8 + ((size_t)2 << 20);   // ctx_buf's rounding
@@ -1278,7 +1282,10 @@ static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
     int64_t *cnt = (int64_t *)ctx_buf(c, B_HUB_CNT, sizeof(int64_t) * (size_t)(n + 1));
     int64_t *base = (int64_t *)ctx_buf(c, B_HUB_BASE, sizeof(int64_t) * (size_t)(n + 1));
     int32_t *kr = (int32_t *)ctx_buf(c, B_HUB_KR, sizeof(int32_t) * 2 * (size_t)(c->m / HUB_EC + 2));
-    uint32_t *wtop = (uint32_t *)ctx_buf(c, B_HUB_W, sizeof(uint32_t) * (size_t)R * R);
+    // W(i,j) <= d(i): 16-bit entries when every degree is below 2^16
+    c->hub_w16 = c->maxdeg < 65536;
+    const size_t wbytes = (c->hub_w16 ? 2 : 4) * (size_t)R * R;
+    void *wtop = ctx_buf(c, B_HUB_W, wbytes);
     uint8_t *y = (uint8_t *)ctx_buf(c, B_HUB_Y, (size_t)R * HUB_EC / 2);
     if (!did || !cnt || !base || !kr || !wtop || !y) return ESC_OK;   // no room after all: off
     c->pairs_hub_used = R;
@@ -1298,7 +1305,7 @@ static esc_status hub_prepare(esc_ctx *c, int32_t *hub0, int64_t *ndense) {
     HIP_TRY(hipGetLastError());
     int64_t nd = 0;
     HIP_TRY(hipMemcpyAsync(&nd, base + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemsetAsync(wtop, 0, sizeof(uint32_t) * (size_t)R * R, st));
+    HIP_TRY(hipMemsetAsync(wtop, 0, wbytes, st));
     HIP_TRY(hipStreamSynchronize(st));
     *hub0 = h0;
     *ndense = nd;
@@ -1327,7 +1334,7 @@ static esc_status hub_product(esc_ctx *c, int32_t hub0, int64_t ndense) {
                                          (const int32_t *)c->buf[B_HUB_DID], base, kb,
                                          (const int32_t *)c->buf[B_HUB_KR], (int32_t)ch, y);
         HIP_TRY(hipGetLastError());
-        k_hub_gemm<<<nwg, 64 * HUB_WAVES, lds, st>>>(y, R, kb, (const uint32_t *)c->buf[B_HUB_W], nb,
+        k_hub_gemm<<<nwg, 64 * HUB_WAVES, lds, st>>>(y, R, kb, c->buf[B_HUB_W], c->hub_w16 ? 1 : 0, nb,
                                           (unsigned long long *)c->buf[B_ACC]);
         HIP_TRY(hipGetLastError());
         c->prod_macs[STAGE_PAIRS] += (uint64_t)(nb * (nb + 1) / 2) * HUB_T * HUB_T * 2 * (uint64_t)kb;
@@ -1357,13 +1364,14 @@ esc_status stage_pairs(esc_ctx *c) {
     const int32_t lds_words = 8 * pw_words > slab ? 8 * pw_words : (slab > 0 ? slab : 1);
     auto kern = c->av ? k_pairs_wd<true> : k_pairs_wd<false>;
     const int32_t *did = hub0 < n ? (const int32_t *)c->buf[B_HUB_DID] : nullptr;
-    uint32_t *wtop = hub0 < n ? (uint32_t *)c->buf[B_HUB_W] : nullptr;
+    void *wtop = hub0 < n ? c->buf[B_HUB_W] : nullptr;
     ESC_TRY(run_sliced(c, "pairs_13_17", task + 8, task, [&](uint64_t ticks) -> esc_status {
         kern<<<slab_wgs_per_cu(c) * c->num_cu, 512, sizeof(uint32_t) * (size_t)lds_words, st>>>(
             n, (const int32_t *)c->buf[B_OFF], (const int32_t *)c->buf[B_ADJ], (const int32_t *)c->buf[B_REV],
             (const int64_t *)c->buf[B_AOFF], (const uint32_t *)c->buf[B_AA], c->av, tab, touch, c->tab_n,
             c->task_chunk, gmap_of(c), task, slab, pw_words, (unsigned long long *)c->buf[B_ACC],
-            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6, ticks, task + 8, hub0, c->pairs_hub_used, did, wtop);
+            (unsigned long long *)c->buf[B_WORK] + WORK_VISITS + 6, ticks, task + 8, hub0, c->pairs_hub_used, did, wtop,
+            c->hub_w16 ? 1 : 0);
         HIP_TRY(hipGetLastError());
         return ESC_OK;
     }));

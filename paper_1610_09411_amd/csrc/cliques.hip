@@ -679,8 +679,9 @@ template <bool IDS>
 __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int32_t *split, const int64_t *aoff,
                                                   const uint32_t *aa, const int32_t *dlist, const int *ndense,
                                                   unsigned long long *scr_all, int64_t scr_words, int32_t hcap,
-                                                  int *task, GMap gm, unsigned long long *acc,
+                                                  int32_t vbc, int *task, GMap gm, unsigned long long *acc,
                                                   unsigned long long *visits, unsigned long long *dbp_out) {
+    extern __shared__ unsigned long long tl[];   // a block of vbc columns of T, word-major
     __shared__ unsigned long long fu[4][K5_DENSE_HMAX / 64];
     __shared__ int fsum[4][K5_DENSE_HMAX / 64 + 1];   // popcounts of fu[w..] per wave
     __shared__ int s_t;
@@ -774,8 +775,17 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
             }
             __syncthreads();   // red is reused by the flushes
         }
-        // 3. pairs u < v
-        for (int u = wid; u < h; u += nwv) {
+        // 3. pairs u < v, the columns v in blocks of vbc staged in LDS (tl),
+        //    so that T is read from memory once per block, not once per u
+        for (int vb = 0; vb < h; vb += vbc) {
+            const int ve = vb + vbc < h ? vb + vbc : h;
+            __syncthreads();   // the previous block is read by every wave
+            for (int q = threadIdx.x; q < wa * vbc; q += blockDim.x) {
+                const int w = q / vbc, vv = q - w * vbc;
+                tl[q] = vb + vv < h ? T[(size_t)w * h + vb + vv] : 0ull;
+            }
+            __syncthreads();
+            for (int u = wid; u < ve - 1; u += nwv) {
             for (int w = lane; w < wa; w += 64) fu[wid][w] = T[(size_t)w * h + u];
             wave_sync();
             if (lane == 0) {
@@ -787,19 +797,19 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
             const uint64_t du = (uint64_t)dc[u];
             const int w0 = (u + 1) >> 6;
             const unsigned long long m0 = ~0ull << ((u + 1) & 63);   // positions after u in word w0
-            for (int v = u + 1 + lane; v < h; v += 64) {
+            for (int v = (u + 1 > vb ? u + 1 : vb) + lane; v < ve; v += 64) {
                 // w0 < wa: v <= h - 1 lies in the last word at the latest
-                const unsigned long long *tv = T + v;
-                uint32_t cnt = (uint32_t)__popcll(fu[wid][w0] & tv[(size_t)w0 * h] & m0);
+                const unsigned long long *tv = tl + (v - vb);   // column v: tv[w * vbc]
+                uint32_t cnt = (uint32_t)__popcll(fu[wid][w0] & tv[w0 * vbc] & m0);
                 int w = w0 + 1;
-                for (; w + 8 <= wa; w += 8) {   // eight loads in flight
+                for (; w + 8 <= wa; w += 8) {
                     unsigned long long x[8];
 #pragma unroll
-                    for (int r = 0; r < 8; r++) x[r] = tv[(size_t)(w + r) * h];
+                    for (int r = 0; r < 8; r++) x[r] = tv[(w + r) * vbc];
 #pragma unroll
                     for (int r = 0; r < 8; r++) cnt += (uint32_t)__popcll(fu[wid][w + r] & x[r]);
                 }
-                for (; w < wa; w++) cnt += (uint32_t)__popcll(fu[wid][w] & tv[(size_t)w * h]);
+                for (; w < wa; w++) cnt += (uint32_t)__popcll(fu[wid][w] & tv[w * vbc]);
                 nvis += (uint64_t)(wa - w0);
                 k5[0] += c2(cnt);
                 if (!((fu[wid][v >> 6] >> (v & 63)) & 1ull)) {
@@ -808,8 +818,8 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                     // there) close C(s,2) directed bipyramids
                     const int wv = v >> 6;
                     const unsigned long long mg = (v & 63) == 63 ? 0ull : ~0ull << ((v & 63) + 1);
-                    uint32_t chi = (uint32_t)__popcll(fu[wid][wv] & tv[(size_t)wv * h] & mg);
-                    for (int w = wv + 1; w < wa; w++) chi += (uint32_t)__popcll(fu[wid][w] & tv[(size_t)w * h]);
+                    uint32_t chi = (uint32_t)__popcll(fu[wid][wv] & tv[wv * vbc] & mg);
+                    for (int w = wv + 1; w < wa; w++) chi += (uint32_t)__popcll(fu[wid][w] & tv[w * vbc]);
                     const int duh = __popcll(fu[wid][wv] & mg) + fsum[wid][wv + 1];
                     const int sh = (h - 1 - v) - duh - dch[v] + (int)chi;
                     dbp += c2((uint64_t)sh);
@@ -818,7 +828,7 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                 // an edge of Hc
                 uint32_t tf = cnt;
                 for (int w = 0; w <= w0 && w < wa; w++) {
-                    unsigned long long x = fu[wid][w] & T[(size_t)w * h + v];
+                    unsigned long long x = fu[wid][w] & tv[w * vbc];
                     if (w == w0) x &= ~m0;
                     tf += (uint32_t)__popcll(x);
                 }
@@ -826,7 +836,7 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                 k5[0] -= (u128)((du - 1) * (dv - 1)) + (u128)c2(tf);
                 const int wv = v >> 6;
                 for (int w = wv; w < wa; w++) {
-                    unsigned long long sx = fu[wid][w] & T[(size_t)w * h + v];
+                    unsigned long long sx = fu[wid][w] & tv[w * vbc];
                     if (w == wv) sx &= (v & 63) == 63 ? 0ull : ~0ull << ((v & 63) + 1);
                     while (sx) {
                         const int x = w * 64 + __ffsll((long long)sx) - 1;
@@ -835,7 +845,7 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                         k5[0] -= (u128)h;
                         const int wx = x >> 6;
                         for (int w2 = wx; w2 < wa; w2++) {
-                            unsigned long long y = fu[wid][w2] & T[(size_t)w2 * h + v] & T[(size_t)w2 * h + x];
+                            unsigned long long y = fu[wid][w2] & tv[w2 * vbc] & T[(size_t)w2 * h + x];
                             if (w2 == wx) y &= (x & 63) == 63 ? 0ull : ~0ull << ((x & 63) + 1);
                             k5[0] += (uint64_t)__popcll(y);
                         }
@@ -844,6 +854,7 @@ __global__ void __launch_bounds__(256) k_k5_dense(const int32_t *off, const int3
                 }
             }
             wave_sync();   // fu is reused by the wave's next u
+            }
         }
         __syncthreads();   // T, los and dc are rewritten for the next vertex
     }
@@ -1073,11 +1084,18 @@ esc_status stage_k5(esc_ctx *c) {
         const int64_t per_wg = (int64_t)hcap * (hcap / 64) + hcap + hcap;   // rows, list starts, two degree arrays
         int nwg = 4 * c->num_cu;   // 113 VGPRs: four 4-wave workgroups per CU are resident
         while (nwg > c->num_cu && (size_t)nwg * (size_t)per_wg * 8 > c->dev_mem / 16) nwg -= c->num_cu;
+        // a block of vbc columns of the complement rows in LDS: about 32 KB
+        // (four workgroups a CU), 64 to 256 columns
+        const int32_t wa_cap = hcap / 64;
+        int32_t vbc = (int32_t)(32768 / (8 * wa_cap)) & ~63;
+        if (vbc > 256) vbc = 256;
+        if (vbc < 64) vbc = 64;
+        const size_t tl_bytes = sizeof(uint64_t) * (size_t)wa_cap * vbc;
         unsigned long long *scr = (unsigned long long *)ctx_buf(c, B_K5_DENSE_SCR, sizeof(uint64_t) * (size_t)per_wg * nwg);
         if (!scr) return ESC_ENOMEM;
         auto kern = c->av ? k_k5_dense<true> : k_k5_dense<false>;
-        kern<<<nwg, 256, 0, st>>>(off, split, aoff, aa, dlist, task + 5, scr, per_wg, hcap, task + 6, gmap_of(c), acc,
-                                  vis, dbp);
+        kern<<<nwg, 256, tl_bytes, st>>>(off, split, aoff, aa, dlist, task + 5, scr, per_wg, hcap, vbc, task + 6,
+                                         gmap_of(c), acc, vis, dbp);
         HIP_TRY(hipGetLastError());
     }
     return ESC_OK;

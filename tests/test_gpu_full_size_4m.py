@@ -3,8 +3,13 @@ degree 5e4, seed 0: 7.65e7 edges, 9.2e9 triangles) at full size, 4-vertex
 counts: the 11 counts sum to C(n,4), and per-vertex / per-edge fragment
 counts on sampled vertices and edges (hubs included) equal their definitions
 recomputed one by one.  Its per-arc triangle lists hold 5.5e10 entries, so
-they are kept in the compact layout (arc positions only).
+they are kept in the compact layout (arc positions only).  5-vertex counts:
+the oracle cannot count this graph, so the call with the matrix-core
+products (hub pairs, dense-hub wheels, dense-row 4-cliques) is checked
+against the call that walks every list (each path equals the oracle on
+smaller graphs), count by count, non-induced counts included.
 """
+import os
 import random
 from math import comb
 
@@ -55,3 +60,30 @@ def test_chung_lu_4m_four_vertex_full_size():
             assert fr["tri_v"][v] == oracle.vertex_triangles(g, v)
         print("vertex", v, "degree", int(deg[v]), "ok", flush=True)
     assert checked > 20
+
+
+@pytest.mark.skipif(not os.environ.get("ESC_FULL_SIZE_5"),
+                    reason="two k=5 calls on the 4M-vertex graph, about three minutes without output "
+                           "(the walk-only call alone takes some 100 s); set ESC_FULL_SIZE_5=1 to run it")
+def test_chung_lu_4m_five_vertex_products_equal_walks():
+    import paper_1610_09411_amd as esc
+    g = synth.chung_lu_4m(0)
+    print("chung_lu_4m", g.n, g.m, flush=True)
+    ctx = esc.Context(0)
+    try:
+        with_products = ctx.count(g, 5)
+        prods = ctx.last_products()
+        non_p = ctx.last_noninduced(5)
+        print("with products", {k: v for k, v in prods.items() if v[2]}, flush=True)
+        ctx.set_params(dict(esc.PARAM_DEFAULTS, task_chunk=1, wg_per_cu=2, k5_work_log2=20,
+                            pairs_hub_ranks=0, wheel_dense_deg=0, k4_dense_dplus=0))
+        walks = ctx.count(g, 5)
+        assert all(v[2] == 0 for v in ctx.last_products().values())
+        non_w = ctx.last_noninduced(5)
+        print("walks only", flush=True)
+    finally:
+        ctx.close()
+    assert sum(with_products[:11]) == comb(g.n, 4) and sum(with_products[11:]) == comb(g.n, 5)
+    assert all(prods[st][2] > 0 for st in ("k4_triangles", "pairs_13_17", "wheels"))
+    assert with_products == walks
+    assert non_p == non_w

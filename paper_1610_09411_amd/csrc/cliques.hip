@@ -117,10 +117,9 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
             if (lane < nb) {
                 const int32_t p = earc[e];
                 const int64_t l0 = aoff[p], l1 = aoff[p + 1];
-                const int32_t b = adj[p];
-                int64_t hi = l1;   // first apex after b
+                int64_t hi = l1;   // first apex after b = adj[p]: the first arc of row a after p
                 lo = l0;
-                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
+                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (aa[mid] <= (uint32_t)p) lo = mid + 1; else hi = mid; }
                 cnt = (int)(l1 - lo);
             }
             int incl = cnt;
@@ -173,8 +172,8 @@ __global__ void __launch_bounds__(256) k_k4_triangles(int64_t m, const int32_t *
         if (l1 == l0) continue;
         const int32_t a = elo[e], b = adj[p];
         if (kdense && kdense[a]) continue;   // its triangles take the product (below)
-        int64_t lo = l0, hi = l1;   // first apex after b
-        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= b) lo = mid + 1; else hi = mid; }
+        int64_t lo = l0, hi = l1;   // first apex after b: the list holds arcs (a,c) of row a, after p
+        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (aa[mid] <= (uint32_t)p) lo = mid + 1; else hi = mid; }
         if (lo == l1) continue;
         const int32_t oa = off[a];
         const int32_t da_i = off[a + 1] - oa;
@@ -345,8 +344,8 @@ __global__ void __launch_bounds__(256) k_k4_lookup(const int32_t *off, const int
         const int64_t i = w - ap[lo];
         const int32_t sa = split[a], p = sa + (int32_t)i, b = adj[p];
         const int64_t l0 = aoff[p], l1 = aoff[p + 1];
-        int64_t kl = l0, kh = l1;   // first apex after b
-        while (kl < kh) { const int64_t mid = (kl + kh) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= b) kl = mid + 1; else kh = mid; }
+        int64_t kl = l0, kh = l1;   // first apex after b: the first arc of row a after p
+        while (kl < kh) { const int64_t mid = (kl + kh) >> 1; if (aa[mid] <= (uint32_t)p) kl = mid + 1; else kh = mid; }
         if (kl == l1) continue;
         nvis += (uint64_t)(l1 - kl);
         const int32_t e = arc_eid[p];

@@ -150,11 +150,12 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                             const int32_t pk = pb + y;
                             const int64_t e0 = aoff[pk];
                             const int64_t x = e0 + (f - (wrun[wid][y] - (int)(aoff[pk + 1] - e0)));
-                            if (apex_at<IDS>(av, adj, aa, x) > adj[pk]) {
-                                const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - e0)];   // arc (k,l) in row k
+                            if (aa[x] > (uint32_t)pk) {   // l > k, compared as arcs of row i (as below)
+                                const uint32_t ki = (uint32_t)rev[pk];   // arc (k,i) in row k
+                                const int32_t qkl = (int32_t)aa[aoff[ki] + (x - e0)];   // arc (k,l) in row k
                                 int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
                                 a1 = hi2;
-                                while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
+                                while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (aa[mid] <= ki) lo2 = mid + 1; else hi2 = mid; }
                                 a0 = lo2;
                             }
                         }
@@ -274,18 +275,26 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                         const int32_t pk = base + lo;
                         const int64_t e0 = aoff[pk];
                         const int64_t x = e0 + (f - pref[lo]);
-                        const int32_t l = apex_at<IDS>(av, adj, aa, x);
-                        const int32_t qkl = l > adj[pk] ? (int32_t)aa[aoff[rev[pk]] + (x - e0)] : 0;   // arc (k,l) in row k
+                        // the list of (i,k) holds the arcs (i,l) of row i and
+                        // rows are sorted, so l > k is aa[x] > pk; the list of
+                        // (k,l) holds arcs (k,j) of row k, so j > i is an entry
+                        // after the arc (k,i) = rev[pk]: no apex is read
+                        bool skip = aa[x] <= (uint32_t)pk;
+                        uint32_t ki = 0;
+                        int32_t qkl = 0;
+                        if (!skip) {
+                            ki = (uint32_t)rev[pk];
+                            qkl = (int32_t)aa[aoff[ki] + (x - e0)];   // arc (k,l) in row k
+                        }
                         // a hub source leaves the edges with many hub apexes
                         // to the hub-pair product (every j after it is a hub);
                         // such an edge has a number at its arc in the row of
                         // its earlier end
-                        bool skip = l <= adj[pk];
                         if (!skip && i >= hub0) skip = did[qkl] >= 0;
                         if (!skip) {
                             int64_t lo2 = aoff[qkl], hi2 = aoff[qkl + 1];
                             a1 = hi2;
-                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) <= i) lo2 = mid + 1; else hi2 = mid; }
+                            while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (aa[mid] <= ki) lo2 = mid + 1; else hi2 = mid; }
                             a0 = lo2;
                         }
                     }
@@ -514,16 +523,16 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                 }
                 for (int q = lane; q < (dh * dh + 1) / 2; q += 64) tt[q] = 0;
                 // lane a < d(h): rim vertex i = adj[oh + a] and its entries l below i
-                int32_t ia = 0;
+                // (lists hold arcs of row h, so "below i" is "before its arc")
+                const uint32_t ia = (uint32_t)(oh + lane);   // arc (h,i) in row h
                 long long la = 0;
                 int na = 0;
                 if (lane < dh) {
-                    ia = adj[oh + lane];
                     const int64_t l0 = aoff[oh + lane], l1 = aoff[oh + lane + 1];
                     la = l0;
                     if (l1 - l0 >= 2) {   // a rim 4-cycle needs two triangles on (h,i)
                         int64_t lo = l0, hi = l1;
-                        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < ia) lo = mid + 1; else hi = mid; }
+                        while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (aa[mid] < ia) lo = mid + 1; else hi = mid; }
                         na = (int)(lo - l0);
                     }
                 }
@@ -543,7 +552,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                     for (int sb = 32; sb > 0; sb >>= 1)
                         if (__shfl(incl, a + sb - 1) <= x) a += sb;
                     a = a < 63 ? a : 63;
-                    const int32_t iA = __shfl(ia, a);
+                    const uint32_t iA = (uint32_t)(oh + a);   // arc (h,i) of rim index a
                     const long long lA = __shfl(la, a);
                     const int eA = __shfl(incl, a) - __shfl(na, a);   // pairs before rim index a
                     int64_t b0 = 0, b1 = 0;
@@ -551,7 +560,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                         const int32_t qhl = (int32_t)aa[lA + (x - eA)];   // arc (h,l) in row h
                         b0 = aoff[qhl];
                         int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < iA) lo2 = mid + 1; else hi2 = mid; }
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (aa[mid] < iA) lo2 = mid + 1; else hi2 = mid; }
                         b1 = lo2;
                     }
                     nvis += (uint64_t)(b1 - b0);
@@ -572,11 +581,10 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
             for (int q = lane; q < (dh + 1) / 2; q += 64) wc[q] = 0;
             wave_sync();
             for (int32_t pi = oh + wid; pi < oh + dh; pi += nw) {
-                const int32_t i = adj[pi];
-                const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];
+                const int64_t l0 = aoff[pi], l1 = aoff[pi + 1];   // rim vertex i = adj[pi]
                 if (l1 - l0 < 2) continue;
-                int64_t lo = l0, hi = l1;
-                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo = mid + 1; else hi = mid; }
+                int64_t lo = l0, hi = l1;   // entries before the arc (h,i): apexes below i
+                while (lo < hi) { int64_t mid = (lo + hi) >> 1; if (aa[mid] < (uint32_t)pi) lo = mid + 1; else hi = mid; }
                 const int nl = (int)(lo - l0);
                 if (nl == 0) continue;
                 if (lane == 0) s_ntw[wid] = 0;
@@ -588,7 +596,7 @@ __global__ void __launch_bounds__(64 * WHEEL_WAVES) k_wheels(int32_t n, const in
                         const int32_t qhl = (int32_t)aa[l0 + x];       // arc (h,l) in row h
                         b0 = aoff[qhl];
                         int64_t lo2 = b0, hi2 = aoff[qhl + 1];
-                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (apex_at<IDS>(av, adj, aa, mid) < i) lo2 = mid + 1; else hi2 = mid; }
+                        while (lo2 < hi2) { int64_t mid = (lo2 + hi2) >> 1; if (aa[mid] < (uint32_t)pi) lo2 = mid + 1; else hi2 = mid; }
                         b1 = lo2;
                     }
                     nvis += (uint64_t)(b1 - b0);
@@ -1093,7 +1101,7 @@ __global__ void __launch_bounds__(256) k_hub_rows(const int32_t *off, const int3
         if (p < p1) { start = aoff[p]; len = (int)(aoff[p + 1] - start); }
         lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t x) {
             const int32_t pk = bp + s;
-            if (apex_at<IDS>(av, adj, aa, x) > adj[pk]) {
+            if (aa[x] > (uint32_t)pk) {   // l > k: the arc (i,l) after (i,k) in row i
                 const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - beg[s])];   // arc (k,l) in row k
                 const int64_t e = (int64_t)did[qkl] - base;
                 if (did[qkl] >= 0 && e >= 0 && e < 2 * (int64_t)kb) fp4_set_one(rowb, e);

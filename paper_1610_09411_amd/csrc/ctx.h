@@ -87,6 +87,7 @@ enum Buf {
     B_WD_Y, B_WD_META,          // their adjacency matrices (a batch of hubs) and batch tables
     B_K4_LIST, B_K4_CNT, B_K4_FLAG,   // 4-cliques of dense rows: candidates, count, chosen flags
     B_K4_Y, B_K4_META,          // their B_a and C_a matrices (a batch) and batch tables
+    B_TRIBIG,                   // triangles: vertices whose N+ takes a workgroup's hash set
     B_COUNT
 };
 

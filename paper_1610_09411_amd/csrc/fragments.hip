@@ -36,52 +36,193 @@ struct TriRec {
 #define TRI_REGIONS 256
 #define TRI_CSTRIDE 16   // u64 words between region counters (own cache lines)
 
+// the six list entries of triangle u<v<w from arcs p=(u,v) x=(u,w) y=(v,w),
+// each at a slot taken from its arc's cursor
+__device__ inline void tri_fill6(const int32_t *rev, unsigned long long *cur, uint32_t *aa, int32_t p, int32_t x,
+                                 int32_t y) {
+    const int32_t rp = rev[p], rx = rev[x], ry = rev[y];
+    aa[atomicAdd(&cur[p], 1ull)] = (uint32_t)x;    // list(u->v): apex w -> (u,w)
+    aa[atomicAdd(&cur[rp], 1ull)] = (uint32_t)y;   // list(v->u): apex w -> (v,w)
+    aa[atomicAdd(&cur[x], 1ull)] = (uint32_t)p;    // list(u->w): apex v -> (u,v)
+    aa[atomicAdd(&cur[rx], 1ull)] = (uint32_t)ry;  // list(w->u): apex v -> (w,v)
+    aa[atomicAdd(&cur[y], 1ull)] = (uint32_t)rp;   // list(v->w): apex u -> (v,u)
+    aa[atomicAdd(&cur[ry], 1ull)] = (uint32_t)rx;  // list(w->v): apex u -> (w,u)
+}
+
+__device__ inline void tri_record(TriRec *rec, unsigned long long *rec_n, int64_t rec_cap, int region, int32_t p,
+                                  int32_t x, int32_t y) {
+    const unsigned long long k = atomicAdd(&rec_n[region * TRI_CSTRIDE], 1ull);
+    if ((int64_t)k < rec_cap) {
+        TriRec *r = rec + (int64_t)region * rec_cap + (int64_t)k;
+        r->p = p;
+        r->x = x;
+        r->y = y;
+    } else {
+        atomicMax(&rec_n[TRI_REGIONS * TRI_CSTRIDE], 1ull);
+    }
+}
+
+__device__ inline unsigned long long shfl_u64(unsigned long long v, int src) {
+    const int lo = __shfl((int)(uint32_t)v, src), hi = __shfl((int)(uint32_t)(v >> 32), src);
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// One step of a wave's walk over the lists N+(v) of 64 out-arcs pb + y of u:
+// the lane's entry q (arc (v,w)) hit N+(u) at arc xw = (u,w), or xw < 0.  A
+// step's lanes holding the same list y are consecutive; the first hit among
+// them makes the one atomic the group needs on the arc pb + y (its count in
+// mode 0, the slots of the group's entries in the lists of that arc and of
+// its reverse in mode 1) and shares the result, so a dense list does not
+// send 64 atomics to one address.  Every active lane of the step calls it.
+// The active lanes need not be a prefix, nor their lists in order (the
+// walk's last steps): a group is a run of active lanes with one list, and a
+// lane whose lower neighbour is inactive starts one.
+__device__ inline void tri_step(int mode, int32_t pb, int yl, int64_t q, int32_t xw, const int32_t *rev,
+                                const int32_t *arc_eid, uint32_t *te, uint32_t *wcn, unsigned long long *cur,
+                                uint32_t *aa, TriRec *rec, unsigned long long *rec_n, int64_t rec_cap, int region) {
+    const int lane = threadIdx.x & 63;
+    const bool hit = xw >= 0;
+    const uint64_t hm = __ballot(hit);
+    if (hm == 0) return;
+    const uint64_t act = __ballot(1);
+    const bool below_act = lane > 0 && ((act >> (lane - 1)) & 1);
+    const int yprev = __shfl_up(yl, 1);
+    const uint64_t heads = __ballot(!below_act || yprev != yl);
+    const uint64_t before = (1ull << lane) - 1, upto = before | (1ull << lane);
+    const int h0 = 63 - __clzll(heads & upto);                 // first lane of the lane's list
+    const uint64_t later = heads & ~upto;                       // first lanes of the lists after it
+    const uint64_t grp = hm & (later ? (later & (0ull - later)) - 1 : ~0ull) & ~((1ull << h0) - 1);
+    const int rank = __popcll(grp & before), cnt = __popcll(grp);
+    const int lead = grp ? __ffsll((long long)grp) - 1 : lane;
+    const int32_t p = pb + yl, y = (int32_t)q;
+    if (mode == 0) {
+        if (hit) {
+            atomicAdd(&te[arc_eid[xw]], 1u);
+            atomicAdd(&te[arc_eid[y]], 1u);
+            if (rank == 0) atomicAdd(&wcn[yl], (uint32_t)cnt);
+            if (rec) tri_record(rec, rec_n, rec_cap, region, p, xw, y);
+        }
+        return;
+    }
+    unsigned long long s0 = 0, s1 = 0;
+    if (hit && rank == 0) {
+        s0 = atomicAdd(&cur[p], (unsigned long long)cnt);
+        s1 = atomicAdd(&cur[rev[p]], (unsigned long long)cnt);
+    }
+    s0 = shfl_u64(s0, lead);
+    s1 = shfl_u64(s1, lead);
+    if (hit) {
+        const int32_t rp = rev[p], rx = rev[xw], ry = rev[y];
+        aa[s0 + rank] = (uint32_t)xw;                     // list(u->v): apex w -> (u,w)
+        aa[s1 + rank] = (uint32_t)y;                      // list(v->u): apex w -> (v,w)
+        aa[atomicAdd(&cur[xw], 1ull)] = (uint32_t)p;      // list(u->w): apex v -> (u,v)
+        aa[atomicAdd(&cur[rx], 1ull)] = (uint32_t)ry;     // list(w->u): apex v -> (w,v)
+        aa[atomicAdd(&cur[y], 1ull)] = (uint32_t)rp;      // list(v->w): apex u -> (v,u)
+        aa[atomicAdd(&cur[ry], 1ull)] = (uint32_t)rx;     // list(w->v): apex u -> (w,u)
+    }
+}
+
+// Vertices with 2 d+(u) above a wave's table but at most 2^big_hbits (the
+// list big, *nbig of them) come first: workgroups take them from the counter
+// grab, and N+(u) goes into one hash set over the LDS of all four waves'
+// tables, which the waves probe as they walk the lists N+(v) of the out-arcs
+// (64 arcs a wave at a time, in turn).  A workgroup with no such vertex left
+// goes on to the others, so those vertices' triangles (in a dense core, most
+// of the graph's) are found while the rest of the grid works.  Larger N+
+// merge.
 __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off, const int32_t *adj,
                                                    const int32_t *split, const int32_t *arc_eid,
                                                    const int32_t *rev, uint32_t *te, int mode,
-                                                   unsigned long long *cur, uint32_t *aa, int hbits,
-                                                   TriRec *rec, unsigned long long *rec_n, int64_t rec_cap,
+                                                   unsigned long long *cur, uint32_t *aa, int hbits, int big_hbits,
+                                                   const int32_t *big, const unsigned long long *nbig,
+                                                   unsigned long long *grab, TriRec *rec,
+                                                   unsigned long long *rec_n, int64_t rec_cap,
                                                    unsigned long long *visits) {
     extern __shared__ uint32_t hdyn[];   // per wave: keys[H] then values[H]
     __shared__ int64_t wsa[4][64];
     __shared__ int32_t wse[4][64], wsi[4][64];
     __shared__ uint32_t wcn[4][64];
+    __shared__ int64_t s_t;
     uint64_t nvis = 0;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int H = 1 << hbits;
+    const int region = blockIdx.x % TRI_REGIONS;
+    auto fill6 = [&](int32_t p, int32_t x, int32_t y) { tri_fill6(rev, cur, aa, p, x, y); };
+    auto record = [&](int32_t p, int32_t x, int32_t y) { tri_record(rec, rec_n, rec_cap, region, p, x, y); };
+    wcn[wid][lane] = 0;
+    if (big_hbits > 0) {
+        // keys [0, 2^big_hbits), values after them: within the 4 x 2 x H words
+        const int HB = 1 << big_hbits;
+        uint32_t *bk = hdyn, *bv = hdyn + HB;
+        for (int q = threadIdx.x; q < HB; q += blockDim.x) bk[q] = 0;
+        const int64_t nb = (int64_t)*nbig;
+        for (;;) {
+            __syncthreads();   // the set is clear; s_t is free
+            if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(grab, 1ull);
+            __syncthreads();
+            const int64_t t = s_t;
+            if (t >= nb) break;
+            const int32_t u = big[t];
+            const int32_t su = split[u], eu = off[u + 1];
+            const int32_t dp = eu - su;   // 2^hbits < 2 dp <= 2^big_hbits
+            int lb = hbits;
+            while ((1 << lb) < 2 * dp) lb++;
+            const uint32_t lm = (1u << lb) - 1;
+            for (int32_t p = su + threadIdx.x; p < eu; p += blockDim.x) {
+                const uint32_t x = (uint32_t)adj[p];
+                uint32_t h = hash_slot(x, lb);
+                while (atomicCAS(&bk[h], 0u, x + 1) != 0u) h = (h + 1) & lm;
+                bv[h] = (uint32_t)p;
+            }
+            __syncthreads();
+            auto find = [&](uint32_t x) -> int32_t {
+                uint32_t h = hash_slot(x, lb);
+                for (;;) {
+                    const uint32_t k = bk[h];
+                    if (k == x + 1) return (int32_t)bv[h];
+                    if (k == 0) return -1;
+                    h = (h + 1) & lm;
+                }
+            };
+            for (int32_t pb = su + wid * 64; pb < eu; pb += nw * 64) {
+                const int32_t p = pb + lane;
+                int64_t a0 = 0, a1 = 0;
+                if (p < eu) {
+                    const int32_t v = adj[p];
+                    a0 = split[v];
+                    a1 = off[v + 1];
+                }
+                nvis += (uint64_t)(a1 - a0);
+                wave_walk_seg(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return (uint32_t)adj[q]; },
+                              [&](int yl, int64_t q, uint32_t w) {
+                                  // find: arc (u,w) in u's row, or -1
+                                  tri_step(mode, pb, yl, q, find(w), rev, arc_eid, te, wcn[wid], cur, aa, rec,
+                                           rec_n, rec_cap, region);
+                              });
+                if (mode == 0) {
+                    const uint32_t c = wcn[wid][lane];
+                    if (c) {
+                        atomicAdd(&te[arc_eid[p]], c);
+                        wcn[wid][lane] = 0;
+                    }
+                    wave_sync();
+                }
+            }
+            __syncthreads();   // every wave is done with the set
+            for (int q = threadIdx.x; q <= (int)lm; q += blockDim.x) bk[q] = 0;
+        }
+    }
     uint32_t *hk = hdyn + (size_t)wid * 2 * H, *hv = hk + H;
     for (int q = lane; q < H; q += 64) hk[q] = 0;
-    wcn[wid][lane] = 0;
     wave_sync();
     const int32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    // the six list entries of triangle u<v<w from arcs p=(u,v) x=(u,w) y=(v,w)
-    auto fill6 = [&](int32_t p, int32_t x, int32_t y) {
-        int32_t rp = rev[p], rx = rev[x], ry = rev[y];
-        aa[atomicAdd(&cur[p], 1ull)] = (uint32_t)x;    // list(u->v): apex w -> (u,w)
-        aa[atomicAdd(&cur[rp], 1ull)] = (uint32_t)y;   // list(v->u): apex w -> (v,w)
-        aa[atomicAdd(&cur[x], 1ull)] = (uint32_t)p;    // list(u->w): apex v -> (u,v)
-        aa[atomicAdd(&cur[rx], 1ull)] = (uint32_t)ry;  // list(w->u): apex v -> (w,v)
-        aa[atomicAdd(&cur[y], 1ull)] = (uint32_t)rp;   // list(v->w): apex u -> (v,u)
-        aa[atomicAdd(&cur[ry], 1ull)] = (uint32_t)rx;  // list(w->v): apex u -> (w,u)
-    };
-    const int region = blockIdx.x % TRI_REGIONS;
-    auto record = [&](int32_t p, int32_t x, int32_t y) {
-        const unsigned long long k = atomicAdd(&rec_n[region * TRI_CSTRIDE], 1ull);
-        if ((int64_t)k < rec_cap) {
-            TriRec *r = rec + (int64_t)region * rec_cap + (int64_t)k;
-            r->p = p;
-            r->x = x;
-            r->y = y;
-        } else {
-            atomicMax(&rec_n[TRI_REGIONS * TRI_CSTRIDE], 1ull);
-        }
-    };
     for (int32_t u = wave; u < n; u += nwaves) {
         const int32_t su = split[u], eu = off[u + 1];
         const int32_t dp = eu - su;
         if (dp < 2) continue;
         if (2 * dp > H) {
+            if (big_hbits > 0 && 2 * dp <= (1 << big_hbits)) continue;   // done in the first phase
             // merge fallback: lanes take the out-arcs u->v
             for (int32_t p = su + lane; p < eu; p += 64) {
                 const int32_t v = adj[p];
@@ -140,16 +281,9 @@ __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off
             nvis += (uint64_t)(a1 - a0);
             wave_walk_seg(a0, a1, wsa[wid], wse[wid], wsi[wid], [&](int64_t q) { return (uint32_t)adj[q]; },
                           [&](int yl, int64_t q, uint32_t w) {
-                              const int32_t xw = find(w);   // arc (u,w) in u's row
-                              if (xw < 0) return;
-                              if (mode == 0) {
-                                  atomicAdd(&te[arc_eid[xw]], 1u);
-                                  atomicAdd(&te[arc_eid[q]], 1u);
-                                  atomicAdd(&wcn[wid][yl], 1u);
-                                  if (rec) record(pb + yl, xw, (int32_t)q);
-                              } else {
-                                  fill6(pb + yl, xw, (int32_t)q);
-                              }
+                              // find: arc (u,w) in u's row, or -1
+                              tri_step(mode, pb, yl, q, find(w), rev, arc_eid, te, wcn[wid], cur, aa, rec, rec_n,
+                                       rec_cap, region);
                           });
             if (mode == 0) {
                 const uint32_t c = wcn[wid][lane];
@@ -164,6 +298,15 @@ __global__ void __launch_bounds__(256) k_triangles(int32_t n, const int32_t *off
         wave_sync();
     }
     if (visits) flush_count(nvis, visits);
+}
+
+// the vertices whose N+ takes a workgroup's hash set in k_triangles
+__global__ void k_tri_big_list(int32_t n, const int32_t *off, const int32_t *split, int hbits, int big_hbits,
+                               int32_t *big, unsigned long long *nbig) {
+    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const int32_t dp = off[u + 1] - split[u];
+        if (2 * dp > (1 << hbits) && 2 * dp <= (1 << big_hbits)) big[atomicAdd(nbig, 1ull)] = u;
+    }
 }
 
 // the six list entries of every recorded triangle u<v<w: it takes a slot on
@@ -243,7 +386,9 @@ esc_status stage_triangles(esc_ctx *c) {
     // Triangle records (12 B each, room for the bound sum C(d+(v),2)) when
     // they take at most an eighth of the free device memory and the lists
     // are not kept compact; otherwise the fill pass intersects again.
-    const size_t ncnt = TRI_REGIONS * TRI_CSTRIDE + TRI_CSTRIDE + 1;   // region counters, overflow word, bound
+    // region counters, overflow word, the two passes' grab counters of the
+    // big vertices, their count, bound
+    const size_t ncnt = TRI_REGIONS * TRI_CSTRIDE + TRI_CSTRIDE + 4;
     unsigned long long *rcnt = (unsigned long long *)ctx_buf(c, B_TRICNT, sizeof(uint64_t) * ncnt);
     if (!rcnt) return ESC_ENOMEM;
     HIP_TRY(hipMemsetAsync(rcnt, 0, sizeof(uint64_t) * ncnt, st));
@@ -262,8 +407,24 @@ esc_status stage_triangles(esc_ctx *c) {
         const size_t want = sizeof(TriRec) * (size_t)rcap * TRI_REGIONS;
         if (want <= (fr + ctx_held(c, B_TRIREC)) / 8) rec = (TriRec *)ctx_buf(c, B_TRIREC, want);
     }
-    k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr, hbits, rec, rcnt,
-                                      rec ? rcap : 0, work + WORK_VISITS + 1);
+    // vertices with 2 d+ above a wave's table take their workgroup's four
+    // (one set of at most 4 H slots: 2^13 with H = 2^11), listed first;
+    // larger ones merge
+    int big_hbits = 0;
+    int32_t *big = nullptr;
+    unsigned long long *nbig = rcnt + ncnt - 2;
+    if (2 * (int64_t)c->maxdplus > (1 << hbits)) {
+        big_hbits = hbits + 1;
+        while ((1 << big_hbits) < 2 * c->maxdplus && big_hbits < hbits + 2) big_hbits++;
+        // fewer than m / 2^(hbits-1) + 1 vertices have 2 d+ > 2^hbits
+        big = (int32_t *)ctx_buf(c, B_TRIBIG, sizeof(int32_t) * (size_t)(m / ((int64_t)1 << (hbits - 1)) + 1));
+        if (!big) return ESC_ENOMEM;
+        k_tri_big_list<<<grid_cap(c, n, 256), 256, 0, st>>>(n, off, split, hbits, big_hbits, big, nbig);
+        HIP_TRY(hipGetLastError());
+    }
+    k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 0, nullptr, nullptr, hbits, big_hbits,
+                                      big, nbig, rcnt + ncnt - 4, rec, rcnt, rec ? rcap : 0,
+                                      work + WORK_VISITS + 1);
     HIP_TRY(hipGetLastError());
     k_arc_len<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, arc_eid, te, len, tarc);
     HIP_TRY(hipGetLastError());
@@ -309,8 +470,8 @@ esc_status stage_triangles(esc_ctx *c) {
     } else {
         k_copy_cursor<<<grid_cap(c, m2, 256), 256, 0, st>>>(m2, aoff, cur);
         HIP_TRY(hipGetLastError());
-        k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, hbits, nullptr,
-                                          nullptr, 0, nullptr);
+        k_triangles<<<g, 256, hlds, st>>>(n, off, adj, split, arc_eid, rev, te, 1, cur, aa, hbits, big_hbits, big,
+                                          nbig, rcnt + ncnt - 3, nullptr, nullptr, 0, nullptr);
         HIP_TRY(hipGetLastError());
     }
     ESC_TRY(dev_segsort_u32(c, aa, aoff, m2, c->maxdeg));

@@ -613,3 +613,50 @@ def test_noninduced_and_work_counters(ctx):
             # them; the 5-clique pass, and so DBP, runs for k = 5 only)
             assert w["DP"] == S["DP"], (g.name, k)
             assert w["DBP"] == (S["DBP"] if k == 5 else 0), (g.name, k)
+
+
+def _big_core_graph(seed, core=2300, per=1500):
+    """A near-clique core (pairs missing with probability 0.03) and periphery
+    vertices tied to random fractions (up to 0.3) of it and sparsely to each
+    other; returns the graph and its dense 0/1 adjacency."""
+    rng = np.random.default_rng(seed)
+    n = core + per
+    p = np.full((n, n), 0.01)
+    p[:core, :core] = 0.97
+    p[:core, core:] = (rng.random(per) * 0.3)[None, :]
+    a = np.triu(rng.random((n, n)) < p, 1)
+    a = a | a.T
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(a.sum(1))
+    col = np.nonzero(a)[1].astype(np.int32)
+    return synth.Graph(n, rp, col, "big core %d" % seed), a
+
+
+def test_triangles_of_large_out_neighbourhoods(ctx):
+    """Thm 4vertex-tri on out-neighbourhoods too large for one wave's hash set
+    (d+ above 1024, up to beyond 2048: a workgroup's set of 2^12 or 2^13
+    slots): t of every arc equals (A^2)(u,v) and t of every vertex half the
+    diagonal of A^3, the definitions over the dense adjacency; sampled
+    per-edge K4 and C4 equal the oracle's; the 11 counts sum to C(n,4)."""
+    g, a = _big_core_graph(3)
+    deg = g.degrees()
+    rank = np.empty(g.n, np.int64)
+    rank[np.lexsort((np.arange(g.n), deg))] = np.arange(g.n)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    dplus = np.bincount(rows[rank[g.col] > rank[rows]], minlength=g.n)
+    assert dplus.max() > 2048 and ((dplus > 1024) & (dplus <= 2048)).any()
+    counts, fr = ctx.fragments(g, 4)
+    assert sum(counts) == comb(g.n, 4)
+    af = a.astype(np.float64)
+    a2 = af @ af
+    assert np.array_equal(fr["tri_e"], a2[rows, g.col].astype(np.uint64))
+    assert np.array_equal(fr["tri_v"], np.rint((a2 * af).sum(1) / 2).astype(np.uint64))
+    rng = random.Random(3)
+    big = [int(v) for v in np.argsort(-dplus)[:4]]
+    for v in big + [rng.randrange(g.n) for _ in range(8)]:
+        s, t = int(g.row_ptr[v]), int(g.row_ptr[v + 1])
+        for p in [s, t - 1, rng.randrange(s, t)]:
+            u = int(g.col[p])
+            exp = oracle.edge_fragments(g, v, u)
+            assert fr["k4_e"][p] == exp["k4"], (v, u)
+            assert fr["c4_e"][p] == exp["c4"], (v, u)

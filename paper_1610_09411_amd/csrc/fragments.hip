@@ -495,22 +495,22 @@ esc_status stage_triangles(esc_ctx *c) {
 //   (c-1) * c * (d(h) + d(o) - 4)  per key }
 // With per_edge set, pass 2 also adds c-1 to C4 of edges hk and ko.
 //
-// A top vertex with more than range_deg neighbours is split into tasks by
-// key range: task r counts the keys o in [gb + r*R, gb + (r+1)*R) (R = the
-// LDS slab in keys at h's packing), its pass 1 and 2 reading from every row
-// N(k) only the run of keys in the range (rows are sorted, so two binary
-// searches find it).  All keys of a task are in LDS, and the workgroups of
-// the chip share the few large tops in progress, whose rows stay in L2.
-// Smaller tops go one per workgroup: keys in the latest `slab` ranks of h's
-// graph are counted in LDS, the rest in the workgroup's dense table (relative
-// to the graph's first rank).
-__global__ void k_four_tasks(int32_t n, const int32_t *off, GMap gm, int32_t slab, int32_t range_deg, int64_t *len) {
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const int32_t d = off[v + 1] - off[v];
-        const int64_t keys = v - gm.begin(gm.graph(v));   // keys before v in its graph
-        const int64_t rk = (int64_t)slab << count_shift(d);
-        len[v] = d > range_deg && slab > 0 ? (keys + rk - 1) / rk : 0;
-    }
+// A top vertex with more than range_deg neighbours is taken by one workgroup
+// and counted by key range: range r holds the keys o in [gb + r*R,
+// gb + (r+1)*R) (R = the LDS slab in keys at h's packing), and passes 1 and 2
+// read from every row N(k) only the run of keys in the range, so all counts
+// of a range are in LDS.  Ranges go in key order, and each in-neighbour's run
+// starts where its previous one ended (a cursor per in-neighbour in the
+// workgroup's touched-key array, which pass 2 reads as well); the end is
+// found by galloping from the start, so an empty run costs one element read
+// (two binary searches per range and in-neighbour cost more than the runs
+// themselves).  Without room for the cursors each run is found by binary
+// searches.  Smaller tops go one per workgroup: keys in the latest `slab`
+// ranks of h's graph are counted in LDS, the rest in the workgroup's dense
+// table (relative to the graph's first rank).
+__global__ void k_four_tasks(int32_t n, const int32_t *off, int32_t slab, int32_t range_deg, int64_t *len) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        len[v] = off[v + 1] - off[v] > range_deg && slab > 0 ? 1 : 0;
 }
 
 __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *off, const int32_t *adj,
@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     const uint64_t slice_end = slice_end_of(slice_ticks);
     __shared__ int pref[513], tmp[16];
     __shared__ int64_t beg[513];
-    __shared__ int s_h, s_r, s_nt;
+    __shared__ int s_h, s_nt;
     __shared__ u128 red[3 * 8];
     __shared__ int64_t wsa[8][64];
     __shared__ int32_t wse[8][64], wsi[8][64];
@@ -538,20 +538,15 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
     u128 sums[3] = {0, 0, 0};
     int gcur = -1;
 
-    // large tops: one key range per task, latest tops first
+    // large tops: one per workgroup, latest tops first, key ranges in order
     for (;;) {
         if (threadIdx.x == 0) {
             const int64_t u = nbig - 1 - slice_grab(task_big, slice_end);
-            int32_t v = -1;
-            if (u >= 0) {
-                v = town[u];
-                s_r = (int)(u - toff[v]);
-            }
-            s_h = v;
+            s_h = u >= 0 ? town[u] : -1;
         }
         __syncthreads();
-        const int32_t h = s_h, r = s_r;
-        __syncthreads();   // s_h, s_r are read by every thread before they are taken again
+        const int32_t h = s_h;
+        __syncthreads();   // s_h is read by every thread before it is taken again
         if (h < 0) break;
         const int g = gm.graph(h);
         block_switch_graph<3>(sums, gcur, g, red, acc, ACC_STRIDE, ids);
@@ -561,85 +556,105 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
         const int cb = 32 >> shift;
         const uint32_t cmask = cb == 32 ? 0xFFFFFFFFu : (1u << cb) - 1u;
         const int64_t rk = (int64_t)slab << shift;
-        const int32_t o0 = (int32_t)(gm.begin(g) + r * rk);
-        const int32_t o1 = (int32_t)(o0 + rk < h ? o0 + rk : h);
-        const int32_t nwd = ((o1 - o0) + (1 << shift) - 1) >> shift;
-        for (int q = threadIdx.x; q < nwd; q += blockDim.x) sl[q] = 0;
-        __syncthreads();
-        auto slot = [&](int32_t o, uint32_t &s) -> uint32_t * {
-            const int32_t idx = o - o0;
-            s = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
-            return &sl[idx >> shift];
-        };
-        // the run of row k below h with keys in [o0, o1)
-        auto run = [&](int32_t p, int64_t &start, int &len) {
-            start = 0;
-            len = 0;
-            if (p < sh) {
-                const int32_t k = adj[p];
-                const int a = lower_bound_i32(adj, off[k], rev[p], o0);
-                const int b = lower_bound_i32(adj, a, rev[p], o1);
-                start = a;
-                len = b - a;
-            }
-        };
-        // pass 1 keeps the runs in the workgroup's touched-key array (free
-        // until the smaller tops), two ints per in-neighbour, for pass 2
+        const int32_t gb = gm.begin(g);
+        const int32_t nr = (int32_t)(((int64_t)(h - gb) + rk - 1) / rk);
+        // the cursors: start and length of each in-neighbour's last run
         const bool keep = 2 * (int64_t)(sh - oh) <= tab_n;
-        // pass 1: counts
-        for (int32_t base = oh; base < sh; base += blockDim.x) {
-            int64_t start;
-            int len;
-            run(base + threadIdx.x, start, len);
-            if (keep && base + (int32_t)threadIdx.x < sh) {
-                touch[2 * (base + threadIdx.x - oh)] = (int32_t)start;
-                touch[2 * (base + threadIdx.x - oh) + 1] = len;
-            }
-            lbs_batch(start, len, pref, beg, tmp, [&](int, int64_t q) {
-                uint32_t s;
-                uint32_t *w = slot(adj[q], s);
-                nvis++;
-                atomicAdd(w, 1u << s);
-            });
-        }
-        __syncthreads();
-        // pass 2: per-wedge terms
-        for (int32_t base = oh; base < sh; base += blockDim.x) {
-            int64_t start = 0;
-            int len = 0;
-            if (!keep) {
-                run(base + threadIdx.x, start, len);
-            } else if (base + (int32_t)threadIdx.x < sh) {
-                start = touch[2 * (base + threadIdx.x - oh)];
-                len = touch[2 * (base + threadIdx.x - oh) + 1];
-            }
-            lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t q) {
-                const int32_t pk = base + s;
-                uint32_t sb;
-                const uint32_t cc = (*slot(adj[q], sb) >> sb) & cmask;
-                if (cc >= 2) {
-                    const int32_t k = adj[pk];
-                    sums[1] += (uint64_t)(cc - 1) * (tarc[pk] + tarc[q]);
-                    sums[2] += (uint64_t)(cc - 1) * (uint64_t)(2 * (off[k + 1] - off[k]) - 4);
-                    if (c4e) {
-                        atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
-                        atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
-                    }
+        for (int32_t r = 0; r < nr; r++) {
+            const int32_t o0 = (int32_t)(gb + r * rk);
+            const int32_t o1 = (int32_t)(o0 + rk < h ? o0 + rk : h);
+            const int32_t nwd = ((o1 - o0) + (1 << shift) - 1) >> shift;
+            __syncthreads();   // the previous range's pass 3 is done with the slab
+            for (int q = threadIdx.x; q < nwd; q += blockDim.x) sl[q] = 0;
+            __syncthreads();
+            auto slot = [&](int32_t o, uint32_t &s) -> uint32_t * {
+                const int32_t idx = o - o0;
+                s = (uint32_t)((idx & ((1 << shift) - 1)) * cb);
+                return &sl[idx >> shift];
+            };
+            // the run of row k below h with keys in [o0, o1)
+            auto run = [&](int32_t p, int64_t &start, int &len) {
+                start = 0;
+                len = 0;
+                if (p >= sh) return;
+                const int32_t k = adj[p];
+                int32_t a;
+                if (!keep) {
+                    a = lower_bound_i32(adj, off[k], rev[p], o0);
+                } else {
+                    const int32_t i = 2 * (p - oh);
+                    a = r == 0 ? off[k] : touch[i] + touch[i + 1];   // rows hold only keys of k's graph
                 }
-            });
-        }
-        // pass 3: per-key terms (the next task clears the slab behind a barrier)
-        for (int q = threadIdx.x; q < nwd; q += blockDim.x) {
-            const uint32_t x = sl[q];
-            if (x == 0) continue;
-            for (int f = 0; f < (1 << shift); f++) {
-                const uint64_t cc = (x >> (f * cb)) & cmask;
-                if (cc < 2) continue;
-                const int32_t o = o0 + (q << shift) + f;
-                sums[0] += c2(cc);
-                sums[2] += (u128)(cc - 1) * cc * (uint64_t)(dh + (off[o + 1] - off[o]) - 4);
+                // first key >= o1 in [a, rev[p]): gallop from a, then halve
+                const int64_t lim = rev[p];
+                int64_t b = a;
+                if (a < lim && adj[a] < o1) {
+                    int64_t lo = a, step = 1;   // adj[lo] < o1
+                    while (lo + step < lim && adj[lo + step] < o1) { lo += step; step <<= 1; }
+                    int64_t hi = lo + step < lim ? lo + step : lim;
+                    lo++;
+                    while (lo < hi) { const int64_t mid = (lo + hi) >> 1; if (adj[mid] < o1) lo = mid + 1; else hi = mid; }
+                    b = lo;
+                }
+                start = a;
+                len = (int)(b - a);
+                if (keep) {
+                    touch[2 * (p - oh)] = a;
+                    touch[2 * (p - oh) + 1] = len;
+                }
+            };
+            // pass 1: counts
+            for (int32_t base = oh; base < sh; base += blockDim.x) {
+                int64_t start;
+                int len;
+                run(base + threadIdx.x, start, len);
+                lbs_batch(start, len, pref, beg, tmp, [&](int, int64_t q) {
+                    uint32_t s;
+                    uint32_t *w = slot(adj[q], s);
+                    nvis++;
+                    atomicAdd(w, 1u << s);
+                });
+            }
+            __syncthreads();
+            // pass 2: per-wedge terms
+            for (int32_t base = oh; base < sh; base += blockDim.x) {
+                int64_t start = 0;
+                int len = 0;
+                if (!keep) {
+                    run(base + threadIdx.x, start, len);
+                } else if (base + (int32_t)threadIdx.x < sh) {
+                    start = touch[2 * (base + threadIdx.x - oh)];
+                    len = touch[2 * (base + threadIdx.x - oh) + 1];
+                }
+                lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t q) {
+                    const int32_t pk = base + s;
+                    uint32_t sb;
+                    const uint32_t cc = (*slot(adj[q], sb) >> sb) & cmask;
+                    if (cc >= 2) {
+                        const int32_t k = adj[pk];
+                        sums[1] += (uint64_t)(cc - 1) * (tarc[pk] + tarc[q]);
+                        sums[2] += (uint64_t)(cc - 1) * (uint64_t)(2 * (off[k + 1] - off[k]) - 4);
+                        if (c4e) {
+                            atomicAdd(&c4e[arc_eid[pk]], (unsigned long long)(cc - 1));
+                            atomicAdd(&c4e[arc_eid[q]], (unsigned long long)(cc - 1));
+                        }
+                    }
+                });
+            }
+            // pass 3: per-key terms
+            for (int q = threadIdx.x; q < nwd; q += blockDim.x) {
+                const uint32_t x = sl[q];
+                if (x == 0) continue;
+                for (int f = 0; f < (1 << shift); f++) {
+                    const uint64_t cc = (x >> (f * cb)) & cmask;
+                    if (cc < 2) continue;
+                    const int32_t o = o0 + (q << shift) + f;
+                    sums[0] += c2(cc);
+                    sums[2] += (u128)(cc - 1) * cc * (uint64_t)(dh + (off[o + 1] - off[o]) - 4);
+                }
             }
         }
+        __syncthreads();   // the touched-key array is read until pass 2 of the last range ends
     }
 
     if (pw_words > 0) {
@@ -867,8 +882,8 @@ esc_status stage_four(esc_ctx *c, bool per_edge_c4) {
     int64_t *len = (int64_t *)ctx_buf(c, B_EOFF, sizeof(int64_t) * (size_t)(n + 2));
     int64_t *toff = (int64_t *)ctx_buf(c, B_K5_UNITS, sizeof(int64_t) * (size_t)(n + 2));
     if (!len || !toff) return ESC_ENOMEM;
-    k_four_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], gmap_of(c), slab,
-                                                      c->four_range_deg, len);
+    k_four_tasks<<<grid_cap(c, n, 256), 256, 0, st>>>(n, (const int32_t *)c->buf[B_OFF], slab, c->four_range_deg,
+                                                      len);
     HIP_TRY(hipGetLastError());
     ESC_TRY(dev_exclusive_scan_i64(c, len, toff, n));
     int64_t nbig = 0;

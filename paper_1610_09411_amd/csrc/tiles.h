@@ -107,8 +107,12 @@ __device__ inline bool hub_patch_tile(int nb, int patch, int within, int *ti, in
 // the loop: the wheel products took 10.1 s against 6.4 s with eight waves
 // of 128 x 64 on the 4M-vertex graph, so eight it is.  Operands pass
 // through two LDS buffers: the loads of the next step's bytes are in
-// flight while the current step computes.  Every thread of the workgroup
-// calls it.
+// flight while the current step computes.  A step moves as many bytes
+// through LDS (64 KB in, 192 KB of fragments out) as its products take
+// cycles on the matrix cores; reading the second operand's fragments from
+// memory into registers instead, one step ahead, cut that to 160 KB but
+// left the products waiting on L2 (wheels 3.4 -> 5.8 s).  Every thread of
+// the workgroup calls it.
 __device__ inline void hub_tile(lds_u8 *lds, const uint8_t *y, int32_t kb, int ti, int tj,
                                 hub_v4f (&cacc)[8][HUB_BC]) {
     const uint8_t *ya = y + (size_t)ti * HUB_T * kb, *yb = y + (size_t)tj * HUB_T * kb;

@@ -186,12 +186,20 @@ __device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg
     if (len > 0 && ex + len == total) tmp[blockDim.x / ESC_WAVE + 1] = threadIdx.x;
     __syncthreads();
     const int last = total > 0 ? tmp[blockDim.x / ESC_WAVE + 1] : 0;
+    // the element's segment: the last one whose prefix is <= x.  A thread's
+    // x only grow, so the search goes on from its previous segment: one
+    // read while x stays in it, else a gallop and a halving past it.
+    int lo = 0;
     for (int x = threadIdx.x; x < total; x += blockDim.x) {
-        // last segment whose prefix is <= x
-        int lo = 0, hi = last;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (pref[mid] <= x) lo = mid; else hi = mid - 1;
+        if (lo < last && pref[lo + 1] <= x) {
+            int a = lo + 1, step = 1;   // pref[a] <= x
+            while (a + step <= last && pref[a + step] <= x) { a += step; step <<= 1; }
+            int hi = a + step <= last ? a + step - 1 : last;
+            while (a < hi) {
+                const int mid = (a + hi + 1) >> 1;
+                if (pref[mid] <= x) a = mid; else hi = mid - 1;
+            }
+            lo = a;
         }
         item(lo, beg[lo] + (x - pref[lo]));
     }

@@ -188,8 +188,10 @@ __device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg
     const int last = total > 0 ? tmp[blockDim.x / ESC_WAVE + 1] : 0;
     // the element's segment: the last one whose prefix is <= x.  A thread's
     // x only grow, so the search goes on from its previous segment: one
-    // read while x stays in it, else a gallop and a halving past it.
+    // read while x stays in it (the segment's offset start - prefix stays
+    // in a register), else a gallop and a halving past it.
     int lo = 0;
+    int64_t base = beg[0] - pref[0];
     for (int x = threadIdx.x; x < total; x += blockDim.x) {
         if (lo < last && pref[lo + 1] <= x) {
             int a = lo + 1, step = 1;   // pref[a] <= x
@@ -200,8 +202,9 @@ __device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg
                 if (pref[mid] <= x) a = mid; else hi = mid - 1;
             }
             lo = a;
+            base = beg[lo] - pref[lo];
         }
-        item(lo, beg[lo] + (x - pref[lo]));
+        item(lo, base + x);
     }
     __syncthreads();
 }

@@ -263,14 +263,21 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                 pref[threadIdx.x] = ex;
                 if (threadIdx.x == 0) pref[blockDim.x] = total;
                 __syncthreads();
+                int lo = 0;   // the arc whose entries hold f: f only grows, so
+                              // its search goes on from the previous arc
                 for (int fb = 0; fb < total; fb += nw * 64) {
                     const int f = fb + lane * nw + wid;
                     int64_t a0 = 0, a1 = 0;
                     if (f < total) {
-                        int lo = 0, hi = blockDim.x - 1;   // the arc whose entries hold f
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (pref[mid] <= f) lo = mid; else hi = mid - 1;
+                        if (pref[lo + 1] <= f) {
+                            int a = lo + 1, step = 1, lim = (int)blockDim.x - 1;   // pref[a] <= f
+                            while (a + step <= lim && pref[a + step] <= f) { a += step; step <<= 1; }
+                            int hi = a + step <= lim ? a + step - 1 : lim;
+                            while (a < hi) {
+                                const int mid = (a + hi + 1) >> 1;
+                                if (pref[mid] <= f) a = mid; else hi = mid - 1;
+                            }
+                            lo = a;
                         }
                         const int32_t pk = base + lo;
                         const int64_t e0 = aoff[pk];

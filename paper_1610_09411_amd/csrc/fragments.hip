@@ -18,7 +18,8 @@
 // (key: rank, value: position of the arc in u's row); the lanes take 64
 // out-arcs u->v at a time and the wave walks the 64 lists N+(v) together,
 // probing every entry x: a hit is the triangle u<v<x, found once, from its
-// first arc.  Vertices whose N+ does not fit the table fall back to one
+// first arc.  Vertices whose N+ does not fit a wave's table take a whole
+// workgroup's (k_triangles' first phase); beyond that they fall back to one
 // merge per lane.
 // mode 0: count t(e) (atomics on the three edges)
 // mode 1: write the six per-arc list entries through per-arc cursors

@@ -257,7 +257,7 @@ struct SegCursor {
 // sa/se/si are 64-entry LDS arrays private to the calling wave (the
 // segments of one call hold fewer than 2^31 elements in all).  Every lane
 // of the wave must call it.
-template <class L, class U>
+template <int NU = 8, class L, class U>
 __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
     const int lane = threadIdx.x & (ESC_WAVE - 1);
     const int32_t len = (int32_t)(a1 - a0);
@@ -274,7 +274,7 @@ __device__ inline void wave_walk_seg(int64_t a0, int64_t a1, int64_t *sa, int32_
     SegCursor c;
     c.init(sa, se, si);
     int32_t e = lane;
-    constexpr int NU = 8;   // steps in flight
+    // NU steps in flight
     for (; e + (NU - 1) * ESC_WAVE < total; e += NU * ESC_WAVE) {
         int64_t q[NU];
         int yy[NU];
@@ -345,9 +345,9 @@ __device__ inline void wave_walk_act(int64_t a0, int64_t a1, int64_t *sa, int32_
 }
 
 // wave_walk_seg with use(value) only
-template <class L, class U>
+template <int NU = 8, class L, class U>
 __device__ inline void wave_walk(int64_t a0, int64_t a1, int64_t *sa, int32_t *se, int32_t *si, L load, U use) {
-    wave_walk_seg(a0, a1, sa, se, si, load, [&](int, int64_t, decltype(load(a0)) v) { use(v); });
+    wave_walk_seg<NU>(a0, a1, sa, se, si, load, [&](int, int64_t, decltype(load(a0)) v) { use(v); });
 }
 
 // Same walk as wave_walk, counting for every segment the elements x with

@@ -307,7 +307,9 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
                     }
                     nvis += (uint64_t)(a1 - a0);
                     uint64_t acc17 = 0;
-                    wave_walk(a0, a1, wsa[wid], wse[wid], wsi[wid],
+                    // twelve steps in flight: each element of compact lists is
+                    // two dependent loads
+                    wave_walk<IDS ? 8 : 12>(a0, a1, wsa[wid], wse[wid], wsi[wid],
                               [&](int64_t q) { return apex_at<IDS>(av, adj, aa, q); },
                               [&](int32_t j) { acc17 += (uint64_t)(j >= hi0 ? SLAB_GET(j) : TAB_GET(j)) - 2; });
                     sv[1] += acc17;

@@ -221,6 +221,54 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// lbs_batch with the element's read split from its use: load(q) reads the
+// element at position q, use(s, q, v) consumes it.  A thread takes U of its
+// elements at a time and issues their reads before any use, so U reads are
+// in flight where an atomic use would otherwise wait for each read in turn.
+template <int U, class L, class Use>
+__device__ inline void lbs_batch_lu(int64_t start, int len, int *pref, int64_t *beg, int *tmp, L load, Use use) {
+    int total;
+    int ex = block_exclusive_scan(len, tmp, &total);
+    pref[threadIdx.x] = ex;
+    beg[threadIdx.x] = start;
+    if (threadIdx.x == 0) pref[blockDim.x] = total;
+    if (len > 0 && ex + len == total) tmp[blockDim.x / ESC_WAVE + 1] = threadIdx.x;
+    __syncthreads();
+    const int last = total > 0 ? tmp[blockDim.x / ESC_WAVE + 1] : 0;
+    int lo = 0;
+    int64_t base = beg[0] - pref[0];
+    const int stride = (int)blockDim.x;
+    for (int x0 = threadIdx.x; x0 < total; x0 += U * stride) {
+        int ss[U];
+        int64_t qq[U];
+        decltype(load((int64_t)0)) vv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int x = x0 + u * stride;
+            if (x < total && lo < last && pref[lo + 1] <= x) {
+                int a = lo + 1, step = 1;   // pref[a] <= x
+                while (a + step <= last && pref[a + step] <= x) { a += step; step <<= 1; }
+                int hi = a + step <= last ? a + step - 1 : last;
+                while (a < hi) {
+                    const int mid = (a + hi + 1) >> 1;
+                    if (pref[mid] <= x) a = mid; else hi = mid - 1;
+                }
+                lo = a;
+                base = beg[lo] - pref[lo];
+            }
+            ss[u] = lo;
+            qq[u] = base + x;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (x0 + u * stride < total) vv[u] = load(qq[u]);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (x0 + u * stride < total) use(ss[u], qq[u], vv[u]);
+    }
+    __syncthreads();
+}
+
 // A lane's place in the concatenation of a wave's 64 segments (LDS arrays
 // sa = first position, se = exclusive and si = inclusive element prefix):
 // the segment y holding element e is the first with si[y] > e.  Its end and

@@ -609,12 +609,13 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                 int64_t start;
                 int len;
                 run(base + threadIdx.x, start, len);
-                lbs_batch(start, len, pref, beg, tmp, [&](int, int64_t q) {
-                    uint32_t s;
-                    uint32_t *w = slot(adj[q], s);
-                    nvis++;
-                    atomicAdd(w, 1u << s);
-                });
+                nvis += (uint64_t)len;
+                lbs_batch_lu<4>(start, len, pref, beg, tmp, [&](int64_t q) { return adj[q]; },
+                                [&](int, int64_t, int32_t o) {
+                                    uint32_t s;
+                                    uint32_t *w = slot(o, s);
+                                    atomicAdd(w, 1u << s);
+                                });
             }
             __syncthreads();
             // pass 2: per-wedge terms
@@ -627,10 +628,11 @@ __global__ void __launch_bounds__(512) k_four_cycles(int32_t n, const int32_t *o
                     start = touch[2 * (base + threadIdx.x - oh)];
                     len = touch[2 * (base + threadIdx.x - oh) + 1];
                 }
-                lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t q) {
+                lbs_batch_lu<4>(start, len, pref, beg, tmp, [&](int64_t q) { return adj[q]; },
+                                [&](int s, int64_t q, int32_t o) {
                     const int32_t pk = base + s;
                     uint32_t sb;
-                    const uint32_t cc = (*slot(adj[q], sb) >> sb) & cmask;
+                    const uint32_t cc = (*slot(o, sb) >> sb) & cmask;
                     if (cc >= 2) {
                         const int32_t k = adj[pk];
                         sums[1] += (uint64_t)(cc - 1) * (tarc[pk] + tarc[q]);

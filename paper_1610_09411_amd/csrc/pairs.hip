@@ -229,11 +229,11 @@ __global__ void __launch_bounds__(512) k_pairs_wd(int32_t n, const int32_t *off,
             int start = 0, len = 0;
             if (p < ei) { int32_t k = adj[p]; start = rev[p] + 1; len = off[k + 1] - start; }
             nvis += (uint64_t)len;
-            lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
-                int32_t j = adj[q];
-                if (j >= hi0) SLAB_INC(j);
-                else if (TAB_INC(j) == 0) touch[atomicAdd(&s_nt, 1)] = j;
-            });
+            lbs_batch_lu<4>(start, len, pref, beg, tmp, [&](int64_t q) { return adj[q]; },
+                            [&](int, int64_t, int32_t j) {
+                                if (j >= hi0) SLAB_INC(j);
+                                else if (TAB_INC(j) == 0) touch[atomicAdd(&s_nt, 1)] = j;
+                            });
         }
         __syncthreads();
         // a hub source keeps its row W(i, j) over the later hubs for the
@@ -835,12 +835,12 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
             int32_t p = base + threadIdx.x;
             int start = 0, len = 0;
             if (p < si) { int32_t a = adj[p]; start = split[a]; len = off[a + 1] - split[a]; }
-            lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
-                int32_t b = adj[q];
-                nvis++;
-                if (b == i) return;
-                if (inc(sX, Xt, b) == 0) tx[atomicAdd(&s_nx, 1)] = b;
-            });
+            nvis += (uint64_t)len;
+            lbs_batch_lu<4>(start, len, pref, beg, tmp, [&](int64_t q) { return adj[q]; },
+                            [&](int, int64_t, int32_t b) {
+                                if (b == i) return;
+                                if (inc(sX, Xt, b) == 0) tx[atomicAdd(&s_nx, 1)] = b;
+                            });
         }
         __syncthreads();
         if (s_nx == 0) continue;   // s_nw is still zero; the next write of s_nx is behind a barrier
@@ -867,8 +867,8 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                     int start = 0, len = 0;
                     if (xi < nx) { const int32_t b = tx[xi]; start = split[b]; len = off[b + 1] - split[b]; }
                     nvis += (uint64_t)len;
-                    lbs_batch(start, len, pref, beg, tmp,
-                              [&](int s, int q) { yadd(adj[q], get(sX, Xt, tx[base + s])); });
+                    lbs_batch_lu<4>(start, len, pref, beg, tmp, [&](int64_t q) { return adj[q]; },
+                                    [&](int s, int64_t, int32_t j) { yadd(j, get(sX, Xt, tx[base + s])); });
                 }
             } else {
                 const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
@@ -901,12 +901,12 @@ __global__ void __launch_bounds__(512) k_five_cycles(int32_t n, const int32_t *o
                     if (cv < i) { start = off[cv]; len = off[cv + 1] - off[cv]; }
                     else { start = split[cv]; len = off[cv + 1] - split[cv]; }
                 }
-                lbs_batch(start, len, pref, beg, tmp, [&](int, int q) {
-                    const int32_t j = adj[q];
-                    nvis++;
-                    if (j == i) return;
-                    part += j >= hy ? sW[j - hy] : Wt[j - gb];
-                });
+                nvis += (uint64_t)len;
+                lbs_batch_lu<4>(start, len, pref, beg, tmp, [&](int64_t q) { return adj[q]; },
+                                [&](int, int64_t, int32_t j) {
+                                    if (j == i) return;
+                                    part += j >= hy ? sW[j - hy] : Wt[j - gb];
+                                });
             }
             sc[0] += part;
             __syncthreads();
@@ -1108,9 +1108,10 @@ __global__ void __launch_bounds__(256) k_hub_rows(const int32_t *off, const int3
         int64_t start = 0;
         int len = 0;
         if (p < p1) { start = aoff[p]; len = (int)(aoff[p + 1] - start); }
-        lbs_batch(start, len, pref, beg, tmp, [&](int s, int64_t x) {
+        lbs_batch_lu<4>(start, len, pref, beg, tmp, [&](int64_t x) { return aa[x]; },
+                        [&](int s, int64_t x, uint32_t ax) {
             const int32_t pk = bp + s;
-            if (aa[x] > (uint32_t)pk) {   // l > k: the arc (i,l) after (i,k) in row i
+            if (ax > (uint32_t)pk) {   // l > k: the arc (i,l) after (i,k) in row i
                 const int32_t qkl = (int32_t)aa[aoff[rev[pk]] + (x - beg[s])];   // arc (k,l) in row k
                 const int64_t e = (int64_t)did[qkl] - base;
                 if (did[qkl] >= 0 && e >= 0 && e < 2 * (int64_t)kb) fp4_set_one(rowb, e);

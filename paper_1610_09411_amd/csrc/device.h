@@ -173,37 +173,49 @@ __device__ inline int slice_grab(int *task, uint64_t slice_end) {
 // start_s + r) is visited exactly once, spread evenly over the block.
 // `pref` and `beg` are LDS arrays of blockDim+1 entries, `tmp` as above
 // with two more entries (blockDim / 64 + 2 in all).
-template <class Item>
-__device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg, int *tmp, Item item) {
+//
+// lbs_setup publishes the batch (prefixes, starts, total) and returns the
+// total and the last non-empty segment (the one whose inclusive prefix
+// reaches total: every later segment starts at total > x, so it bounds the
+// searches; tmp[nw + 1] is free once the scan has returned).
+__device__ inline int lbs_setup(int64_t start, int len, int *pref, int64_t *beg, int *tmp, int *last) {
     int total;
     int ex = block_exclusive_scan(len, tmp, &total);
     pref[threadIdx.x] = ex;
     beg[threadIdx.x] = start;
     if (threadIdx.x == 0) pref[blockDim.x] = total;
-    // the last non-empty segment (the one whose inclusive prefix reaches
-    // total) bounds the search: every later segment starts at total > x.
-    // tmp[nw + 1] is free once the scan has returned.
     if (len > 0 && ex + len == total) tmp[blockDim.x / ESC_WAVE + 1] = threadIdx.x;
     __syncthreads();
-    const int last = total > 0 ? tmp[blockDim.x / ESC_WAVE + 1] : 0;
-    // the element's segment: the last one whose prefix is <= x.  A thread's
-    // x only grow, so the search goes on from its previous segment: one
-    // read while x stays in it (the segment's offset start - prefix stays
-    // in a register), else a gallop and a halving past it.
+    *last = total > 0 ? tmp[blockDim.x / ESC_WAVE + 1] : 0;
+    return total;
+}
+
+// element x's segment: the last one whose prefix is <= x.  A thread's x only
+// grow, so the search goes on from its previous segment lo: one read while x
+// stays in it (the segment's offset start - prefix stays in `base`), else a
+// gallop and a halving past it.
+__device__ inline void lbs_advance(const int *pref, const int64_t *beg, int last, int x, int &lo, int64_t &base) {
+    if (lo < last && pref[lo + 1] <= x) {
+        int a = lo + 1, step = 1;   // pref[a] <= x
+        while (a + step <= last && pref[a + step] <= x) { a += step; step <<= 1; }
+        int hi = a + step <= last ? a + step - 1 : last;
+        while (a < hi) {
+            const int mid = (a + hi + 1) >> 1;
+            if (pref[mid] <= x) a = mid; else hi = mid - 1;
+        }
+        lo = a;
+        base = beg[lo] - pref[lo];
+    }
+}
+
+template <class Item>
+__device__ inline void lbs_batch(int64_t start, int len, int *pref, int64_t *beg, int *tmp, Item item) {
+    int last;
+    const int total = lbs_setup(start, len, pref, beg, tmp, &last);
     int lo = 0;
     int64_t base = beg[0] - pref[0];
     for (int x = threadIdx.x; x < total; x += blockDim.x) {
-        if (lo < last && pref[lo + 1] <= x) {
-            int a = lo + 1, step = 1;   // pref[a] <= x
-            while (a + step <= last && pref[a + step] <= x) { a += step; step <<= 1; }
-            int hi = a + step <= last ? a + step - 1 : last;
-            while (a < hi) {
-                const int mid = (a + hi + 1) >> 1;
-                if (pref[mid] <= x) a = mid; else hi = mid - 1;
-            }
-            lo = a;
-            base = beg[lo] - pref[lo];
-        }
+        lbs_advance(pref, beg, last, x, lo, base);
         item(lo, base + x);
     }
     __syncthreads();
@@ -227,14 +239,8 @@ __device__ inline void wave_sync() {
 // in flight where an atomic use would otherwise wait for each read in turn.
 template <int U, class L, class Use>
 __device__ inline void lbs_batch_lu(int64_t start, int len, int *pref, int64_t *beg, int *tmp, L load, Use use) {
-    int total;
-    int ex = block_exclusive_scan(len, tmp, &total);
-    pref[threadIdx.x] = ex;
-    beg[threadIdx.x] = start;
-    if (threadIdx.x == 0) pref[blockDim.x] = total;
-    if (len > 0 && ex + len == total) tmp[blockDim.x / ESC_WAVE + 1] = threadIdx.x;
-    __syncthreads();
-    const int last = total > 0 ? tmp[blockDim.x / ESC_WAVE + 1] : 0;
+    int last;
+    const int total = lbs_setup(start, len, pref, beg, tmp, &last);
     int lo = 0;
     int64_t base = beg[0] - pref[0];
     const int stride = (int)blockDim.x;
@@ -245,17 +251,7 @@ __device__ inline void lbs_batch_lu(int64_t start, int len, int *pref, int64_t *
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int x = x0 + u * stride;
-            if (x < total && lo < last && pref[lo + 1] <= x) {
-                int a = lo + 1, step = 1;   // pref[a] <= x
-                while (a + step <= last && pref[a + step] <= x) { a += step; step <<= 1; }
-                int hi = a + step <= last ? a + step - 1 : last;
-                while (a < hi) {
-                    const int mid = (a + hi + 1) >> 1;
-                    if (pref[mid] <= x) a = mid; else hi = mid - 1;
-                }
-                lo = a;
-                base = beg[lo] - pref[lo];
-            }
+            if (x < total) lbs_advance(pref, beg, last, x, lo, base);
             ss[u] = lo;
             qq[u] = base + x;
         }
